@@ -1,0 +1,285 @@
+"""Seeded synthetic workloads for the LBM - immersed-boundary capsule solver.
+
+This module only generates inputs: lattice sizes, wall speeds, the uniform
+body force that drives a periodic channel, capsule node coordinates and the
+membrane constants handed to the solver.  It performs no step of the method
+(no equilibrium, collision, interpolation, spreading or membrane force).  Both
+the HIP library and the FP64 reference consume the dictionaries built here.
+
+Shapes follow the paper's test cases (Sec. 3.1 shear capsule, Sec. 3.2-3.3
+Poiseuille capsules, Eq. 26 biconcave outline); every random draw comes from
+``numpy.random.default_rng(seed)`` in the order documented in each builder.
+
+Units are lattice units: dx = dt = 1, reference density 1, c_s^2 = 1/3, so the
+kinematic viscosity is nu = (tau - 1/2)/3 (Sec. 2.1).
+"""
+from __future__ import annotations
+
+import math
+from typing import Any, Dict, List
+
+import numpy as np
+
+# init_profile codes understood by both implementations
+INIT_REST = 0
+INIT_COUETTE = 1      # linear profile between the two wall speeds
+INIT_POISEUILLE = 2   # u(y) = g/(2 nu) * y * (H - y), H = ny - 1
+INIT_UNIFORM = 3      # uniform (ux, uy) everywhere (fully periodic boxes)
+
+
+def viscosity(tau: float) -> float:
+    """Lattice kinematic viscosity for relaxation time tau (Sec. 2.1)."""
+    return (tau - 0.5) / 3.0
+
+
+def poiseuille_body_force(tau: float, ny: int, u_max: float) -> float:
+    """Uniform x-force that gives peak speed u_max in a channel with on-node walls
+    at y = 0 and y = ny - 1 (channel height H = ny - 1):  g = 8 nu u_max / H^2."""
+    H = ny - 1
+    return 8.0 * viscosity(tau) * u_max / (H * H)
+
+
+def ks_from_ca(tau: float, u_max: float, ca: float, rho_ref: float = 1.0) -> float:
+    """Capillary-number definition Ca = nu rho u_max / k_s (Sec. 2.2.1)."""
+    return viscosity(tau) * rho_ref * u_max / ca
+
+
+def ks_from_g(tau: float, shear_rate: float, diameter: float, g_num: float,
+              rho_ref: float = 1.0) -> float:
+    """Dimensionless shear rate G = nu rho gamma d / k_s (Sec. 2.2.1, Sec. 3.1)."""
+    return viscosity(tau) * rho_ref * shear_rate * diameter / g_num
+
+
+def polygon_area(nodes: np.ndarray) -> float:
+    """Signed area of a closed polygon (positive for counter-clockwise order).
+    Used only to turn a density ratio into the capsule mass handed to the solver."""
+    x, y = nodes[:, 0], nodes[:, 1]
+    return 0.5 * float(np.sum(x * np.roll(y, -1) - np.roll(x, -1) * y))
+
+
+def circle_nodes(cx: float, cy: float, radius: float, n: int, phase: float = 0.5) -> np.ndarray:
+    """n counter-clockwise nodes on a circle at angles 2 pi (k + phase) / n.
+    phase = 0.5 keeps nodes off the symmetry axes, so no node sits exactly on a
+    half-integer lattice coordinate for the centred shear case."""
+    ang = 2.0 * math.pi * (np.arange(n) + phase) / n
+    return np.stack([cx + radius * np.cos(ang), cy + radius * np.sin(ang)], axis=1)
+
+
+def _resample_closed(curve: np.ndarray, n: int) -> np.ndarray:
+    """Place n points equispaced in arc length along a densely sampled closed curve."""
+    closed = np.vstack([curve, curve[:1]])
+    seg = np.hypot(np.diff(closed[:, 0]), np.diff(closed[:, 1]))
+    s = np.concatenate([[0.0], np.cumsum(seg)])
+    targets = np.arange(n) * (s[-1] / n)
+    x = np.interp(targets, s, closed[:, 0])
+    y = np.interp(targets, s, closed[:, 1])
+    return np.stack([x, y], axis=1)
+
+
+def biconcave_nodes(cx: float, cy: float, length: float, n: int, angle: float = 0.0,
+                    dense: int = 40000) -> np.ndarray:
+    """Biconcave outline of Eq. 26 with the printed alpha/2 thickness factor.
+
+    x = (L/2) sin q,  y = (L/4)(0.207 + 2.003 sin^2 q - 1.123 sin^4 q) cos q,
+    q in [-pi/2, 3pi/2).  The paper's a*alpha only sets the scale, so it is
+    chosen to make the long axis equal to ``length``.  As printed, increasing q
+    runs clockwise; the samples are reversed to counter-clockwise order, then
+    n nodes are placed equispaced in arc length and the shape is rotated by
+    ``angle`` about its centre and moved to (cx, cy)."""
+    q = -0.5 * math.pi + 2.0 * math.pi * np.arange(dense) / dense
+    s = np.sin(q)
+    half = 0.5 * length
+    x = half * s
+    y = 0.5 * half * (0.207 + 2.003 * s * s - 1.123 * s ** 4) * np.cos(q)
+    curve = np.stack([x, y], axis=1)[::-1]
+    pts = _resample_closed(curve, n)
+    c, sn = math.cos(angle), math.sin(angle)
+    rot = np.stack([c * pts[:, 0] - sn * pts[:, 1], sn * pts[:, 0] + c * pts[:, 1]], axis=1)
+    return rot + np.array([cx, cy])
+
+
+def capsule(nodes: np.ndarray, ks: float, kb: float = 0.0, ka: float = 1.0,
+            density_ratio: float = 1.0) -> Dict[str, Any]:
+    """Capsule record: nodes (n, 2) FP64 counter-clockwise, per-element stiffness
+    (a scalar here), bending and area constants, and the total membrane mass
+    m = (rho_s / rho_f) * rho_ref * A0 spread evenly over the n nodes (Eq. 21)."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    return {
+        "nodes": nodes,
+        "ks": float(ks),
+        "kb": float(kb),
+        "ka": float(ka),
+        "mass": float(density_ratio * polygon_area(nodes)),
+        "density_ratio": float(density_ratio),
+    }
+
+
+def _base(name: str, nx: int, ny: int, tau: float, real_bytes: int, mode: str, steps: int,
+          **kw: Any) -> Dict[str, Any]:
+    cfg = {
+        "name": name, "nx": nx, "ny": ny, "tau": tau, "real_bytes": real_bytes,
+        "periodic_y": 0, "u_bottom": 0.0, "u_top": 0.0, "body_force_x": 0.0,
+        "init_profile": INIT_REST, "init_u": (0.0, 0.0), "mode": mode, "steps": steps,
+        "capsules": [],
+    }
+    cfg.update(kw)
+    return cfg
+
+
+# ---------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------
+
+def shear_capsule(nx: int = 64, ny: int = 64, tau: float = 1.0, u_wall: float = 0.01,
+                  radius: float = 8.0, n_nodes: int = 64, g_num: float = 0.05,
+                  eb: float = 0.05, mode: str = "kinematic", steps: int = 2000,
+                  real_bytes: int = 8) -> Dict[str, Any]:
+    """Circular capsule centred in a wall-driven shear flow (Sec. 3.1 analogue).
+
+    Walls at y = 0 and y = ny-1 move at -u_wall and +u_wall; x is periodic; the
+    fluid starts from the linear profile.  Stiffness from the G form with
+    gamma = 2 u_wall / H and d = 2R; k_b = E_b k_s R^2; density ratio 1."""
+    H = ny - 1
+    gamma = 2.0 * u_wall / H
+    ks = ks_from_g(tau, gamma, 2.0 * radius, g_num)
+    kb = eb * ks * radius * radius
+    cx, cy = 0.5 * (nx - 1), 0.5 * H
+    caps = [capsule(circle_nodes(cx, cy, radius, n_nodes), ks, kb, 1.0, 1.0)]
+    return _base("shear64", nx, ny, tau, real_bytes, mode, steps,
+                 u_bottom=-u_wall, u_top=u_wall, init_profile=INIT_COUETTE, capsules=caps)
+
+
+def poiseuille_biconcave(ca: float, nx: int = 1024, ny: int = 256, tau: float = 0.8,
+                         u_max: float = 0.02, length: float = 40.0, n_nodes: int = 128,
+                         centre=(256.0, None), steps: int = 20000, mode: str = "dynamic",
+                         real_bytes: int = 4) -> Dict[str, Any]:
+    """Biconcave capsule in a body-force-driven periodic channel (Sec. 3.3 analogue).
+
+    Centre height 6.5/15 of the channel (the paper's lowest start, Sec. 3.2);
+    fluid starts from the analytic parabola; E_b = 0, k_a = 1, density ratio 1."""
+    H = ny - 1
+    g = poiseuille_body_force(tau, ny, u_max)
+    cx = centre[0]
+    cy = centre[1] if centre[1] is not None else 6.5 / 15.0 * H
+    ks = ks_from_ca(tau, u_max, ca)
+    caps = [capsule(biconcave_nodes(cx, cy, length, n_nodes), ks, 0.0, 1.0, 1.0)]
+    return _base(f"poiseuille_biconcave_ca{ca:g}", nx, ny, tau, real_bytes, mode, steps,
+                 body_force_x=g, init_profile=INIT_POISEUILLE, capsules=caps)
+
+
+def stability_ratio(ks: float, mass: float, n_nodes: int) -> float:
+    """Gershgorin bound on half the largest spring-network eigenvalue over the
+    nodal mass, 2 k_s / m_v: the explicit node update needs it below 2."""
+    return 2.0 * ks / (mass / n_nodes)
+
+
+def inertial_capsules(seed: int = 0, nx: int = 2048, ny: int = 512, n_caps: int = 32,
+                      tau: float = 0.8, u_max: float = 0.02, steps: int = 50000,
+                      screen_limit: float = 1.5, real_bytes: int = 4,
+                      mode: str = "dynamic", max_tries: int = 200000) -> Dict[str, Any]:
+    """32 circular or biconcave capsules in a periodic channel.
+
+    Draw order per capsule, from default_rng(seed): shape (biconcave if
+    u < 0.5), node count U{96..160}, radius U[6, 12] (biconcave half-length),
+    orientation U[0, 2 pi), density ratio U[1, 2], log10 Ca U[-3, -1], centre x
+    U[0, nx), centre y U[R + 4, H - R - 4].  A draw is rejected (and drawn
+    again) if its bounding circle comes within 3 lu of an earlier capsule, or if
+    its stability ratio 2 k_s / m_v exceeds ``screen_limit``."""
+    rng = np.random.default_rng(seed)
+    H = ny - 1
+    g = poiseuille_body_force(tau, ny, u_max)
+    caps: List[Dict[str, Any]] = []
+    placed: List[tuple] = []
+    tries = 0
+    while len(caps) < n_caps:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("could not place all capsules")
+        biconcave = rng.uniform() < 0.5
+        n = int(rng.integers(96, 161))
+        R = float(rng.uniform(6.0, 12.0))
+        angle = float(rng.uniform(0.0, 2.0 * math.pi))
+        ratio = float(rng.uniform(1.0, 2.0))
+        ca = float(10.0 ** rng.uniform(-3.0, -1.0))
+        cx = float(rng.uniform(0.0, nx))
+        cy = float(rng.uniform(R + 4.0, H - R - 4.0))
+        ok = True
+        for (px, py, pr) in placed:
+            dx = abs(cx - px)
+            dx = min(dx, nx - dx)
+            if math.hypot(dx, cy - py) < R + pr + 3.0:
+                ok = False
+                break
+        if not ok:
+            continue
+        if biconcave:
+            nodes = biconcave_nodes(cx, cy, 2.0 * R, n, angle)
+        else:
+            nodes = circle_nodes(cx, cy, R, n, phase=0.5)
+        ks = ks_from_ca(tau, u_max, ca)
+        cap = capsule(nodes, ks, 0.0, 1.0, ratio)
+        if stability_ratio(ks, cap["mass"], n) > screen_limit:
+            continue
+        cap.update({"shape": "biconcave" if biconcave else "circle", "radius": R, "ca": ca})
+        caps.append(cap)
+        placed.append((cx, cy, R))
+    return _base(f"inertial{n_caps}_{nx}x{ny}", nx, ny, tau, real_bytes, mode, steps,
+                 body_force_x=g, init_profile=INIT_POISEUILLE, capsules=caps)
+
+
+def fused_bench(seed: int = 0, n: int = 4096, n_caps: int = 32, steps: int = 1000,
+                tau: float = 0.8, u_max: float = 0.02) -> Dict[str, Any]:
+    """n x n channel with the capsules of ``inertial_capsules`` (2048 x 512 draw)
+    moved to the larger domain by scaling their centres (x by n/2048, y by the
+    ratio of channel heights).  Shapes and constants are unchanged."""
+    base = inertial_capsules(seed=seed, n_caps=n_caps, tau=tau, u_max=u_max)
+    sx = n / 2048.0
+    sy = (n - 1) / 511.0
+    caps = []
+    for cap in base["capsules"]:
+        nodes = cap["nodes"]
+        c = nodes.mean(axis=0)
+        shift = np.array([c[0] * (sx - 1.0), c[1] * (sy - 1.0)])
+        new = dict(cap)
+        new["nodes"] = np.ascontiguousarray(nodes + shift)
+        caps.append(new)
+    g = poiseuille_body_force(tau, n, u_max)
+    return _base(f"fused{n}x{n}_{n_caps}caps", n, n, tau, 4, "dynamic", steps,
+                 body_force_x=g, init_profile=INIT_POISEUILLE, capsules=caps)
+
+
+def grid_bench(n: int = 4096, tau: float = 0.8, u_max: float = 0.02, steps: int = 1000) -> Dict[str, Any]:
+    """n x n channel without capsules (grid-only roofline case)."""
+    g = poiseuille_body_force(tau, n, u_max)
+    return _base(f"grid{n}x{n}", n, n, tau, 4, "dynamic", steps,
+                 body_force_x=g, init_profile=INIT_POISEUILLE)
+
+
+def adjoint_channel(nx: int = 512, ny: int = 128, tau: float = 0.8, u_max: float = 0.02,
+                    radius: float = 10.0, n_nodes: int = 96, ca: float = 1e-2,
+                    steps: int = 5000) -> Dict[str, Any]:
+    """Circular capsule at 0.4 H in a 512 x 128 channel (the differentiated case)."""
+    H = ny - 1
+    g = poiseuille_body_force(tau, ny, u_max)
+    ks = ks_from_ca(tau, u_max, ca)
+    caps = [capsule(circle_nodes(128.0, 0.4 * H, radius, n_nodes), ks, 0.0, 1.0, 1.0)]
+    return _base("adjoint512x128", nx, ny, tau, 4, "dynamic", steps,
+                 body_force_x=g, init_profile=INIT_POISEUILLE, capsules=caps)
+
+
+def periodic_box(nx: int, ny: int, tau: float, u0=(0.0, 0.0), real_bytes: int = 8,
+                 mode: str = "dynamic", steps: int = 10) -> Dict[str, Any]:
+    """Fully periodic box at uniform velocity u0 (no walls, no body force)."""
+    return _base(f"box{nx}x{ny}", nx, ny, tau, real_bytes, mode, steps, periodic_y=1,
+                 init_profile=INIT_UNIFORM, init_u=tuple(float(v) for v in u0))
+
+
+def random_populations(nx: int, ny: int, seed: int, amp: float = 0.02) -> np.ndarray:
+    """Seeded non-equilibrium population field, layout [9][ny][nx] FP64.
+
+    Each population is a typical magnitude (4/9 rest, 1/9 axis, 1/36 diagonal)
+    times (1 + amp * N(0, 1)): positive, of realistic size, and far from any
+    equilibrium, so every term of a collision is exercised."""
+    rng = np.random.default_rng(seed)
+    mag = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    return mag[:, None, None] * (1.0 + amp * rng.standard_normal((9, ny, nx)))

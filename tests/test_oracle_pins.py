@@ -1,0 +1,433 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test ties one part of the oracle to something other than the oracle's
+own formulas: lattice identities, closed-form flows, MLS reproduction
+properties, conservation laws, energy gradients, polygon closed forms,
+symmetry, and the paper's printed values (tests/golden/paper_values.json).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1903_03356_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
+
+
+def lattice_from_eq3():
+    """Velocities of Eq. 3 evaluated from their trigonometric definition."""
+    e = [(0, 0)]
+    for i in range(1, 5):
+        a = (i - 1) * math.pi / 2
+        e.append((round(math.cos(a)), round(math.sin(a))))
+    for i in range(5, 9):
+        a = (2 * i - 9) * math.pi / 4
+        e.append((round(math.sqrt(2) * math.cos(a)), round(math.sqrt(2) * math.sin(a))))
+    w = json.load(open(GOLDEN))["lattice_weights"]["value"]
+    wts = [w[0]] + [w[1]] * 4 + [w[2]] * 4
+    return np.array(e, dtype=float), np.array(wts)
+
+
+E, WTS = lattice_from_eq3()
+
+
+# ---------------------------------------------------------------- P1, P2 ----
+
+def test_p1_equilibrium_moments(orc):
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        rho = 1 + 0.1 * rng.standard_normal()
+        u = 0.05 * rng.standard_normal(2)
+        f = orc.equilibrium(rho, u[0], u[1])
+        assert abs(f.sum() - rho) < 1e-14
+        np.testing.assert_allclose(f @ E, rho * u, atol=1e-15)
+        second = np.einsum("i,ia,ib->ab", f, E, E)
+        np.testing.assert_allclose(second, rho * (np.eye(2) / 3 + np.outer(u, u)), atol=1e-15)
+    assert abs(WTS.sum() - 1) < 1e-15
+
+
+def test_p2_forcing_moments(orc):
+    rng = np.random.default_rng(2)
+    for tau in (0.6, 0.8, 1.3):
+        for _ in range(10):
+            u = 0.05 * rng.standard_normal(2)
+            F = 1e-3 * rng.standard_normal(2)
+            s = orc.forcing(tau, u[0], u[1], F[0], F[1])
+            pre = 1 - 1 / (2 * tau)
+            assert abs(s.sum()) < 1e-17
+            np.testing.assert_allclose(s @ E, pre * F, atol=1e-18)
+            second = np.einsum("i,ia,ib->ab", s, E, E)
+            np.testing.assert_allclose(second, pre * (np.outer(u, F) + np.outer(F, u)), atol=1e-18)
+
+
+def test_p2_one_step_adds_force_periodic(orc):
+    """Fully periodic box, uniform force g: one step adds exactly N g of momentum."""
+    nx, ny = 12, 9
+    g = 3e-5
+    cfg = wl._base("box", nx, ny, 0.7, 8, "kinematic", 1, periodic_y=1, body_force_x=g)
+    sim = orc.Sim(cfg)
+    sim.set_pops(wl.random_populations(nx, ny, seed=3))
+    f0 = sim.pops()
+    p0 = np.einsum("iyx,ia->a", f0, E)
+    m0 = f0.sum()
+    sim.step(1)
+    f1 = sim.pops()
+    p1 = np.einsum("iyx,ia->a", f1, E)
+    assert abs(f1.sum() - m0) < 1e-12 * m0
+    # momentum sums of ~100 cells of O(0.1): rounding ~1e-15
+    np.testing.assert_allclose(p1 - p0, [nx * ny * g, 0.0], atol=2e-14)
+
+
+# ---------------------------------------------------------------- P3 --------
+
+def test_p3_mass_conserved_with_ib_forcing(orc):
+    """Periodic box with a deforming capsule: total mass constant to rounding."""
+    nx, ny = 40, 32
+    cfg = wl.periodic_box(nx, ny, 0.8, u0=(0.01, 0.0), mode="kinematic")
+    nodes = wl.circle_nodes(20.2, 15.7, 6.0, 48)
+    stretched = nodes.copy()
+    stretched[:, 0] = 20.2 + 1.2 * (nodes[:, 0] - 20.2)
+    cfg["capsules"] = [wl.capsule(nodes, 0.02, 0.002, 1.0)]
+    sim = orc.Sim(cfg)
+    sim.set_pops(wl.random_populations(nx, ny, seed=5))
+    sim.set_capsule(0, stretched, stretched, np.zeros_like(stretched))
+    m0 = sim.pops().sum()
+    sim.step(50)
+    assert abs(sim.pops().sum() - m0) < 1e-13 * m0
+    assert sim.status == 0
+
+
+# ---------------------------------------------------------------- P4, P5 ----
+
+@pytest.mark.parametrize("tau", [0.6, 0.8, 1.0])
+def test_p4_poiseuille_closed_form(orc, tau):
+    """Body-force channel with Zou-He walls converges to g/(2 nu) y (H - y)."""
+    ny, g = 17, 1e-6
+    cfg = wl._base("p", 4, ny, tau, 8, "kinematic", 0, body_force_x=g)
+    sim = orc.Sim(cfg)
+    sim.step(40000)
+    nu = (tau - 0.5) / 3
+    y = np.arange(ny)
+    ua = g / (2 * nu) * y * (ny - 1 - y)
+    m = sim.moments()
+    assert np.abs(m[1] - ua[:, None]).max() < 1e-10 * ua.max()
+    assert np.abs(m[2]).max() < 1e-14
+
+
+def test_p5_couette_closed_form(orc):
+    ny = 17
+    cfg = wl._base("c", 4, ny, 0.8, 8, "kinematic", 0, u_bottom=-0.01, u_top=0.02)
+    sim = orc.Sim(cfg)
+    sim.step(40000)
+    y = np.arange(ny)
+    ua = -0.01 + 0.03 * y / (ny - 1)
+    m = sim.moments()
+    assert np.abs(m[1] - ua[:, None]).max() < 1e-12
+    assert np.abs(m[2]).max() < 1e-14
+
+
+def test_p4_init_profile_is_analytic(orc):
+    """The Poiseuille start state carries the analytic profile (plus half of g)."""
+    cfg = wl.poiseuille_biconcave(1e-2, nx=16, ny=33)
+    cfg["capsules"] = []
+    sim = orc.Sim(cfg)
+    m = sim.moments()
+    nu = (cfg["tau"] - 0.5) / 3
+    g = cfg["body_force_x"]
+    y = np.arange(33)
+    ua = g / (2 * nu) * y * (32 - y)
+    # walls carry the Zou-He velocity exactly; interior: equilibrium + g/2
+    assert np.abs(m[1, 0]).max() < 1e-16 and np.abs(m[1, -1]).max() < 1e-16
+    np.testing.assert_allclose(m[1, 1:-1], (ua[1:-1] + 0.5 * g)[:, None] * np.ones((1, 16)),
+                               rtol=0, atol=1e-16)
+
+
+# ---------------------------------------------------------------- P6 --------
+
+def test_p6_mls_reproduction(orc):
+    rng = np.random.default_rng(6)
+    for _ in range(200):
+        x, y = rng.uniform(5, 50, 2)
+        cells, phi, dx, dy = orc.mls(x, y)
+        # support: 3x3 around the nearest node (ties up)
+        c0 = np.array([math.floor(x + 0.5), math.floor(y + 0.5)])
+        assert set(map(tuple, cells - c0)) == {(a, b) for a in (-1, 0, 1) for b in (-1, 0, 1)}
+        assert abs(phi.sum() - 1) < 1e-14
+        np.testing.assert_allclose(phi @ cells, [x, y], atol=1e-12)
+        # gradient rows reproduce the gradient of linear fields exactly
+        np.testing.assert_allclose([dx.sum(), dy.sum()], [0, 0], atol=1e-13)
+        np.testing.assert_allclose(dx @ cells, [1, 0], atol=1e-12)
+        np.testing.assert_allclose(dy @ cells, [0, 1], atol=1e-12)
+        # a random linear field and its gradient
+        a, b, c = rng.standard_normal(3)
+        vals = a + b * cells[:, 0] + c * cells[:, 1]
+        assert abs(phi @ vals - (a + b * x + c * y)) < 1e-11
+        assert abs(dx @ vals - b) < 1e-12 and abs(dy @ vals - c) < 1e-12
+
+
+def test_p6_mls_node_centred_closed_form(orc):
+    """At a lattice node the symmetric support makes the moment matrix diagonal,
+    so phi_k = W_k / sum W (Eq. 9 weight with r_w, alpha as printed)."""
+    gv = json.load(open(GOLDEN))
+    rw, alpha = gv["mls_support_side"]["value"], gv["mls_alpha"]["value"]
+    cells, phi, _, _ = orc.mls(17.0, 23.0)
+    r = np.hypot(cells[:, 0] - 17.0, cells[:, 1] - 23.0) / rw
+    W = np.exp(-(r / alpha) ** 2)
+    np.testing.assert_allclose(phi, W / W.sum(), atol=1e-15)
+    assert abs(phi.max() - 0.5201545) < 1e-7
+
+
+# ---------------------------------------------------------------- P7 --------
+
+def test_p7_spread_conserves_force_and_is_adjoint(orc):
+    nx, ny = 32, 24
+    cfg = wl.periodic_box(nx, ny, 0.8)
+    sim = orc.Sim(cfg)
+    rng = np.random.default_rng(7)
+    field = np.zeros((3, ny, nx))
+    field[0] = 1.0
+    field[1:] = rng.standard_normal((2, ny, nx))
+    sim.set_moments(field)
+    n = 25
+    xy = np.stack([rng.uniform(0, nx, n), rng.uniform(0, ny, n)], 1)
+    c = rng.uniform(0.2, 1.5, n)
+    F = rng.standard_normal((n, 2))
+    fib = sim.spread(xy, c, F)
+    np.testing.assert_allclose(fib.sum(axis=(1, 2)), (c[:, None] * F).sum(0), atol=1e-12)
+    U = sim.interpolate(xy)
+    lhs = np.sum(fib * field[1:])
+    rhs = np.sum(c[:, None] * F * U)
+    assert abs(lhs - rhs) < 1e-11 * max(1, abs(rhs))
+
+
+# ---------------------------------------------------------------- P8, P9 ----
+
+def _stress_free(nodes):
+    nv = len(nodes)
+    nxt = np.roll(nodes, -1, 0)
+    prv = np.roll(nodes, 1, 0)
+    l0 = np.hypot(*(nxt - nodes).T)
+    a = nodes - prv
+    b = nxt - nodes
+    th = np.arctan2(a[:, 0] * b[:, 1] - a[:, 1] * b[:, 0], (a * b).sum(1))
+    return l0, th, wl.polygon_area(nodes)
+
+
+def _perturbed(seed, nv=40):
+    rng = np.random.default_rng(seed)
+    ref = wl.circle_nodes(10.0, 12.0, 5.0, nv)
+    cur = ref + 0.15 * rng.standard_normal(ref.shape)
+    ks = rng.uniform(0.5, 2.0, nv)
+    return ref, cur, ks
+
+
+def test_p8_zero_net_force_and_torque(orc):
+    ref, cur, ks = _perturbed(8)
+    l0, th0, A0 = _stress_free(ref)
+    for part in orc.internal_forces(cur, l0, th0, ks, 0.3, 1.0, A0):
+        np.testing.assert_allclose(part.sum(0), [0, 0], atol=1e-13)
+        r = cur - cur.mean(0)
+        torque = np.sum(r[:, 0] * part[:, 1] - r[:, 1] * part[:, 0])
+        assert abs(torque) < 1e-12
+    for part in orc.internal_forces(ref, l0, th0, ks, 0.3, 1.0, A0):
+        assert np.abs(part).max() < 1e-14
+
+
+def _energies(x, l0, th0, ks, kb, ka, A0):
+    """Stretch (Eq. 10), bending (reading of Eq. 12-13: k_b(1 - cos)) and the
+    area-penalty energy k_a p_ref (A - A0)^2 / (2 A0) whose gradient Eq. 14 is."""
+    nxt = np.roll(x, -1, 0)
+    prv = np.roll(x, 1, 0)
+    l = np.hypot(*(nxt - x).T)
+    es = 0.5 * np.sum(ks * (l - l0) ** 2)
+    a = x - prv
+    b = nxt - x
+    th = np.arctan2(a[:, 0] * b[:, 1] - a[:, 1] * b[:, 0], (a * b).sum(1))
+    eb = kb * np.sum(1 - np.cos(th - th0))
+    A = wl.polygon_area(x)
+    ea = ka * (1 / 3) * (A - A0) ** 2 / (2 * A0)
+    return es, eb, ea
+
+
+def test_p9_forces_are_energy_gradients(orc):
+    ref, cur, ks = _perturbed(9, nv=24)
+    l0, th0, A0 = _stress_free(ref)
+    kb, ka = 0.37, 1.0
+    fs, fb, fa = orc.internal_forces(cur, l0, th0, ks, kb, ka, A0)
+    h = 1e-6
+    for v in range(len(cur)):
+        for d in range(2):
+            xp, xm = cur.copy(), cur.copy()
+            xp[v, d] += h
+            xm[v, d] -= h
+            ep = _energies(xp, l0, th0, ks, kb, ka, A0)
+            em = _energies(xm, l0, th0, ks, kb, ka, A0)
+            grad = [(p - m) / (2 * h) for p, m in zip(ep, em)]
+            for F, gr in zip((fs, fb, fa), grad):
+                assert abs(F[v, d] + gr) < 1e-8 * max(1.0, abs(gr)), (v, d)
+
+
+# ---------------------------------------------------------------- P10 -------
+
+@pytest.mark.parametrize("N", [3, 5, 12, 64])
+def test_p10_regular_polygon(orc, N):
+    R = 7.3
+    x = wl.circle_nodes(3.0, -2.0, R, N, phase=0.13)
+    d = orc.polygon_diag(x)
+    assert abs(d["Sw"] - (math.pi / N) / math.tan(math.pi / N)) < 1e-13
+    assert abs(d["perimeter"] - 2 * N * R * math.sin(math.pi / N)) < 1e-12
+    assert abs(d["area"] - 0.5 * N * R * R * math.sin(2 * math.pi / N)) < 1e-11
+    assert abs(d["D"]) < 1e-9
+    assert abs(d["cx"] - 3.0) < 1e-12 and abs(d["cy"] + 2.0) < 1e-12
+
+
+@pytest.mark.parametrize("N,a,b,rot", [(3, 2.0, 1.0, 0.3), (7, 5.0, 4.0, 1.1), (64, 9.0, 3.0, -0.4)])
+def test_p10_affine_polygon_taylor(orc, N, a, b, rot):
+    u = wl.circle_nodes(0.0, 0.0, 1.0, N, phase=0.37)
+    p = u * np.array([a, b])
+    c, s = math.cos(rot), math.sin(rot)
+    p = p @ np.array([[c, s], [-s, c]]) + np.array([40.0, 20.0])
+    d = orc.polygon_diag(p)
+    assert abs(d["D"] - (a - b) / (a + b)) < 1e-12
+
+
+def test_p11_biconcave_swelling_ratio(orc):
+    """Eq. 26 as printed gives Sw0 = 0.4609, not the 0.481 printed beside it."""
+    gv = json.load(open(GOLDEN))
+    nodes = wl.biconcave_nodes(100.0, 50.0, 40.0, 2000)
+    d = orc.polygon_diag(nodes)
+    assert abs(d["Sw"] - 0.4609) < 5e-4
+    assert abs(d["Sw"] - gv["biconcave_sw0_printed"]["value"]) > 0.015
+    assert wl.polygon_area(nodes) > 0  # counter-clockwise
+
+
+# ------------------------------------------------------ Eqs. 15-16 pins -----
+
+def test_hydro_linear_pressure_field(orc):
+    """rho = 1 + beta . x, u = 0: each element gets -(p+ - p-) n+ l with
+    p+ - p- = (beta . 2.4 n+)/3 exactly (linear reproduction)."""
+    nx, ny = 48, 40
+    sim = orc.Sim(wl.periodic_box(nx, ny, 0.8))
+    beta = np.array([2e-3, -1.3e-3])
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    field = np.zeros((3, ny, nx))
+    field[0] = 1 + beta[0] * xx + beta[1] * yy
+    sim.set_moments(field)
+    x = wl.circle_nodes(24.3, 19.6, 6.0, 30)
+    fext = sim.external_forces(x)
+    probe = json.load(open(GOLDEN))["probe_length"]["value"]
+    exp = np.zeros_like(x)
+    for l in range(len(x)):
+        t = x[(l + 1) % len(x)] - x[l]
+        L = np.hypot(*t)
+        n = np.array([t[1], -t[0]]) / L
+        Fl = -(beta @ (2 * probe * n)) / 3 * n * L
+        exp[l] += 0.5 * Fl
+        exp[(l + 1) % len(x)] += 0.5 * Fl
+    np.testing.assert_allclose(fext, exp, atol=1e-14)
+
+
+def test_hydro_piecewise_shear(orc):
+    """Two-node element (both orientations) across a kink in u_x(y): the
+    viscous force is nu (g1 - g2) L along -x on each node."""
+    nx, ny = 40, 24
+    tau = 0.9
+    nu = (tau - 0.5) / 3
+    sim = orc.Sim(wl.periodic_box(nx, ny, tau))
+    g1, g2 = 3e-3, -1e-3
+    yy, xx = np.mgrid[0:ny, 0:nx].astype(float)
+    field = np.zeros((3, ny, nx))
+    field[0] = 1.0
+    field[1] = np.where(yy <= 10.5, g1 * (yy - 10.5), g2 * (yy - 10.5))
+    sim.set_moments(field)
+    L = 0.8
+    x = np.array([[20.1, 10.4], [20.1 + L, 10.4]])  # element 0 has n+ = (0, -1)
+    fext = sim.external_forces(x)
+    np.testing.assert_allclose(fext, [[-nu * (g1 - g2) * L, 0]] * 2, atol=1e-15)
+
+
+# ---------------------------------------------------------------- P13 -------
+
+@pytest.mark.parametrize("mode", ["kinematic", "dynamic"])
+def test_p13_uniform_translation(orc, mode):
+    U = (0.013, -0.007)
+    cfg = wl.periodic_box(48, 40, 0.8, u0=U, mode=mode)
+    nodes = wl.circle_nodes(22.3, 19.1, 6.0, 60)
+    cfg["capsules"] = [wl.capsule(nodes, 0.05, 0.01, 1.0)]
+    sim = orc.Sim(cfg)
+    D0 = sim.diag(0)["D"]
+    n = 60
+    sim.step(n)
+    x, xm1, uv = sim.capsule(0)
+    np.testing.assert_allclose(x, nodes + n * np.array(U), atol=1e-11)
+    np.testing.assert_allclose(x - xm1, np.tile(U, (60, 1)), atol=1e-13)
+    if mode == "dynamic":
+        np.testing.assert_allclose(uv, np.tile(U, (60, 1)), atol=1e-13)
+    assert abs(sim.diag(0)["D"] - D0) < 1e-12
+    m = sim.moments()
+    assert np.abs(m[1] - U[0]).max() < 1e-13 and np.abs(m[2] - U[1]).max() < 1e-13
+
+
+# ---------------------------------------------------------------- P14 -------
+
+@pytest.mark.parametrize("mode", ["kinematic", "dynamic"])
+def test_p14_point_symmetry_shear(orc, mode):
+    """Centred capsule in symmetric shear: the state is symmetric under the
+    point reflection (x, y) -> (63 - x, 63 - y), so the centroid stays put and
+    u(63 - x, 63 - y) = -u(x, y)."""
+    cfg = wl.shear_capsule(mode=mode)
+    sim = orc.Sim(cfg)
+    sim.step(300)
+    d = sim.diag(0)
+    assert abs(d["cx"] - 31.5) < 1e-11 and abs(d["cy"] - 31.5) < 1e-11
+    m = sim.moments()
+    np.testing.assert_allclose(m[1], -m[1][::-1, ::-1], atol=1e-14)
+    np.testing.assert_allclose(m[2], -m[2][::-1, ::-1], atol=1e-14)
+    np.testing.assert_allclose(m[0], m[0][::-1, ::-1], atol=1e-14)
+    x, _, _ = sim.capsule(0)
+    np.testing.assert_allclose(x[32:], 63.0 - x[:32], atol=1e-11)
+    assert d["D"] > 0 and sim.status == 0
+
+
+def test_wall_support_flag(orc):
+    """A node whose MLS support reaches a wall row is flagged."""
+    cfg = wl._base("w", 32, 24, 0.8, 8, "kinematic", 1)
+    cfg["capsules"] = [wl.capsule(wl.circle_nodes(16.0, 6.0, 5.0, 40), 0.01)]
+    sim = orc.Sim(cfg)
+    sim.step(1)
+    assert sim.status & orc.E_WALL
+
+
+def test_mode_is_fixed(orc):
+    cfg = wl.periodic_box(16, 16, 0.8)
+    sim = orc.Sim(cfg)
+    sim.step(1, "dynamic")
+    with pytest.raises(RuntimeError):
+        sim.step(1, "kinematic")
+
+
+# ---------------------------------------------------------------- P15 -------
+
+@pytest.mark.slow
+def test_p15_small_deformation_shear_trend(orc):
+    """Circular capsule in shear (Sec. 3.1 geometry, shrunk): D grows linearly
+    with G at small G, and Dynamic and Kinematic agree (Sec. 3.1 reports both
+    within 1 % of the benchmark at small G)."""
+    orc.set_threads(min(8, os.cpu_count() or 1))
+    res = {}
+    for mode in ("kinematic", "dynamic"):
+        for G in (0.00625, 0.0125):
+            cfg = wl.shear_capsule(g_num=G, eb=0.0, mode=mode)
+            sim = orc.Sim(cfg)
+            sim.step(6000)
+            res[(mode, G)] = sim.diag(0)["D"]
+            assert sim.status == 0
+    for mode in ("kinematic", "dynamic"):
+        ratio = res[(mode, 0.0125)] / res[(mode, 0.00625)]
+        assert 1.8 < ratio < 2.2, (mode, ratio, res)
+    for G in (0.00625, 0.0125):
+        k, d = res[("kinematic", G)], res[("dynamic", G)]
+        assert abs(k - d) / k < 0.05, (G, k, d)
