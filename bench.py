@@ -1,0 +1,216 @@
+"""Throughput of the fused LBM - Dynamic IB step on one MI355X.
+
+Workload: a 4096 x 4096 D2Q9 channel (periodic x, Zou-He walls, body-force
+Poiseuille drive, tau = 0.8, FP32 populations) carrying 32 capsules.  They are
+circular or biconcave, 96-160 nodes, radii 6-12 lu, density ratio 1-2,
+Ca 1e-3..1e-1, drawn with seed 0.  One step = one IB kernel launch (node update
+of the previous step + direct forcing and spreading of this step) + one fused
+collide-stream launch.
+
+Prints one JSON line:
+  value     MLUPS = cells x steps / wall time, with the timed region bracketed by
+            device synchronisation
+  roofline  the grid kernel (dominant): algorithmic bytes 72 B/cell (9 FP32 reads
+            + 9 FP32 writes) x cells / its mean duration from HIP events
+            recorded around every launch of the timed region, against 8 TB/s
+  cpu_baseline  the FP64 oracle on the host cores, a bounded sample of steps of
+            the same workload
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM peak, fused LBM-IB step; batched speedup; adjoint/fwd cost"
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_CELL = 72  # 9 reads + 9 writes of FP32 populations
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def traffic_from_profile(kernel_sha: str):
+    """HBM bytes per grid-kernel launch from the committed rocprofv3 counter
+    summary, used only if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "grid_step_fused4096_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != kernel_sha:
+        return None
+    return float(t.group(1))
+
+
+def kernel_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("lbib_kernels.hip", "lbib_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1903_03356_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def time_gpu(cfg, steps: int, warmup: int, timing: bool):
+    import torch
+    from paper_1903_03356_amd import lbib
+
+    sim = lbib.Sim(cfg)
+    mode = cfg["mode"]
+    sim.step(warmup, mode)
+    torch.cuda.synchronize()
+    flags = sim.check()
+    if flags:
+        raise RuntimeError(f"device flags {flags} after warm-up")
+    if timing:
+        sim.set_timing(True)
+        sim.get_timing()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps, mode)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm = sim.get_timing() if timing else None
+    flags = sim.check()
+    if flags:
+        raise RuntimeError(f"device flags {flags} in the timed region")
+    cells = cfg["nx"] * cfg["ny"]
+    return {"seconds": t1 - t0, "mlups": cells * steps / (t1 - t0) / 1e6,
+            "ms_per_step": (t1 - t0) * 1e3 / steps, "timing": tm, "sim": sim}
+
+
+def cpu_baseline(cfg, budget_s: float = 20.0):
+    from oracle import oracle as orc
+
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    orc.set_threads(threads)
+    sim = orc.Sim(cfg)
+    sim.step(1)  # first touch of the arrays
+    n, t = 0, 0.0
+    while t < budget_s and n < 200:
+        t0 = time.perf_counter()
+        sim.step(1)
+        t += time.perf_counter() - t0
+        n += 1
+    cells = cfg["nx"] * cfg["ny"]
+    return {"value": round(cells * n / t / 1e6, 3), "unit": "MLUPS", "cores": orc.get_threads(),
+            "kind": "oracle",
+            "sample": f"{n} steps of the same {cfg['nx']}x{cfg['ny']} workload with its "
+                      f"{len(cfg['capsules'])} capsules (FP64 oracle, {t:.1f} s)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--n", type=int, default=4096, help="grid side of the fused workload")
+    ap.add_argument("--only-fused", action="store_true",
+                    help="skip the grid-only and 1024x256 side measurements (profiling runs)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 20 device-to-device copies of MIB MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, device="cuda", dtype=torch.float32)
+        b = torch.empty_like(a)
+        for _ in range(20):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 4, "copies": 20}), flush=True)
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(this build is single-GPU)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1903_03356_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    cfg = wl.fused_bench(seed=0, n=args.n, steps=args.steps)
+    nodes = sum(len(c["nodes"]) for c in cfg["capsules"])
+    log(f"fused workload {args.n}x{args.n}, {len(cfg['capsules'])} capsules, {nodes} nodes")
+    r = time_gpu(cfg, args.steps, args.warmup, timing=True)
+    tm = r["timing"]
+    del r["sim"]
+    cells = cfg["nx"] * cfg["ny"]
+    grid_ms = tm["grid_ms"] / max(1.0, tm["grid_launches"])
+    ib_ms = tm["ib_ms"] / max(1.0, tm["ib_launches"])
+    achieved = BYTES_PER_CELL * cells / (grid_ms * 1e-3) / 1e9
+    log(f"fused: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.4f} ms/step; grid kernel "
+        f"{grid_ms * 1e3:.1f} us ({achieved:.0f} GB/s), IB kernel {ib_ms * 1e3:.1f} us")
+
+    # grid-only and the 1024 x 256 biconcave channel, reported beside the main line
+    side = {}
+    if not args.only_fused:
+        g = time_gpu(wl.grid_bench(n=args.n), args.steps, args.warmup, timing=False)
+        log(f"grid only: {g['mlups']:.0f} MLUPS")
+        side["grid_only_mlups"] = round(g["mlups"], 1)
+        del g["sim"]
+        c2 = wl.poiseuille_biconcave(1e-2, steps=args.steps)
+        c2r = time_gpu(c2, args.steps, args.warmup, timing=False)
+        del c2r["sim"]
+        log(f"1024x256 biconcave channel: {c2r['mlups']:.0f} MLUPS")
+        side["biconcave_1024x256_mlups"] = round(c2r["mlups"], 1)
+
+    sha = kernel_sha()
+    traffic = traffic_from_profile(sha)
+    out = {
+        "metric": METRIC,
+        "value": round(r["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"fused Dynamic-IB step, {args.n}x{args.n} D2Q9 channel, "
+                        f"{len(cfg['capsules'])} capsules ({nodes} nodes), FP32 populations",
+            "nx": cfg["nx"], "ny": cfg["ny"], "tau": cfg["tau"], "capsules": len(cfg["capsules"]),
+            "nodes": nodes, "seed": 0, "mode": "dynamic",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_grid_step<float>",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "bytes_per_cell": BYTES_PER_CELL,
+            "kernel_mean_us": round(grid_ms * 1e3, 2),
+            "ib_kernel_mean_us": round(ib_ms * 1e3, 2),
+        },
+        **side,
+        "hbm_fraction_step": round(BYTES_PER_CELL * cells * args.steps / r["seconds"] / 1e9
+                                   / PEAK_HBM_GBS, 4),
+    }
+    if not args.no_cpu:
+        log("cpu baseline (FP64 oracle) ...")
+        cb = cpu_baseline(cfg)
+        out["cpu_baseline"] = cb
+        log(f"cpu baseline: {cb['value']} MLUPS on {cb['cores']} threads")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

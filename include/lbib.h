@@ -1,0 +1,212 @@
+/*
+ * lbib: lattice Boltzmann - Kinematic / Dynamic immersed boundary solver for
+ * deformable capsules on one AMD MI355X (gfx950).
+ *
+ * Method: Coclite, Ranaldo, de Tullio, Decuzzi, Pascazio, "Kinematic and
+ * Dynamic Forcing Strategies for Predicting the Transport of Inertial Capsules
+ * via a combined Lattice Boltzmann - Immersed Boundary Method",
+ * arXiv:1903.03356.  Section and equation numbers below refer to that paper.
+ *
+ * Conventions for every call
+ *  - Plain C ABI.  Every call returns an lbib_status (0 = success, < 0 =
+ *    error).  No C++ exception and no abort crosses the ABI.  On error,
+ *    lbib_last_error() describes the cause.
+ *  - Lattice units: dx = dt = 1, reference density 1, c_s^2 = 1/3,
+ *    viscosity nu = (tau - 1/2)/3 (Sec. 2.1).
+ *  - D2Q9 population order (Eq. 3): 0 rest; 1..4 = E, N, W, S; 5..8 = NE, NW,
+ *    SW, SE.
+ *  - Field arrays exchanged through get/set use the layout
+ *    [component][y][x] (x fastest), FP64.  Capsule node arrays are
+ *    [node][2] (x, y), FP64.
+ *  - The library never allocates device memory.  The caller allocates the
+ *    buffers listed by lbib_buffer_id, with the sizes given by
+ *    lbib_required_bytes, and binds them at lbib_create.  They remain
+ *    owned by the caller and must outlive the context.  Host arrays passed
+ *    in are copied before the call returns.
+ *  - Work is queued on the HIP stream bound at lbib_create.  Calls do not
+ *    synchronise, except: get/set with a host pointer, lbib_check and
+ *    lbib_get_timing.  Those wait for the stream.
+ */
+#ifndef LBIB_H
+#define LBIB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbib_ctx lbib_ctx;
+
+typedef enum {
+    LBIB_OK = 0,
+    LBIB_EINVAL = -1,    /* invalid argument (size, range, orientation, non-finite value) */
+    LBIB_ECAPACITY = -2, /* capsule / node capacity exceeded, buffer too small */
+    LBIB_EDEVICE = -3,   /* a HIP runtime call failed */
+    LBIB_ESTATE = -4,    /* call not allowed in the current state */
+    LBIB_ENUMERIC = -5   /* the device raised a status flag (see lbib_device_flags) */
+} lbib_status;
+
+/* Coupling scheme, fixed for the life of a context after the first step.
+ * KINEMATIC: Sec. 2.4, steps i-viii, node update Eq. 25 (density ratio 1).
+ * DYNAMIC:   Sec. 2.3.2, steps 1-8, Newton law Eqs. 21-22, Verlet Eq. 23,
+ *            BDF2 node velocity Eq. 24. */
+typedef enum { LBIB_KINEMATIC = 0, LBIB_DYNAMIC = 1 } lbib_mode;
+
+/* Status bits raised by the device.  lbib_check returns LBIB_ENUMERIC if any
+ * is set: */
+enum lbib_device_flags {
+    LBIB_FLAG_WALL = 1,       /* an MLS support touched a wall row (needs 1 <= y <= ny-2) */
+    LBIB_FLAG_NONFINITE = 2,  /* a node position or staged density is NaN/Inf */
+    LBIB_FLAG_PATCH = 4,      /* a capsule's fluid patch exceeded the on-chip capacity */
+    LBIB_FLAG_OVERFLOW = 8,   /* a spread force left the fixed-point range (|f| >= 2^14) */
+    LBIB_FLAG_MOVE = 16       /* a node moved one lattice unit or more in one step */
+};
+
+typedef struct {
+    int32_t nx, ny;            /* lattice nodes; walls are the rows y = 0 and y = ny-1 */
+    int32_t real_bytes;        /* 4: FP32 populations and node offsets, 8: FP64 */
+    int32_t max_capsules;      /* capacity of the capsule table (>= 1) */
+    int32_t max_nodes_total;   /* capacity of the node arrays, all capsules (>= 3) */
+    int32_t max_nodes_capsule; /* largest node count of any one capsule (3..2048) */
+} lbib_grid;
+
+typedef struct {
+    int32_t periodic_x;     /* must be 1: x is periodic */
+    int32_t periodic_y;     /* 1: fully periodic box; 0: Zou-He walls at y = 0, ny-1 (Sec. 2.1, ref. [36]) */
+    double u_bottom, u_top; /* tangential wall speeds (lattice units) */
+    double body_force_x;    /* uniform body force g added to the IB force everywhere (0 for none) */
+    int32_t init_profile;   /* initial velocity: 0 rest, 1 linear between the wall speeds,
+                               2 body-force Poiseuille g/(2 nu) y (H - y), H = ny - 1,
+                               3 uniform (init_ux, init_uy) */
+    double init_ux, init_uy;
+} lbib_walls;
+
+/* Caller-owned device buffers, bound at lbib_create in this order. */
+typedef enum {
+    LBIB_BUF_POPS_A = 0, /* populations, ping */
+    LBIB_BUF_POPS_B = 1, /* populations, pong */
+    LBIB_BUF_FORCE = 2,  /* IB force field, two time levels, fixed point */
+    LBIB_BUF_FLAGS = 3,  /* active-segment flags of the force field */
+    LBIB_BUF_NODES = 4,  /* per-node capsule state */
+    LBIB_BUF_CAPS = 5,   /* per-capsule records */
+    LBIB_BUF_DIAG = 6,   /* per-capsule FP64 diagnostics and the device status word */
+    LBIB_BUF_STAGE = 7,  /* staging for host transfers and layout conversion */
+    LBIB_NUM_BUFFERS = 8
+} lbib_buffer_id;
+
+/* What lbib_get_state / lbib_set_state transfer. */
+typedef enum {
+    LBIB_F_POPS = 0,      /* f^n after streaming and walls, [9][ny][nx]                     (get, set) */
+    LBIB_F_POPS_DEV = 1,  /* f^n - w_i (deviation from the rest weights), [9][ny][nx]        (get) */
+    LBIB_F_MOMENTS = 2,   /* rho, ux, uy [3][ny][nx]; u = (sum f e + F^{n-1}/2)/rho (Eqs. 6-7) (get) */
+    LBIB_F_FORCE = 3,     /* total force F^{n-1} = f_ib + g of the last collision [2][ny][nx] (get) */
+    LBIB_C_NODES = 4,     /* x^n of one capsule [nv][2]                                       (get) */
+    LBIB_C_PREV = 5,      /* x^{n-1} [nv][2]                                                   (get) */
+    LBIB_C_VEL = 6,       /* u_v^n (Eq. 24; Dynamic) [nv][2]                                   (get) */
+    LBIB_C_FORCE = 7,     /* last nodal force: total (Dynamic) or internal (Kinematic) [nv][2] (get) */
+    LBIB_C_STATE = 8,     /* x^n, x^{n-1}, u_v^n stacked, [3][nv][2]                           (get, set) */
+    LBIB_C_DIAG = 9,      /* 16 FP64 values, see lbib_diag_index                              (get) */
+    LBIB_STATUS = 10      /* int32 device status word (lbib_device_flags)                     (get) */
+} lbib_state_id;
+
+/* Layout of the LBIB_C_DIAG record (Sec. 3.1-3.2 diagnostics, all FP64). */
+enum lbib_diag_index {
+    LBIB_D_AREA = 0,      /* enclosed area A (Green's theorem) */
+    LBIB_D_PERIMETER = 1, /* perimeter P */
+    LBIB_D_CX = 2,        /* area centroid x */
+    LBIB_D_CY = 3,        /* area centroid y */
+    LBIB_D_TAYLOR = 4,    /* Taylor deformation (a - b)/(a + b), a, b from the area second moments */
+    LBIB_D_SWELLING = 5,  /* swelling ratio A / (P^2 / 4 pi) */
+    LBIB_D_DPERIM = 6,    /* perimeter variation (P - P0)/P0 */
+    LBIB_D_DAREA = 7,     /* A / A0 - 1 */
+    LBIB_D_JXX = 8,       /* central second moments of area */
+    LBIB_D_JYY = 9,
+    LBIB_D_JXY = 10,
+    LBIB_D_A0 = 11,
+    LBIB_D_P0 = 12
+};
+
+/* Size in bytes of buffer `buffer_id` for this grid, or 0 if the grid is
+ * invalid.  Allocate each buffer with at least this many bytes, 256-byte aligned. */
+size_t lbib_required_bytes(const lbib_grid* grid, int32_t buffer_id);
+
+/* Creates a context on the current HIP device (Sec. 2.1 lattice, Sec. 2.2 forcing).
+ * tau > 1/2 is the BGK relaxation time (Eq. 1).  device_buffers[LBIB_NUM_BUFFERS]
+ * are caller-owned device pointers sized by lbib_required_bytes.  hip_stream is a
+ * hipStream_t (NULL = the default stream).
+ * The call zeroes the force and flag buffers and writes the initial
+ * populations f^0 = f^eq(1, u_init) (Eq. 2), queued on the stream.
+ * Errors: EINVAL (nx or ny < 8, tau <= 1/2, periodic_x != 1, real_bytes not 4 or 8,
+ * non-finite values, NULL buffers), ECAPACITY (capacities out of range),
+ * EDEVICE (HIP failure).  *out is set only on success. */
+lbib_status lbib_create(const lbib_grid* grid, double tau, const lbib_walls* walls,
+                        void* const* device_buffers, int32_t n_buffers, void* hip_stream,
+                        lbib_ctx** out);
+
+/* Adds one closed capsule membrane (Sec. 2.2, 2.2.1).  nodes_xy: host array
+ * [n][2] FP64, counter-clockwise.  The given shape is the stress-free one,
+ * from which it takes l0, theta0, A0 and P0.
+ * ks: n_ks = 1 (uniform) or n (element l joins node l to l+1) stretching
+ * constants (Eq. 10).  kb: bending constant (Eqs. 12-13).  ka: area
+ * constant (Eq. 14).  mass_total: membrane mass, spread evenly over the nodes
+ * (Sec. 2.3.2).  It must be > 0 (it is unused by the Kinematic scheme).
+ * Errors: EINVAL (n < 3, n_ks not 1 or n, clockwise order, non-finite input, a
+ * node outside 3 <= y <= ny - 4 when walls are present, mass <= 0, ks < 0),
+ * ECAPACITY (capsule or node capacity, n > max_nodes_capsule, initial patch too large),
+ * ESTATE (after the first step). *capsule_id receives the index (0, 1, ...). */
+lbib_status lbib_add_capsule(lbib_ctx* ctx, const double* nodes_xy, int32_t n, const double* ks,
+                             int32_t n_ks, double kb, double ka, double mass_total,
+                             int32_t* capsule_id);
+
+/* Queues nsteps >= 0 time steps of the chosen scheme on the bound stream.
+ * Each step is one IB kernel launch (node update of the previous step fused
+ * with the forcing of this step) and one fused collide-stream kernel launch.
+ * The call ends with the node update of the last step, so between calls the
+ * state is the complete state at time n.
+ * Errors: EINVAL (nsteps < 0, bad mode), ESTATE (mode differs from the first
+ * step's), EDEVICE.  Device-side problems raise status flags (lbib_check). */
+lbib_status lbib_step(lbib_ctx* ctx, int32_t nsteps, lbib_mode mode);
+
+/* Copies state `what` into dst (dst_bytes long).  capsule_id selects the capsule
+ * for LBIB_C_*.  dst_is_device = 1: dst is device memory and the copy is queued;
+ * 0: host memory and the call waits for the stream.  Errors: EINVAL (unknown
+ * what, bad capsule id, dst too small), EDEVICE. */
+lbib_status lbib_get_state(lbib_ctx* ctx, int32_t what, int32_t capsule_id, void* dst,
+                           size_t dst_bytes, int32_t dst_is_device);
+
+/* Overwrites state `what` (LBIB_F_POPS or LBIB_C_STATE) from src.  F_POPS replaces
+ * f^n.  The wall populations that Zou-He determines are recomputed.  C_STATE sets
+ * x^n, x^{n-1}, u_v^n of one capsule and marks it started.  The stress-free shape
+ * is unchanged.  Errors: EINVAL, EDEVICE. */
+lbib_status lbib_set_state(lbib_ctx* ctx, int32_t what, int32_t capsule_id, const void* src,
+                           size_t src_bytes, int32_t src_is_device);
+
+/* Waits for the stream and reads the device status word.  Returns LBIB_OK if it
+ * is clear, LBIB_ENUMERIC otherwise.  The flags are written to *flags_out if it
+ * is not NULL.  The word is not cleared. */
+lbib_status lbib_check(lbib_ctx* ctx, int32_t* flags_out);
+
+/* Timing of the kernels with HIP events on the bound stream.  enable = 1 starts
+ * recording an event before and after every kernel of lbib_step, enable = 0
+ * stops.  lbib_get_timing waits for the stream and returns out[6] = {grid kernel
+ * total ms, grid launches, IB kernel total ms, IB launches, 0, 0}.  It then
+ * resets the counters. */
+lbib_status lbib_set_timing(lbib_ctx* ctx, int32_t enable);
+lbib_status lbib_get_timing(lbib_ctx* ctx, double* out6);
+
+/* Number of completed steps n, or -1 for a NULL context. */
+int64_t lbib_steps_done(const lbib_ctx* ctx);
+
+/* Last error message of ctx (or of the calling thread when ctx is NULL). */
+const char* lbib_last_error(const lbib_ctx* ctx);
+
+/* Frees the host-side context.  Device buffers stay with the caller.  Waits for
+ * the stream first. */
+void lbib_destroy(lbib_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBIB_H */

@@ -1,0 +1,649 @@
+// C-ABI host layer of the LBM - immersed boundary capsule library: argument
+// validation, binding of caller-owned device buffers, the per-step launch
+// schedule and state transfers.  Declarations and contracts: include/lbib.h.
+#include "lbib.h"
+#include "lbib_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace lbib;
+
+static thread_local std::string t_err;
+
+struct TimedLaunch {
+    int kind;  // 0 grid, 1 IB
+    hipEvent_t start, stop;
+};
+
+struct lbib_ctx {
+    lbib_grid grid;
+    lbib_walls walls;
+    double tau = 0, nu = 0;
+    int nxp = 0, nseg = 0, rb = 4;
+    void* buf[LBIB_NUM_BUFFERS] = {};
+    hipStream_t stream = nullptr;
+    int ncap = 0, nodes_used = 0;
+    int patch_cap = 0;
+    size_t lds_bytes = 0;
+    long long steps = 0;
+    int mode = -1;
+    std::string err;
+    bool timing = false;
+    std::vector<TimedLaunch> timed;
+    std::vector<hipEvent_t> pool;
+    std::vector<int> cap_off, cap_nv;  // host copy of the capsule table layout
+};
+
+// ----------------------------------------------------------------- helpers
+
+static lbib_status fail(lbib_ctx* ctx, lbib_status code, const std::string& msg)
+{
+    if (ctx) ctx->err = msg;
+    t_err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail(ctx, LBIB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static bool grid_ok(const lbib_grid* g)
+{
+    return g && g->nx >= 8 && g->ny >= 8 && g->nx <= (1 << 20) && g->ny <= (1 << 20) &&
+           (long long)g->nx * g->ny <= (1LL << 31) && (g->real_bytes == 4 || g->real_bytes == 8) &&
+           g->max_capsules >= 1 && g->max_capsules <= (1 << 20) && g->max_nodes_total >= 3 &&
+           g->max_nodes_total <= (1 << 26) && g->max_nodes_capsule >= 3 &&
+           g->max_nodes_capsule <= 2048;
+}
+
+static size_t status_offset(const lbib_grid* g)
+{
+    return (size_t)g->max_capsules * kDiagStride * sizeof(double);
+}
+
+extern "C" size_t lbib_required_bytes(const lbib_grid* g, int32_t id)
+{
+    if (!grid_ok(g)) return 0;
+    const size_t nxp = ((size_t)g->nx + kSegW - 1) / kSegW * kSegW;
+    const size_t nseg = nxp / kSegW;
+    const size_t cells = nxp * g->ny;
+    const size_t plane = (size_t)g->nx * g->ny;
+    switch (id) {
+    case LBIB_BUF_POPS_A:
+    case LBIB_BUF_POPS_B: return round256(9 * cells * g->real_bytes);
+    case LBIB_BUF_FORCE: return round256(2 * cells * 2 * sizeof(long long));
+    case LBIB_BUF_FLAGS: return round256(2 * (size_t)g->ny * nseg * sizeof(int));
+    case LBIB_BUF_NODES: return round256((size_t)NF_COUNT * g->max_nodes_total * g->real_bytes);
+    case LBIB_BUF_CAPS: return round256((size_t)g->max_capsules * sizeof(CapsuleDev));
+    case LBIB_BUF_DIAG: return round256(status_offset(g) + 64);
+    case LBIB_BUF_STAGE: {
+        size_t n = 3 * plane;
+        if ((size_t)6 * g->max_nodes_total > n) n = (size_t)6 * g->max_nodes_total;
+        if (n < 64) n = 64;
+        return round256(n * sizeof(double));
+    }
+    default: return 0;
+    }
+}
+
+static GridArgs grid_args(const lbib_ctx* c)
+{
+    GridArgs g;
+    g.nx = c->grid.nx;
+    g.ny = c->grid.ny;
+    g.nxp = c->nxp;
+    g.nseg = c->nseg;
+    g.periodic_y = c->walls.periodic_y;
+    g.omega = 1.0 / c->tau;
+    g.gx = c->walls.body_force_x;
+    g.u_bot = c->walls.periodic_y ? 0.0 : c->walls.u_bottom;
+    g.u_top = c->walls.periodic_y ? 0.0 : c->walls.u_top;
+    return g;
+}
+
+static char* bufp(const lbib_ctx* c, int id) { return static_cast<char*>(c->buf[id]); }
+
+static void* pops(const lbib_ctx* c, long long parity)
+{
+    return bufp(c, (parity & 1) ? LBIB_BUF_POPS_B : LBIB_BUF_POPS_A);
+}
+
+static long long* fib(const lbib_ctx* c, long long parity)
+{
+    const size_t half = (size_t)c->nxp * c->grid.ny * 2;
+    return reinterpret_cast<long long*>(bufp(c, LBIB_BUF_FORCE)) + (parity & 1) * half;
+}
+
+static int* flags(const lbib_ctx* c, long long parity)
+{
+    const size_t half = (size_t)c->nseg * c->grid.ny;
+    return reinterpret_cast<int*>(bufp(c, LBIB_BUF_FLAGS)) + (parity & 1) * half;
+}
+
+static int* status_word(const lbib_ctx* c)
+{
+    return reinterpret_cast<int*>(bufp(c, LBIB_BUF_DIAG) + status_offset(&c->grid));
+}
+
+static hipEvent_t take_event(lbib_ctx* c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// ------------------------------------------------------------------ create
+
+extern "C" lbib_status lbib_create(const lbib_grid* grid, double tau, const lbib_walls* walls,
+                                   void* const* device_buffers, int32_t n_buffers,
+                                   void* hip_stream, lbib_ctx** out)
+{
+    if (!out) return fail(nullptr, LBIB_EINVAL, "out is NULL");
+    if (!grid || !walls || !device_buffers) return fail(nullptr, LBIB_EINVAL, "NULL argument");
+    if (grid->nx < 8 || grid->ny < 8) return fail(nullptr, LBIB_EINVAL, "nx and ny must be >= 8");
+    if (grid->real_bytes != 4 && grid->real_bytes != 8)
+        return fail(nullptr, LBIB_EINVAL, "real_bytes must be 4 or 8");
+    if (!grid_ok(grid)) return fail(nullptr, LBIB_ECAPACITY, "grid capacities out of range");
+    if (!(std::isfinite(tau) && tau > 0.5)) return fail(nullptr, LBIB_EINVAL, "tau must be > 1/2");
+    if (walls->periodic_x != 1) return fail(nullptr, LBIB_EINVAL, "periodic_x must be 1");
+    if (walls->periodic_y != 0 && walls->periodic_y != 1)
+        return fail(nullptr, LBIB_EINVAL, "periodic_y must be 0 or 1");
+    if (!(std::isfinite(walls->u_bottom) && std::isfinite(walls->u_top) &&
+          std::isfinite(walls->body_force_x) && std::isfinite(walls->init_ux) &&
+          std::isfinite(walls->init_uy)))
+        return fail(nullptr, LBIB_EINVAL, "non-finite wall or profile value");
+    if (walls->init_profile < 0 || walls->init_profile > 3)
+        return fail(nullptr, LBIB_EINVAL, "init_profile must be 0..3");
+    if (n_buffers != LBIB_NUM_BUFFERS)
+        return fail(nullptr, LBIB_EINVAL, "n_buffers must be LBIB_NUM_BUFFERS");
+    for (int i = 0; i < LBIB_NUM_BUFFERS; i++)
+        if (!device_buffers[i]) return fail(nullptr, LBIB_EINVAL, "NULL device buffer");
+
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(nullptr, LBIB_EDEVICE, "no HIP device");
+
+    lbib_ctx* c = new lbib_ctx();
+    c->grid = *grid;
+    c->walls = *walls;
+    c->tau = tau;
+    c->nu = (tau - 0.5) / 3.0;
+    c->rb = grid->real_bytes;
+    c->nxp = (grid->nx + kSegW - 1) / kSegW * kSegW;
+    c->nseg = c->nxp / kSegW;
+    for (int i = 0; i < LBIB_NUM_BUFFERS; i++) c->buf[i] = device_buffers[i];
+    c->stream = static_cast<hipStream_t>(hip_stream);
+
+    // LDS of the IB kernel: node scratch for the largest capsule, the rest
+    // holds the capsule's fluid patch.
+    const size_t lds_max = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
+    const size_t budget = lds_max - 1024;  // static shared memory of the kernel
+    const size_t per_node = (size_t)14 * c->rb, per_cell = (size_t)3 * c->rb;
+    const size_t node_bytes = per_node * grid->max_nodes_capsule;
+    if (node_bytes + 1024 * per_cell > budget) {
+        delete c;
+        return fail(nullptr, LBIB_ECAPACITY, "max_nodes_capsule too large for the on-chip memory");
+    }
+    c->patch_cap = (int)((budget - node_bytes) / per_cell);
+    c->lds_bytes = c->rb == 4 ? ib_lds_bytes<float>(c->patch_cap, grid->max_nodes_capsule)
+                              : ib_lds_bytes<double>(c->patch_cap, grid->max_nodes_capsule);
+    hipError_t e = c->rb == 4 ? ib_set_lds_limit<float>(c->lds_bytes)
+                              : ib_set_lds_limit<double>(c->lds_bytes);
+    if (e != hipSuccess) {
+        std::string m = std::string("hipFuncSetAttribute: ") + hipGetErrorString(e);
+        delete c;
+        return fail(nullptr, LBIB_EDEVICE, m);
+    }
+
+    const int zero_ids[] = {LBIB_BUF_POPS_B, LBIB_BUF_FORCE, LBIB_BUF_FLAGS, LBIB_BUF_NODES,
+                            LBIB_BUF_CAPS, LBIB_BUF_DIAG};
+    for (int id : zero_ids) {
+        e = hipMemsetAsync(c->buf[id], 0, lbib_required_bytes(grid, id), c->stream);
+        if (e != hipSuccess) {
+            std::string m = std::string("hipMemsetAsync: ") + hipGetErrorString(e);
+            delete c;
+            return fail(nullptr, LBIB_EDEVICE, m);
+        }
+    }
+    GridArgs g = grid_args(c);
+    e = c->rb == 4 ? launch_init<float>((float*)pops(c, 0), g, walls->init_profile, walls->init_ux,
+                                        walls->init_uy, c->nu, c->stream)
+                   : launch_init<double>((double*)pops(c, 0), g, walls->init_profile,
+                                         walls->init_ux, walls->init_uy, c->nu, c->stream);
+    if (e != hipSuccess) {
+        std::string m = std::string("init kernel: ") + hipGetErrorString(e);
+        delete c;
+        return fail(nullptr, LBIB_EDEVICE, m);
+    }
+    *out = c;
+    return LBIB_OK;
+}
+
+// ------------------------------------------------------------- add_capsule
+
+template <typename T>
+static lbib_status add_capsule_t(lbib_ctx* c, const double* xy, int n, const double* ks, int n_ks,
+                                 double kb, double ka, double mass, int32_t* id)
+{
+    // stress-free shape (Sec. 2.2.1): element lengths, turning angles, area, perimeter
+    std::vector<double> l0(n), th0(n);
+    double A2 = 0, P = 0, mx = 0, my = 0;
+    double minx = 1e300, maxx = -1e300, miny = 1e300, maxy = -1e300;
+    for (int v = 0; v < n; v++) {
+        const int m = (v + 1) % n, p = (v + n - 1) % n;
+        const double tx = xy[2 * m] - xy[2 * v], ty = xy[2 * m + 1] - xy[2 * v + 1];
+        l0[v] = std::sqrt(tx * tx + ty * ty);
+        P += l0[v];
+        A2 += xy[2 * v] * xy[2 * m + 1] - xy[2 * m] * xy[2 * v + 1];
+        const double ax = xy[2 * v] - xy[2 * p], ay = xy[2 * v + 1] - xy[2 * p + 1];
+        th0[v] = std::atan2(ax * ty - ay * tx, ax * tx + ay * ty);
+        mx += xy[2 * v];
+        my += xy[2 * v + 1];
+        minx = std::fmin(minx, xy[2 * v]);
+        maxx = std::fmax(maxx, xy[2 * v]);
+        miny = std::fmin(miny, xy[2 * v + 1]);
+        maxy = std::fmax(maxy, xy[2 * v + 1]);
+        if (l0[v] <= 0.0) return fail(c, LBIB_EINVAL, "coincident consecutive nodes");
+    }
+    const double A0 = 0.5 * A2;
+    if (!(A0 > 0)) return fail(c, LBIB_EINVAL, "nodes must be counter-clockwise (positive area)");
+    const long long W = (long long)std::floor(maxx) - (long long)std::floor(minx) + 7;
+    const long long H = (long long)std::floor(maxy) - (long long)std::floor(miny) + 7;
+    if (W * H > c->patch_cap)
+        return fail(c, LBIB_ECAPACITY, "capsule patch exceeds the on-chip capacity");
+
+    const double refx = std::nearbyint(mx / n), refy = std::nearbyint(my / n);
+    const int off = c->nodes_used;
+    const size_t S = c->grid.max_nodes_total;
+    std::vector<T> f((size_t)NF_COUNT * n, T(0));
+    for (int v = 0; v < n; v++) {
+        const double rx = xy[2 * v] - refx, ry = xy[2 * v + 1] - refy;
+        const T hx = (T)rx, hy = (T)ry;
+        f[NF_HX * n + v] = hx;
+        f[NF_HY * n + v] = hy;
+        f[NF_LX * n + v] = (T)(rx - (double)hx);
+        f[NF_LY * n + v] = (T)(ry - (double)hy);
+        f[NF_L0 * n + v] = (T)l0[v];
+        f[NF_TH0 * n + v] = (T)th0[v];
+        f[NF_KS * n + v] = (T)(n_ks == 1 ? ks[0] : ks[v]);
+    }
+    for (int k = 0; k < NF_COUNT; k++)
+        HIPCHK(c, hipMemcpyAsync(bufp(c, LBIB_BUF_NODES) + (k * S + off) * sizeof(T),
+                                 f.data() + (size_t)k * n, n * sizeof(T), hipMemcpyHostToDevice,
+                                 c->stream));
+    CapsuleDev cd;
+    std::memset(&cd, 0, sizeof(cd));
+    cd.node_offset = off;
+    cd.nv = n;
+    cd.primed = 0;
+    cd.ref_x = refx;
+    cd.ref_y = refy;
+    cd.kb = kb;
+    cd.ka = ka;
+    cd.mv = mass / n;
+    cd.A0 = A0;
+    cd.P0 = P;
+    HIPCHK(c, hipMemcpyAsync(bufp(c, LBIB_BUF_CAPS) + (size_t)c->ncap * sizeof(CapsuleDev), &cd,
+                             sizeof(cd), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *id = c->ncap;
+    c->cap_off.push_back(off);
+    c->cap_nv.push_back(n);
+    c->ncap++;
+    c->nodes_used += n;
+    return LBIB_OK;
+}
+
+extern "C" lbib_status lbib_add_capsule(lbib_ctx* c, const double* xy, int32_t n, const double* ks,
+                                        int32_t n_ks, double kb, double ka, double mass,
+                                        int32_t* id)
+{
+    if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
+    if (!xy || !ks || !id) return fail(c, LBIB_EINVAL, "NULL argument");
+    if (c->steps > 0) return fail(c, LBIB_ESTATE, "capsules must be added before the first step");
+    if (n < 3) return fail(c, LBIB_EINVAL, "a capsule needs at least 3 nodes");
+    if (n_ks != 1 && n_ks != n) return fail(c, LBIB_EINVAL, "n_ks must be 1 or n");
+    if (n > c->grid.max_nodes_capsule)
+        return fail(c, LBIB_ECAPACITY, "n exceeds max_nodes_capsule");
+    if (c->ncap >= c->grid.max_capsules) return fail(c, LBIB_ECAPACITY, "capsule table full");
+    if (c->nodes_used + n > c->grid.max_nodes_total)
+        return fail(c, LBIB_ECAPACITY, "node arrays full");
+    if (!(std::isfinite(kb) && std::isfinite(ka) && std::isfinite(mass) && mass > 0))
+        return fail(c, LBIB_EINVAL, "kb, ka must be finite and mass > 0");
+    for (int i = 0; i < n_ks; i++)
+        if (!(std::isfinite(ks[i]) && ks[i] >= 0)) return fail(c, LBIB_EINVAL, "ks must be >= 0");
+    for (int v = 0; v < 2 * n; v++)
+        if (!std::isfinite(xy[v])) return fail(c, LBIB_EINVAL, "non-finite node coordinate");
+    if (!c->walls.periodic_y)
+        for (int v = 0; v < n; v++)
+            if (xy[2 * v + 1] < 3.0 || xy[2 * v + 1] > c->grid.ny - 4.0)
+                return fail(c, LBIB_EINVAL, "nodes must satisfy 3 <= y <= ny - 4");
+    return c->rb == 4 ? add_capsule_t<float>(c, xy, n, ks, n_ks, kb, ka, mass, id)
+                      : add_capsule_t<double>(c, xy, n, ks, n_ks, kb, ka, mass, id);
+}
+
+// -------------------------------------------------------------------- step
+
+template <typename T>
+static IBArgs<T> ib_args(const lbib_ctx* c, long long n, int phase)
+{
+    // state n: populations f*^{n-1} in buffer n%2, force F^{n-1} in level (n-1)%2
+    IBArgs<T> a;
+    a.pops = static_cast<const T*>(pops(c, n));
+    a.fib_prev = fib(c, n + 1);
+    a.fib_next = fib(c, n);
+    a.flags_next = flags(c, n);
+    a.nodes = reinterpret_cast<T*>(bufp(c, LBIB_BUF_NODES));
+    a.caps = reinterpret_cast<CapsuleDev*>(bufp(c, LBIB_BUF_CAPS));
+    a.diag = reinterpret_cast<double*>(bufp(c, LBIB_BUF_DIAG));
+    a.status = status_word(c);
+    a.node_stride = c->grid.max_nodes_total;
+    a.nx = c->grid.nx;
+    a.ny = c->grid.ny;
+    a.nxp = c->nxp;
+    a.nseg = c->nseg;
+    a.periodic_y = c->walls.periodic_y;
+    a.phase = phase;
+    a.dynamic = c->mode == LBIB_DYNAMIC;
+    a.patch_cap = c->patch_cap;
+    a.max_nv = c->grid.max_nodes_capsule;
+    a.gx = c->walls.body_force_x;
+    a.nu = c->nu;
+    return a;
+}
+
+template <typename T>
+static lbib_status launch_timed(lbib_ctx* c, int kind, hipError_t (*fn)(lbib_ctx*, void*),
+                                void* arg)
+{
+    TimedLaunch t{kind, nullptr, nullptr};
+    if (c->timing) {
+        t.start = take_event(c);
+        t.stop = take_event(c);
+        if (!t.start || !t.stop) return fail(c, LBIB_EDEVICE, "hipEventCreate failed");
+        HIPCHK(c, hipEventRecord(t.start, c->stream));
+    }
+    HIPCHK(c, fn(c, arg));
+    if (c->timing) {
+        HIPCHK(c, hipEventRecord(t.stop, c->stream));
+        c->timed.push_back(t);
+    }
+    return LBIB_OK;
+}
+
+template <typename T>
+struct IBLaunch {
+    long long n;
+    int phase;
+};
+
+template <typename T>
+static hipError_t do_ib(lbib_ctx* c, void* p)
+{
+    const IBLaunch<T>* q = static_cast<const IBLaunch<T>*>(p);
+    return launch_ib<T>(ib_args<T>(c, q->n, q->phase), c->ncap, c->lds_bytes, c->stream);
+}
+
+template <typename T>
+static hipError_t do_grid(lbib_ctx* c, void* p)
+{
+    const long long n = *static_cast<const long long*>(p);
+    GridArgs g = grid_args(c);
+    return launch_grid_step<T>(static_cast<const T*>(pops(c, n)), static_cast<T*>(pops(c, n + 1)),
+                               fib(c, n), flags(c, n), fib(c, n + 1), flags(c, n + 1), g,
+                               c->stream);
+}
+
+template <typename T>
+static lbib_status step_t(lbib_ctx* c, int nsteps)
+{
+    for (int k = 0; k < nsteps; k++) {
+        const long long n = c->steps + k;
+        if (c->ncap > 0) {
+            IBLaunch<T> q{n, k == 0 ? (n == 0 ? (PH_PRIME | PH_A) : PH_A) : (PH_B | PH_A)};
+            lbib_status s = launch_timed<T>(c, 1, do_ib<T>, &q);
+            if (s != LBIB_OK) return s;
+        }
+        long long nn = n;
+        lbib_status s = launch_timed<T>(c, 0, do_grid<T>, &nn);
+        if (s != LBIB_OK) return s;
+    }
+    if (c->ncap > 0) {
+        IBLaunch<T> q{c->steps + nsteps, PH_B};
+        lbib_status s = launch_timed<T>(c, 1, do_ib<T>, &q);
+        if (s != LBIB_OK) return s;
+    }
+    c->steps += nsteps;
+    return LBIB_OK;
+}
+
+extern "C" lbib_status lbib_step(lbib_ctx* c, int32_t nsteps, lbib_mode mode)
+{
+    if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
+    if (nsteps < 0) return fail(c, LBIB_EINVAL, "nsteps must be >= 0");
+    if (mode != LBIB_KINEMATIC && mode != LBIB_DYNAMIC) return fail(c, LBIB_EINVAL, "bad mode");
+    if (c->mode >= 0 && c->mode != (int)mode)
+        return fail(c, LBIB_ESTATE, "the coupling mode is fixed after the first step");
+    if (nsteps == 0) return LBIB_OK;
+    c->mode = mode;
+    return c->rb == 4 ? step_t<float>(c, nsteps) : step_t<double>(c, nsteps);
+}
+
+// ------------------------------------------------------------- get / set
+
+template <typename T>
+static lbib_status get_t(lbib_ctx* c, int what, int cap, void* dst, size_t bytes, int on_dev)
+{
+    const GridArgs g = grid_args(c);
+    const size_t plane = (size_t)c->grid.nx * c->grid.ny;
+    double* stage = reinterpret_cast<double*>(bufp(c, LBIB_BUF_STAGE));
+    const hipMemcpyKind d2h = hipMemcpyDeviceToHost;
+    auto finish = [&](const double* src, size_t n) -> lbib_status {
+        if (!on_dev) {
+            HIPCHK(c, hipMemcpyAsync(dst, src, n * sizeof(double), d2h, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
+        return LBIB_OK;
+    };
+    switch (what) {
+    case LBIB_F_POPS:
+    case LBIB_F_POPS_DEV: {
+        if (bytes < 9 * plane * sizeof(double)) return fail(c, LBIB_EINVAL, "dst too small");
+        for (int i = 0; i < 9; i++) {
+            double* o = on_dev ? static_cast<double*>(dst) + i * plane : stage;
+            HIPCHK(c, launch_get_pop_plane<T>(static_cast<const T*>(pops(c, c->steps)), o, i,
+                                              what == LBIB_F_POPS, g, c->stream));
+            if (!on_dev)
+                HIPCHK(c, hipMemcpyAsync(static_cast<double*>(dst) + i * plane, stage,
+                                         plane * sizeof(double), d2h, c->stream));
+        }
+        if (!on_dev) HIPCHK(c, hipStreamSynchronize(c->stream));
+        return LBIB_OK;
+    }
+    case LBIB_F_MOMENTS: {
+        if (bytes < 3 * plane * sizeof(double)) return fail(c, LBIB_EINVAL, "dst too small");
+        double* o = on_dev ? static_cast<double*>(dst) : stage;
+        HIPCHK(c, launch_get_moments<T>(static_cast<const T*>(pops(c, c->steps)),
+                                        fib(c, c->steps + 1), o, g, c->stream));
+        return finish(o, 3 * plane);
+    }
+    case LBIB_F_FORCE: {
+        if (bytes < 2 * plane * sizeof(double)) return fail(c, LBIB_EINVAL, "dst too small");
+        double* o = on_dev ? static_cast<double*>(dst) : stage;
+        HIPCHK(c, launch_get_force(fib(c, c->steps + 1), o, g, c->stream));
+        return finish(o, 2 * plane);
+    }
+    case LBIB_C_NODES:
+    case LBIB_C_PREV:
+    case LBIB_C_VEL:
+    case LBIB_C_FORCE:
+    case LBIB_C_STATE: {
+        if (cap < 0 || cap >= c->ncap) return fail(c, LBIB_EINVAL, "bad capsule id");
+        const int nv = c->cap_nv[cap];
+        const size_t n = (what == LBIB_C_STATE ? 6 : 2) * (size_t)nv;
+        if (bytes < n * sizeof(double)) return fail(c, LBIB_EINVAL, "dst too small");
+        double* o = on_dev ? static_cast<double*>(dst) : stage;
+        HIPCHK(c, launch_get_nodes<T>(reinterpret_cast<const T*>(bufp(c, LBIB_BUF_NODES)),
+                                      reinterpret_cast<const CapsuleDev*>(bufp(c, LBIB_BUF_CAPS)),
+                                      cap, nv, c->grid.max_nodes_total, what, o, c->stream));
+        return finish(o, n);
+    }
+    case LBIB_C_DIAG: {
+        if (cap < 0 || cap >= c->ncap) return fail(c, LBIB_EINVAL, "bad capsule id");
+        if (bytes < kDiagStride * sizeof(double)) return fail(c, LBIB_EINVAL, "dst too small");
+        IBArgs<T> a = ib_args<T>(c, c->steps, PH_DIAG);
+        HIPCHK(c, launch_ib<T>(a, c->ncap, c->lds_bytes, c->stream));
+        const double* src = reinterpret_cast<const double*>(bufp(c, LBIB_BUF_DIAG)) +
+                            (size_t)cap * kDiagStride;
+        if (on_dev)
+            HIPCHK(c, hipMemcpyAsync(dst, src, kDiagStride * sizeof(double),
+                                     hipMemcpyDeviceToDevice, c->stream));
+        return finish(src, kDiagStride);
+    }
+    case LBIB_STATUS: {
+        if (bytes < sizeof(int)) return fail(c, LBIB_EINVAL, "dst too small");
+        const hipMemcpyKind k = on_dev ? hipMemcpyDeviceToDevice : d2h;
+        HIPCHK(c, hipMemcpyAsync(dst, status_word(c), sizeof(int), k, c->stream));
+        if (!on_dev) HIPCHK(c, hipStreamSynchronize(c->stream));
+        return LBIB_OK;
+    }
+    default: return fail(c, LBIB_EINVAL, "unknown state id");
+    }
+}
+
+extern "C" lbib_status lbib_get_state(lbib_ctx* c, int32_t what, int32_t cap, void* dst,
+                                      size_t bytes, int32_t on_dev)
+{
+    if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
+    if (!dst) return fail(c, LBIB_EINVAL, "dst is NULL");
+    return c->rb == 4 ? get_t<float>(c, what, cap, dst, bytes, on_dev)
+                      : get_t<double>(c, what, cap, dst, bytes, on_dev);
+}
+
+template <typename T>
+static lbib_status set_t(lbib_ctx* c, int what, int cap, const void* src, size_t bytes, int on_dev)
+{
+    const GridArgs g = grid_args(c);
+    const size_t plane = (size_t)c->grid.nx * c->grid.ny;
+    double* stage = reinterpret_cast<double*>(bufp(c, LBIB_BUF_STAGE));
+    if (what == LBIB_F_POPS) {
+        if (bytes < 9 * plane * sizeof(double)) return fail(c, LBIB_EINVAL, "src too small");
+        for (int i = 0; i < 9; i++) {
+            const double* in = static_cast<const double*>(src) + i * plane;
+            if (!on_dev) {
+                HIPCHK(c, hipMemcpyAsync(stage, in, plane * sizeof(double), hipMemcpyHostToDevice,
+                                         c->stream));
+                in = stage;
+            }
+            HIPCHK(c, launch_set_pop_plane<T>(static_cast<T*>(pops(c, c->steps)), in, i, g,
+                                              c->stream));
+        }
+        if (!on_dev) HIPCHK(c, hipStreamSynchronize(c->stream));
+        return LBIB_OK;
+    }
+    if (what == LBIB_C_STATE) {
+        if (cap < 0 || cap >= c->ncap) return fail(c, LBIB_EINVAL, "bad capsule id");
+        const int nv = c->cap_nv[cap];
+        const size_t n = 6 * (size_t)nv;
+        if (bytes < n * sizeof(double)) return fail(c, LBIB_EINVAL, "src too small");
+        const double* in = static_cast<const double*>(src);
+        if (!on_dev) {
+            for (size_t j = 0; j < n; j++)
+                if (!std::isfinite(in[j])) return fail(c, LBIB_EINVAL, "non-finite node state");
+            HIPCHK(c, hipMemcpyAsync(stage, in, n * sizeof(double), hipMemcpyHostToDevice,
+                                     c->stream));
+            in = stage;
+        }
+        HIPCHK(c, launch_set_nodes<T>(reinterpret_cast<T*>(bufp(c, LBIB_BUF_NODES)),
+                                      reinterpret_cast<CapsuleDev*>(bufp(c, LBIB_BUF_CAPS)), cap,
+                                      nv, c->grid.max_nodes_total, in, c->stream));
+        if (!on_dev) HIPCHK(c, hipStreamSynchronize(c->stream));
+        return LBIB_OK;
+    }
+    return fail(c, LBIB_EINVAL, "state id cannot be set");
+}
+
+extern "C" lbib_status lbib_set_state(lbib_ctx* c, int32_t what, int32_t cap, const void* src,
+                                      size_t bytes, int32_t on_dev)
+{
+    if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
+    if (!src) return fail(c, LBIB_EINVAL, "src is NULL");
+    return c->rb == 4 ? set_t<float>(c, what, cap, src, bytes, on_dev)
+                      : set_t<double>(c, what, cap, src, bytes, on_dev);
+}
+
+// ---------------------------------------------------------- check, timing
+
+extern "C" lbib_status lbib_check(lbib_ctx* c, int32_t* flags_out)
+{
+    if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
+    int st = 0;
+    HIPCHK(c, hipMemcpyAsync(&st, status_word(c), sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (flags_out) *flags_out = st;
+    if (st) return fail(c, LBIB_ENUMERIC, "device status flags set: " + std::to_string(st));
+    return LBIB_OK;
+}
+
+extern "C" lbib_status lbib_set_timing(lbib_ctx* c, int32_t enable)
+{
+    if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
+    c->timing = enable != 0;
+    return LBIB_OK;
+}
+
+extern "C" lbib_status lbib_get_timing(lbib_ctx* c, double* out)
+{
+    if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
+    if (!out) return fail(c, LBIB_EINVAL, "out is NULL");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double t[2] = {0, 0}, cnt[2] = {0, 0};
+    for (const TimedLaunch& tl : c->timed) {
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, tl.start, tl.stop));
+        t[tl.kind] += ms;
+        cnt[tl.kind] += 1;
+        c->pool.push_back(tl.start);
+        c->pool.push_back(tl.stop);
+    }
+    c->timed.clear();
+    out[0] = t[0];
+    out[1] = cnt[0];
+    out[2] = t[1];
+    out[3] = cnt[1];
+    out[4] = out[5] = 0;
+    return LBIB_OK;
+}
+
+extern "C" int64_t lbib_steps_done(const lbib_ctx* c) { return c ? c->steps : -1; }
+
+extern "C" const char* lbib_last_error(const lbib_ctx* c)
+{
+    return c ? c->err.c_str() : t_err.c_str();
+}
+
+extern "C" void lbib_destroy(lbib_ctx* c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (const TimedLaunch& tl : c->timed) {
+        (void)hipEventDestroy(tl.start);
+        (void)hipEventDestroy(tl.stop);
+    }
+    for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    delete c;
+}

@@ -1,0 +1,109 @@
+// Internal declarations shared by the HIP kernels and the C-ABI host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbib {
+
+// Force field: one 64-cell row segment per wavefront of the grid kernel.
+constexpr int kSegW = 64;
+constexpr int kGridRows = 4;     // grid kernel block = 64 x 4 cells
+constexpr int kIBThreads = 256;  // IB kernel block (one block per capsule)
+
+// The spread force is accumulated as a signed 64-bit fixed-point number with
+// 48 fractional bits.  Integer addition is associative, so the sum of
+// contributions from many nodes and capsules is bit-identical whatever order
+// the atomics land in.
+constexpr double kFixScale = 281474976710656.0;        // 2^48
+constexpr double kFixInv = 1.0 / 281474976710656.0;
+constexpr double kFixLimit = 16384.0;                  // |contribution| bound, 2^14
+
+// Per-node arrays of BUF_NODES, each max_nodes_total long, element type real.
+enum NodeField {
+    NF_HX = 0, NF_HY,   // position relative to the capsule reference point (high part)
+    NF_LX, NF_LY,       // low part (compensated sum)
+    NF_DX, NF_DY,       // last displacement d^n = x^n - x^{n-1}
+    NF_UX, NF_UY,       // node velocity u_v^n (Eq. 24)
+    NF_L0,              // stress-free length of element l (node l -> l+1)
+    NF_TH0,             // stress-free turning angle at node v
+    NF_KS,              // stretching constant of element l
+    NF_FX, NF_FY,       // last nodal force (total Dynamic / internal Kinematic)
+    NF_EX, NF_EY,       // last hydrodynamic nodal force (Dynamic)
+    NF_COUNT
+};
+
+struct CapsuleDev {
+    int32_t node_offset;
+    int32_t nv;
+    int32_t primed;
+    int32_t pad0;
+    double ref_x, ref_y;  // integer-valued reference point (world coordinates)
+    double kb, ka, mv, A0, P0;
+    double pad1[3];
+};
+static_assert(sizeof(CapsuleDev) == 96, "CapsuleDev layout");
+
+constexpr int kDiagStride = 16;  // doubles per capsule in BUF_DIAG
+
+enum StatusBits { ST_WALL = 1, ST_NONFINITE = 2, ST_PATCH = 4, ST_OVERFLOW = 8, ST_MOVE = 16 };
+
+enum Phase { PH_PRIME = 1, PH_B = 2, PH_A = 4, PH_DIAG = 8 };
+
+struct GridArgs {
+    int nx, ny, nxp, nseg, periodic_y;
+    double omega;  // 1 / tau
+    double gx;     // uniform body force
+    double u_bot, u_top;
+};
+
+template <typename T>
+struct IBArgs {
+    const T* pops;              // f*^{n-1} (the stream source of the next step)
+    const long long* fib_prev;  // F^{n-1} - g, fixed point, [ny][nxp][2]
+    long long* fib_next;        // F^n - g accumulator, [ny][nxp][2]
+    int* flags_next;            // [ny][nseg]
+    T* nodes;                   // [NF_COUNT][node_stride]
+    CapsuleDev* caps;
+    double* diag;               // [max_capsules][kDiagStride]
+    int* status;
+    int node_stride;
+    int nx, ny, nxp, nseg, periodic_y;
+    int phase, dynamic;
+    int patch_cap, max_nv;
+    double gx, nu;
+};
+
+// ---- launchers (lbib_kernels.hip) ----
+template <typename T>
+hipError_t launch_init(T* pops, const GridArgs& g, int profile, double ux0, double uy0,
+                       double nu, hipStream_t s);
+template <typename T>
+hipError_t launch_grid_step(const T* src, T* dst, const long long* fib_now, const int* flags_now,
+                            long long* fib_old, int* flags_old, const GridArgs& g, hipStream_t s);
+template <typename T>
+hipError_t launch_ib(const IBArgs<T>& a, int ncap, size_t lds_bytes, hipStream_t s);
+template <typename T>
+size_t ib_lds_bytes(int patch_cap, int max_nv);
+template <typename T>
+hipError_t ib_set_lds_limit(size_t bytes);
+
+// get/set helpers.  plane: population index for the per-plane calls.
+template <typename T>
+hipError_t launch_get_pop_plane(const T* src, double* out, int plane, int unshift,
+                                const GridArgs& g, hipStream_t s);
+template <typename T>
+hipError_t launch_set_pop_plane(T* dst, const double* in, int plane, const GridArgs& g,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_get_moments(const T* src, const long long* fib, double* out,
+                              const GridArgs& g, hipStream_t s);
+hipError_t launch_get_force(const long long* fib, double* out, const GridArgs& g, hipStream_t s);
+template <typename T>
+hipError_t launch_get_nodes(const T* nodes, const CapsuleDev* caps, int cap, int nv,
+                            int node_stride, int what, double* out, hipStream_t s);
+template <typename T>
+hipError_t launch_set_nodes(T* nodes, CapsuleDev* caps, int cap, int nv, int node_stride,
+                            const double* in, hipStream_t s);
+
+}  // namespace lbib

@@ -1,0 +1,1039 @@
+// HIP kernels (gfx950, wave64) of the lattice Boltzmann - immersed boundary
+// capsule solver (arXiv:1903.03356).
+//
+// Grid kernel: one fused pass per time step.  It pulls the nine populations
+// (streaming, Eq. 1 left side), applies the Zou-He walls (Sec. 2.1), takes the
+// force-corrected moments (Eqs. 6-7) and writes the BGK collision with the
+// forcing term (Eqs. 2, 4, 5).  Populations are stored as deviations
+// f_i - w_i, structure of arrays [9][ny][nxp], x fastest.  The stored buffer
+// holds post-collision values; the next pass pulls them.
+//
+// IB kernel: one workgroup per capsule.  It stages the moments of the
+// capsule's fluid patch in LDS and runs the Lagrangian part of the step
+// (Secs. 2.2-2.4).  It spreads the force with 64-bit fixed-point atomics, so
+// the force field is bit-reproducible.
+#include "lbib_internal.h"
+
+#include <math.h>
+
+namespace lbib {
+
+// ------------------------------------------------------------------ lattice
+// Eq. 3 velocities in the order rest, E, N, W, S, NE, NW, SW, SE.
+__device__ constexpr int kEx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+template <typename T>
+__device__ __forceinline__ T lat_w(int i)
+{
+    return i == 0 ? T(4.0 / 9.0) : (i < 5 ? T(1.0 / 9.0) : T(1.0 / 36.0));
+}
+
+template <typename T>
+__device__ __forceinline__ T fix_to_real(long long v)
+{
+    return (T)v * (T)kFixInv;
+}
+
+// BGK relaxation with the forcing term for one direction, deviation form:
+// s* = s - omega (s - (f_eq - w)) + (1 - omega/2) w [3 (e - u).F + 9 (e.u)(e.F)]
+template <typename T>
+__device__ __forceinline__ T relax(T s, T w, T eu, T eF, T drho, T rho, T usq15, T uF, T om,
+                                   T pre)
+{
+    const T seq = w * (drho + rho * (T(3) * eu + T(4.5) * eu * eu - usq15));
+    const T src = pre * w * (T(3) * (eF - uF) + T(9) * eu * eF);
+    return s - om * (s - seq) + src;
+}
+
+// Pulls the nine populations arriving at (x, y) from the post-collision field
+// and completes the wall rows with Zou-He (unknowns from the knowns, tangential
+// momentum target rho_w u_w - F_x / 2).
+template <typename T>
+__device__ __forceinline__ void pull(const T* __restrict__ src, int x, int y, const GridArgs& g,
+                                     T Fx, T s[9])
+{
+    const size_t plane = (size_t)g.ny * g.nxp;
+    const int xm = x == 0 ? g.nx - 1 : x - 1;
+    const int xp = x == g.nx - 1 ? 0 : x + 1;
+    int ym, yp;
+    if (g.periodic_y) {
+        ym = y == 0 ? g.ny - 1 : y - 1;
+        yp = y == g.ny - 1 ? 0 : y + 1;
+    } else {  // clamped: the out-of-domain slots are replaced by Zou-He below
+        ym = y == 0 ? 0 : y - 1;
+        yp = y == g.ny - 1 ? y : y + 1;
+    }
+    const size_t r0 = (size_t)y * g.nxp, rm = (size_t)ym * g.nxp, rp = (size_t)yp * g.nxp;
+    s[0] = src[r0 + x];
+    s[1] = src[plane + r0 + xm];
+    s[2] = src[2 * plane + rm + x];
+    s[3] = src[3 * plane + r0 + xp];
+    s[4] = src[4 * plane + rp + x];
+    s[5] = src[5 * plane + rm + xm];
+    s[6] = src[6 * plane + rm + xp];
+    s[7] = src[7 * plane + rp + xp];
+    s[8] = src[8 * plane + rp + xm];
+    if (!g.periodic_y) {
+        if (y == 0) {
+            const T rw = T(1) + s[0] + s[1] + s[3] + T(2) * (s[4] + s[7] + s[8]);
+            const T mx = rw * (T)g.u_bot - T(0.5) * Fx;
+            const T d13 = s[1] - s[3];
+            s[2] = s[4];
+            s[5] = s[7] - T(0.5) * d13 + T(0.5) * mx;
+            s[6] = s[8] + T(0.5) * d13 - T(0.5) * mx;
+        } else if (y == g.ny - 1) {
+            const T rw = T(1) + s[0] + s[1] + s[3] + T(2) * (s[2] + s[5] + s[6]);
+            const T mx = rw * (T)g.u_top - T(0.5) * Fx;
+            const T d13 = s[1] - s[3];
+            s[4] = s[2];
+            s[7] = s[5] + T(0.5) * d13 - T(0.5) * mx;
+            s[8] = s[6] - T(0.5) * d13 + T(0.5) * mx;
+        }
+    }
+}
+
+// ------------------------------------------------------------ grid kernel
+// Block = 64 x 4: each wavefront owns one 64-cell row segment, which is also
+// the granularity of the force-field activity flags.  The wave that owns a
+// segment clears the force accumulator of the previous time level there (if
+// it was active), so the next IB launch finds it zeroed.
+template <typename T>
+__global__ __launch_bounds__(kSegW* kGridRows) void k_grid_step(
+    const T* __restrict__ src, T* __restrict__ dst, const long long* __restrict__ fib_now,
+    const int* __restrict__ flags_now, long long* __restrict__ fib_old,
+    int* __restrict__ flags_old, GridArgs g)
+{
+    const int lane = threadIdx.x;
+    const int y = blockIdx.y * kGridRows + threadIdx.y;
+    if (y >= g.ny) return;
+    const int seg = blockIdx.x;
+    const int x = seg * kSegW + lane;
+    const int fidx = y * g.nseg + seg;
+    const int act = flags_now[fidx];
+    const int old = flags_old[fidx];
+    const size_t cell = (size_t)y * g.nxp + x;
+    if (x < g.nx) {
+        T Fx = (T)g.gx, Fy = T(0);
+        if (act) {
+            const longlong2 f = *reinterpret_cast<const longlong2*>(fib_now + 2 * cell);
+            Fx += fix_to_real<T>(f.x);
+            Fy += fix_to_real<T>(f.y);
+        }
+        T s[9];
+        pull(src, x, y, g, Fx, s);
+        const T drho = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])) + s[8];
+        const T rho = T(1) + drho;
+        const T jx = (s[1] - s[3]) + (s[5] - s[6]) + (s[8] - s[7]);
+        const T jy = (s[2] - s[4]) + (s[5] + s[6]) - (s[7] + s[8]);
+        const T irho = T(1) / rho;
+        const T ux = (jx + T(0.5) * Fx) * irho;
+        const T uy = (jy + T(0.5) * Fy) * irho;
+        const T om = (T)g.omega;
+        const T pre = T(1) - T(0.5) * om;
+        const T usq15 = T(1.5) * (ux * ux + uy * uy);
+        const T uF = ux * Fx + uy * Fy;
+        const T wa = T(1.0 / 9.0), wd = T(1.0 / 36.0);
+        const size_t plane = (size_t)g.ny * g.nxp;
+        T* o = dst + cell;
+        o[0] = relax(s[0], T(4.0 / 9.0), T(0), T(0), drho, rho, usq15, uF, om, pre);
+        o[plane] = relax(s[1], wa, ux, Fx, drho, rho, usq15, uF, om, pre);
+        o[2 * plane] = relax(s[2], wa, uy, Fy, drho, rho, usq15, uF, om, pre);
+        o[3 * plane] = relax(s[3], wa, -ux, -Fx, drho, rho, usq15, uF, om, pre);
+        o[4 * plane] = relax(s[4], wa, -uy, -Fy, drho, rho, usq15, uF, om, pre);
+        o[5 * plane] = relax(s[5], wd, ux + uy, Fx + Fy, drho, rho, usq15, uF, om, pre);
+        o[6 * plane] = relax(s[6], wd, uy - ux, Fy - Fx, drho, rho, usq15, uF, om, pre);
+        o[7 * plane] = relax(s[7], wd, -ux - uy, -Fx - Fy, drho, rho, usq15, uF, om, pre);
+        o[8 * plane] = relax(s[8], wd, ux - uy, Fx - Fy, drho, rho, usq15, uF, om, pre);
+    }
+    if (old) {
+        *reinterpret_cast<longlong2*>(fib_old + 2 * cell) = make_longlong2(0, 0);
+        if (lane == 0) flags_old[fidx] = 0;
+    }
+}
+
+template <typename T>
+hipError_t launch_grid_step(const T* src, T* dst, const long long* fib_now, const int* flags_now,
+                            long long* fib_old, int* flags_old, const GridArgs& g, hipStream_t s)
+{
+    dim3 block(kSegW, kGridRows);
+    dim3 grid(g.nseg, (g.ny + kGridRows - 1) / kGridRows);
+    hipLaunchKernelGGL(k_grid_step<T>, grid, block, 0, s, src, dst, fib_now, flags_now, fib_old,
+                       flags_old, g);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ init kernel
+// Post-collision field whose pull gives f^0 = f^eq(1, u_init(y)) (Eq. 2) at
+// every node: slot i at source (x, y) holds the equilibrium at (x, y + e_iy).
+template <typename T>
+__global__ void k_init(T* pops, GridArgs g, int profile, double ux0, double uy0, double nu)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= g.nxp || y >= g.ny) return;
+    const size_t plane = (size_t)g.ny * g.nxp;
+    const double H = g.ny - 1;
+    for (int i = 0; i < 9; i++) {
+        int yd = y + kEy[i];
+        if (g.periodic_y) yd = (yd + g.ny) % g.ny;
+        else yd = yd < 0 ? 0 : (yd > g.ny - 1 ? g.ny - 1 : yd);
+        double ux = 0, uy = 0;
+        if (profile == 1) ux = g.u_bot + (g.u_top - g.u_bot) * yd / H;
+        else if (profile == 2) ux = g.gx / (2.0 * nu) * yd * (H - yd);
+        else if (profile == 3) { ux = ux0; uy = uy0; }
+        const double eu = kEx[i] * ux + kEy[i] * uy;
+        const double w = i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+        const double dev = w * (3.0 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy));
+        pops[i * plane + (size_t)y * g.nxp + x] = x < g.nx ? (T)dev : T(0);
+    }
+}
+
+template <typename T>
+hipError_t launch_init(T* pops, const GridArgs& g, int profile, double ux0, double uy0, double nu,
+                       hipStream_t s)
+{
+    dim3 block(256), grid((g.nxp + 255) / 256, g.ny);
+    hipLaunchKernelGGL(k_init<T>, grid, block, 0, s, pops, g, profile, ux0, uy0, nu);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- IB kernel
+
+template <typename T>
+__device__ __forceinline__ void two_sum(T a, T b, T& s, T& e)
+{
+    s = a + b;
+    const T bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// Adds d to the compensated coordinate (hi, lo).
+template <typename T>
+__device__ __forceinline__ void comp_add(T& hi, T& lo, T d)
+{
+    T s, e;
+    two_sum(hi, d, s, e);
+    e += lo;
+    T s2, e2;
+    two_sum(s, e, s2, e2);
+    hi = s2;
+    lo = e2;
+}
+
+// Deterministic block reductions (block = 4 wavefronts of 64).
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double (*red)[8])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; k++)
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < N; k++) red[wave][k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; k++) v[k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+    __syncthreads();
+}
+
+__device__ __forceinline__ void block_minmax(float (&mn)[2], float (&mx)[2], double (*red)[8])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = 0; k < 2; k++)
+        for (int o = 32; o > 0; o >>= 1) {
+            mn[k] = fminf(mn[k], __shfl_xor(mn[k], o));
+            mx[k] = fmaxf(mx[k], __shfl_xor(mx[k], o));
+        }
+    if (lane == 0) {
+        red[wave][0] = mn[0];
+        red[wave][1] = mn[1];
+        red[wave][2] = mx[0];
+        red[wave][3] = mx[1];
+    }
+    __syncthreads();
+    for (int k = 0; k < 2; k++) {
+        mn[k] = fminf(fminf((float)red[0][k], (float)red[1][k]), fminf((float)red[2][k], (float)red[3][k]));
+        mx[k] = fmaxf(fmaxf((float)red[0][2 + k], (float)red[1][2 + k]),
+                      fmaxf((float)red[2][2 + k], (float)red[3][2 + k]));
+    }
+    __syncthreads();
+}
+
+// MLS shape functions of Eq. 9 at p = (px, py), given relative to an integer
+// origin.  Support: the 3x3 nodes around floor(p + 1/2).  Weight
+// exp(-(|x_k - p| / (r_w alpha))^2) with r_w = 2.6, alpha = 0.3.  Linear basis
+// centred on p.  The 3x3 moment matrix is accumulated and inverted (cofactors)
+// in FP64.  Outputs: centre (cx, cy), phi (value) and, if G, the slope rows
+// (dphi/dx, dphi/dy) of the local fit.
+template <typename T, bool G>
+__device__ __forceinline__ void mls(T px, T py, int& cx, int& cy, T* phi, T* gx, T* gy)
+{
+    cx = (int)floor(px + T(0.5));
+    cy = (int)floor(py + T(0.5));
+    const T inv2 = T(1.0 / (2.6 * 0.3 * 2.6 * 0.3));
+    T w[9], rx[9], ry[9];
+    double a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0;
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        rx[k] = (T)(cx + k % 3 - 1) - px;
+        ry[k] = (T)(cy + k / 3 - 1) - py;
+        w[k] = exp(-(rx[k] * rx[k] + ry[k] * ry[k]) * inv2);
+        const double W = w[k], X = rx[k], Y = ry[k];
+        a00 += W;
+        a01 += W * X;
+        a02 += W * Y;
+        a11 += W * X * X;
+        a12 += W * X * Y;
+        a22 += W * Y * Y;
+    }
+    const double c00 = a11 * a22 - a12 * a12;
+    const double c01 = a02 * a12 - a01 * a22;
+    const double c02 = a01 * a12 - a02 * a11;
+    const double det = a00 * c00 + a01 * c01 + a02 * c02;
+    const double id = 1.0 / det;
+    const double i00 = c00 * id, i01 = c01 * id, i02 = c02 * id;
+    double i11 = 0, i12 = 0, i22 = 0;
+    if (G) {
+        i11 = (a00 * a22 - a02 * a02) * id;
+        i12 = (a01 * a02 - a00 * a12) * id;
+        i22 = (a00 * a11 - a01 * a01) * id;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        const double W = w[k], X = rx[k], Y = ry[k];
+        phi[k] = (T)(W * (i00 + i01 * X + i02 * Y));
+        if (G) {
+            gx[k] = (T)(W * (i01 + i11 * X + i12 * Y));
+            gy[k] = (T)(W * (i02 + i12 * X + i22 * Y));
+        }
+    }
+}
+
+// Moments of the capsule's fluid patch, staged in LDS: density deviation
+// rho - 1 and the force-corrected velocity.  Cells on a wall row hold NaN
+// and raise ST_WALL if a support touches them.
+template <typename T>
+struct Patch {
+    T* drho;
+    T* ux;
+    T* uy;
+    int ox, oy, W, H;  // origin relative to the capsule reference point, size
+};
+
+template <typename T>
+__device__ __forceinline__ bool patch_index(const Patch<T>& P, int cx, int cy, int k, int& idx)
+{
+    const int lx = cx + k % 3 - 1 - P.ox, ly = cy + k / 3 - 1 - P.oy;
+    idx = ly * P.W + lx;
+    return lx >= 0 && lx < P.W && ly >= 0 && ly < P.H;
+}
+
+// Eq. 8 interpolation of the velocity at p.
+template <typename T>
+__device__ __forceinline__ void interp_u(const Patch<T>& P, T px, T py, T& Ux, T& Uy, int& st)
+{
+    int cx, cy;
+    T phi[9];
+    mls<T, false>(px, py, cx, cy, phi, nullptr, nullptr);
+    Ux = Uy = T(0);
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        int idx;
+        if (!patch_index(P, cx, cy, k, idx)) { st |= ST_PATCH; continue; }
+        if (isnan(P.drho[idx])) { st |= ST_WALL; continue; }
+        Ux += phi[k] * P.ux[idx];
+        Uy += phi[k] * P.uy[idx];
+    }
+}
+
+// Probe state for Eqs. 15-16: pressure deviation c_s^2 (rho - 1) and the
+// velocity gradient G[a][b] = d u_a / d x_b from the slope rows of the fit.
+template <typename T>
+__device__ __forceinline__ void probe(const Patch<T>& P, T px, T py, T& dp, T (&Gr)[2][2], int& st)
+{
+    int cx, cy;
+    T phi[9], gx[9], gy[9];
+    mls<T, true>(px, py, cx, cy, phi, gx, gy);
+    T r = 0, g00 = 0, g01 = 0, g10 = 0, g11 = 0;
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        int idx;
+        if (!patch_index(P, cx, cy, k, idx)) { st |= ST_PATCH; continue; }
+        const T d = P.drho[idx];
+        if (isnan(d)) { st |= ST_WALL; continue; }
+        const T u = P.ux[idx], v = P.uy[idx];
+        r += phi[k] * d;
+        g00 += gx[k] * u;
+        g01 += gy[k] * u;
+        g10 += gx[k] * v;
+        g11 += gy[k] * v;
+    }
+    dp = r * T(1.0 / 3.0);
+    Gr[0][0] = g00;
+    Gr[0][1] = g01;
+    Gr[1][0] = g10;
+    Gr[1][1] = g11;
+}
+
+// Scratch arrays of the IB kernel, each max_nv long.
+template <typename T>
+struct Scratch {
+    T* px;  // node positions (high parts, relative to the reference point)
+    T* py;
+    T* qx;  // low parts of the compensated positions
+    T* qy;
+    T* t[10];
+};
+
+// Edge vector x_m - x_l from compensated coordinates: the difference of the
+// high parts of nearby nodes is exact, the low parts restore the rest.
+template <typename T>
+__device__ __forceinline__ void edge(const Scratch<T>& S, int l, int m, T& tx, T& ty)
+{
+    tx = (S.px[m] - S.px[l]) + (S.qx[m] - S.qx[l]);
+    ty = (S.py[m] - S.py[l]) + (S.qy[m] - S.qy[l]);
+}
+
+// Eqs. 10-14: internal nodal forces at positions (px, py); result in
+// (S.t[8], S.t[9]).  Stretch on element l: k_s (len - l0) t / len on node l and
+// its negative on node l+1.  Area: F_l = -k_a (1 - A/A0) c_s^2 n- len, half to
+// each end.  Bending (outer terms of Eq. 13 as printed, middle node takes
+// minus their sum): k_b sin(theta - theta0) n / len on the two neighbours.
+// The area A is an FP64 block reduction.
+template <typename T>
+__device__ void internal_forces(const Scratch<T>& S, int nv, const T* __restrict__ l0,
+                                const T* __restrict__ th0, const T* __restrict__ ks, double kb,
+                                double ka, double A0, double (*red)[8])
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    double acc[1] = {0.0};
+    for (int l = tid; l < nv; l += nt) {
+        const int m = l + 1 == nv ? 0 : l + 1;
+        const double xl = (double)S.px[l] + (double)S.qx[l], yl = (double)S.py[l] + (double)S.qy[l];
+        const double xm = (double)S.px[m] + (double)S.qx[m], ym = (double)S.py[m] + (double)S.qy[m];
+        acc[0] += xl * ym - xm * yl;
+    }
+    block_sum<1>(acc, red);
+    const double A = 0.5 * acc[0];
+    const T cA = (T)(0.5 * ka * (1.0 - A / A0) / 3.0);  // half element area force per (t_y, -t_x)
+    T* Px = S.t[0];
+    T* Py = S.t[1];
+    T* Qx = S.t[2];
+    T* Qy = S.t[3];
+    for (int l = tid; l < nv; l += nt) {
+        const int m = l + 1 == nv ? 0 : l + 1;
+        T tx, ty;
+        edge(S, l, m, tx, ty);
+        const T len = sqrt(tx * tx + ty * ty);
+        const T c = ks[l] * (len - l0[l]) / len;
+        const T ax = cA * ty, ay = -cA * tx;
+        Px[l] = c * tx + ax;  // onto node l
+        Py[l] = c * ty + ay;
+        Qx[l] = -c * tx + ax;  // onto node l+1
+        Qy[l] = -c * ty + ay;
+    }
+    T* BLx = S.t[4];
+    T* BLy = S.t[5];
+    T* BRx = S.t[6];
+    T* BRy = S.t[7];
+    const T kbt = (T)kb;
+    if (kb != 0.0) {
+        for (int v = tid; v < nv; v += nt) {
+            const int vl = v == 0 ? nv - 1 : v - 1, vr = v + 1 == nv ? 0 : v + 1;
+            T ax, ay, bx, by;
+            edge(S, vl, v, ax, ay);
+            edge(S, v, vr, bx, by);
+            const T la = sqrt(ax * ax + ay * ay), lb = sqrt(bx * bx + by * by);
+            const T th = atan2(ax * by - ay * bx, ax * bx + ay * by);
+            const T sn = kbt * sin(th - th0[v]);
+            BLx[v] = sn * ay / (la * la);  // k_b s n_left / l_left, n_left = (a_y, -a_x)/l
+            BLy[v] = -sn * ax / (la * la);
+            BRx[v] = sn * by / (lb * lb);
+            BRy[v] = -sn * bx / (lb * lb);
+        }
+    }
+    __syncthreads();
+    for (int v = tid; v < nv; v += nt) {
+        const int vl = v == 0 ? nv - 1 : v - 1, vr = v + 1 == nv ? 0 : v + 1;
+        T fx = Px[v] + Qx[vl], fy = Py[v] + Qy[vl];
+        if (kb != 0.0) {
+            fx += BRx[vl] + BLx[vr] - BLx[v] - BRx[v];
+            fy += BRy[vl] + BLy[vr] - BLy[v] - BRy[v];
+        }
+        S.t[8][v] = fx;
+        S.t[9][v] = fy;
+    }
+    __syncthreads();
+}
+
+// Eqs. 15-16: hydrodynamic nodal forces at positions (px, py) into
+// (S.t[2], S.t[3]), using S.t[0..1] for the element halves.
+template <typename T>
+__device__ void external_forces(const Scratch<T>& S, const Patch<T>& P, int nv, T nu, int& st)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    T* Ex = S.t[0];
+    T* Ey = S.t[1];
+    for (int l = tid; l < nv; l += nt) {
+        const int m = l + 1 == nv ? 0 : l + 1;
+        T tx, ty;
+        edge(S, l, m, tx, ty);
+        const T len = sqrt(tx * tx + ty * ty);
+        const T nx = ty / len, ny = -tx / len;  // outward normal n+
+        const T xc = T(0.5) * (S.px[l] + S.px[m]), yc = T(0.5) * (S.py[l] + S.py[m]);
+        T dpp, dpm, Gp[2][2], Gm[2][2];
+        probe(P, xc + T(1.2) * nx, yc + T(1.2) * ny, dpp, Gp, st);
+        probe(P, xc - T(1.2) * nx, yc - T(1.2) * ny, dpm, Gm, st);
+        // (tau+ - tau-) . n+ with tau = nu (G + G^T)
+        const T d00 = T(2) * (Gp[0][0] - Gm[0][0]);
+        const T d11 = T(2) * (Gp[1][1] - Gm[1][1]);
+        const T d01 = (Gp[0][1] - Gm[0][1]) + (Gp[1][0] - Gm[1][0]);
+        const T dpr = dpp - dpm;
+        const T fx = (-dpr * nx + nu * (d00 * nx + d01 * ny)) * len;
+        const T fy = (-dpr * ny + nu * (d01 * nx + d11 * ny)) * len;
+        Ex[l] = T(0.5) * fx;
+        Ey[l] = T(0.5) * fy;
+    }
+    __syncthreads();
+    for (int v = tid; v < nv; v += nt) {
+        const int vl = v == 0 ? nv - 1 : v - 1;
+        S.t[2][v] = Ex[v] + Ex[vl];
+        S.t[3][v] = Ey[v] + Ey[vl];
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ long long to_fix(T v, int& st)
+{
+    if (!(fabs(v) < (T)kFixLimit)) {
+        st |= isnan(v) ? ST_NONFINITE : ST_OVERFLOW;
+        return 0;
+    }
+    return (long long)rint((double)v * kFixScale);
+}
+
+// Spreads c * phi_k(p) * (Fx, Fy) to the 3x3 support of p (Dynamic step 3,
+// Kinematic step iii).
+template <typename T>
+__device__ __forceinline__ void spread(const IBArgs<T>& a, long long refx, long long refy, T px,
+                                       T py, T c, T Fx, T Fy, int& st)
+{
+    int cx, cy;
+    T phi[9];
+    mls<T, false>(px, py, cx, cy, phi, nullptr, nullptr);
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        long long gy = refy + cy + k / 3 - 1;
+        if (a.periodic_y) gy = ((gy % a.ny) + a.ny) % a.ny;
+        else if (gy < 1 || gy > a.ny - 2) { st |= ST_WALL; continue; }
+        long long gx = refx + cx + k % 3 - 1;
+        gx = ((gx % a.nx) + a.nx) % a.nx;
+        const T cp = c * phi[k];
+        const long long fx = to_fix(cp * Fx, st), fy = to_fix(cp * Fy, st);
+        const size_t cell = (size_t)gy * a.nxp + (size_t)gx;
+        unsigned long long* dst = reinterpret_cast<unsigned long long*>(a.fib_next + 2 * cell);
+        atomicAdd(dst, (unsigned long long)fx);
+        atomicAdd(dst + 1, (unsigned long long)fy);
+        a.flags_next[gy * a.nseg + gx / kSegW] = 1;
+    }
+}
+
+// Sec. 3 diagnostics of the polygon (FP64): area, perimeter, centroid, central
+// second moments of area -> Taylor deformation of the equivalent ellipse,
+// swelling ratio, perimeter and area change.
+template <typename T>
+__device__ void diagnostics(const IBArgs<T>& a, const CapsuleDev& cap, int c, double (*red)[8])
+{
+    const int tid = threadIdx.x, nt = blockDim.x, nv = cap.nv, off = cap.node_offset;
+    const T* N = a.nodes;
+    const size_t S = a.node_stride;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int l = tid; l < nv; l += nt) {
+        const int m = l + 1 == nv ? 0 : l + 1;
+        const double x0 = (double)N[NF_HX * S + off + l] + (double)N[NF_LX * S + off + l];
+        const double y0 = (double)N[NF_HY * S + off + l] + (double)N[NF_LY * S + off + l];
+        const double x1 = (double)N[NF_HX * S + off + m] + (double)N[NF_LX * S + off + m];
+        const double y1 = (double)N[NF_HY * S + off + m] + (double)N[NF_LY * S + off + m];
+        const double cr = x0 * y1 - x1 * y0;
+        v[0] += cr;
+        v[1] += sqrt((x1 - x0) * (x1 - x0) + (y1 - y0) * (y1 - y0));
+        v[2] += (x0 + x1) * cr;
+        v[3] += (y0 + y1) * cr;
+        v[4] += (x0 * x0 + x0 * x1 + x1 * x1) * cr;
+        v[5] += (y0 * y0 + y0 * y1 + y1 * y1) * cr;
+        v[6] += (x0 * y1 + 2.0 * x0 * y0 + 2.0 * x1 * y1 + x1 * y0) * cr;
+    }
+    block_sum<7>(v, red);
+    if (tid == 0) {
+        const double A = 0.5 * v[0], P = v[1];
+        const double cx = v[2] / (6.0 * A), cy = v[3] / (6.0 * A);
+        const double jxx = v[4] / 12.0 - A * cx * cx;
+        const double jyy = v[5] / 12.0 - A * cy * cy;
+        const double jxy = v[6] / 24.0 - A * cx * cy;
+        const double tr = 0.5 * (jxx + jyy);
+        const double disc = sqrt(0.25 * (jxx - jyy) * (jxx - jyy) + jxy * jxy);
+        const double l1 = tr + disc, l2 = fmax(tr - disc, 0.0);
+        const double sa = sqrt(l1), sb = sqrt(l2);
+        double* d = a.diag + (size_t)c * kDiagStride;
+        d[0] = A;
+        d[1] = P;
+        d[2] = cap.ref_x + cx;
+        d[3] = cap.ref_y + cy;
+        d[4] = (sa - sb) / (sa + sb);
+        d[5] = 4.0 * M_PI * A / (P * P);
+        d[6] = (P - cap.P0) / cap.P0;
+        d[7] = A / cap.A0 - 1.0;
+        d[8] = jxx;
+        d[9] = jyy;
+        d[10] = jxy;
+        d[11] = cap.A0;
+        d[12] = cap.P0;
+    }
+}
+
+// One block per capsule.  Phases (bit set):
+//   PH_PRIME  start-up of a capsule not yet started: u_v^0 = U(x^0), d^0 = U(x^0)
+//   PH_B      node update closing step n-1 from the fields after its collision:
+//             Dynamic steps 7-8 (Eqs. 21-24), Kinematic steps vii-viii (Eq. 25)
+//   PH_A      forcing of step n: Dynamic steps 1-3 (direct forcing, spreading
+//             with c_v = node arc length), Kinematic steps i-iii (internal
+//             forces, c_v = 1)
+//   PH_DIAG   diagnostics of the current shape only
+template <typename T>
+__global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[kIBThreads / 64][8];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int c = blockIdx.x;
+    CapsuleDev cap = a.caps[c];
+    const int nv = cap.nv, off = cap.node_offset;
+    const size_t NS = a.node_stride;
+    T* N = a.nodes;
+
+    if (a.phase == PH_DIAG) {
+        diagnostics(a, cap, c, red);
+        return;
+    }
+
+    Patch<T> P;
+    P.drho = reinterpret_cast<T*>(smem);
+    P.ux = P.drho + a.patch_cap;
+    P.uy = P.ux + a.patch_cap;
+    Scratch<T> S;
+    S.px = P.uy + a.patch_cap;
+    S.py = S.px + a.max_nv;
+    S.qx = S.py + a.max_nv;
+    S.qy = S.qx + a.max_nv;
+    for (int k = 0; k < 10; k++) S.t[k] = S.qy + (size_t)(k + 1) * a.max_nv;
+
+    int st = 0;
+    const bool prime = (a.phase & PH_PRIME) && !cap.primed;
+    const bool doB = (a.phase & PH_B) && cap.primed;
+    const bool doA = (a.phase & PH_A) != 0;
+    long long refx = (long long)cap.ref_x, refy = (long long)cap.ref_y;
+
+    float mn[2] = {3e38f, 3e38f}, mxv[2] = {-3e38f, -3e38f};
+    bool finite = true;
+    for (int v = tid; v < nv; v += nt) {
+        const T x = N[NF_HX * NS + off + v], y = N[NF_HY * NS + off + v];
+        S.px[v] = x;
+        S.py[v] = y;
+        S.qx[v] = N[NF_LX * NS + off + v];
+        S.qy[v] = N[NF_LY * NS + off + v];
+        finite = finite && isfinite(x) && isfinite(y);
+        mn[0] = fminf(mn[0], (float)x);
+        mn[1] = fminf(mn[1], (float)y);
+        mxv[0] = fmaxf(mxv[0], (float)x);
+        mxv[1] = fmaxf(mxv[1], (float)y);
+    }
+    if (!finite) { mn[0] = -3e38f; }
+    block_minmax(mn, mxv, red);  // ends with a barrier, so S.px/py are visible
+
+    // ---- fluid patch: bounding box + 3 cells (probe 1.2 + support 1.5 + motion)
+    const bool need_field = prime || doB || (doA && a.dynamic);
+    if (need_field) {
+        if (!(mn[0] > -1e30f && mxv[0] < 1e30f && mn[1] > -1e30f && mxv[1] < 1e30f)) {
+            if (tid == 0) atomicOr(a.status, ST_NONFINITE);
+            return;
+        }
+        // offsets from the reference point stay small; anything else cannot be staged
+        if (!(mn[0] > -1e6f && mxv[0] < 1e6f && mn[1] > -1e6f && mxv[1] < 1e6f)) {
+            if (tid == 0) atomicOr(a.status, ST_PATCH);
+            return;
+        }
+        P.ox = (int)floorf(mn[0]) - 3;
+        P.oy = (int)floorf(mn[1]) - 3;
+        P.W = (int)floorf(mxv[0]) - (int)floorf(mn[0]) + 7;
+        P.H = (int)floorf(mxv[1]) - (int)floorf(mn[1]) + 7;
+        if ((long long)P.W * P.H > a.patch_cap) {
+            if (tid == 0) atomicOr(a.status, ST_PATCH);
+            return;
+        }
+        GridArgs g;
+        g.nx = a.nx;
+        g.ny = a.ny;
+        g.nxp = a.nxp;
+        g.nseg = a.nseg;
+        g.periodic_y = a.periodic_y;
+        g.u_bot = g.u_top = 0.0;  // wall rows are never staged
+        const T gxf = (T)a.gx;
+        for (int i = tid; i < P.W * P.H; i += nt) {
+            const int lx = i % P.W, ly = i / P.W;
+            long long wy = refy + P.oy + ly;
+            if (a.periodic_y) wy = ((wy % a.ny) + a.ny) % a.ny;
+            else if (wy < 1 || wy > a.ny - 2) {
+                P.drho[i] = T(NAN);
+                P.ux[i] = P.uy[i] = T(0);
+                continue;
+            }
+            long long wx = refx + P.ox + lx;
+            wx = ((wx % a.nx) + a.nx) % a.nx;
+            T s[9];
+            pull(a.pops, (int)wx, (int)wy, g, gxf, s);
+            const size_t cell = (size_t)wy * a.nxp + (size_t)wx;
+            const T Fx = gxf + fix_to_real<T>(a.fib_prev[2 * cell]);
+            const T Fy = fix_to_real<T>(a.fib_prev[2 * cell + 1]);
+            const T drho = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])) + s[8];
+            const T jx = (s[1] - s[3]) + (s[5] - s[6]) + (s[8] - s[7]);
+            const T jy = (s[2] - s[4]) + (s[5] + s[6]) - (s[7] + s[8]);
+            const T irho = T(1) / (T(1) + drho);
+            P.drho[i] = drho;
+            P.ux[i] = (jx + T(0.5) * Fx) * irho;
+            P.uy[i] = (jy + T(0.5) * Fy) * irho;
+        }
+        __syncthreads();
+    }
+
+    // ---- start-up (reading: u_v^0 = U(x^0), x^{-1} = x^0 - U(x^0))
+    if (prime) {
+        for (int v = tid; v < nv; v += nt) {
+            T Ux, Uy;
+            interp_u(P, S.px[v], S.py[v], Ux, Uy, st);
+            N[NF_UX * NS + off + v] = Ux;
+            N[NF_UY * NS + off + v] = Uy;
+            N[NF_DX * NS + off + v] = Ux;
+            N[NF_DY * NS + off + v] = Uy;
+        }
+    }
+
+    // ---- node update closing the previous step
+    if (doB) {
+        const T* l0 = N + NF_L0 * NS + off;
+        const T* th0 = N + NF_TH0 * NS + off;
+        const T* ks = N + NF_KS * NS + off;
+        if (a.dynamic) {
+            internal_forces(S, nv, l0, th0, ks, cap.kb, cap.ka, cap.A0, red);  // -> t8, t9
+            external_forces(S, P, nv, (T)a.nu, st);                            // -> t2, t3
+        }
+        const T half_inv_m = (T)(0.5 / cap.mv);
+        double csum[2] = {0.0, 0.0};
+        for (int v = tid; v < nv; v += nt) {
+            T Ux, Uy;
+            interp_u(P, S.px[v], S.py[v], Ux, Uy, st);  // tentative velocity, Eq. 23
+            const T dox = N[NF_DX * NS + off + v], doy = N[NF_DY * NS + off + v];
+            T dx, dy;
+            if (a.dynamic) {
+                const T fx = S.t[8][v] + S.t[2][v], fy = S.t[9][v] + S.t[3][v];
+                dx = Ux + half_inv_m * fx;  // Eq. 23
+                dy = Uy + half_inv_m * fy;
+                N[NF_UX * NS + off + v] = T(1.5) * dx - T(0.5) * dox;  // Eq. 24
+                N[NF_UY * NS + off + v] = T(1.5) * dy - T(0.5) * doy;
+                N[NF_FX * NS + off + v] = fx;
+                N[NF_FY * NS + off + v] = fy;
+                N[NF_EX * NS + off + v] = S.t[2][v];
+                N[NF_EY * NS + off + v] = S.t[3][v];
+            } else {
+                dx = dox * T(1.0 / 3.0) + Ux * T(2.0 / 3.0);  // Eq. 25 as an increment
+                dy = doy * T(1.0 / 3.0) + Uy * T(2.0 / 3.0);
+            }
+            if (!(fabs(dx) < T(1) && fabs(dy) < T(1))) st |= ST_MOVE;
+            N[NF_DX * NS + off + v] = dx;
+            N[NF_DY * NS + off + v] = dy;
+            T hx = S.px[v], lx = S.qx[v];
+            T hy = S.py[v], ly = S.qy[v];
+            comp_add(hx, lx, dx);
+            comp_add(hy, ly, dy);
+            S.t[4][v] = hx;  // new positions, published after the barrier
+            S.t[5][v] = hy;
+            S.t[6][v] = lx;
+            S.t[7][v] = ly;
+            csum[0] += (double)hx;
+            csum[1] += (double)hy;
+        }
+        block_sum<2>(csum, red);
+        // keep the reference point within one lattice unit of the node mean
+        const double mx = csum[0] / nv, my = csum[1] / nv;
+        const T kx = fabs(mx) >= 1.0 ? (T)rint(mx) : T(0);
+        const T ky = fabs(my) >= 1.0 ? (T)rint(my) : T(0);
+        for (int v = tid; v < nv; v += nt) {
+            T hx = S.t[4][v], hy = S.t[5][v], lx = S.t[6][v], ly = S.t[7][v];
+            if (kx != T(0) || ky != T(0)) {
+                comp_add(hx, lx, -kx);
+                comp_add(hy, ly, -ky);
+            }
+            S.px[v] = hx;
+            S.py[v] = hy;
+            S.qx[v] = lx;
+            S.qy[v] = ly;
+            N[NF_HX * NS + off + v] = hx;
+            N[NF_HY * NS + off + v] = hy;
+            N[NF_LX * NS + off + v] = lx;
+            N[NF_LY * NS + off + v] = ly;
+        }
+        if (kx != T(0) || ky != T(0)) {
+            cap.ref_x += (double)kx;
+            cap.ref_y += (double)ky;
+            refx += (long long)kx;
+            refy += (long long)ky;
+            P.ox -= (int)kx;
+            P.oy -= (int)ky;
+            if (tid == 0) {
+                a.caps[c].ref_x = cap.ref_x;
+                a.caps[c].ref_y = cap.ref_y;
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- forcing of the new step
+    if (doA) {
+        if (a.dynamic) {
+            for (int v = tid; v < nv; v += nt) {
+                const int vl = v == 0 ? nv - 1 : v - 1, vr = v + 1 == nv ? 0 : v + 1;
+                T Ux, Uy;
+                interp_u(P, S.px[v], S.py[v], Ux, Uy, st);
+                const T Fx = N[NF_UX * NS + off + v] - Ux;  // (U_b - U) / dt, step 1
+                const T Fy = N[NF_UY * NS + off + v] - Uy;
+                T ax, ay, bx, by;
+                edge(S, vl, v, ax, ay);
+                edge(S, v, vr, bx, by);
+                const T cv = T(0.5) * (sqrt(ax * ax + ay * ay) + sqrt(bx * bx + by * by));
+                spread(a, refx, refy, S.px[v], S.py[v], cv, Fx, Fy, st);
+            }
+        } else {
+            const T* l0 = N + NF_L0 * NS + off;
+            const T* th0 = N + NF_TH0 * NS + off;
+            const T* ks = N + NF_KS * NS + off;
+            internal_forces(S, nv, l0, th0, ks, cap.kb, cap.ka, cap.A0, red);
+            for (int v = tid; v < nv; v += nt) {
+                const T Fx = S.t[8][v], Fy = S.t[9][v];
+                N[NF_FX * NS + off + v] = Fx;
+                N[NF_FY * NS + off + v] = Fy;
+                spread(a, refx, refy, S.px[v], S.py[v], T(1), Fx, Fy, st);
+            }
+        }
+    }
+    if (prime && tid == 0) a.caps[c].primed = 1;
+    if (st) atomicOr(a.status, st);
+}
+
+template <typename T>
+size_t ib_lds_bytes(int patch_cap, int max_nv)
+{
+    return sizeof(T) * ((size_t)3 * patch_cap + (size_t)14 * max_nv);
+}
+
+template <typename T>
+hipError_t ib_set_lds_limit(size_t bytes)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ib<T>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename T>
+hipError_t launch_ib(const IBArgs<T>& a, int ncap, size_t lds_bytes, hipStream_t s)
+{
+    if (ncap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ib<T>, dim3(ncap), dim3(kIBThreads), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- state transfers
+
+template <typename T>
+__global__ void k_get_pop_plane(const T* src, double* out, int plane, int unshift, GridArgs g)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= g.nx) return;
+    T s[9];
+    pull(src, x, y, g, (T)g.gx, s);
+    T v = s[0];
+#pragma unroll
+    for (int i = 1; i < 9; i++)
+        if (i == plane) v = s[i];
+    double d = (double)v;
+    if (unshift) d += plane == 0 ? 4.0 / 9.0 : (plane < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+    out[(size_t)y * g.nx + x] = d;
+}
+
+template <typename T>
+hipError_t launch_get_pop_plane(const T* src, double* out, int plane, int unshift,
+                                const GridArgs& g, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_get_pop_plane<T>, dim3((g.nx + 255) / 256, g.ny), dim3(256), 0, s, src,
+                       out, plane, unshift, g);
+    return hipGetLastError();
+}
+
+// f*_i(x) = f^n_i(x + e_i): the pull of the next step then returns f^n.
+template <typename T>
+__global__ void k_set_pop_plane(T* dst, const double* in, int plane, GridArgs g)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= g.nx) return;
+    int xd = x + kEx[plane];
+    xd = xd < 0 ? xd + g.nx : (xd >= g.nx ? xd - g.nx : xd);
+    int yd = y + kEy[plane];
+    if (g.periodic_y) yd = yd < 0 ? yd + g.ny : (yd >= g.ny ? yd - g.ny : yd);
+    else if (yd < 0 || yd >= g.ny) return;
+    const double w = plane == 0 ? 4.0 / 9.0 : (plane < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+    dst[(size_t)plane * g.ny * g.nxp + (size_t)y * g.nxp + x] = (T)(in[(size_t)yd * g.nx + xd] - w);
+}
+
+template <typename T>
+hipError_t launch_set_pop_plane(T* dst, const double* in, int plane, const GridArgs& g,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_pop_plane<T>, dim3((g.nx + 255) / 256, g.ny), dim3(256), 0, s, dst,
+                       in, plane, g);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_get_moments(const T* src, const long long* fib, double* out, GridArgs g)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= g.nx) return;
+    const size_t cell = (size_t)y * g.nxp + x;
+    const double Fx = g.gx + (double)fib[2 * cell] * kFixInv;
+    const double Fy = (double)fib[2 * cell + 1] * kFixInv;
+    T s[9];
+    pull(src, x, y, g, (T)Fx, s);
+    double drho = 0, jx = 0, jy = 0;
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+        drho += (double)s[i];
+        jx += (double)s[i] * kEx[i];
+        jy += (double)s[i] * kEy[i];
+    }
+    const double rho = 1.0 + drho;
+    const size_t plane = (size_t)g.nx * g.ny, o = (size_t)y * g.nx + x;
+    out[o] = rho;
+    out[plane + o] = (jx + 0.5 * Fx) / rho;
+    out[2 * plane + o] = (jy + 0.5 * Fy) / rho;
+}
+
+template <typename T>
+hipError_t launch_get_moments(const T* src, const long long* fib, double* out, const GridArgs& g,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_get_moments<T>, dim3((g.nx + 255) / 256, g.ny), dim3(256), 0, s, src, fib,
+                       out, g);
+    return hipGetLastError();
+}
+
+__global__ void k_get_force(const long long* fib, double* out, GridArgs g)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= g.nx) return;
+    const size_t cell = (size_t)y * g.nxp + x;
+    const size_t plane = (size_t)g.nx * g.ny, o = (size_t)y * g.nx + x;
+    out[o] = g.gx + (double)fib[2 * cell] * kFixInv;
+    out[plane + o] = (double)fib[2 * cell + 1] * kFixInv;
+}
+
+hipError_t launch_get_force(const long long* fib, double* out, const GridArgs& g, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_get_force, dim3((g.nx + 255) / 256, g.ny), dim3(256), 0, s, fib, out, g);
+    return hipGetLastError();
+}
+
+// what: 4 x^n, 5 x^{n-1}, 6 u_v^n, 7 last nodal force, 8 all three stacked
+template <typename T>
+__global__ void k_get_nodes(const T* N, const CapsuleDev* caps, int c, int nv, int NS, int what,
+                            double* out)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    const CapsuleDev cap = caps[c];
+    const int j = cap.node_offset + v;
+    const size_t S = NS;
+    const double x = cap.ref_x + ((double)N[NF_HX * S + j] + (double)N[NF_LX * S + j]);
+    const double y = cap.ref_y + ((double)N[NF_HY * S + j] + (double)N[NF_LY * S + j]);
+    const double px = x - (double)N[NF_DX * S + j], py = y - (double)N[NF_DY * S + j];
+    const double ux = N[NF_UX * S + j], uy = N[NF_UY * S + j];
+    if (what == 4 || what == 8) { out[2 * v] = x; out[2 * v + 1] = y; }
+    double* o = what == 8 ? out + 2 * nv : out;
+    if (what == 5 || what == 8) { o[2 * v] = px; o[2 * v + 1] = py; }
+    o = what == 8 ? out + 4 * nv : out;
+    if (what == 6 || what == 8) { o[2 * v] = ux; o[2 * v + 1] = uy; }
+    if (what == 7) { out[2 * v] = N[NF_FX * S + j]; out[2 * v + 1] = N[NF_FY * S + j]; }
+}
+
+template <typename T>
+hipError_t launch_get_nodes(const T* nodes, const CapsuleDev* caps, int cap, int nv,
+                            int node_stride, int what, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_get_nodes<T>, dim3((nv + 255) / 256), dim3(256), 0, s, nodes, caps, cap, nv,
+                       node_stride, what, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_set_nodes(T* N, CapsuleDev* caps, int c, int nv, int NS, const double* in)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    const CapsuleDev cap = caps[c];
+    const int j = cap.node_offset + v;
+    const size_t S = NS;
+    const double rx = in[2 * v] - cap.ref_x, ry = in[2 * v + 1] - cap.ref_y;
+    const T hx = (T)rx, hy = (T)ry;
+    N[NF_HX * S + j] = hx;
+    N[NF_HY * S + j] = hy;
+    N[NF_LX * S + j] = (T)(rx - (double)hx);
+    N[NF_LY * S + j] = (T)(ry - (double)hy);
+    N[NF_DX * S + j] = (T)(in[2 * v] - in[2 * nv + 2 * v]);
+    N[NF_DY * S + j] = (T)(in[2 * v + 1] - in[2 * nv + 2 * v + 1]);
+    N[NF_UX * S + j] = (T)in[4 * nv + 2 * v];
+    N[NF_UY * S + j] = (T)in[4 * nv + 2 * v + 1];
+    if (v == 0) caps[c].primed = 1;
+}
+
+template <typename T>
+hipError_t launch_set_nodes(T* nodes, CapsuleDev* caps, int cap, int nv, int node_stride,
+                            const double* in, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_nodes<T>, dim3((nv + 255) / 256), dim3(256), 0, s, nodes, caps, cap, nv,
+                       node_stride, in);
+    return hipGetLastError();
+}
+
+// ---- explicit instantiations
+#define LBIB_INST(T)                                                                              \
+    template hipError_t launch_init<T>(T*, const GridArgs&, int, double, double, double,          \
+                                       hipStream_t);                                              \
+    template hipError_t launch_grid_step<T>(const T*, T*, const long long*, const int*,           \
+                                            long long*, int*, const GridArgs&, hipStream_t);      \
+    template hipError_t launch_ib<T>(const IBArgs<T>&, int, size_t, hipStream_t);                 \
+    template size_t ib_lds_bytes<T>(int, int);                                                    \
+    template hipError_t ib_set_lds_limit<T>(size_t);                                              \
+    template hipError_t launch_get_pop_plane<T>(const T*, double*, int, int, const GridArgs&,     \
+                                                hipStream_t);                                     \
+    template hipError_t launch_set_pop_plane<T>(T*, const double*, int, const GridArgs&,          \
+                                                hipStream_t);                                     \
+    template hipError_t launch_get_moments<T>(const T*, const long long*, double*,                \
+                                              const GridArgs&, hipStream_t);                      \
+    template hipError_t launch_get_nodes<T>(const T*, const CapsuleDev*, int, int, int, int,      \
+                                            double*, hipStream_t);                                \
+    template hipError_t launch_set_nodes<T>(T*, CapsuleDev*, int, int, int, const double*,        \
+                                            hipStream_t);
+
+LBIB_INST(float)
+LBIB_INST(double)
+
+}  // namespace lbib

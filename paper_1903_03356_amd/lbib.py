@@ -1,0 +1,268 @@
+"""Thin ctypes binding of the C-ABI library ``liblbib.so`` (include/lbib.h).
+
+Argument marshalling only.  Every step of the method runs in the HIP kernels
+behind the ABI.  PyTorch supplies the device buffers (``torch.empty`` on the
+current device) and the HIP stream (``torch.cuda.current_stream()``).  If the
+compiled library is missing, loading fails loudly.  There is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Any, Dict, List, Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbib.so")
+
+# lbib_status
+OK, EINVAL, ECAPACITY, EDEVICE, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ECAPACITY", -3: "EDEVICE", -4: "ESTATE",
+                -5: "ENUMERIC"}
+KINEMATIC, DYNAMIC = 0, 1
+FLAG_WALL, FLAG_NONFINITE, FLAG_PATCH, FLAG_OVERFLOW, FLAG_MOVE = 1, 2, 4, 8, 16
+NUM_BUFFERS = 8
+BUFFER_NAMES = ["pops_a", "pops_b", "force", "flags", "nodes", "caps", "diag", "stage"]
+# lbib_state_id
+F_POPS, F_POPS_DEV, F_MOMENTS, F_FORCE = 0, 1, 2, 3
+C_NODES, C_PREV, C_VEL, C_FORCE, C_STATE, C_DIAG, STATUS = 4, 5, 6, 7, 8, 9, 10
+DIAG_KEYS = ["area", "perimeter", "cx", "cy", "D", "Sw", "dp", "dA", "Jxx", "Jyy", "Jxy", "A0",
+             "P0"]
+
+EXPORTS = ["lbib_required_bytes", "lbib_create", "lbib_add_capsule", "lbib_step",
+           "lbib_get_state", "lbib_set_state", "lbib_check", "lbib_set_timing",
+           "lbib_get_timing", "lbib_steps_done", "lbib_last_error", "lbib_destroy"]
+
+
+class lbib_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("real_bytes", C.c_int32),
+                ("max_capsules", C.c_int32), ("max_nodes_total", C.c_int32),
+                ("max_nodes_capsule", C.c_int32)]
+
+
+class lbib_walls(C.Structure):
+    _fields_ = [("periodic_x", C.c_int32), ("periodic_y", C.c_int32),
+                ("u_bottom", C.c_double), ("u_top", C.c_double),
+                ("body_force_x", C.c_double), ("init_profile", C.c_int32),
+                ("init_ux", C.c_double), ("init_uy", C.c_double)]
+
+
+class LbibError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib: Optional[C.CDLL] = None
+
+
+def load() -> C.CDLL:
+    """Loads liblbib.so (built by ``python -m paper_1903_03356_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1903_03356_amd.build` (hipcc, gfx950)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32 = C.c_void_p, C.c_int32
+    L.lbib_required_bytes.restype = C.c_size_t
+    L.lbib_required_bytes.argtypes = [C.POINTER(lbib_grid), i32]
+    L.lbib_create.restype = i32
+    L.lbib_create.argtypes = [C.POINTER(lbib_grid), C.c_double, C.POINTER(lbib_walls),
+                              C.POINTER(vp), i32, vp, C.POINTER(vp)]
+    L.lbib_add_capsule.restype = i32
+    L.lbib_add_capsule.argtypes = [vp, C.POINTER(C.c_double), i32, C.POINTER(C.c_double), i32,
+                                   C.c_double, C.c_double, C.c_double, C.POINTER(i32)]
+    L.lbib_step.restype = i32
+    L.lbib_step.argtypes = [vp, i32, i32]
+    L.lbib_get_state.restype = i32
+    L.lbib_get_state.argtypes = [vp, i32, i32, vp, C.c_size_t, i32]
+    L.lbib_set_state.restype = i32
+    L.lbib_set_state.argtypes = [vp, i32, i32, vp, C.c_size_t, i32]
+    L.lbib_check.restype = i32
+    L.lbib_check.argtypes = [vp, C.POINTER(i32)]
+    L.lbib_set_timing.restype = i32
+    L.lbib_set_timing.argtypes = [vp, i32]
+    L.lbib_get_timing.restype = i32
+    L.lbib_get_timing.argtypes = [vp, C.POINTER(C.c_double)]
+    L.lbib_steps_done.restype = C.c_int64
+    L.lbib_steps_done.argtypes = [vp]
+    L.lbib_last_error.restype = C.c_char_p
+    L.lbib_last_error.argtypes = [vp]
+    L.lbib_destroy.restype = None
+    L.lbib_destroy.argtypes = [vp]
+    _lib = L
+    return L
+
+
+def _check(rc: int, ctx=None) -> None:
+    if rc != OK:
+        msg = load().lbib_last_error(ctx)
+        raise LbibError(rc, msg.decode() if msg else "")
+
+
+def make_grid(nx: int, ny: int, real_bytes: int, max_capsules: int = 1,
+              max_nodes_total: int = 3, max_nodes_capsule: int = 3) -> lbib_grid:
+    return lbib_grid(nx, ny, real_bytes, max(1, max_capsules), max(3, max_nodes_total),
+                     max(3, max_nodes_capsule))
+
+
+def required_bytes(grid: lbib_grid, buffer_id: int) -> int:
+    return int(load().lbib_required_bytes(C.byref(grid), buffer_id))
+
+
+class Sim:
+    """One context: device buffers allocated with torch, kernels in liblbib.so.
+
+    ``cfg`` is a workload dictionary (paper_1903_03356_amd.workloads)."""
+
+    def __init__(self, cfg: Dict[str, Any], device: Optional[Any] = None, stream=None,
+                 max_capsules: int = 0, max_nodes_total: int = 0, max_nodes_capsule: int = 0):
+        import torch
+        L = load()
+        self.torch = torch
+        self.cfg = cfg
+        self.device = torch.device(device if device is not None else "cuda")
+        caps = cfg.get("capsules", [])
+        nodes_total = sum(len(c["nodes"]) for c in caps)
+        nv_max = max([len(c["nodes"]) for c in caps] + [3])
+        self.grid = make_grid(int(cfg["nx"]), int(cfg["ny"]), int(cfg["real_bytes"]),
+                              max(1, len(caps), max_capsules), max(3, nodes_total, max_nodes_total),
+                              max(nv_max, max_nodes_capsule))
+        ux0, uy0 = cfg.get("init_u", (0.0, 0.0))
+        self.walls = lbib_walls(1, int(cfg.get("periodic_y", 0)), float(cfg.get("u_bottom", 0.0)),
+                                float(cfg.get("u_top", 0.0)), float(cfg.get("body_force_x", 0.0)),
+                                int(cfg.get("init_profile", 0)), float(ux0), float(uy0))
+        self.buffers: List[Any] = []
+        with torch.cuda.device(self.device):
+            for i in range(NUM_BUFFERS):
+                nb = required_bytes(self.grid, i)
+                if nb == 0:
+                    raise LbibError(ECAPACITY, "invalid grid for buffer sizing")
+                self.buffers.append(torch.empty(nb, dtype=torch.uint8, device=self.device))
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            ptrs = (C.c_void_p * NUM_BUFFERS)(*[b.data_ptr() for b in self.buffers])
+            h = C.c_void_p()
+            _check(L.lbib_create(C.byref(self.grid), float(cfg["tau"]), C.byref(self.walls), ptrs,
+                                 NUM_BUFFERS, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.nv: List[int] = []
+        for cap in caps:
+            self.add_capsule(cap["nodes"], cap["ks"], cap["kb"], cap["ka"], cap["mass"])
+        self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
+
+    # -- ABI wrappers with the same names ------------------------------------
+    def add_capsule(self, nodes, ks, kb: float, ka: float, mass: float) -> int:
+        nodes = np.ascontiguousarray(nodes, np.float64)
+        ks = np.ascontiguousarray(np.atleast_1d(np.asarray(ks, np.float64)))
+        cid = C.c_int32()
+        dp = C.POINTER(C.c_double)
+        with self.torch.cuda.device(self.device):
+            _check(load().lbib_add_capsule(self.h, nodes.ctypes.data_as(dp), nodes.shape[0],
+                                           ks.ctypes.data_as(dp), ks.size, float(kb), float(ka),
+                                           float(mass), C.byref(cid)), self.h)
+        self.nv.append(nodes.shape[0])
+        return cid.value
+
+    def step(self, n: int, mode: Optional[str] = None) -> None:
+        mode = mode or self.cfg.get("mode", "dynamic")
+        m = DYNAMIC if mode == "dynamic" else KINEMATIC
+        with self.torch.cuda.device(self.device):
+            _check(load().lbib_step(self.h, int(n), m), self.h)
+
+    def get_state(self, what: int, capsule: int = 0, out=None):
+        """Host copy (numpy FP64) or, with ``out`` a CUDA FP64 tensor, a queued device copy."""
+        shapes = {F_POPS: (9, self.ny, self.nx), F_POPS_DEV: (9, self.ny, self.nx),
+                  F_MOMENTS: (3, self.ny, self.nx), F_FORCE: (2, self.ny, self.nx),
+                  C_DIAG: (16,), STATUS: (1,)}
+        if what in shapes:
+            shape = shapes[what]
+        elif what == C_STATE:
+            shape = (3, self.nv[capsule], 2)
+        else:
+            shape = (self.nv[capsule], 2)
+        with self.torch.cuda.device(self.device):
+            if out is not None:
+                _check(load().lbib_get_state(self.h, what, capsule, C.c_void_p(out.data_ptr()),
+                                             out.numel() * out.element_size(), 1), self.h)
+                return out
+            arr = np.zeros(shape, np.int32 if what == STATUS else np.float64)
+            _check(load().lbib_get_state(self.h, what, capsule, arr.ctypes.data_as(C.c_void_p),
+                                         arr.nbytes, 0), self.h)
+        return arr
+
+    def set_state(self, what: int, src, capsule: int = 0) -> None:
+        with self.torch.cuda.device(self.device):
+            if hasattr(src, "data_ptr"):
+                _check(load().lbib_set_state(self.h, what, capsule, C.c_void_p(src.data_ptr()),
+                                             src.numel() * src.element_size(), 1), self.h)
+            else:
+                a = np.ascontiguousarray(src, np.float64)
+                _check(load().lbib_set_state(self.h, what, capsule, a.ctypes.data_as(C.c_void_p),
+                                             a.nbytes, 0), self.h)
+
+    def check(self) -> int:
+        flags = C.c_int32()
+        with self.torch.cuda.device(self.device):
+            rc = load().lbib_check(self.h, C.byref(flags))
+        if rc not in (OK, ENUMERIC):
+            _check(rc, self.h)
+        return flags.value
+
+    def set_timing(self, enable: bool) -> None:
+        _check(load().lbib_set_timing(self.h, 1 if enable else 0), self.h)
+
+    def get_timing(self) -> Dict[str, float]:
+        out = (C.c_double * 6)()
+        with self.torch.cuda.device(self.device):
+            _check(load().lbib_get_timing(self.h, out), self.h)
+        return {"grid_ms": out[0], "grid_launches": out[1], "ib_ms": out[2],
+                "ib_launches": out[3]}
+
+    @property
+    def steps_done(self) -> int:
+        return int(load().lbib_steps_done(self.h))
+
+    # -- conveniences -----------------------------------------------------------
+    def pops(self) -> np.ndarray:
+        return self.get_state(F_POPS)
+
+    def pops_dev(self) -> np.ndarray:
+        return self.get_state(F_POPS_DEV)
+
+    def set_pops(self, f) -> None:
+        self.set_state(F_POPS, f)
+
+    def moments(self) -> np.ndarray:
+        return self.get_state(F_MOMENTS)
+
+    def force(self) -> np.ndarray:
+        return self.get_state(F_FORCE)
+
+    def capsule(self, c: int):
+        s = self.get_state(C_STATE, c)
+        return s[0], s[1], s[2]
+
+    def set_capsule(self, c: int, x, xm1, uv) -> None:
+        self.set_state(C_STATE, np.stack([np.asarray(x), np.asarray(xm1), np.asarray(uv)]), c)
+
+    def capsule_force(self, c: int) -> np.ndarray:
+        return self.get_state(C_FORCE, c)
+
+    def diag(self, c: int) -> Dict[str, float]:
+        d = self.get_state(C_DIAG, c)
+        return dict(zip(DIAG_KEYS, d.tolist()))
+
+    def close(self) -> None:
+        h = getattr(self, "h", None)
+        if h:
+            load().lbib_destroy(h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

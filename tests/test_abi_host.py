@@ -1,0 +1,96 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every symbol include/lbib.h declares, sizes its buffers, and rejects invalid
+arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1903_03356_amd import lbib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "lbib.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    return lbib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbib_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(lbib.EXPORTS) == names
+
+
+def test_required_bytes(L):
+    g = lbib.make_grid(100, 37, 4, 3, 300, 128)
+    nxp = 128
+    assert lbib.required_bytes(g, 0) == -(-9 * nxp * 37 * 4 // 256) * 256
+    assert lbib.required_bytes(g, 1) == lbib.required_bytes(g, 0)
+    assert lbib.required_bytes(g, 2) >= 2 * nxp * 37 * 16
+    assert lbib.required_bytes(g, 3) >= 2 * 37 * 2 * 4
+    assert lbib.required_bytes(g, 7) >= 3 * 100 * 37 * 8
+    assert lbib.required_bytes(g, 8) == 0  # unknown buffer id
+    g8 = lbib.make_grid(100, 37, 8, 3, 300, 128)
+    assert lbib.required_bytes(g8, 0) == 2 * lbib.required_bytes(g, 0)
+    for i in range(8):
+        assert lbib.required_bytes(g, i) % 256 == 0
+    bad = lbib.make_grid(4, 37, 4)
+    assert all(lbib.required_bytes(bad, i) == 0 for i in range(8))
+    bad = lbib.make_grid(100, 37, 2)
+    assert lbib.required_bytes(bad, 0) == 0
+
+
+def _create(L, grid, tau, walls, nbuf=lbib.NUM_BUFFERS, null=False):
+    ptrs = (C.c_void_p * lbib.NUM_BUFFERS)(*([None] * lbib.NUM_BUFFERS if null else
+                                            [C.c_void_p(256 * (i + 1)) for i in range(lbib.NUM_BUFFERS)]))
+    h = C.c_void_p()
+    rc = L.lbib_create(C.byref(grid), tau, C.byref(walls), ptrs, nbuf, None, C.byref(h))
+    return rc, h
+
+
+def test_create_rejects_invalid_arguments(L):
+    g = lbib.make_grid(64, 64, 8, 1, 64, 64)
+    w = lbib.lbib_walls(1, 0, 0.0, 0.0, 0.0, 0, 0.0, 0.0)
+    rc, h = _create(L, g, 0.5, w)
+    assert rc == lbib.EINVAL and not h.value
+    assert b"tau" in L.lbib_last_error(None)
+    rc, _ = _create(L, g, float("nan"), w)
+    assert rc == lbib.EINVAL
+    rc, _ = _create(L, lbib.make_grid(7, 64, 8), 0.8, w)
+    assert rc == lbib.EINVAL
+    rc, _ = _create(L, lbib.make_grid(64, 64, 2), 0.8, w)
+    assert rc == lbib.EINVAL
+    rc, _ = _create(L, lbib.make_grid(64, 64, 4, 1, 64, 5000), 0.8, w)
+    assert rc == lbib.ECAPACITY
+    w0 = lbib.lbib_walls(0, 0, 0.0, 0.0, 0.0, 0, 0.0, 0.0)
+    rc, _ = _create(L, g, 0.8, w0)
+    assert rc == lbib.EINVAL and b"periodic_x" in L.lbib_last_error(None)
+    wbad = lbib.lbib_walls(1, 0, float("inf"), 0.0, 0.0, 0, 0.0, 0.0)
+    rc, _ = _create(L, g, 0.8, wbad)
+    assert rc == lbib.EINVAL
+    wprof = lbib.lbib_walls(1, 0, 0.0, 0.0, 0.0, 7, 0.0, 0.0)
+    rc, _ = _create(L, g, 0.8, wprof)
+    assert rc == lbib.EINVAL
+    rc, _ = _create(L, g, 0.8, w, nbuf=3)
+    assert rc == lbib.EINVAL
+    rc, _ = _create(L, g, 0.8, w, null=True)
+    assert rc == lbib.EINVAL and b"NULL" in L.lbib_last_error(None)
+
+
+def test_null_context_calls(L):
+    assert L.lbib_step(None, 1, 0) == lbib.EINVAL
+    assert L.lbib_check(None, None) == lbib.EINVAL
+    assert L.lbib_steps_done(None) == -1
+    assert L.lbib_get_state(None, 0, 0, None, 0, 0) == lbib.EINVAL
+    assert L.lbib_set_timing(None, 1) == lbib.EINVAL
+    L.lbib_destroy(None)
