@@ -55,6 +55,18 @@ static lbib_status fail(lbib_ctx* ctx, lbib_status code, const std::string& msg)
 
 static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Row stride of the lattice arrays, in cells: nx rounded up to whole 64-cell
+// segments, plus one segment when that is a multiple of 512 cells, so that the
+// row and plane strides are not large powers of two (equal strides map the
+// nine population planes and the rows the XCDs sweep onto the same HBM
+// channels).
+static int row_stride(int nx)
+{
+    int nxp = (nx + kSegW - 1) / kSegW * kSegW;
+    if (nxp % 512 == 0) nxp += kSegW;
+    return nxp;
+}
+
 static bool grid_ok(const lbib_grid* g)
 {
     return g && g->nx >= 8 && g->ny >= 8 && g->nx <= (1 << 20) && g->ny <= (1 << 20) &&
@@ -72,7 +84,7 @@ static size_t status_offset(const lbib_grid* g)
 extern "C" size_t lbib_required_bytes(const lbib_grid* g, int32_t id)
 {
     if (!grid_ok(g)) return 0;
-    const size_t nxp = ((size_t)g->nx + kSegW - 1) / kSegW * kSegW;
+    const size_t nxp = (size_t)row_stride(g->nx);
     const size_t nseg = nxp / kSegW;
     const size_t cells = nxp * g->ny;
     const size_t plane = (size_t)g->nx * g->ny;
@@ -183,7 +195,7 @@ extern "C" lbib_status lbib_create(const lbib_grid* grid, double tau, const lbib
     c->tau = tau;
     c->nu = (tau - 0.5) / 3.0;
     c->rb = grid->real_bytes;
-    c->nxp = (grid->nx + kSegW - 1) / kSegW * kSegW;
+    c->nxp = row_stride(grid->nx);
     c->nseg = c->nxp / kSegW;
     for (int i = 0; i < LBIB_NUM_BUFFERS; i++) c->buf[i] = device_buffers[i];
     c->stream = static_cast<hipStream_t>(hip_stream);
@@ -192,7 +204,7 @@ extern "C" lbib_status lbib_create(const lbib_grid* grid, double tau, const lbib
     // holds the capsule's fluid patch.
     const size_t lds_max = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
     const size_t budget = lds_max - 1024;  // static shared memory of the kernel
-    const size_t per_node = (size_t)14 * c->rb, per_cell = (size_t)3 * c->rb;
+    const size_t per_node = (size_t)18 * c->rb, per_cell = (size_t)3 * c->rb;
     const size_t node_bytes = per_node * grid->max_nodes_capsule;
     if (node_bytes + 1024 * per_cell > budget) {
         delete c;
@@ -278,6 +290,7 @@ static lbib_status add_capsule_t(lbib_ctx* c, const double* xy, int n, const dou
         f[NF_LX * n + v] = (T)(rx - (double)hx);
         f[NF_LY * n + v] = (T)(ry - (double)hy);
         f[NF_L0 * n + v] = (T)l0[v];
+        f[NF_L0L * n + v] = (T)(l0[v] - (double)(T)l0[v]);
         f[NF_TH0 * n + v] = (T)th0[v];
         f[NF_KS * n + v] = (T)(n_ks == 1 ? ks[0] : ks[v]);
     }

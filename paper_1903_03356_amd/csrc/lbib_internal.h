@@ -8,8 +8,9 @@ namespace lbib {
 
 // Force field: one 64-cell row segment per wavefront of the grid kernel.
 constexpr int kSegW = 64;
-constexpr int kGridRows = 4;     // grid kernel block = 64 x 4 cells
-constexpr int kIBThreads = 256;  // IB kernel block (one block per capsule)
+constexpr int kGridRowsPerThread = 1;  // grid kernel: nodes per thread, 4 rows apart
+constexpr int kNumXcd = 8;       // MI355X: workgroups are dealt round-robin to 8 XCDs
+constexpr int kIBThreads = 512;  // IB kernel block (one block per capsule)
 
 // The spread force is accumulated as a signed 64-bit fixed-point number with
 // 48 fractional bits.  Integer addition is associative, so the sum of
@@ -30,6 +31,7 @@ enum NodeField {
     NF_KS,              // stretching constant of element l
     NF_FX, NF_FY,       // last nodal force (total Dynamic / internal Kinematic)
     NF_EX, NF_EY,       // last hydrodynamic nodal force (Dynamic)
+    NF_L0L,             // low part of the stress-free length (l0 = NF_L0 + NF_L0L)
     NF_COUNT
 };
 

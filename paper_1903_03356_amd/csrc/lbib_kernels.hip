@@ -35,14 +35,28 @@ __device__ __forceinline__ T fix_to_real(long long v)
     return (T)v * (T)kFixInv;
 }
 
+// First-order weights 3 w_i of the equilibrium and forcing terms.  3 w_axis is
+// the rounded 1/3 and 3 w_diag is chosen as (1 - 2 * 3 w_axis) / 4, so that
+// 2 (3 w_axis) + 4 (3 w_diag) = 1 exactly in binary: the first moment of the
+// equilibrium then returns the momentum exactly instead of (1 + 7e-9) times it,
+// a bias that would otherwise add up coherently over a channel flow in FP32.
+template <typename T>
+struct FirstOrderW {
+    static constexpr T axis = T(1.0 / 3.0);
+    static constexpr T diag = (T(1) - T(2) * axis) / T(4);
+};
+
 // BGK relaxation with the forcing term for one direction, deviation form:
 // s* = s - omega (s - (f_eq - w)) + (1 - omega/2) w [3 (e - u).F + 9 (e.u)(e.F)]
+// with f_eq - w = w (rho - 1) + 3 w (e . m) + w rho (4.5 (e.u)^2 - 1.5 u^2),
+// m = rho u = sum f e + F/2 taken as is, so that rho * (m / rho) rounding does
+// not leak into the momentum.
 template <typename T>
-__device__ __forceinline__ T relax(T s, T w, T eu, T eF, T drho, T rho, T usq15, T uF, T om,
-                                   T pre)
+__device__ __forceinline__ T relax(T s, T w, T w3, T eu, T em, T eF, T drho, T rho, T usq15,
+                                   T uF, T om, T pre)
 {
-    const T seq = w * (drho + rho * (T(3) * eu + T(4.5) * eu * eu - usq15));
-    const T src = pre * w * (T(3) * (eF - uF) + T(9) * eu * eF);
+    const T seq = w * drho + w3 * em + w * rho * (T(4.5) * eu * eu - usq15);
+    const T src = pre * (w3 * eF + w * (T(9) * eu * eF - T(3) * uF));
     return s - om * (s - seq) + src;
 }
 
@@ -94,20 +108,19 @@ __device__ __forceinline__ void pull(const T* __restrict__ src, int x, int y, co
 }
 
 // ------------------------------------------------------------ grid kernel
-// Block = 64 x 4: each wavefront owns one 64-cell row segment, which is also
-// the granularity of the force-field activity flags.  The wave that owns a
-// segment clears the force accumulator of the previous time level there (if
-// it was active), so the next IB launch finds it zeroed.
+// One lattice node: pull, walls, force-corrected moments, BGK + forcing,
+// store.  The wave that owns the node's 64-cell row segment also clears the
+// force accumulator of the previous time level there (if that segment was
+// active), so the next IB launch finds it zeroed; each segment has exactly one
+// owning wave, which reads its two activity flags before clearing one.
 template <typename T>
-__global__ __launch_bounds__(kSegW* kGridRows) void k_grid_step(
-    const T* __restrict__ src, T* __restrict__ dst, const long long* __restrict__ fib_now,
-    const int* __restrict__ flags_now, long long* __restrict__ fib_old,
-    int* __restrict__ flags_old, GridArgs g)
+__device__ __forceinline__ void grid_cell(const T* __restrict__ src, T* __restrict__ dst,
+                                          const long long* __restrict__ fib_now,
+                                          const int* __restrict__ flags_now,
+                                          long long* __restrict__ fib_old,
+                                          int* __restrict__ flags_old, const GridArgs& g, int y,
+                                          int seg, int lane)
 {
-    const int lane = threadIdx.x;
-    const int y = blockIdx.y * kGridRows + threadIdx.y;
-    if (y >= g.ny) return;
-    const int seg = blockIdx.x;
     const int x = seg * kSegW + lane;
     const int fidx = y * g.nseg + seg;
     const int act = flags_now[fidx];
@@ -127,24 +140,25 @@ __global__ __launch_bounds__(kSegW* kGridRows) void k_grid_step(
         const T jx = (s[1] - s[3]) + (s[5] - s[6]) + (s[8] - s[7]);
         const T jy = (s[2] - s[4]) + (s[5] + s[6]) - (s[7] + s[8]);
         const T irho = T(1) / rho;
-        const T ux = (jx + T(0.5) * Fx) * irho;
-        const T uy = (jy + T(0.5) * Fy) * irho;
+        const T mx = jx + T(0.5) * Fx, my = jy + T(0.5) * Fy;  // rho u (Eq. 7)
+        const T ux = mx * irho, uy = my * irho;
         const T om = (T)g.omega;
         const T pre = T(1) - T(0.5) * om;
         const T usq15 = T(1.5) * (ux * ux + uy * uy);
         const T uF = ux * Fx + uy * Fy;
         const T wa = T(1.0 / 9.0), wd = T(1.0 / 36.0);
+        const T w3a = FirstOrderW<T>::axis, w3d = FirstOrderW<T>::diag;
         const size_t plane = (size_t)g.ny * g.nxp;
         T* o = dst + cell;
-        o[0] = relax(s[0], T(4.0 / 9.0), T(0), T(0), drho, rho, usq15, uF, om, pre);
-        o[plane] = relax(s[1], wa, ux, Fx, drho, rho, usq15, uF, om, pre);
-        o[2 * plane] = relax(s[2], wa, uy, Fy, drho, rho, usq15, uF, om, pre);
-        o[3 * plane] = relax(s[3], wa, -ux, -Fx, drho, rho, usq15, uF, om, pre);
-        o[4 * plane] = relax(s[4], wa, -uy, -Fy, drho, rho, usq15, uF, om, pre);
-        o[5 * plane] = relax(s[5], wd, ux + uy, Fx + Fy, drho, rho, usq15, uF, om, pre);
-        o[6 * plane] = relax(s[6], wd, uy - ux, Fy - Fx, drho, rho, usq15, uF, om, pre);
-        o[7 * plane] = relax(s[7], wd, -ux - uy, -Fx - Fy, drho, rho, usq15, uF, om, pre);
-        o[8 * plane] = relax(s[8], wd, ux - uy, Fx - Fy, drho, rho, usq15, uF, om, pre);
+        o[0] = relax(s[0], T(4.0 / 9.0), T(0), T(0), T(0), T(0), drho, rho, usq15, uF, om, pre);
+        o[plane] = relax(s[1], wa, w3a, ux, mx, Fx, drho, rho, usq15, uF, om, pre);
+        o[2 * plane] = relax(s[2], wa, w3a, uy, my, Fy, drho, rho, usq15, uF, om, pre);
+        o[3 * plane] = relax(s[3], wa, w3a, -ux, -mx, -Fx, drho, rho, usq15, uF, om, pre);
+        o[4 * plane] = relax(s[4], wa, w3a, -uy, -my, -Fy, drho, rho, usq15, uF, om, pre);
+        o[5 * plane] = relax(s[5], wd, w3d, ux + uy, mx + my, Fx + Fy, drho, rho, usq15, uF, om, pre);
+        o[6 * plane] = relax(s[6], wd, w3d, uy - ux, my - mx, Fy - Fx, drho, rho, usq15, uF, om, pre);
+        o[7 * plane] = relax(s[7], wd, w3d, -ux - uy, -mx - my, -Fx - Fy, drho, rho, usq15, uF, om, pre);
+        o[8 * plane] = relax(s[8], wd, w3d, ux - uy, mx - my, Fx - Fy, drho, rho, usq15, uF, om, pre);
     }
     if (old) {
         *reinterpret_cast<longlong2*>(fib_old + 2 * cell) = make_longlong2(0, 0);
@@ -152,14 +166,44 @@ __global__ __launch_bounds__(kSegW* kGridRows) void k_grid_step(
     }
 }
 
+// Block = 4 wavefronts; a block covers one 64-cell column of a band of
+// 4 * ROWS rows, each thread ROWS nodes 4 rows apart (more loads in flight per
+// thread).  Workgroups are dealt to the 8 XCDs round-robin; block b is
+// remapped so that XCD b % 8 takes whole bands (band = 8 k + b % 8) and walks
+// each band along x.  The 8 XCDs then sweep neighbouring bands together
+// (accesses spread over all HBM channels), and the cache lines that the
+// x-shifted pulls share between neighbouring segments of a band stay in the L2
+// of the XCD that owns the band.
+template <typename T, int ROWS>
+__global__ __launch_bounds__(kSegW * 4) void k_grid_step(
+    const T* __restrict__ src, T* __restrict__ dst, const long long* __restrict__ fib_now,
+    const int* __restrict__ flags_now, long long* __restrict__ fib_old,
+    int* __restrict__ flags_old, GridArgs g)
+{
+    const int b = blockIdx.x;
+    const int j = b / kNumXcd;  // j-th block dealt to this XCD
+    const int group = j / g.nseg;
+    const int band = group * kNumXcd + (b - j * kNumXcd);
+    const int seg = j - group * g.nseg;
+    const int lane = threadIdx.x & (kSegW - 1);
+    const int y0 = band * (4 * ROWS) + (threadIdx.x >> 6);
+#pragma unroll
+    for (int r = 0; r < ROWS; r++) {
+        const int y = y0 + 4 * r;
+        if (y < g.ny) grid_cell(src, dst, fib_now, flags_now, fib_old, flags_old, g, y, seg, lane);
+    }
+}
+
 template <typename T>
 hipError_t launch_grid_step(const T* src, T* dst, const long long* fib_now, const int* flags_now,
                             long long* fib_old, int* flags_old, const GridArgs& g, hipStream_t s)
 {
-    dim3 block(kSegW, kGridRows);
-    dim3 grid(g.nseg, (g.ny + kGridRows - 1) / kGridRows);
-    hipLaunchKernelGGL(k_grid_step<T>, grid, block, 0, s, src, dst, fib_now, flags_now, fib_old,
-                       flags_old, g);
+    constexpr int R = kGridRowsPerThread;
+    const long long bands = (g.ny + 4 * R - 1) / (4 * R);
+    const long long groups = (bands + kNumXcd - 1) / kNumXcd;
+    const long long blocks = groups * g.nseg * kNumXcd;
+    hipLaunchKernelGGL((k_grid_step<T, R>), dim3((unsigned)blocks), dim3(kSegW * 4), 0, s, src, dst,
+                       fib_now, flags_now, fib_old, flags_old, g);
     return hipGetLastError();
 }
 
@@ -203,6 +247,7 @@ hipError_t launch_init(T* pops, const GridArgs& g, int profile, double ux0, doub
 template <typename T>
 __device__ __forceinline__ void two_sum(T a, T b, T& s, T& e)
 {
+#pragma clang fp contract(off)
     s = a + b;
     const T bb = s - a;
     e = (a - (s - bb)) + (b - bb);
@@ -212,6 +257,7 @@ __device__ __forceinline__ void two_sum(T a, T b, T& s, T& e)
 template <typename T>
 __device__ __forceinline__ void comp_add(T& hi, T& lo, T d)
 {
+#pragma clang fp contract(off)
     T s, e;
     two_sum(hi, d, s, e);
     e += lo;
@@ -221,7 +267,10 @@ __device__ __forceinline__ void comp_add(T& hi, T& lo, T d)
     lo = e2;
 }
 
-// Deterministic block reductions (block = 4 wavefronts of 64).
+// Deterministic block reductions over the kIBThreads / 64 wavefronts of the
+// IB kernel: butterfly within each wave, then the wave partials in order.
+constexpr int kIBWaves = kIBThreads / 64;
+
 template <int N>
 __device__ __forceinline__ void block_sum(double (&v)[N], double (*red)[8])
 {
@@ -234,7 +283,11 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double (*red)[8])
         for (int k = 0; k < N; k++) red[wave][k] = v[k];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < N; k++) v[k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+    for (int k = 0; k < N; k++) {
+        double acc = red[0][k];
+        for (int w = 1; w < kIBWaves; w++) acc += red[w][k];
+        v[k] = acc;
+    }
     __syncthreads();
 }
 
@@ -254,9 +307,13 @@ __device__ __forceinline__ void block_minmax(float (&mn)[2], float (&mx)[2], dou
     }
     __syncthreads();
     for (int k = 0; k < 2; k++) {
-        mn[k] = fminf(fminf((float)red[0][k], (float)red[1][k]), fminf((float)red[2][k], (float)red[3][k]));
-        mx[k] = fmaxf(fmaxf((float)red[0][2 + k], (float)red[1][2 + k]),
-                      fmaxf((float)red[2][2 + k], (float)red[3][2 + k]));
+        float a = (float)red[0][k], b = (float)red[0][2 + k];
+        for (int w = 1; w < kIBWaves; w++) {
+            a = fminf(a, (float)red[w][k]);
+            b = fmaxf(b, (float)red[w][2 + k]);
+        }
+        mn[k] = a;
+        mx[k] = b;
     }
     __syncthreads();
 }
@@ -384,7 +441,7 @@ struct Scratch {
     T* py;
     T* qx;  // low parts of the compensated positions
     T* qy;
-    T* t[10];
+    T* t[14];
 };
 
 // Edge vector x_m - x_l from compensated coordinates: the difference of the
@@ -396,6 +453,40 @@ __device__ __forceinline__ void edge(const Scratch<T>& S, int l, int m, T& tx, T
     ty = (S.py[m] - S.py[l]) + (S.qy[m] - S.qy[l]);
 }
 
+// Error-free product a * b = p + e (FMA).
+template <typename T>
+__device__ __forceinline__ void two_prod(T a, T b, T& p, T& e)
+{
+#pragma clang fp contract(off)
+    p = a * b;
+    e = fma(a, b, -p);
+}
+
+// Stretch of element l -> m, len - l0, and len.  In FP32 the two lengths are
+// nearly equal, so the difference is formed as (len^2 - l0^2) / (len + l0)
+// with len^2 and l0^2 carried as unevaluated float pairs: the edge vector from
+// the compensated coordinates, l0 from its stored high and low parts.
+template <typename T>
+__device__ __forceinline__ T stretch(const Scratch<T>& S, int l, int m, T l0h, T l0l, T& len)
+{
+#pragma clang fp contract(off)
+    T hx, ex, hy, ey;
+    two_sum(S.px[m], -S.px[l], hx, ex);
+    two_sum(S.py[m], -S.py[l], hy, ey);
+    const T lx = ex + (S.qx[m] - S.qx[l]);
+    const T ly = ey + (S.qy[m] - S.qy[l]);
+    T p1, e1, p2, e2, s, es, q, eq;
+    two_prod(hx, hx, p1, e1);
+    two_prod(hy, hy, p2, e2);
+    two_sum(p1, p2, s, es);
+    const T lo = es + e1 + e2 + T(2) * (hx * lx + hy * ly) + (lx * lx + ly * ly);
+    two_prod(l0h, l0h, q, eq);
+    const T lo0 = eq + T(2) * l0h * l0l + l0l * l0l;
+    const T diff = (s - q) + (lo - lo0);
+    len = sqrt(s + lo);
+    return diff / (len + (l0h + l0l));
+}
+
 // Eqs. 10-14: internal nodal forces at positions (px, py); result in
 // (S.t[8], S.t[9]).  Stretch on element l: k_s (len - l0) t / len on node l and
 // its negative on node l+1.  Area: F_l = -k_a (1 - A/A0) c_s^2 n- len, half to
@@ -404,8 +495,9 @@ __device__ __forceinline__ void edge(const Scratch<T>& S, int l, int m, T& tx, T
 // The area A is an FP64 block reduction.
 template <typename T>
 __device__ void internal_forces(const Scratch<T>& S, int nv, const T* __restrict__ l0,
-                                const T* __restrict__ th0, const T* __restrict__ ks, double kb,
-                                double ka, double A0, double (*red)[8])
+                                const T* __restrict__ l0l, const T* __restrict__ th0,
+                                const T* __restrict__ ks, double kb, double ka, double A0,
+                                double (*red)[8])
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     double acc[1] = {0.0};
@@ -424,10 +516,9 @@ __device__ void internal_forces(const Scratch<T>& S, int nv, const T* __restrict
     T* Qy = S.t[3];
     for (int l = tid; l < nv; l += nt) {
         const int m = l + 1 == nv ? 0 : l + 1;
-        T tx, ty;
+        T tx, ty, len;
         edge(S, l, m, tx, ty);
-        const T len = sqrt(tx * tx + ty * ty);
-        const T c = ks[l] * (len - l0[l]) / len;
+        const T c = ks[l] * stretch(S, l, m, l0[l], l0l[l], len) / len;
         const T ax = cA * ty, ay = -cA * tx;
         Px[l] = c * tx + ax;  // onto node l
         Py[l] = c * ty + ay;
@@ -469,28 +560,46 @@ __device__ void internal_forces(const Scratch<T>& S, int nv, const T* __restrict
 }
 
 // Eqs. 15-16: hydrodynamic nodal forces at positions (px, py) into
-// (S.t[2], S.t[3]), using S.t[0..1] for the element halves.
+// (S.t[2], S.t[3]).  One work item per (element, side) evaluates a probe
+// (pressure deviation and the symmetric velocity-gradient terms) into
+// S.t[0..7]; one per element combines both sides into its half force
+// (S.t[10..11]); one per node adds the halves of its two elements.
 template <typename T>
 __device__ void external_forces(const Scratch<T>& S, const Patch<T>& P, int nv, T nu, int& st)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
-    T* Ex = S.t[0];
-    T* Ey = S.t[1];
+    for (int w = tid; w < 2 * nv; w += nt) {
+        const int l = w >> 1, side = w & 1;
+        const int m = l + 1 == nv ? 0 : l + 1;
+        T tx, ty;
+        edge(S, l, m, tx, ty);
+        const T len = sqrt(tx * tx + ty * ty);
+        const T sg = side ? T(-1.2) : T(1.2);
+        const T nx = ty / len, ny = -tx / len;  // outward normal n+
+        const T xc = T(0.5) * (S.px[l] + S.px[m]), yc = T(0.5) * (S.py[l] + S.py[m]);
+        T dp, G[2][2];
+        probe(P, xc + sg * nx, yc + sg * ny, dp, G, st);
+        T* o = S.t[0] + (size_t)side * 4 * (S.t[1] - S.t[0]);
+        const size_t stride = S.t[1] - S.t[0];
+        o[l] = dp;
+        o[stride + l] = T(2) * G[0][0];
+        o[2 * stride + l] = T(2) * G[1][1];
+        o[3 * stride + l] = G[0][1] + G[1][0];
+    }
+    __syncthreads();
+    T* Ex = S.t[10];
+    T* Ey = S.t[11];
     for (int l = tid; l < nv; l += nt) {
         const int m = l + 1 == nv ? 0 : l + 1;
         T tx, ty;
         edge(S, l, m, tx, ty);
         const T len = sqrt(tx * tx + ty * ty);
-        const T nx = ty / len, ny = -tx / len;  // outward normal n+
-        const T xc = T(0.5) * (S.px[l] + S.px[m]), yc = T(0.5) * (S.py[l] + S.py[m]);
-        T dpp, dpm, Gp[2][2], Gm[2][2];
-        probe(P, xc + T(1.2) * nx, yc + T(1.2) * ny, dpp, Gp, st);
-        probe(P, xc - T(1.2) * nx, yc - T(1.2) * ny, dpm, Gm, st);
+        const T nx = ty / len, ny = -tx / len;
         // (tau+ - tau-) . n+ with tau = nu (G + G^T)
-        const T d00 = T(2) * (Gp[0][0] - Gm[0][0]);
-        const T d11 = T(2) * (Gp[1][1] - Gm[1][1]);
-        const T d01 = (Gp[0][1] - Gm[0][1]) + (Gp[1][0] - Gm[1][0]);
-        const T dpr = dpp - dpm;
+        const T dpr = S.t[0][l] - S.t[4][l];
+        const T d00 = S.t[1][l] - S.t[5][l];
+        const T d11 = S.t[2][l] - S.t[6][l];
+        const T d01 = S.t[3][l] - S.t[7][l];
         const T fx = (-dpr * nx + nu * (d00 * nx + d01 * ny)) * len;
         const T fy = (-dpr * ny + nu * (d01 * nx + d11 * ny)) * len;
         Ex[l] = T(0.5) * fx;
@@ -515,29 +624,52 @@ __device__ __forceinline__ long long to_fix(T v, int& st)
     return (long long)rint((double)v * kFixScale);
 }
 
-// Spreads c * phi_k(p) * (Fx, Fy) to the 3x3 support of p (Dynamic step 3,
-// Kinematic step iii).
+// One spreading contribution (Dynamic step 3, Kinematic step iii): the value
+// (vx, vy) = c phi_k F goes to support node k of the 3x3 support centred on
+// (cx, cy), relative to the reference point.
 template <typename T>
-__device__ __forceinline__ void spread(const IBArgs<T>& a, long long refx, long long refy, T px,
-                                       T py, T c, T Fx, T Fy, int& st)
+__device__ __forceinline__ void spread_one(const IBArgs<T>& a, long long refx, long long refy,
+                                           int cx, int cy, int k, T vx, T vy, int& st)
 {
-    int cx, cy;
-    T phi[9];
-    mls<T, false>(px, py, cx, cy, phi, nullptr, nullptr);
+    long long gy = refy + cy + k / 3 - 1;
+    if (a.periodic_y) gy = ((gy % a.ny) + a.ny) % a.ny;
+    else if (gy < 1 || gy > a.ny - 2) { st |= ST_WALL; return; }
+    long long gx = refx + cx + k % 3 - 1;
+    gx = ((gx % a.nx) + a.nx) % a.nx;
+    const long long fx = to_fix(vx, st), fy = to_fix(vy, st);
+    const size_t cell = (size_t)gy * a.nxp + (size_t)gx;
+    unsigned long long* dst = reinterpret_cast<unsigned long long*>(a.fib_next + 2 * cell);
+    atomicAdd(dst, (unsigned long long)fx);
+    atomicAdd(dst + 1, (unsigned long long)fy);
+    a.flags_next[gy * a.nseg + gx / kSegW] = 1;
+}
+
+// MLS weights of node v cached for the spreading: phi_0..7 in S.t[0..7],
+// phi_8 in S.t[12], support centre in S.t[10..11] (exact small integers).
+template <typename T>
+__device__ __forceinline__ void cache_weights(const Scratch<T>& S, int v, int cx, int cy,
+                                              const T* phi)
+{
 #pragma unroll
-    for (int k = 0; k < 9; k++) {
-        long long gy = refy + cy + k / 3 - 1;
-        if (a.periodic_y) gy = ((gy % a.ny) + a.ny) % a.ny;
-        else if (gy < 1 || gy > a.ny - 2) { st |= ST_WALL; continue; }
-        long long gx = refx + cx + k % 3 - 1;
-        gx = ((gx % a.nx) + a.nx) % a.nx;
-        const T cp = c * phi[k];
-        const long long fx = to_fix(cp * Fx, st), fy = to_fix(cp * Fy, st);
-        const size_t cell = (size_t)gy * a.nxp + (size_t)gx;
-        unsigned long long* dst = reinterpret_cast<unsigned long long*>(a.fib_next + 2 * cell);
-        atomicAdd(dst, (unsigned long long)fx);
-        atomicAdd(dst + 1, (unsigned long long)fy);
-        a.flags_next[gy * a.nseg + gx / kSegW] = 1;
+    for (int k = 0; k < 8; k++) S.t[k][v] = phi[k];
+    S.t[12][v] = phi[8];
+    S.t[10][v] = (T)cx;
+    S.t[11][v] = (T)cy;
+}
+
+// Spreads the cached c_v F_v (S.t[8..9]) with the cached weights; one work
+// item per (node, support node).
+template <typename T>
+__device__ __forceinline__ void spread_cached(const IBArgs<T>& a, const Scratch<T>& S, int nv,
+                                              long long refx, long long refy, int& st)
+{
+    const T* base = S.t[0];
+    const size_t stride = S.t[1] - S.t[0];  // the scratch arrays are contiguous
+    for (int w = threadIdx.x; w < 9 * nv; w += blockDim.x) {
+        const int v = w / 9, k = w - 9 * v;
+        const T phi = base[(size_t)(k < 8 ? k : 12) * stride + v];
+        spread_one(a, refx, refy, (int)S.t[10][v], (int)S.t[11][v], k, phi * S.t[8][v],
+                   phi * S.t[9][v], st);
     }
 }
 
@@ -628,7 +760,7 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
     S.py = S.px + a.max_nv;
     S.qx = S.py + a.max_nv;
     S.qy = S.qx + a.max_nv;
-    for (int k = 0; k < 10; k++) S.t[k] = S.qy + (size_t)(k + 1) * a.max_nv;
+    for (int k = 0; k < 14; k++) S.t[k] = S.qy + (size_t)(k + 1) * a.max_nv;
 
     int st = 0;
     const bool prime = (a.phase & PH_PRIME) && !cap.primed;
@@ -723,10 +855,11 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
     // ---- node update closing the previous step
     if (doB) {
         const T* l0 = N + NF_L0 * NS + off;
+        const T* l0l = N + NF_L0L * NS + off;
         const T* th0 = N + NF_TH0 * NS + off;
         const T* ks = N + NF_KS * NS + off;
         if (a.dynamic) {
-            internal_forces(S, nv, l0, th0, ks, cap.kb, cap.ka, cap.A0, red);  // -> t8, t9
+            internal_forces(S, nv, l0, l0l, th0, ks, cap.kb, cap.ka, cap.A0, red);  // -> t8, t9
             external_forces(S, P, nv, (T)a.nu, st);                            // -> t2, t3
         }
         const T half_inv_m = (T)(0.5 / cap.mv);
@@ -804,28 +937,45 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
         if (a.dynamic) {
             for (int v = tid; v < nv; v += nt) {
                 const int vl = v == 0 ? nv - 1 : v - 1, vr = v + 1 == nv ? 0 : v + 1;
-                T Ux, Uy;
-                interp_u(P, S.px[v], S.py[v], Ux, Uy, st);
+                int cx, cy;
+                T phi[9];
+                mls<T, false>(S.px[v], S.py[v], cx, cy, phi, nullptr, nullptr);
+                T Ux = T(0), Uy = T(0);  // Eq. 8
+#pragma unroll
+                for (int k = 0; k < 9; k++) {
+                    int idx;
+                    if (!patch_index(P, cx, cy, k, idx)) { st |= ST_PATCH; continue; }
+                    if (isnan(P.drho[idx])) { st |= ST_WALL; continue; }
+                    Ux += phi[k] * P.ux[idx];
+                    Uy += phi[k] * P.uy[idx];
+                }
                 const T Fx = N[NF_UX * NS + off + v] - Ux;  // (U_b - U) / dt, step 1
                 const T Fy = N[NF_UY * NS + off + v] - Uy;
                 T ax, ay, bx, by;
                 edge(S, vl, v, ax, ay);
                 edge(S, v, vr, bx, by);
                 const T cv = T(0.5) * (sqrt(ax * ax + ay * ay) + sqrt(bx * bx + by * by));
-                spread(a, refx, refy, S.px[v], S.py[v], cv, Fx, Fy, st);
+                cache_weights(S, v, cx, cy, phi);
+                S.t[8][v] = cv * Fx;
+                S.t[9][v] = cv * Fy;
             }
         } else {
             const T* l0 = N + NF_L0 * NS + off;
+            const T* l0l = N + NF_L0L * NS + off;
             const T* th0 = N + NF_TH0 * NS + off;
             const T* ks = N + NF_KS * NS + off;
-            internal_forces(S, nv, l0, th0, ks, cap.kb, cap.ka, cap.A0, red);
+            internal_forces(S, nv, l0, l0l, th0, ks, cap.kb, cap.ka, cap.A0, red);  // -> t8, t9
             for (int v = tid; v < nv; v += nt) {
-                const T Fx = S.t[8][v], Fy = S.t[9][v];
-                N[NF_FX * NS + off + v] = Fx;
-                N[NF_FY * NS + off + v] = Fy;
-                spread(a, refx, refy, S.px[v], S.py[v], T(1), Fx, Fy, st);
+                N[NF_FX * NS + off + v] = S.t[8][v];
+                N[NF_FY * NS + off + v] = S.t[9][v];
+                int cx, cy;
+                T phi[9];
+                mls<T, false>(S.px[v], S.py[v], cx, cy, phi, nullptr, nullptr);
+                cache_weights(S, v, cx, cy, phi);  // c_v = 1
             }
         }
+        __syncthreads();
+        spread_cached(a, S, nv, refx, refy, st);
     }
     if (prime && tid == 0) a.caps[c].primed = 1;
     if (st) atomicOr(a.status, st);
@@ -834,7 +984,7 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
 template <typename T>
 size_t ib_lds_bytes(int patch_cap, int max_nv)
 {
-    return sizeof(T) * ((size_t)3 * patch_cap + (size_t)14 * max_nv);
+    return sizeof(T) * ((size_t)3 * patch_cap + (size_t)18 * max_nv);
 }
 
 template <typename T>

@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol(L):
 
 def test_required_bytes(L):
     g = lbib.make_grid(100, 37, 4, 3, 300, 128)
-    nxp = 128
+    nxp = 128  # 100 rounded up to whole 64-cell segments
     assert lbib.required_bytes(g, 0) == -(-9 * nxp * 37 * 4 // 256) * 256
     assert lbib.required_bytes(g, 1) == lbib.required_bytes(g, 0)
     assert lbib.required_bytes(g, 2) >= 2 * nxp * 37 * 16
@@ -44,6 +44,9 @@ def test_required_bytes(L):
     assert lbib.required_bytes(g8, 0) == 2 * lbib.required_bytes(g, 0)
     for i in range(8):
         assert lbib.required_bytes(g, i) % 256 == 0
+    # a row of 1024 cells is padded by one segment (no power-of-two strides)
+    g2 = lbib.make_grid(1024, 16, 4)
+    assert lbib.required_bytes(g2, 0) == -(-9 * 1088 * 16 * 4 // 256) * 256
     bad = lbib.make_grid(4, 37, 4)
     assert all(lbib.required_bytes(bad, i) == 0 for i in range(8))
     bad = lbib.make_grid(100, 37, 2)
