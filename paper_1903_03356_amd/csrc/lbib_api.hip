@@ -204,7 +204,7 @@ extern "C" lbib_status lbib_create(const lbib_grid* grid, double tau, const lbib
     // holds the capsule's fluid patch.
     const size_t lds_max = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
     const size_t budget = lds_max - 1024;  // static shared memory of the kernel
-    const size_t per_node = (size_t)18 * c->rb, per_cell = (size_t)3 * c->rb;
+    const size_t per_node = (size_t)26 * c->rb, per_cell = (size_t)3 * c->rb;
     const size_t node_bytes = per_node * grid->max_nodes_capsule;
     if (node_bytes + 1024 * per_cell > budget) {
         delete c;

@@ -441,6 +441,14 @@ struct Scratch {
     T* py;
     T* qx;  // low parts of the compensated positions
     T* qy;
+    T* dx;  // last displacement d^n
+    T* dy;
+    T* ux;  // node velocity u_v^n
+    T* uy;
+    T* l0;  // stress-free length (high, low), stretching constant, turning angle
+    T* l0l;
+    T* ks;
+    T* th0;
     T* t[14];
 };
 
@@ -494,11 +502,13 @@ __device__ __forceinline__ T stretch(const Scratch<T>& S, int l, int m, T l0h, T
 // minus their sum): k_b sin(theta - theta0) n / len on the two neighbours.
 // The area A is an FP64 block reduction.
 template <typename T>
-__device__ void internal_forces(const Scratch<T>& S, int nv, const T* __restrict__ l0,
-                                const T* __restrict__ l0l, const T* __restrict__ th0,
-                                const T* __restrict__ ks, double kb, double ka, double A0,
+__device__ void internal_forces(const Scratch<T>& S, int nv, double kb, double ka, double A0,
                                 double (*red)[8])
 {
+    const T* l0 = S.l0;
+    const T* l0l = S.l0l;
+    const T* th0 = S.th0;
+    const T* ks = S.ks;
     const int tid = threadIdx.x, nt = blockDim.x;
     double acc[1] = {0.0};
     for (int l = tid; l < nv; l += nt) {
@@ -726,6 +736,37 @@ __device__ void diagnostics(const IBArgs<T>& a, const CapsuleDev& cap, int c, do
     }
 }
 
+// Moments of one patch cell from the pulled populations f^n and the force
+// F^{n-1} of the last collision (Eqs. 6-7): rho - 1 and the force-corrected
+// velocity.  Cells on a wall row are marked NaN.
+template <typename T>
+__device__ __forceinline__ void stage_cell(const IBArgs<T>& a, const GridArgs& g, const Patch<T>& P,
+                                           long long refx, long long refy, T gxf, int i)
+{
+    const int lx = i % P.W, ly = i / P.W;
+    long long wy = refy + P.oy + ly;
+    if (a.periodic_y) wy = ((wy % a.ny) + a.ny) % a.ny;
+    else if (wy < 1 || wy > a.ny - 2) {
+        P.drho[i] = T(NAN);
+        P.ux[i] = P.uy[i] = T(0);
+        return;
+    }
+    long long wx = refx + P.ox + lx;
+    wx = ((wx % a.nx) + a.nx) % a.nx;
+    T s[9];
+    pull(a.pops, (int)wx, (int)wy, g, gxf, s);
+    const size_t cell = (size_t)wy * a.nxp + (size_t)wx;
+    const T Fx = gxf + fix_to_real<T>(a.fib_prev[2 * cell]);
+    const T Fy = fix_to_real<T>(a.fib_prev[2 * cell + 1]);
+    const T drho = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])) + s[8];
+    const T jx = (s[1] - s[3]) + (s[5] - s[6]) + (s[8] - s[7]);
+    const T jy = (s[2] - s[4]) + (s[5] + s[6]) - (s[7] + s[8]);
+    const T irho = T(1) / (T(1) + drho);
+    P.drho[i] = drho;
+    P.ux[i] = (jx + T(0.5) * Fx) * irho;
+    P.uy[i] = (jy + T(0.5) * Fy) * irho;
+}
+
 // One block per capsule.  Phases (bit set):
 //   PH_PRIME  start-up of a capsule not yet started: u_v^0 = U(x^0), d^0 = U(x^0)
 //   PH_B      node update closing step n-1 from the fields after its collision:
@@ -760,7 +801,17 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
     S.py = S.px + a.max_nv;
     S.qx = S.py + a.max_nv;
     S.qy = S.qx + a.max_nv;
-    for (int k = 0; k < 14; k++) S.t[k] = S.qy + (size_t)(k + 1) * a.max_nv;
+    T* node_lds[8];
+    for (int k = 0; k < 8; k++) node_lds[k] = S.qy + (size_t)(k + 1) * a.max_nv;
+    S.dx = node_lds[0];
+    S.dy = node_lds[1];
+    S.ux = node_lds[2];
+    S.uy = node_lds[3];
+    S.l0 = node_lds[4];
+    S.l0l = node_lds[5];
+    S.ks = node_lds[6];
+    S.th0 = node_lds[7];
+    for (int k = 0; k < 14; k++) S.t[k] = S.th0 + (size_t)(k + 1) * a.max_nv;
 
     int st = 0;
     const bool prime = (a.phase & PH_PRIME) && !cap.primed;
@@ -776,6 +827,14 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
         S.py[v] = y;
         S.qx[v] = N[NF_LX * NS + off + v];
         S.qy[v] = N[NF_LY * NS + off + v];
+        S.dx[v] = N[NF_DX * NS + off + v];
+        S.dy[v] = N[NF_DY * NS + off + v];
+        S.ux[v] = N[NF_UX * NS + off + v];
+        S.uy[v] = N[NF_UY * NS + off + v];
+        S.l0[v] = N[NF_L0 * NS + off + v];
+        S.l0l[v] = N[NF_L0L * NS + off + v];
+        S.ks[v] = N[NF_KS * NS + off + v];
+        S.th0[v] = N[NF_TH0 * NS + off + v];
         finite = finite && isfinite(x) && isfinite(y);
         mn[0] = fminf(mn[0], (float)x);
         mn[1] = fminf(mn[1], (float)y);
@@ -813,29 +872,11 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
         g.periodic_y = a.periodic_y;
         g.u_bot = g.u_top = 0.0;  // wall rows are never staged
         const T gxf = (T)a.gx;
-        for (int i = tid; i < P.W * P.H; i += nt) {
-            const int lx = i % P.W, ly = i / P.W;
-            long long wy = refy + P.oy + ly;
-            if (a.periodic_y) wy = ((wy % a.ny) + a.ny) % a.ny;
-            else if (wy < 1 || wy > a.ny - 2) {
-                P.drho[i] = T(NAN);
-                P.ux[i] = P.uy[i] = T(0);
-                continue;
-            }
-            long long wx = refx + P.ox + lx;
-            wx = ((wx % a.nx) + a.nx) % a.nx;
-            T s[9];
-            pull(a.pops, (int)wx, (int)wy, g, gxf, s);
-            const size_t cell = (size_t)wy * a.nxp + (size_t)wx;
-            const T Fx = gxf + fix_to_real<T>(a.fib_prev[2 * cell]);
-            const T Fy = fix_to_real<T>(a.fib_prev[2 * cell + 1]);
-            const T drho = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])) + s[8];
-            const T jx = (s[1] - s[3]) + (s[5] - s[6]) + (s[8] - s[7]);
-            const T jy = (s[2] - s[4]) + (s[5] + s[6]) - (s[7] + s[8]);
-            const T irho = T(1) / (T(1) + drho);
-            P.drho[i] = drho;
-            P.ux[i] = (jx + T(0.5) * Fx) * irho;
-            P.uy[i] = (jy + T(0.5) * Fy) * irho;
+        // two cells per iteration, so that both cells' loads are in flight together
+        const int ncell = P.W * P.H;
+        for (int i = tid; i < ncell; i += 2 * nt) {
+            stage_cell(a, g, P, refx, refy, gxf, i);
+            if (i + nt < ncell) stage_cell(a, g, P, refx, refy, gxf, i + nt);
         }
         __syncthreads();
     }
@@ -849,17 +890,17 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
             N[NF_UY * NS + off + v] = Uy;
             N[NF_DX * NS + off + v] = Ux;
             N[NF_DY * NS + off + v] = Uy;
+            S.ux[v] = Ux;
+            S.uy[v] = Uy;
+            S.dx[v] = Ux;
+            S.dy[v] = Uy;
         }
     }
 
     // ---- node update closing the previous step
     if (doB) {
-        const T* l0 = N + NF_L0 * NS + off;
-        const T* l0l = N + NF_L0L * NS + off;
-        const T* th0 = N + NF_TH0 * NS + off;
-        const T* ks = N + NF_KS * NS + off;
         if (a.dynamic) {
-            internal_forces(S, nv, l0, l0l, th0, ks, cap.kb, cap.ka, cap.A0, red);  // -> t8, t9
+            internal_forces(S, nv, cap.kb, cap.ka, cap.A0, red);  // -> t8, t9
             external_forces(S, P, nv, (T)a.nu, st);                            // -> t2, t3
         }
         const T half_inv_m = (T)(0.5 / cap.mv);
@@ -867,14 +908,17 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
         for (int v = tid; v < nv; v += nt) {
             T Ux, Uy;
             interp_u(P, S.px[v], S.py[v], Ux, Uy, st);  // tentative velocity, Eq. 23
-            const T dox = N[NF_DX * NS + off + v], doy = N[NF_DY * NS + off + v];
+            const T dox = S.dx[v], doy = S.dy[v];
             T dx, dy;
             if (a.dynamic) {
                 const T fx = S.t[8][v] + S.t[2][v], fy = S.t[9][v] + S.t[3][v];
                 dx = Ux + half_inv_m * fx;  // Eq. 23
                 dy = Uy + half_inv_m * fy;
-                N[NF_UX * NS + off + v] = T(1.5) * dx - T(0.5) * dox;  // Eq. 24
-                N[NF_UY * NS + off + v] = T(1.5) * dy - T(0.5) * doy;
+                const T uvx = T(1.5) * dx - T(0.5) * dox, uvy = T(1.5) * dy - T(0.5) * doy;  // Eq. 24
+                N[NF_UX * NS + off + v] = uvx;
+                N[NF_UY * NS + off + v] = uvy;
+                S.ux[v] = uvx;
+                S.uy[v] = uvy;
                 N[NF_FX * NS + off + v] = fx;
                 N[NF_FY * NS + off + v] = fy;
                 N[NF_EX * NS + off + v] = S.t[2][v];
@@ -885,7 +929,9 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
             }
             if (!(fabs(dx) < T(1) && fabs(dy) < T(1))) st |= ST_MOVE;
             N[NF_DX * NS + off + v] = dx;
+            S.dx[v] = dx;
             N[NF_DY * NS + off + v] = dy;
+            S.dy[v] = dy;
             T hx = S.px[v], lx = S.qx[v];
             T hy = S.py[v], ly = S.qy[v];
             comp_add(hx, lx, dx);
@@ -949,8 +995,8 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
                     Ux += phi[k] * P.ux[idx];
                     Uy += phi[k] * P.uy[idx];
                 }
-                const T Fx = N[NF_UX * NS + off + v] - Ux;  // (U_b - U) / dt, step 1
-                const T Fy = N[NF_UY * NS + off + v] - Uy;
+                const T Fx = S.ux[v] - Ux;  // (U_b - U) / dt, step 1
+                const T Fy = S.uy[v] - Uy;
                 T ax, ay, bx, by;
                 edge(S, vl, v, ax, ay);
                 edge(S, v, vr, bx, by);
@@ -960,11 +1006,7 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
                 S.t[9][v] = cv * Fy;
             }
         } else {
-            const T* l0 = N + NF_L0 * NS + off;
-            const T* l0l = N + NF_L0L * NS + off;
-            const T* th0 = N + NF_TH0 * NS + off;
-            const T* ks = N + NF_KS * NS + off;
-            internal_forces(S, nv, l0, l0l, th0, ks, cap.kb, cap.ka, cap.A0, red);  // -> t8, t9
+            internal_forces(S, nv, cap.kb, cap.ka, cap.A0, red);  // -> t8, t9
             for (int v = tid; v < nv; v += nt) {
                 N[NF_FX * NS + off + v] = S.t[8][v];
                 N[NF_FY * NS + off + v] = S.t[9][v];
@@ -984,7 +1026,7 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
 template <typename T>
 size_t ib_lds_bytes(int patch_cap, int max_nv)
 {
-    return sizeof(T) * ((size_t)3 * patch_cap + (size_t)18 * max_nv);
+    return sizeof(T) * ((size_t)3 * patch_cap + (size_t)26 * max_nv);
 }
 
 template <typename T>
