@@ -15,6 +15,10 @@ Prints one JSON line:
             recorded around every launch of the timed region, against 8 TB/s
   cpu_baseline  the FP64 oracle on the host cores, a bounded sample of steps of
             the same workload
+  batched   side measurement: 256 independent channels (seeded ensemble, about
+            8.0 M cells, 388 capsules) stepped as one batch context, against one
+            context per simulation stepped in turn; speedup = loop time / batch
+            time per step
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -89,6 +93,64 @@ def time_gpu(cfg, steps: int, warmup: int, timing: bool):
             "ms_per_step": (t1 - t0) * 1e3 / steps, "timing": tm, "sim": sim}
 
 
+def bench_ensemble(steps: int, warmup: int, loop_steps: int):
+    """The 256-lattice seeded ensemble: one batch context (two launches per step
+    for all lattices) against one context per simulation stepped in turn on the
+    same stream (two launches per step per simulation)."""
+    import torch
+    from paper_1903_03356_amd import lbib
+    from paper_1903_03356_amd import workloads as wl
+
+    cfgs = wl.ensemble(seed=0)
+    cells = sum(c["nx"] * c["ny"] for c in cfgs)
+    caps = sum(len(c["capsules"]) for c in cfgs)
+    bat = lbib.Batch(cfgs)
+    bat.step(warmup)
+    torch.cuda.synchronize()
+    bat.set_timing(True)
+    bat.get_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bat.step(steps)
+    torch.cuda.synchronize()
+    t_bat = (time.perf_counter() - t0) / steps
+    tm = bat.get_timing()
+    flags = bat.check()
+    if flags:
+        raise RuntimeError(f"device flags {flags} in the batched ensemble")
+    grid_us = tm["grid_ms"] / max(1.0, tm["grid_launches"]) * 1e3
+    ib_us = tm["ib_ms"] / max(1.0, tm["ib_launches"]) * 1e3
+    del bat
+    sims = [lbib.Sim(c) for c in cfgs]
+    for s in sims:
+        s.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.step(loop_steps)
+    torch.cuda.synchronize()
+    t_loop = (time.perf_counter() - t0) / loop_steps
+    flags = 0
+    for s in sims:
+        flags |= s.check()
+    if flags:
+        raise RuntimeError(f"device flags {flags} in the per-simulation loop")
+    del sims
+    return {
+        "workload": f"{len(cfgs)} independent Dynamic-IB channels (seed 0), {cells} cells, "
+                    f"{caps} capsules, FP32",
+        "lattices": len(cfgs), "cells": cells, "capsules": caps,
+        "steps": steps, "loop_steps": loop_steps,
+        "mlups": round(cells / t_bat / 1e6, 1),
+        "ms_per_step": round(t_bat * 1e3, 4),
+        "loop_ms_per_step": round(t_loop * 1e3, 4),
+        "speedup": round(t_loop / t_bat, 2),
+        "grid_kernel_us": round(grid_us, 2),
+        "grid_kernel_frac": round(BYTES_PER_CELL * cells / (grid_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
+        "ib_kernel_us": round(ib_us, 2),
+    }
+
+
 def cpu_baseline(cfg, budget_s: float = 20.0):
     from oracle import oracle as orc
 
@@ -117,7 +179,10 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=4096, help="grid side of the fused workload")
     ap.add_argument("--only-fused", action="store_true",
-                    help="skip the grid-only and 1024x256 side measurements (profiling runs)")
+                    help="skip the grid-only, 1024x256 and ensemble side measurements "
+                         "(profiling runs)")
+    ap.add_argument("--only-ensemble", action="store_true",
+                    help="only the batched ensemble against the per-simulation loop")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 20 device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -140,6 +205,10 @@ def main() -> int:
     from paper_1903_03356_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.only_ensemble:
+        ens = bench_ensemble(min(args.steps, 400), args.warmup, 20)
+        print(json.dumps({"batched": ens}), flush=True)
+        return 0
     cfg = wl.fused_bench(seed=0, n=args.n, steps=args.steps)
     nodes = sum(len(c["nodes"]) for c in cfg["capsules"])
     log(f"fused workload {args.n}x{args.n}, {len(cfg['capsules'])} capsules, {nodes} nodes")
@@ -165,6 +234,12 @@ def main() -> int:
         del c2r["sim"]
         log(f"1024x256 biconcave channel: {c2r['mlups']:.0f} MLUPS")
         side["biconcave_1024x256_mlups"] = round(c2r["mlups"], 1)
+        ens = bench_ensemble(min(args.steps, 400), args.warmup, 20)
+        log(f"ensemble: batched {ens['mlups']:.0f} MLUPS ({ens['ms_per_step']:.3f} ms/step, "
+            f"grid {ens['grid_kernel_us']:.1f} us, IB {ens['ib_kernel_us']:.1f} us), "
+            f"per-simulation loop {ens['loop_ms_per_step']:.3f} ms/step, "
+            f"speedup {ens['speedup']:.1f}x")
+        side["batched"] = ens
 
     sha = kernel_sha()
     traffic = traffic_from_profile(sha)

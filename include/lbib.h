@@ -170,14 +170,15 @@ lbib_status lbib_add_capsule(lbib_ctx* ctx, const double* nodes_xy, int32_t n, c
 lbib_status lbib_step(lbib_ctx* ctx, int32_t nsteps, lbib_mode mode);
 
 /* Copies state `what` into dst (dst_bytes long).  capsule_id selects the capsule
- * for LBIB_C_*.  dst_is_device = 1: dst is device memory and the copy is queued;
+ * for LBIB_C_* and the lattice for LBIB_F_* (always 0 for a context made by
+ * lbib_create).  dst_is_device = 1: dst is device memory and the copy is queued;
  * 0: host memory and the call waits for the stream.  Errors: EINVAL (unknown
  * what, bad capsule id, dst too small), EDEVICE. */
 lbib_status lbib_get_state(lbib_ctx* ctx, int32_t what, int32_t capsule_id, void* dst,
                            size_t dst_bytes, int32_t dst_is_device);
 
-/* Overwrites state `what` (LBIB_F_POPS or LBIB_C_STATE) from src.  F_POPS replaces
- * f^n.  The wall populations that Zou-He determines are recomputed.  C_STATE sets
+/* Overwrites state `what` (LBIB_F_POPS or LBIB_C_STATE) from src; capsule_id
+ * selects as for lbib_get_state.  F_POPS replaces f^n.  The wall populations that Zou-He determines are recomputed.  C_STATE sets
  * x^n, x^{n-1}, u_v^n of one capsule and marks it started.  The stress-free shape
  * is unchanged.  Errors: EINVAL, EDEVICE. */
 lbib_status lbib_set_state(lbib_ctx* ctx, int32_t what, int32_t capsule_id, const void* src,
@@ -201,6 +202,49 @@ int64_t lbib_steps_done(const lbib_ctx* ctx);
 
 /* Last error message of ctx (or of the calling thread when ctx is NULL). */
 const char* lbib_last_error(const lbib_ctx* ctx);
+
+/* ---- Ensembles: many independent lattices in one context ----
+ *
+ * A batch context holds n_inst independent simulations of the method
+ * (Secs. 2.1-2.4 each), every one with its own lattice size, tau, walls and
+ * capsules.  They share the eight buffers (each lattice's arrays follow the
+ * previous lattice's) and step in lockstep: one lbib_step queues, per time
+ * step, one IB launch over the capsules of all lattices and one grid launch
+ * over the cells of all lattices, instead of two launches per simulation.
+ * Results are bit-identical to stepping each lattice in a context of its own.
+ *  - All lattices share real_bytes and the coupling mode.
+ *  - Capacities are per lattice (each lbib_grid's max_capsules and
+ *    max_nodes_total); the largest max_nodes_capsule sets the on-chip budget.
+ *  - Capsule ids count over the whole context, in the order of
+ *    lbib_add_capsule_to calls.
+ *  - For the field states (LBIB_F_*), capsule_id of get/set names the lattice.
+ *  - One device status word serves the whole batch.
+ *  - A context from lbib_create is the batch of one lattice; lbib_add_capsule
+ *    is lbib_add_capsule_to lattice 0. */
+
+/* Size of buffer `buffer_id` for the lattices grids[0..n_inst-1], or 0 if any
+ * grid is invalid, real_bytes differ, or the totals exceed the supported range
+ * (2^20 capsules, 2^26 nodes, 1 <= n_inst <= 65536). */
+size_t lbib_required_bytes_batch(const lbib_grid* grids, int32_t n_inst, int32_t buffer_id);
+
+/* Creates a batch context: lattice i has grids[i], relaxation time taus[i] and
+ * walls[i] (host arrays of n_inst entries, copied).  Buffers, stream, errors
+ * and queued initialisation as for lbib_create, applied to every lattice;
+ * EINVAL also if real_bytes differ between lattices or n_inst is out of range.
+ * The call waits for the stream before it returns. */
+lbib_status lbib_create_batch(const lbib_grid* grids, const double* taus,
+                              const lbib_walls* walls, int32_t n_inst,
+                              void* const* device_buffers, int32_t n_buffers, void* hip_stream,
+                              lbib_ctx** out);
+
+/* lbib_add_capsule into lattice `lattice` (0 <= lattice < n_inst, else
+ * EINVAL); the node-range check uses that lattice's ny and walls. */
+lbib_status lbib_add_capsule_to(lbib_ctx* ctx, int32_t lattice, const double* nodes_xy, int32_t n,
+                                const double* ks, int32_t n_ks, double kb, double ka,
+                                double mass_total, int32_t* capsule_id);
+
+/* Number of lattices of the context, or -1 for a NULL context. */
+int32_t lbib_num_lattices(const lbib_ctx* ctx);
 
 /* Frees the host-side context.  Device buffers stay with the caller.  Waits for
  * the stream first. */

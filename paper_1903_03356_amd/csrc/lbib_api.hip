@@ -4,6 +4,7 @@
 #include "lbib.h"
 #include "lbib_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -18,11 +19,36 @@ struct TimedLaunch {
     hipEvent_t start, stop;
 };
 
-struct lbib_ctx {
+// Host record of one lattice and where its arrays sit in the shared buffers.
+struct Inst {
     lbib_grid grid;
     lbib_walls walls;
     double tau = 0, nu = 0;
-    int nxp = 0, nseg = 0, rb = 4;
+    int nxp = 0, nseg = 0;
+    size_t pop_off = 0;   // elements of a population buffer
+    size_t fib_off = 0;   // long longs of one force level
+    size_t flag_off = 0;  // ints of one flag level
+    int block0 = 0, blocks = 0;
+    int ncap = 0, nodes = 0;
+};
+
+// Buffer layout of a context: the lattices one after the other in every
+// buffer; the capsule table followed by the lattice table and the block-round
+// table of the batched grid launch.
+struct Layout {
+    std::vector<Inst> inst;
+    int rb = 4;
+    size_t pop_elems = 0, fib_level = 0, flag_level = 0;
+    int max_caps = 0, max_nodes = 0, max_nv = 0;
+    int grid_blocks = 0;
+    size_t plane_max = 0;
+    size_t inst_table = 0, round_table = 0;  // byte offsets in BUF_CAPS
+};
+
+struct lbib_ctx {
+    Layout L;
+    double nu0 = 0;
+    int rb = 4;
     void* buf[LBIB_NUM_BUFFERS] = {};
     hipStream_t stream = nullptr;
     int ncap = 0, nodes_used = 0;
@@ -34,7 +60,7 @@ struct lbib_ctx {
     bool timing = false;
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> pool;
-    std::vector<int> cap_off, cap_nv;  // host copy of the capsule table layout
+    std::vector<int> cap_off, cap_nv, cap_inst;  // host copy of the capsule table layout
 };
 
 // ----------------------------------------------------------------- helpers
@@ -76,29 +102,69 @@ static bool grid_ok(const lbib_grid* g)
            g->max_nodes_capsule <= 2048;
 }
 
-static size_t status_offset(const lbib_grid* g)
+constexpr int kMaxInstances = 1 << 16;
+
+// Fills L from the lattices' sizes and capacities; false if any is invalid or
+// the totals leave the supported range.
+static bool make_layout(const lbib_grid* grids, int n, Layout& L)
 {
-    return (size_t)g->max_capsules * kDiagStride * sizeof(double);
+    if (!grids || n < 1 || n > kMaxInstances) return false;
+    L = Layout();
+    L.rb = grids[0].real_bytes;
+    long long caps = 0, nodes = 0, blocks = 0, cells = 0;
+    for (int i = 0; i < n; i++) {
+        const lbib_grid* g = &grids[i];
+        if (!grid_ok(g) || g->real_bytes != L.rb) return false;
+        Inst I;
+        I.grid = *g;
+        I.nxp = row_stride(g->nx);
+        I.nseg = I.nxp / kSegW;
+        const size_t lc = (size_t)I.nxp * g->ny;
+        I.pop_off = L.pop_elems;
+        I.fib_off = L.fib_level;
+        I.flag_off = L.flag_level;
+        I.block0 = (int)blocks;
+        I.blocks = grid_blocks(g->ny, I.nseg);
+        L.pop_elems += 9 * lc;
+        L.fib_level += 2 * lc;
+        L.flag_level += ((size_t)g->ny * I.nseg + 63) / 64 * 64;
+        blocks += I.blocks;
+        caps += g->max_capsules;
+        nodes += g->max_nodes_total;
+        cells += (long long)g->nx * g->ny;
+        L.max_nv = std::max(L.max_nv, g->max_nodes_capsule);
+        L.plane_max = std::max(L.plane_max, (size_t)g->nx * g->ny);
+        L.inst.push_back(I);
+    }
+    if (caps > (1 << 20) || nodes > (1 << 26) || blocks > (1LL << 30) || cells > (1LL << 33))
+        return false;
+    L.max_caps = (int)caps;
+    L.max_nodes = (int)nodes;
+    L.grid_blocks = (int)blocks;
+    L.inst_table = round256((size_t)L.max_caps * sizeof(CapsuleDev));
+    L.round_table = L.inst_table + round256((size_t)n * sizeof(InstDev));
+    return true;
 }
 
-extern "C" size_t lbib_required_bytes(const lbib_grid* g, int32_t id)
+static size_t status_offset(const Layout& L)
 {
-    if (!grid_ok(g)) return 0;
-    const size_t nxp = (size_t)row_stride(g->nx);
-    const size_t nseg = nxp / kSegW;
-    const size_t cells = nxp * g->ny;
-    const size_t plane = (size_t)g->nx * g->ny;
+    return (size_t)L.max_caps * kDiagStride * sizeof(double);
+}
+
+static size_t layout_bytes(const Layout& L, int id)
+{
     switch (id) {
     case LBIB_BUF_POPS_A:
-    case LBIB_BUF_POPS_B: return round256(9 * cells * g->real_bytes);
-    case LBIB_BUF_FORCE: return round256(2 * cells * 2 * sizeof(long long));
-    case LBIB_BUF_FLAGS: return round256(2 * (size_t)g->ny * nseg * sizeof(int));
-    case LBIB_BUF_NODES: return round256((size_t)NF_COUNT * g->max_nodes_total * g->real_bytes);
-    case LBIB_BUF_CAPS: return round256((size_t)g->max_capsules * sizeof(CapsuleDev));
-    case LBIB_BUF_DIAG: return round256(status_offset(g) + 64);
+    case LBIB_BUF_POPS_B: return round256(L.pop_elems * L.rb);
+    case LBIB_BUF_FORCE: return round256(2 * L.fib_level * sizeof(long long));
+    case LBIB_BUF_FLAGS: return round256(2 * L.flag_level * sizeof(int));
+    case LBIB_BUF_NODES: return round256((size_t)NF_COUNT * L.max_nodes * L.rb);
+    case LBIB_BUF_CAPS:
+        return L.round_table + round256((size_t)(L.grid_blocks / kNumXcd) * sizeof(int));
+    case LBIB_BUF_DIAG: return round256(status_offset(L) + 64);
     case LBIB_BUF_STAGE: {
-        size_t n = 3 * plane;
-        if ((size_t)6 * g->max_nodes_total > n) n = (size_t)6 * g->max_nodes_total;
+        size_t n = 3 * L.plane_max;
+        if ((size_t)6 * L.max_nodes > n) n = (size_t)6 * L.max_nodes;
         if (n < 64) n = 64;
         return round256(n * sizeof(double));
     }
@@ -106,18 +172,30 @@ extern "C" size_t lbib_required_bytes(const lbib_grid* g, int32_t id)
     }
 }
 
-static GridArgs grid_args(const lbib_ctx* c)
+extern "C" size_t lbib_required_bytes_batch(const lbib_grid* grids, int32_t n_inst, int32_t id)
+{
+    Layout L;
+    if (!make_layout(grids, n_inst, L)) return 0;
+    return layout_bytes(L, id);
+}
+
+extern "C" size_t lbib_required_bytes(const lbib_grid* g, int32_t id)
+{
+    return lbib_required_bytes_batch(g, 1, id);
+}
+
+static GridArgs grid_args(const Inst& I)
 {
     GridArgs g;
-    g.nx = c->grid.nx;
-    g.ny = c->grid.ny;
-    g.nxp = c->nxp;
-    g.nseg = c->nseg;
-    g.periodic_y = c->walls.periodic_y;
-    g.omega = 1.0 / c->tau;
-    g.gx = c->walls.body_force_x;
-    g.u_bot = c->walls.periodic_y ? 0.0 : c->walls.u_bottom;
-    g.u_top = c->walls.periodic_y ? 0.0 : c->walls.u_top;
+    g.nx = I.grid.nx;
+    g.ny = I.grid.ny;
+    g.nxp = I.nxp;
+    g.nseg = I.nseg;
+    g.periodic_y = I.walls.periodic_y;
+    g.omega = 1.0 / I.tau;
+    g.gx = I.walls.body_force_x;
+    g.u_bot = I.walls.periodic_y ? 0.0 : I.walls.u_bottom;
+    g.u_top = I.walls.periodic_y ? 0.0 : I.walls.u_top;
     return g;
 }
 
@@ -128,21 +206,35 @@ static void* pops(const lbib_ctx* c, long long parity)
     return bufp(c, (parity & 1) ? LBIB_BUF_POPS_B : LBIB_BUF_POPS_A);
 }
 
+template <typename T>
+static T* pops_of(const lbib_ctx* c, long long parity, const Inst& I)
+{
+    return static_cast<T*>(pops(c, parity)) + I.pop_off;
+}
+
 static long long* fib(const lbib_ctx* c, long long parity)
 {
-    const size_t half = (size_t)c->nxp * c->grid.ny * 2;
-    return reinterpret_cast<long long*>(bufp(c, LBIB_BUF_FORCE)) + (parity & 1) * half;
+    return reinterpret_cast<long long*>(bufp(c, LBIB_BUF_FORCE)) + (parity & 1) * c->L.fib_level;
 }
 
 static int* flags(const lbib_ctx* c, long long parity)
 {
-    const size_t half = (size_t)c->nseg * c->grid.ny;
-    return reinterpret_cast<int*>(bufp(c, LBIB_BUF_FLAGS)) + (parity & 1) * half;
+    return reinterpret_cast<int*>(bufp(c, LBIB_BUF_FLAGS)) + (parity & 1) * c->L.flag_level;
 }
 
 static int* status_word(const lbib_ctx* c)
 {
-    return reinterpret_cast<int*>(bufp(c, LBIB_BUF_DIAG) + status_offset(&c->grid));
+    return reinterpret_cast<int*>(bufp(c, LBIB_BUF_DIAG) + status_offset(c->L));
+}
+
+static const InstDev* inst_table(const lbib_ctx* c)
+{
+    return reinterpret_cast<const InstDev*>(bufp(c, LBIB_BUF_CAPS) + c->L.inst_table);
+}
+
+static const int* round_table(const lbib_ctx* c)
+{
+    return reinterpret_cast<const int*>(bufp(c, LBIB_BUF_CAPS) + c->L.round_table);
 }
 
 static hipEvent_t take_event(lbib_ctx* c)
@@ -159,12 +251,8 @@ static hipEvent_t take_event(lbib_ctx* c)
 
 // ------------------------------------------------------------------ create
 
-extern "C" lbib_status lbib_create(const lbib_grid* grid, double tau, const lbib_walls* walls,
-                                   void* const* device_buffers, int32_t n_buffers,
-                                   void* hip_stream, lbib_ctx** out)
+static lbib_status check_lattice(const lbib_grid* grid, double tau, const lbib_walls* walls)
 {
-    if (!out) return fail(nullptr, LBIB_EINVAL, "out is NULL");
-    if (!grid || !walls || !device_buffers) return fail(nullptr, LBIB_EINVAL, "NULL argument");
     if (grid->nx < 8 || grid->ny < 8) return fail(nullptr, LBIB_EINVAL, "nx and ny must be >= 8");
     if (grid->real_bytes != 4 && grid->real_bytes != 8)
         return fail(nullptr, LBIB_EINVAL, "real_bytes must be 4 or 8");
@@ -179,10 +267,32 @@ extern "C" lbib_status lbib_create(const lbib_grid* grid, double tau, const lbib
         return fail(nullptr, LBIB_EINVAL, "non-finite wall or profile value");
     if (walls->init_profile < 0 || walls->init_profile > 3)
         return fail(nullptr, LBIB_EINVAL, "init_profile must be 0..3");
+    return LBIB_OK;
+}
+
+static lbib_status create_common(const lbib_grid* grids, const double* taus,
+                                 const lbib_walls* walls, int32_t n_inst,
+                                 void* const* device_buffers, int32_t n_buffers, void* hip_stream,
+                                 lbib_ctx** out)
+{
+    if (!out) return fail(nullptr, LBIB_EINVAL, "out is NULL");
+    if (!grids || !taus || !walls || !device_buffers)
+        return fail(nullptr, LBIB_EINVAL, "NULL argument");
+    if (n_inst < 1 || n_inst > kMaxInstances)
+        return fail(nullptr, LBIB_EINVAL, "n_inst must be 1..65536");
+    for (int i = 0; i < n_inst; i++) {
+        lbib_status s = check_lattice(&grids[i], taus[i], &walls[i]);
+        if (s != LBIB_OK) return s;
+        if (grids[i].real_bytes != grids[0].real_bytes)
+            return fail(nullptr, LBIB_EINVAL, "all lattices of a batch need the same real_bytes");
+    }
     if (n_buffers != LBIB_NUM_BUFFERS)
         return fail(nullptr, LBIB_EINVAL, "n_buffers must be LBIB_NUM_BUFFERS");
     for (int i = 0; i < LBIB_NUM_BUFFERS; i++)
         if (!device_buffers[i]) return fail(nullptr, LBIB_EINVAL, "NULL device buffer");
+    Layout L;
+    if (!make_layout(grids, n_inst, L))
+        return fail(nullptr, LBIB_ECAPACITY, "batch totals out of range");
 
     int dev = 0;
     hipDeviceProp_t prop;
@@ -190,67 +300,114 @@ extern "C" lbib_status lbib_create(const lbib_grid* grid, double tau, const lbib
         return fail(nullptr, LBIB_EDEVICE, "no HIP device");
 
     lbib_ctx* c = new lbib_ctx();
-    c->grid = *grid;
-    c->walls = *walls;
-    c->tau = tau;
-    c->nu = (tau - 0.5) / 3.0;
-    c->rb = grid->real_bytes;
-    c->nxp = row_stride(grid->nx);
-    c->nseg = c->nxp / kSegW;
+    c->L = L;
+    for (int i = 0; i < n_inst; i++) {
+        Inst& I = c->L.inst[i];
+        I.walls = walls[i];
+        I.tau = taus[i];
+        I.nu = (taus[i] - 0.5) / 3.0;
+    }
+    c->rb = L.rb;
     for (int i = 0; i < LBIB_NUM_BUFFERS; i++) c->buf[i] = device_buffers[i];
     c->stream = static_cast<hipStream_t>(hip_stream);
+    auto bail = [&](lbib_status code, const std::string& m) {
+        delete c;
+        return fail(nullptr, code, m);
+    };
 
     // LDS of the IB kernel: node scratch for the largest capsule, the rest
     // holds the capsule's fluid patch.
     const size_t lds_max = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
     const size_t budget = lds_max - 1024;  // static shared memory of the kernel
     const size_t per_node = (size_t)26 * c->rb, per_cell = (size_t)3 * c->rb;
-    const size_t node_bytes = per_node * grid->max_nodes_capsule;
-    if (node_bytes + 1024 * per_cell > budget) {
-        delete c;
-        return fail(nullptr, LBIB_ECAPACITY, "max_nodes_capsule too large for the on-chip memory");
-    }
+    const size_t node_bytes = per_node * L.max_nv;
+    if (node_bytes + 1024 * per_cell > budget)
+        return bail(LBIB_ECAPACITY, "max_nodes_capsule too large for the on-chip memory");
     c->patch_cap = (int)((budget - node_bytes) / per_cell);
-    c->lds_bytes = c->rb == 4 ? ib_lds_bytes<float>(c->patch_cap, grid->max_nodes_capsule)
-                              : ib_lds_bytes<double>(c->patch_cap, grid->max_nodes_capsule);
+    c->lds_bytes = c->rb == 4 ? ib_lds_bytes<float>(c->patch_cap, L.max_nv)
+                              : ib_lds_bytes<double>(c->patch_cap, L.max_nv);
     hipError_t e = c->rb == 4 ? ib_set_lds_limit<float>(c->lds_bytes)
                               : ib_set_lds_limit<double>(c->lds_bytes);
-    if (e != hipSuccess) {
-        std::string m = std::string("hipFuncSetAttribute: ") + hipGetErrorString(e);
-        delete c;
-        return fail(nullptr, LBIB_EDEVICE, m);
-    }
+    if (e != hipSuccess) return bail(LBIB_EDEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
 
     const int zero_ids[] = {LBIB_BUF_POPS_B, LBIB_BUF_FORCE, LBIB_BUF_FLAGS, LBIB_BUF_NODES,
                             LBIB_BUF_CAPS, LBIB_BUF_DIAG};
     for (int id : zero_ids) {
-        e = hipMemsetAsync(c->buf[id], 0, lbib_required_bytes(grid, id), c->stream);
-        if (e != hipSuccess) {
-            std::string m = std::string("hipMemsetAsync: ") + hipGetErrorString(e);
-            delete c;
-            return fail(nullptr, LBIB_EDEVICE, m);
-        }
+        e = hipMemsetAsync(c->buf[id], 0, layout_bytes(L, id), c->stream);
+        if (e != hipSuccess) return bail(LBIB_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
     }
-    GridArgs g = grid_args(c);
-    e = c->rb == 4 ? launch_init<float>((float*)pops(c, 0), g, walls->init_profile, walls->init_ux,
-                                        walls->init_uy, c->nu, c->stream)
-                   : launch_init<double>((double*)pops(c, 0), g, walls->init_profile,
-                                         walls->init_ux, walls->init_uy, c->nu, c->stream);
-    if (e != hipSuccess) {
-        std::string m = std::string("init kernel: ") + hipGetErrorString(e);
-        delete c;
-        return fail(nullptr, LBIB_EDEVICE, m);
+    // lattice table and block-round table of the batched grid launch
+    std::vector<InstDev> tab(n_inst);
+    std::vector<int> rounds(L.grid_blocks / kNumXcd);
+    for (int i = 0; i < n_inst; i++) {
+        const Inst& I = c->L.inst[i];
+        const GridArgs g = grid_args(I);
+        InstDev& d = tab[i];
+        std::memset(&d, 0, sizeof(d));
+        d.nx = g.nx;
+        d.ny = g.ny;
+        d.nxp = g.nxp;
+        d.nseg = g.nseg;
+        d.periodic_y = g.periodic_y;
+        d.block0 = I.block0;
+        d.pop_off = (int64_t)I.pop_off;
+        d.fib_off = (int64_t)I.fib_off;
+        d.flag_off = (int64_t)I.flag_off;
+        d.omega = g.omega;
+        d.gx = g.gx;
+        d.u_bot = g.u_bot;
+        d.u_top = g.u_top;
+        for (int r = I.block0 / kNumXcd; r < (I.block0 + I.blocks) / kNumXcd; r++) rounds[r] = i;
     }
+    e = hipMemcpyAsync(bufp(c, LBIB_BUF_CAPS) + L.inst_table, tab.data(),
+                       tab.size() * sizeof(InstDev), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && !rounds.empty())
+        e = hipMemcpyAsync(bufp(c, LBIB_BUF_CAPS) + L.round_table, rounds.data(),
+                           rounds.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return bail(LBIB_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+    for (int i = 0; i < n_inst && e == hipSuccess; i++) {
+        const Inst& I = c->L.inst[i];
+        const GridArgs g = grid_args(I);
+        e = c->rb == 4 ? launch_init<float>(pops_of<float>(c, 0, I), g, I.walls.init_profile,
+                                            I.walls.init_ux, I.walls.init_uy, I.nu, c->stream)
+                       : launch_init<double>(pops_of<double>(c, 0, I), g, I.walls.init_profile,
+                                             I.walls.init_ux, I.walls.init_uy, I.nu, c->stream);
+    }
+    if (e != hipSuccess) return bail(LBIB_EDEVICE, std::string("init kernel: ") + hipGetErrorString(e));
+    // the host tables above must outlive their copies
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return bail(LBIB_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
     *out = c;
     return LBIB_OK;
+}
+
+extern "C" lbib_status lbib_create(const lbib_grid* grid, double tau, const lbib_walls* walls,
+                                   void* const* device_buffers, int32_t n_buffers,
+                                   void* hip_stream, lbib_ctx** out)
+{
+    return create_common(grid, &tau, walls, 1, device_buffers, n_buffers, hip_stream, out);
+}
+
+extern "C" lbib_status lbib_create_batch(const lbib_grid* grids, const double* taus,
+                                         const lbib_walls* walls, int32_t n_inst,
+                                         void* const* device_buffers, int32_t n_buffers,
+                                         void* hip_stream, lbib_ctx** out)
+{
+    return create_common(grids, taus, walls, n_inst, device_buffers, n_buffers, hip_stream, out);
+}
+
+extern "C" int32_t lbib_num_lattices(const lbib_ctx* c)
+{
+    return c ? (int32_t)c->L.inst.size() : -1;
 }
 
 // ------------------------------------------------------------- add_capsule
 
 template <typename T>
-static lbib_status add_capsule_t(lbib_ctx* c, const double* xy, int n, const double* ks, int n_ks,
-                                 double kb, double ka, double mass, int32_t* id)
+static lbib_status add_capsule_t(lbib_ctx* c, int inst, const double* xy, int n, const double* ks,
+                                 int n_ks, double kb, double ka, double mass, int32_t* id)
 {
+    Inst& I = c->L.inst[inst];
     // stress-free shape (Sec. 2.2.1): element lengths, turning angles, area, perimeter
     std::vector<double> l0(n), th0(n);
     double A2 = 0, P = 0, mx = 0, my = 0;
@@ -280,7 +437,7 @@ static lbib_status add_capsule_t(lbib_ctx* c, const double* xy, int n, const dou
 
     const double refx = std::nearbyint(mx / n), refy = std::nearbyint(my / n);
     const int off = c->nodes_used;
-    const size_t S = c->grid.max_nodes_total;
+    const size_t S = c->L.max_nodes;
     std::vector<T> f((size_t)NF_COUNT * n, T(0));
     for (int v = 0; v < n; v++) {
         const double rx = xy[2 * v] - refx, ry = xy[2 * v + 1] - refy;
@@ -310,43 +467,66 @@ static lbib_status add_capsule_t(lbib_ctx* c, const double* xy, int n, const dou
     cd.mv = mass / n;
     cd.A0 = A0;
     cd.P0 = P;
+    cd.inst = inst;
+    const GridArgs g = grid_args(I);
+    cd.nx = g.nx;
+    cd.ny = g.ny;
+    cd.nxp = g.nxp;
+    cd.nseg = g.nseg;
+    cd.periodic_y = g.periodic_y;
+    cd.pop_off = (int64_t)I.pop_off;
+    cd.fib_off = (int64_t)I.fib_off;
+    cd.flag_off = (int64_t)I.flag_off;
+    cd.gx = g.gx;
+    cd.nu = I.nu;
     HIPCHK(c, hipMemcpyAsync(bufp(c, LBIB_BUF_CAPS) + (size_t)c->ncap * sizeof(CapsuleDev), &cd,
                              sizeof(cd), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     *id = c->ncap;
     c->cap_off.push_back(off);
     c->cap_nv.push_back(n);
+    c->cap_inst.push_back(inst);
     c->ncap++;
     c->nodes_used += n;
+    I.ncap++;
+    I.nodes += n;
     return LBIB_OK;
 }
 
-extern "C" lbib_status lbib_add_capsule(lbib_ctx* c, const double* xy, int32_t n, const double* ks,
-                                        int32_t n_ks, double kb, double ka, double mass,
-                                        int32_t* id)
+extern "C" lbib_status lbib_add_capsule_to(lbib_ctx* c, int32_t inst, const double* xy,
+                                           int32_t n, const double* ks, int32_t n_ks, double kb,
+                                           double ka, double mass, int32_t* id)
 {
     if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
     if (!xy || !ks || !id) return fail(c, LBIB_EINVAL, "NULL argument");
+    if (inst < 0 || inst >= (int)c->L.inst.size()) return fail(c, LBIB_EINVAL, "bad lattice index");
     if (c->steps > 0) return fail(c, LBIB_ESTATE, "capsules must be added before the first step");
+    const Inst& I = c->L.inst[inst];
     if (n < 3) return fail(c, LBIB_EINVAL, "a capsule needs at least 3 nodes");
     if (n_ks != 1 && n_ks != n) return fail(c, LBIB_EINVAL, "n_ks must be 1 or n");
-    if (n > c->grid.max_nodes_capsule)
+    if (n > I.grid.max_nodes_capsule)
         return fail(c, LBIB_ECAPACITY, "n exceeds max_nodes_capsule");
-    if (c->ncap >= c->grid.max_capsules) return fail(c, LBIB_ECAPACITY, "capsule table full");
-    if (c->nodes_used + n > c->grid.max_nodes_total)
-        return fail(c, LBIB_ECAPACITY, "node arrays full");
+    if (I.ncap >= I.grid.max_capsules) return fail(c, LBIB_ECAPACITY, "capsule table full");
+    if (I.nodes + n > I.grid.max_nodes_total) return fail(c, LBIB_ECAPACITY, "node arrays full");
     if (!(std::isfinite(kb) && std::isfinite(ka) && std::isfinite(mass) && mass > 0))
         return fail(c, LBIB_EINVAL, "kb, ka must be finite and mass > 0");
     for (int i = 0; i < n_ks; i++)
         if (!(std::isfinite(ks[i]) && ks[i] >= 0)) return fail(c, LBIB_EINVAL, "ks must be >= 0");
     for (int v = 0; v < 2 * n; v++)
         if (!std::isfinite(xy[v])) return fail(c, LBIB_EINVAL, "non-finite node coordinate");
-    if (!c->walls.periodic_y)
+    if (!I.walls.periodic_y)
         for (int v = 0; v < n; v++)
-            if (xy[2 * v + 1] < 3.0 || xy[2 * v + 1] > c->grid.ny - 4.0)
+            if (xy[2 * v + 1] < 3.0 || xy[2 * v + 1] > I.grid.ny - 4.0)
                 return fail(c, LBIB_EINVAL, "nodes must satisfy 3 <= y <= ny - 4");
-    return c->rb == 4 ? add_capsule_t<float>(c, xy, n, ks, n_ks, kb, ka, mass, id)
-                      : add_capsule_t<double>(c, xy, n, ks, n_ks, kb, ka, mass, id);
+    return c->rb == 4 ? add_capsule_t<float>(c, inst, xy, n, ks, n_ks, kb, ka, mass, id)
+                      : add_capsule_t<double>(c, inst, xy, n, ks, n_ks, kb, ka, mass, id);
+}
+
+extern "C" lbib_status lbib_add_capsule(lbib_ctx* c, const double* xy, int32_t n, const double* ks,
+                                        int32_t n_ks, double kb, double ka, double mass,
+                                        int32_t* id)
+{
+    return lbib_add_capsule_to(c, 0, xy, n, ks, n_ks, kb, ka, mass, id);
 }
 
 // -------------------------------------------------------------------- step
@@ -364,18 +544,11 @@ static IBArgs<T> ib_args(const lbib_ctx* c, long long n, int phase)
     a.caps = reinterpret_cast<CapsuleDev*>(bufp(c, LBIB_BUF_CAPS));
     a.diag = reinterpret_cast<double*>(bufp(c, LBIB_BUF_DIAG));
     a.status = status_word(c);
-    a.node_stride = c->grid.max_nodes_total;
-    a.nx = c->grid.nx;
-    a.ny = c->grid.ny;
-    a.nxp = c->nxp;
-    a.nseg = c->nseg;
-    a.periodic_y = c->walls.periodic_y;
+    a.node_stride = c->L.max_nodes;
     a.phase = phase;
     a.dynamic = c->mode == LBIB_DYNAMIC;
     a.patch_cap = c->patch_cap;
-    a.max_nv = c->grid.max_nodes_capsule;
-    a.gx = c->walls.body_force_x;
-    a.nu = c->nu;
+    a.max_nv = c->L.max_nv;
     return a;
 }
 
@@ -415,10 +588,16 @@ template <typename T>
 static hipError_t do_grid(lbib_ctx* c, void* p)
 {
     const long long n = *static_cast<const long long*>(p);
-    GridArgs g = grid_args(c);
-    return launch_grid_step<T>(static_cast<const T*>(pops(c, n)), static_cast<T*>(pops(c, n + 1)),
-                               fib(c, n), flags(c, n), fib(c, n + 1), flags(c, n + 1), g,
-                               c->stream);
+    if (c->L.inst.size() == 1) {
+        const GridArgs g = grid_args(c->L.inst[0]);
+        return launch_grid_step<T>(static_cast<const T*>(pops(c, n)),
+                                   static_cast<T*>(pops(c, n + 1)), fib(c, n), flags(c, n),
+                                   fib(c, n + 1), flags(c, n + 1), g, c->stream);
+    }
+    return launch_grid_step_batch<T>(static_cast<const T*>(pops(c, n)),
+                                     static_cast<T*>(pops(c, n + 1)), fib(c, n), flags(c, n),
+                                     fib(c, n + 1), flags(c, n + 1), inst_table(c), round_table(c),
+                                     c->L.grid_blocks, c->stream);
 }
 
 template <typename T>
@@ -461,8 +640,15 @@ extern "C" lbib_status lbib_step(lbib_ctx* c, int32_t nsteps, lbib_mode mode)
 template <typename T>
 static lbib_status get_t(lbib_ctx* c, int what, int cap, void* dst, size_t bytes, int on_dev)
 {
-    const GridArgs g = grid_args(c);
-    const size_t plane = (size_t)c->grid.nx * c->grid.ny;
+    // field states: cap names the lattice
+    const bool field = what == LBIB_F_POPS || what == LBIB_F_POPS_DEV ||
+                       what == LBIB_F_MOMENTS || what == LBIB_F_FORCE;
+    if (field && (cap < 0 || cap >= (int)c->L.inst.size()))
+        return fail(c, LBIB_EINVAL, "bad lattice index");
+    const Inst& I = c->L.inst[field ? cap : 0];
+    const GridArgs g = grid_args(I);
+    const size_t plane = (size_t)I.grid.nx * I.grid.ny;
+    const long long* fib_last = fib(c, c->steps + 1) + I.fib_off;
     double* stage = reinterpret_cast<double*>(bufp(c, LBIB_BUF_STAGE));
     const hipMemcpyKind d2h = hipMemcpyDeviceToHost;
     auto finish = [&](const double* src, size_t n) -> lbib_status {
@@ -478,7 +664,7 @@ static lbib_status get_t(lbib_ctx* c, int what, int cap, void* dst, size_t bytes
         if (bytes < 9 * plane * sizeof(double)) return fail(c, LBIB_EINVAL, "dst too small");
         for (int i = 0; i < 9; i++) {
             double* o = on_dev ? static_cast<double*>(dst) + i * plane : stage;
-            HIPCHK(c, launch_get_pop_plane<T>(static_cast<const T*>(pops(c, c->steps)), o, i,
+            HIPCHK(c, launch_get_pop_plane<T>(pops_of<const T>(c, c->steps, I), o, i,
                                               what == LBIB_F_POPS, g, c->stream));
             if (!on_dev)
                 HIPCHK(c, hipMemcpyAsync(static_cast<double*>(dst) + i * plane, stage,
@@ -490,14 +676,14 @@ static lbib_status get_t(lbib_ctx* c, int what, int cap, void* dst, size_t bytes
     case LBIB_F_MOMENTS: {
         if (bytes < 3 * plane * sizeof(double)) return fail(c, LBIB_EINVAL, "dst too small");
         double* o = on_dev ? static_cast<double*>(dst) : stage;
-        HIPCHK(c, launch_get_moments<T>(static_cast<const T*>(pops(c, c->steps)),
-                                        fib(c, c->steps + 1), o, g, c->stream));
+        HIPCHK(c, launch_get_moments<T>(pops_of<const T>(c, c->steps, I), fib_last, o, g,
+                                        c->stream));
         return finish(o, 3 * plane);
     }
     case LBIB_F_FORCE: {
         if (bytes < 2 * plane * sizeof(double)) return fail(c, LBIB_EINVAL, "dst too small");
         double* o = on_dev ? static_cast<double*>(dst) : stage;
-        HIPCHK(c, launch_get_force(fib(c, c->steps + 1), o, g, c->stream));
+        HIPCHK(c, launch_get_force(fib_last, o, g, c->stream));
         return finish(o, 2 * plane);
     }
     case LBIB_C_NODES:
@@ -512,7 +698,7 @@ static lbib_status get_t(lbib_ctx* c, int what, int cap, void* dst, size_t bytes
         double* o = on_dev ? static_cast<double*>(dst) : stage;
         HIPCHK(c, launch_get_nodes<T>(reinterpret_cast<const T*>(bufp(c, LBIB_BUF_NODES)),
                                       reinterpret_cast<const CapsuleDev*>(bufp(c, LBIB_BUF_CAPS)),
-                                      cap, nv, c->grid.max_nodes_total, what, o, c->stream));
+                                      cap, nv, c->L.max_nodes, what, o, c->stream));
         return finish(o, n);
     }
     case LBIB_C_DIAG: {
@@ -550,10 +736,13 @@ extern "C" lbib_status lbib_get_state(lbib_ctx* c, int32_t what, int32_t cap, vo
 template <typename T>
 static lbib_status set_t(lbib_ctx* c, int what, int cap, const void* src, size_t bytes, int on_dev)
 {
-    const GridArgs g = grid_args(c);
-    const size_t plane = (size_t)c->grid.nx * c->grid.ny;
     double* stage = reinterpret_cast<double*>(bufp(c, LBIB_BUF_STAGE));
     if (what == LBIB_F_POPS) {
+        if (cap < 0 || cap >= (int)c->L.inst.size())
+            return fail(c, LBIB_EINVAL, "bad lattice index");
+        const Inst& I = c->L.inst[cap];
+        const GridArgs g = grid_args(I);
+        const size_t plane = (size_t)I.grid.nx * I.grid.ny;
         if (bytes < 9 * plane * sizeof(double)) return fail(c, LBIB_EINVAL, "src too small");
         for (int i = 0; i < 9; i++) {
             const double* in = static_cast<const double*>(src) + i * plane;
@@ -562,8 +751,7 @@ static lbib_status set_t(lbib_ctx* c, int what, int cap, const void* src, size_t
                                          c->stream));
                 in = stage;
             }
-            HIPCHK(c, launch_set_pop_plane<T>(static_cast<T*>(pops(c, c->steps)), in, i, g,
-                                              c->stream));
+            HIPCHK(c, launch_set_pop_plane<T>(pops_of<T>(c, c->steps, I), in, i, g, c->stream));
         }
         if (!on_dev) HIPCHK(c, hipStreamSynchronize(c->stream));
         return LBIB_OK;
@@ -583,7 +771,7 @@ static lbib_status set_t(lbib_ctx* c, int what, int cap, const void* src, size_t
         }
         HIPCHK(c, launch_set_nodes<T>(reinterpret_cast<T*>(bufp(c, LBIB_BUF_NODES)),
                                       reinterpret_cast<CapsuleDev*>(bufp(c, LBIB_BUF_CAPS)), cap,
-                                      nv, c->grid.max_nodes_total, in, c->stream));
+                                      nv, c->L.max_nodes, in, c->stream));
         if (!on_dev) HIPCHK(c, hipStreamSynchronize(c->stream));
         return LBIB_OK;
     }

@@ -35,16 +35,37 @@ enum NodeField {
     NF_COUNT
 };
 
+// One lattice of a context.  A context holds a single lattice (lbib_create) or
+// an ensemble of independent lattices (lbib_create_batch) that share the
+// buffers, one after the other, and step in lockstep.
+struct InstDev {
+    int32_t nx, ny, nxp, nseg;
+    int32_t periodic_y, block0;  // block0: first block of the lattice in a batched grid launch
+    int32_t pad0, pad1;
+    int64_t pop_off;   // offset of the lattice's planes in a population buffer (elements)
+    int64_t fib_off;   // offset in one time level of the force field (long long elements)
+    int64_t flag_off;  // offset in one time level of the segment flags (ints)
+    int64_t pad2;
+    double omega, gx, u_bot, u_top;
+};
+static_assert(sizeof(InstDev) == 96, "InstDev layout");
+
 struct CapsuleDev {
     int32_t node_offset;
     int32_t nv;
     int32_t primed;
-    int32_t pad0;
+    int32_t inst;         // lattice the capsule lives in
     double ref_x, ref_y;  // integer-valued reference point (world coordinates)
     double kb, ka, mv, A0, P0;
-    double pad1[3];
+    // the capsule's lattice, copied from its InstDev so that the IB kernel
+    // needs no second dependent load
+    int32_t nx, ny, nxp, nseg;
+    int32_t periodic_y, pad0;
+    int64_t pop_off, fib_off, flag_off;
+    double gx, nu;
+    double pad1;
 };
-static_assert(sizeof(CapsuleDev) == 96, "CapsuleDev layout");
+static_assert(sizeof(CapsuleDev) == 144, "CapsuleDev layout");
 
 constexpr int kDiagStride = 16;  // doubles per capsule in BUF_DIAG
 
@@ -59,21 +80,20 @@ struct GridArgs {
     double u_bot, u_top;
 };
 
+// Buffer bases of an IB launch; each block adds its capsule's lattice offsets.
 template <typename T>
 struct IBArgs {
     const T* pops;              // f*^{n-1} (the stream source of the next step)
-    const long long* fib_prev;  // F^{n-1} - g, fixed point, [ny][nxp][2]
-    long long* fib_next;        // F^n - g accumulator, [ny][nxp][2]
-    int* flags_next;            // [ny][nseg]
+    const long long* fib_prev;  // F^{n-1} - g, fixed point, [ny][nxp][2] per lattice
+    long long* fib_next;        // F^n - g accumulator, [ny][nxp][2] per lattice
+    int* flags_next;            // [ny][nseg] per lattice
     T* nodes;                   // [NF_COUNT][node_stride]
     CapsuleDev* caps;
     double* diag;               // [max_capsules][kDiagStride]
     int* status;
     int node_stride;
-    int nx, ny, nxp, nseg, periodic_y;
     int phase, dynamic;
     int patch_cap, max_nv;
-    double gx, nu;
 };
 
 // ---- launchers (lbib_kernels.hip) ----
@@ -83,6 +103,13 @@ hipError_t launch_init(T* pops, const GridArgs& g, int profile, double ux0, doub
 template <typename T>
 hipError_t launch_grid_step(const T* src, T* dst, const long long* fib_now, const int* flags_now,
                             long long* fib_old, int* flags_old, const GridArgs& g, hipStream_t s);
+template <typename T>
+hipError_t launch_grid_step_batch(const T* src, T* dst, const long long* fib_now,
+                                  const int* flags_now, long long* fib_old, int* flags_old,
+                                  const InstDev* inst, const int* round_inst, int blocks,
+                                  hipStream_t s);
+// Blocks of the grid kernel for one lattice (a multiple of kNumXcd).
+int grid_blocks(int ny, int nseg);
 template <typename T>
 hipError_t launch_ib(const IBArgs<T>& a, int ncap, size_t lds_bytes, hipStream_t s);
 template <typename T>

@@ -194,16 +194,75 @@ __global__ __launch_bounds__(kSegW * 4) void k_grid_step(
     }
 }
 
+int grid_blocks(int ny, int nseg)
+{
+    constexpr int R = kGridRowsPerThread;
+    const int bands = (ny + 4 * R - 1) / (4 * R);
+    const int groups = (bands + kNumXcd - 1) / kNumXcd;
+    return groups * nseg * kNumXcd;
+}
+
 template <typename T>
 hipError_t launch_grid_step(const T* src, T* dst, const long long* fib_now, const int* flags_now,
                             long long* fib_old, int* flags_old, const GridArgs& g, hipStream_t s)
 {
     constexpr int R = kGridRowsPerThread;
-    const long long bands = (g.ny + 4 * R - 1) / (4 * R);
-    const long long groups = (bands + kNumXcd - 1) / kNumXcd;
-    const long long blocks = groups * g.nseg * kNumXcd;
+    const int blocks = grid_blocks(g.ny, g.nseg);
     hipLaunchKernelGGL((k_grid_step<T, R>), dim3((unsigned)blocks), dim3(kSegW * 4), 0, s, src, dst,
                        fib_now, flags_now, fib_old, flags_old, g);
+    return hipGetLastError();
+}
+
+// Ensemble of lattices in one launch.  Every lattice owns a run of blocks that
+// starts at a multiple of kNumXcd, so block b still lands on XCD b % 8 and the
+// band-to-XCD mapping above holds inside each lattice.  round_inst[b / 8]
+// names the lattice of block b.
+template <typename T, int ROWS>
+__global__ __launch_bounds__(kSegW * 4) void k_grid_step_batch(
+    const T* __restrict__ src, T* __restrict__ dst, const long long* __restrict__ fib_now,
+    const int* __restrict__ flags_now, long long* __restrict__ fib_old,
+    int* __restrict__ flags_old, const InstDev* __restrict__ inst,
+    const int* __restrict__ round_inst)
+{
+    const int b = blockIdx.x;
+    const InstDev& I = inst[round_inst[b / kNumXcd]];
+    GridArgs g;
+    g.nx = I.nx;
+    g.ny = I.ny;
+    g.nxp = I.nxp;
+    g.nseg = I.nseg;
+    g.periodic_y = I.periodic_y;
+    g.omega = I.omega;
+    g.gx = I.gx;
+    g.u_bot = I.u_bot;
+    g.u_top = I.u_top;
+    const int lb = b - I.block0;
+    const int j = lb / kNumXcd;
+    const int group = j / g.nseg;
+    const int band = group * kNumXcd + (lb - j * kNumXcd);
+    const int seg = j - group * g.nseg;
+    const int lane = threadIdx.x & (kSegW - 1);
+    const int y0 = band * (4 * ROWS) + (threadIdx.x >> 6);
+#pragma unroll
+    for (int r = 0; r < ROWS; r++) {
+        const int y = y0 + 4 * r;
+        if (y < g.ny)
+            grid_cell(src + I.pop_off, dst + I.pop_off, fib_now + I.fib_off,
+                      flags_now + I.flag_off, fib_old + I.fib_off, flags_old + I.flag_off, g, y,
+                      seg, lane);
+    }
+}
+
+template <typename T>
+hipError_t launch_grid_step_batch(const T* src, T* dst, const long long* fib_now,
+                                  const int* flags_now, long long* fib_old, int* flags_old,
+                                  const InstDev* inst, const int* round_inst, int blocks,
+                                  hipStream_t s)
+{
+    constexpr int R = kGridRowsPerThread;
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_grid_step_batch<T, R>), dim3((unsigned)blocks), dim3(kSegW * 4), 0, s,
+                       src, dst, fib_now, flags_now, fib_old, flags_old, inst, round_inst);
     return hipGetLastError();
 }
 
@@ -638,20 +697,21 @@ __device__ __forceinline__ long long to_fix(T v, int& st)
 // (vx, vy) = c phi_k F goes to support node k of the 3x3 support centred on
 // (cx, cy), relative to the reference point.
 template <typename T>
-__device__ __forceinline__ void spread_one(const IBArgs<T>& a, long long refx, long long refy,
-                                           int cx, int cy, int k, T vx, T vy, int& st)
+__device__ __forceinline__ void spread_one(const IBArgs<T>& a, const GridArgs& g, long long refx,
+                                           long long refy, int cx, int cy, int k, T vx, T vy,
+                                           int& st)
 {
     long long gy = refy + cy + k / 3 - 1;
-    if (a.periodic_y) gy = ((gy % a.ny) + a.ny) % a.ny;
-    else if (gy < 1 || gy > a.ny - 2) { st |= ST_WALL; return; }
+    if (g.periodic_y) gy = ((gy % g.ny) + g.ny) % g.ny;
+    else if (gy < 1 || gy > g.ny - 2) { st |= ST_WALL; return; }
     long long gx = refx + cx + k % 3 - 1;
-    gx = ((gx % a.nx) + a.nx) % a.nx;
+    gx = ((gx % g.nx) + g.nx) % g.nx;
     const long long fx = to_fix(vx, st), fy = to_fix(vy, st);
-    const size_t cell = (size_t)gy * a.nxp + (size_t)gx;
+    const size_t cell = (size_t)gy * g.nxp + (size_t)gx;
     unsigned long long* dst = reinterpret_cast<unsigned long long*>(a.fib_next + 2 * cell);
     atomicAdd(dst, (unsigned long long)fx);
     atomicAdd(dst + 1, (unsigned long long)fy);
-    a.flags_next[gy * a.nseg + gx / kSegW] = 1;
+    a.flags_next[gy * g.nseg + gx / kSegW] = 1;
 }
 
 // MLS weights of node v cached for the spreading: phi_0..7 in S.t[0..7],
@@ -670,15 +730,16 @@ __device__ __forceinline__ void cache_weights(const Scratch<T>& S, int v, int cx
 // Spreads the cached c_v F_v (S.t[8..9]) with the cached weights; one work
 // item per (node, support node).
 template <typename T>
-__device__ __forceinline__ void spread_cached(const IBArgs<T>& a, const Scratch<T>& S, int nv,
-                                              long long refx, long long refy, int& st)
+__device__ __forceinline__ void spread_cached(const IBArgs<T>& a, const GridArgs& g,
+                                              const Scratch<T>& S, int nv, long long refx,
+                                              long long refy, int& st)
 {
     const T* base = S.t[0];
     const size_t stride = S.t[1] - S.t[0];  // the scratch arrays are contiguous
     for (int w = threadIdx.x; w < 9 * nv; w += blockDim.x) {
         const int v = w / 9, k = w - 9 * v;
         const T phi = base[(size_t)(k < 8 ? k : 12) * stride + v];
-        spread_one(a, refx, refy, (int)S.t[10][v], (int)S.t[11][v], k, phi * S.t[8][v],
+        spread_one(a, g, refx, refy, (int)S.t[10][v], (int)S.t[11][v], k, phi * S.t[8][v],
                    phi * S.t[9][v], st);
     }
 }
@@ -745,17 +806,17 @@ __device__ __forceinline__ void stage_cell(const IBArgs<T>& a, const GridArgs& g
 {
     const int lx = i % P.W, ly = i / P.W;
     long long wy = refy + P.oy + ly;
-    if (a.periodic_y) wy = ((wy % a.ny) + a.ny) % a.ny;
-    else if (wy < 1 || wy > a.ny - 2) {
+    if (g.periodic_y) wy = ((wy % g.ny) + g.ny) % g.ny;
+    else if (wy < 1 || wy > g.ny - 2) {
         P.drho[i] = T(NAN);
         P.ux[i] = P.uy[i] = T(0);
         return;
     }
     long long wx = refx + P.ox + lx;
-    wx = ((wx % a.nx) + a.nx) % a.nx;
+    wx = ((wx % g.nx) + g.nx) % g.nx;
     T s[9];
     pull(a.pops, (int)wx, (int)wy, g, gxf, s);
-    const size_t cell = (size_t)wy * a.nxp + (size_t)wx;
+    const size_t cell = (size_t)wy * g.nxp + (size_t)wx;
     const T Fx = gxf + fix_to_real<T>(a.fib_prev[2 * cell]);
     const T Fy = fix_to_real<T>(a.fib_prev[2 * cell + 1]);
     const T drho = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])) + s[8];
@@ -776,13 +837,28 @@ __device__ __forceinline__ void stage_cell(const IBArgs<T>& a, const GridArgs& g
 //             forces, c_v = 1)
 //   PH_DIAG   diagnostics of the current shape only
 template <typename T>
-__global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
+__global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[kIBThreads / 64][8];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int c = blockIdx.x;
-    CapsuleDev cap = a.caps[c];
+    CapsuleDev cap = a0.caps[c];
+    // the capsule's lattice: buffer offsets and sizes
+    IBArgs<T> a = a0;
+    a.pops += cap.pop_off;
+    a.fib_prev += cap.fib_off;
+    a.fib_next += cap.fib_off;
+    a.flags_next += cap.flag_off;
+    GridArgs g;
+    g.nx = cap.nx;
+    g.ny = cap.ny;
+    g.nxp = cap.nxp;
+    g.nseg = cap.nseg;
+    g.periodic_y = cap.periodic_y;
+    g.omega = 0.0;
+    g.gx = cap.gx;
+    g.u_bot = g.u_top = 0.0;  // wall rows are never staged
     const int nv = cap.nv, off = cap.node_offset;
     const size_t NS = a.node_stride;
     T* N = a.nodes;
@@ -864,14 +940,7 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
             if (tid == 0) atomicOr(a.status, ST_PATCH);
             return;
         }
-        GridArgs g;
-        g.nx = a.nx;
-        g.ny = a.ny;
-        g.nxp = a.nxp;
-        g.nseg = a.nseg;
-        g.periodic_y = a.periodic_y;
-        g.u_bot = g.u_top = 0.0;  // wall rows are never staged
-        const T gxf = (T)a.gx;
+        const T gxf = (T)cap.gx;
         // two cells per iteration, so that both cells' loads are in flight together
         const int ncell = P.W * P.H;
         for (int i = tid; i < ncell; i += 2 * nt) {
@@ -901,7 +970,7 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
     if (doB) {
         if (a.dynamic) {
             internal_forces(S, nv, cap.kb, cap.ka, cap.A0, red);  // -> t8, t9
-            external_forces(S, P, nv, (T)a.nu, st);                            // -> t2, t3
+            external_forces(S, P, nv, (T)cap.nu, st);                            // -> t2, t3
         }
         const T half_inv_m = (T)(0.5 / cap.mv);
         double csum[2] = {0.0, 0.0};
@@ -1017,7 +1086,7 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a)
             }
         }
         __syncthreads();
-        spread_cached(a, S, nv, refx, refy, st);
+        spread_cached(a, g, S, nv, refx, refy, st);
     }
     if (prime && tid == 0) a.caps[c].primed = 1;
     if (st) atomicOr(a.status, st);
@@ -1211,6 +1280,9 @@ hipError_t launch_set_nodes(T* nodes, CapsuleDev* caps, int cap, int nv, int nod
                                        hipStream_t);                                              \
     template hipError_t launch_grid_step<T>(const T*, T*, const long long*, const int*,           \
                                             long long*, int*, const GridArgs&, hipStream_t);      \
+    template hipError_t launch_grid_step_batch<T>(const T*, T*, const long long*, const int*,     \
+                                                  long long*, int*, const InstDev*, const int*,   \
+                                                  int, hipStream_t);                              \
     template hipError_t launch_ib<T>(const IBArgs<T>&, int, size_t, hipStream_t);                 \
     template size_t ib_lds_bytes<T>(int, int);                                                    \
     template hipError_t ib_set_lds_limit<T>(size_t);                                              \

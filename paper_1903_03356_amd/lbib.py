@@ -32,7 +32,9 @@ DIAG_KEYS = ["area", "perimeter", "cx", "cy", "D", "Sw", "dp", "dA", "Jxx", "Jyy
 
 EXPORTS = ["lbib_required_bytes", "lbib_create", "lbib_add_capsule", "lbib_step",
            "lbib_get_state", "lbib_set_state", "lbib_check", "lbib_set_timing",
-           "lbib_get_timing", "lbib_steps_done", "lbib_last_error", "lbib_destroy"]
+           "lbib_get_timing", "lbib_steps_done", "lbib_last_error", "lbib_destroy",
+           "lbib_required_bytes_batch", "lbib_create_batch", "lbib_add_capsule_to",
+           "lbib_num_lattices"]
 
 
 class lbib_grid(C.Structure):
@@ -93,6 +95,17 @@ def load() -> C.CDLL:
     L.lbib_last_error.argtypes = [vp]
     L.lbib_destroy.restype = None
     L.lbib_destroy.argtypes = [vp]
+    L.lbib_required_bytes_batch.restype = C.c_size_t
+    L.lbib_required_bytes_batch.argtypes = [C.POINTER(lbib_grid), i32, i32]
+    L.lbib_create_batch.restype = i32
+    L.lbib_create_batch.argtypes = [C.POINTER(lbib_grid), C.POINTER(C.c_double),
+                                    C.POINTER(lbib_walls), i32, C.POINTER(vp), i32, vp,
+                                    C.POINTER(vp)]
+    L.lbib_add_capsule_to.restype = i32
+    L.lbib_add_capsule_to.argtypes = [vp, i32, C.POINTER(C.c_double), i32, C.POINTER(C.c_double),
+                                      i32, C.c_double, C.c_double, C.c_double, C.POINTER(i32)]
+    L.lbib_num_lattices.restype = i32
+    L.lbib_num_lattices.argtypes = [vp]
     _lib = L
     return L
 
@@ -113,6 +126,28 @@ def required_bytes(grid: lbib_grid, buffer_id: int) -> int:
     return int(load().lbib_required_bytes(C.byref(grid), buffer_id))
 
 
+def required_bytes_batch(grids, buffer_id: int) -> int:
+    arr = (lbib_grid * len(grids))(*grids)
+    return int(load().lbib_required_bytes_batch(arr, len(grids), buffer_id))
+
+
+def grid_of(cfg: Dict[str, Any], max_capsules: int = 0, max_nodes_total: int = 0,
+            max_nodes_capsule: int = 0) -> lbib_grid:
+    caps = cfg.get("capsules", [])
+    nodes_total = sum(len(c["nodes"]) for c in caps)
+    nv_max = max([len(c["nodes"]) for c in caps] + [3])
+    return make_grid(int(cfg["nx"]), int(cfg["ny"]), int(cfg["real_bytes"]),
+                     max(1, len(caps), max_capsules), max(3, nodes_total, max_nodes_total),
+                     max(nv_max, max_nodes_capsule))
+
+
+def walls_of(cfg: Dict[str, Any]) -> lbib_walls:
+    ux0, uy0 = cfg.get("init_u", (0.0, 0.0))
+    return lbib_walls(1, int(cfg.get("periodic_y", 0)), float(cfg.get("u_bottom", 0.0)),
+                      float(cfg.get("u_top", 0.0)), float(cfg.get("body_force_x", 0.0)),
+                      int(cfg.get("init_profile", 0)), float(ux0), float(uy0))
+
+
 class Sim:
     """One context: device buffers allocated with torch, kernels in liblbib.so.
 
@@ -126,15 +161,8 @@ class Sim:
         self.cfg = cfg
         self.device = torch.device(device if device is not None else "cuda")
         caps = cfg.get("capsules", [])
-        nodes_total = sum(len(c["nodes"]) for c in caps)
-        nv_max = max([len(c["nodes"]) for c in caps] + [3])
-        self.grid = make_grid(int(cfg["nx"]), int(cfg["ny"]), int(cfg["real_bytes"]),
-                              max(1, len(caps), max_capsules), max(3, nodes_total, max_nodes_total),
-                              max(nv_max, max_nodes_capsule))
-        ux0, uy0 = cfg.get("init_u", (0.0, 0.0))
-        self.walls = lbib_walls(1, int(cfg.get("periodic_y", 0)), float(cfg.get("u_bottom", 0.0)),
-                                float(cfg.get("u_top", 0.0)), float(cfg.get("body_force_x", 0.0)),
-                                int(cfg.get("init_profile", 0)), float(ux0), float(uy0))
+        self.grid = grid_of(cfg, max_capsules, max_nodes_total, max_nodes_capsule)
+        self.walls = walls_of(cfg)
         self.buffers: List[Any] = []
         with torch.cuda.device(self.device):
             for i in range(NUM_BUFFERS):
@@ -149,6 +177,7 @@ class Sim:
                                  NUM_BUFFERS, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h
         self.nv: List[int] = []
+        self.dims = [(int(cfg["nx"]), int(cfg["ny"]))]
         for cap in caps:
             self.add_capsule(cap["nodes"], cap["ks"], cap["kb"], cap["ka"], cap["mass"])
         self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
@@ -166,6 +195,23 @@ class Sim:
         self.nv.append(nodes.shape[0])
         return cid.value
 
+    def add_capsule_to(self, lattice: int, nodes, ks, kb: float, ka: float, mass: float) -> int:
+        nodes = np.ascontiguousarray(nodes, np.float64)
+        ks = np.ascontiguousarray(np.atleast_1d(np.asarray(ks, np.float64)))
+        cid = C.c_int32()
+        dp = C.POINTER(C.c_double)
+        with self.torch.cuda.device(self.device):
+            _check(load().lbib_add_capsule_to(self.h, int(lattice), nodes.ctypes.data_as(dp),
+                                              nodes.shape[0], ks.ctypes.data_as(dp), ks.size,
+                                              float(kb), float(ka), float(mass), C.byref(cid)),
+                   self.h)
+        self.nv.append(nodes.shape[0])
+        return cid.value
+
+    @property
+    def num_lattices(self) -> int:
+        return int(load().lbib_num_lattices(self.h))
+
     def step(self, n: int, mode: Optional[str] = None) -> None:
         mode = mode or self.cfg.get("mode", "dynamic")
         m = DYNAMIC if mode == "dynamic" else KINEMATIC
@@ -173,16 +219,19 @@ class Sim:
             _check(load().lbib_step(self.h, int(n), m), self.h)
 
     def get_state(self, what: int, capsule: int = 0, out=None):
-        """Host copy (numpy FP64) or, with ``out`` a CUDA FP64 tensor, a queued device copy."""
-        shapes = {F_POPS: (9, self.ny, self.nx), F_POPS_DEV: (9, self.ny, self.nx),
-                  F_MOMENTS: (3, self.ny, self.nx), F_FORCE: (2, self.ny, self.nx),
+        """Host copy (numpy FP64) or, with ``out`` a CUDA FP64 tensor, a queued device copy.
+        ``capsule`` is the capsule id, or the lattice index for the field states."""
+        field = what in (F_POPS, F_POPS_DEV, F_MOMENTS, F_FORCE)
+        # an index out of range goes to the library, which rejects it (EINVAL)
+        nx, ny = self.dims[capsule] if field and 0 <= capsule < len(self.dims) else (1, 1)
+        shapes = {F_POPS: (9, ny, nx), F_POPS_DEV: (9, ny, nx),
+                  F_MOMENTS: (3, ny, nx), F_FORCE: (2, ny, nx),
                   C_DIAG: (16,), STATUS: (1,)}
         if what in shapes:
             shape = shapes[what]
-        elif what == C_STATE:
-            shape = (3, self.nv[capsule], 2)
         else:
-            shape = (self.nv[capsule], 2)
+            nv = self.nv[capsule] if 0 <= capsule < len(self.nv) else 1
+            shape = (3, nv, 2) if what == C_STATE else (nv, 2)
         with self.torch.cuda.device(self.device):
             if out is not None:
                 _check(load().lbib_get_state(self.h, what, capsule, C.c_void_p(out.data_ptr()),
@@ -226,20 +275,20 @@ class Sim:
         return int(load().lbib_steps_done(self.h))
 
     # -- conveniences -----------------------------------------------------------
-    def pops(self) -> np.ndarray:
-        return self.get_state(F_POPS)
+    def pops(self, lattice: int = 0) -> np.ndarray:
+        return self.get_state(F_POPS, lattice)
 
-    def pops_dev(self) -> np.ndarray:
-        return self.get_state(F_POPS_DEV)
+    def pops_dev(self, lattice: int = 0) -> np.ndarray:
+        return self.get_state(F_POPS_DEV, lattice)
 
-    def set_pops(self, f) -> None:
-        self.set_state(F_POPS, f)
+    def set_pops(self, f, lattice: int = 0) -> None:
+        self.set_state(F_POPS, f, lattice)
 
-    def moments(self) -> np.ndarray:
-        return self.get_state(F_MOMENTS)
+    def moments(self, lattice: int = 0) -> np.ndarray:
+        return self.get_state(F_MOMENTS, lattice)
 
-    def force(self) -> np.ndarray:
-        return self.get_state(F_FORCE)
+    def force(self, lattice: int = 0) -> np.ndarray:
+        return self.get_state(F_FORCE, lattice)
 
     def capsule(self, c: int):
         s = self.get_state(C_STATE, c)
@@ -266,3 +315,49 @@ class Sim:
             self.close()
         except Exception:
             pass
+
+
+class Batch(Sim):
+    """Ensemble context: one lattice per workload dictionary in ``cfgs``, stepped
+    together (lbib_create_batch).  Capsule ids run over the whole batch, lattice
+    by lattice; ``cap_ids[i]`` lists those of lattice i.  Field getters take
+    the lattice index."""
+
+    def __init__(self, cfgs: List[Dict[str, Any]], device: Optional[Any] = None, stream=None):
+        import torch
+        L = load()
+        if not cfgs:
+            raise ValueError("a batch needs at least one lattice")
+        modes = {c.get("mode", "dynamic") for c in cfgs}
+        if len(modes) != 1:
+            raise ValueError("all lattices of a batch share the coupling mode")
+        self.torch = torch
+        self.cfg = dict(cfgs[0])
+        self.cfgs = cfgs
+        self.device = torch.device(device if device is not None else "cuda")
+        grids = [grid_of(c) for c in cfgs]
+        self.grids = (lbib_grid * len(cfgs))(*grids)
+        self.walls_arr = (lbib_walls * len(cfgs))(*[walls_of(c) for c in cfgs])
+        taus = (C.c_double * len(cfgs))(*[float(c["tau"]) for c in cfgs])
+        self.buffers: List[Any] = []
+        with torch.cuda.device(self.device):
+            for i in range(NUM_BUFFERS):
+                nb = int(L.lbib_required_bytes_batch(self.grids, len(cfgs), i))
+                if nb == 0:
+                    raise LbibError(ECAPACITY, "invalid lattices for buffer sizing")
+                self.buffers.append(torch.empty(nb, dtype=torch.uint8, device=self.device))
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            ptrs = (C.c_void_p * NUM_BUFFERS)(*[b.data_ptr() for b in self.buffers])
+            h = C.c_void_p()
+            _check(L.lbib_create_batch(self.grids, taus, self.walls_arr, len(cfgs), ptrs,
+                                       NUM_BUFFERS, C.c_void_p(self.stream.cuda_stream),
+                                       C.byref(h)))
+        self.h = h
+        self.nv: List[int] = []
+        self.dims = [(int(c["nx"]), int(c["ny"])) for c in cfgs]
+        self.cap_ids: List[List[int]] = []
+        for i, c in enumerate(cfgs):
+            ids = [self.add_capsule_to(i, cap["nodes"], cap["ks"], cap["kb"], cap["ka"],
+                                       cap["mass"]) for cap in c.get("capsules", [])]
+            self.cap_ids.append(ids)
+        self.nx, self.ny = self.dims[0]

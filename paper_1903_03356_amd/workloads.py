@@ -255,6 +255,59 @@ def grid_bench(n: int = 4096, tau: float = 0.8, u_max: float = 0.02, steps: int 
                  body_force_x=g, init_profile=INIT_POISEUILLE)
 
 
+def ensemble(seed: int = 0, n_inst: int = 256, u_max: float = 0.02, screen_limit: float = 1.5,
+             real_bytes: int = 4, mode: str = "dynamic", steps: int = 10000,
+             nx_range=(128, 512), ny_range=(64, 128), tau_range=(0.6, 1.2),
+             max_tries: int = 100000) -> List[Dict[str, Any]]:
+    """Independent capsule channels for the batched ensemble.
+
+    Draw order per lattice, from default_rng(seed): nx U{nx_range}, ny
+    U{ny_range}, tau U[tau_range], capsule count U{1, 2}; then per capsule:
+    shape (biconcave if u < 0.5), node count U{64..128}, radius U[5, 9]
+    (biconcave half-length), orientation U[0, 2 pi), density ratio U[1, 2],
+    log10 Ca U[-3, -1], centre x offset U[-4, 4] from (k + 1/2) nx / count,
+    centre y U[R + 4, H - R - 4].  A capsule whose stability ratio
+    2 k_s / m_v exceeds ``screen_limit`` is drawn again (all of its draws).
+    Each channel is driven by the body force for peak speed u_max and starts
+    from the analytic parabola; E_b = 0, k_a = 1."""
+    rng = np.random.default_rng(seed)
+    out: List[Dict[str, Any]] = []
+    for i in range(n_inst):
+        nx = int(rng.integers(nx_range[0], nx_range[1] + 1))
+        ny = int(rng.integers(ny_range[0], ny_range[1] + 1))
+        tau = float(rng.uniform(*tau_range))
+        count = int(rng.integers(1, 3))
+        H = ny - 1
+        g = poiseuille_body_force(tau, ny, u_max)
+        caps: List[Dict[str, Any]] = []
+        tries = 0
+        while len(caps) < count:
+            tries += 1
+            if tries > max_tries:
+                raise RuntimeError(f"lattice {i}: no capsule passes the screen")
+            biconcave = rng.uniform() < 0.5
+            n = int(rng.integers(64, 129))
+            R = float(rng.uniform(5.0, 9.0))
+            angle = float(rng.uniform(0.0, 2.0 * math.pi))
+            ratio = float(rng.uniform(1.0, 2.0))
+            ca = float(10.0 ** rng.uniform(-3.0, -1.0))
+            cx = (len(caps) + 0.5) * nx / count + float(rng.uniform(-4.0, 4.0))
+            cy = float(rng.uniform(R + 4.0, H - R - 4.0))
+            if biconcave:
+                nodes = biconcave_nodes(cx, cy, 2.0 * R, n, angle)
+            else:
+                nodes = circle_nodes(cx, cy, R, n, phase=0.5)
+            ks = ks_from_ca(tau, u_max, ca)
+            cap = capsule(nodes, ks, 0.0, 1.0, ratio)
+            if stability_ratio(ks, cap["mass"], n) > screen_limit:
+                continue
+            cap.update({"shape": "biconcave" if biconcave else "circle", "radius": R, "ca": ca})
+            caps.append(cap)
+        out.append(_base(f"ensemble{seed}_{i}_{nx}x{ny}", nx, ny, tau, real_bytes, mode, steps,
+                         body_force_x=g, init_profile=INIT_POISEUILLE, capsules=caps))
+    return out
+
+
 def adjoint_channel(nx: int = 512, ny: int = 128, tau: float = 0.8, u_max: float = 0.02,
                     radius: float = 10.0, n_nodes: int = 96, ca: float = 1e-2,
                     steps: int = 5000) -> Dict[str, Any]:
