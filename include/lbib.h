@@ -246,6 +246,48 @@ lbib_status lbib_add_capsule_to(lbib_ctx* ctx, int32_t lattice, const double* no
 /* Number of lattices of the context, or -1 for a NULL context. */
 int32_t lbib_num_lattices(const lbib_ctx* ctx);
 
+/* ---- Reverse-mode gradients (adjoint) ----
+ *
+ * Objectives of the final capsule shape (Sec. 3 diagnostics, FP64). */
+enum lbib_objective {
+    LBIB_OBJ_TAYLOR = 0,     /* Taylor deformation D of the equivalent ellipse (LBIB_D_TAYLOR) */
+    LBIB_OBJ_CENTROID_Y = 1  /* area-centroid height y_c (LBIB_D_CY) */
+};
+
+/* Workspace bytes lbib_adjoint needs for nsteps steps of this context, or 0
+ * if the context is not a single lattice or nsteps < 1.  The workspace holds
+ * the whole forward trajectory (populations, IB force field and node state of
+ * every time level: about (36 + 16) B per cell per step in FP32), so it grows
+ * linearly in nsteps. */
+size_t lbib_adjoint_bytes(const lbib_ctx* ctx, int32_t nsteps);
+
+/* Runs nsteps time steps of the chosen scheme from the initial state (the
+ * context must be at step 0), taping the trajectory into `workspace` (device
+ * memory, caller-owned, lbib_adjoint_bytes long), evaluates
+ * J = objective(capsule) at step nsteps, then runs the reverse sweep: the exact
+ * discrete adjoint of the executed step (Secs. 2.1-2.4), one reverse grid
+ * launch and one reverse IB launch per step.  Outputs (host):
+ *   *out_J       J
+ *   *out_dJ_dg   dJ/dg for the uniform body force g (the walls' body_force_x),
+ *                including its use in the initial Poiseuille profile
+ *                (init_profile 2)
+ *   out_dJ_dks   dJ/dk_s for every element of every capsule, in node order
+ *                (capsule after capsule, element l joins node l to l+1);
+ *                n_ks >= total node count
+ * Afterwards the context stands at step nsteps, as after lbib_step(nsteps).
+ * The MLS supports are held fixed (they are piecewise constant in the
+ * positions); the fixed-point rounding of the spread force is not
+ * differentiated.
+ * Errors: EINVAL (batch context, nsteps < 1, bad mode, objective or capsule
+ * id, a capsule with k_b != 0, workspace or n_ks too small, NULL pointers),
+ * ESTATE (context not at step 0, or its mode differs), ECAPACITY (capsules too
+ * large for the on-chip memory of the reverse IB kernel), ENUMERIC (a device
+ * status flag in the forward run or the reverse sweep), EDEVICE.
+ * Waits for the stream. */
+lbib_status lbib_adjoint(lbib_ctx* ctx, int32_t nsteps, lbib_mode mode, int32_t objective,
+                         int32_t capsule, void* workspace, size_t workspace_bytes, double* out_J,
+                         double* out_dJ_dg, double* out_dJ_dks, int32_t n_ks);
+
 /* Frees the host-side context.  Device buffers stay with the caller.  Waits for
  * the stream first. */
 void lbib_destroy(lbib_ctx* ctx);

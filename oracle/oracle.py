@@ -235,3 +235,42 @@ class Sim:
         lib().orc_spread(self.h, xy.shape[0], xy, np.ascontiguousarray(c, np.float64),
                          np.ascontiguousarray(F, np.float64), out)
         return out
+
+
+# ---- gradients by central differences ----------------------------------------
+
+def objective(cfg: Dict[str, Any], steps: int, which: str = "D", capsule: int = 0) -> float:
+    """Objective of the final shape after ``steps`` steps of the FP64 oracle:
+    the Taylor deformation D or the area-centroid height y_c (Sec. 3)."""
+    s = Sim(cfg)
+    s.step(steps)
+    if s.status:
+        raise RuntimeError(f"oracle status {s.status}")
+    return s.diag(capsule)["D" if which == "D" else "cy"]
+
+
+def perturbed(cfg: Dict[str, Any], param: Any, delta: float) -> Dict[str, Any]:
+    """Copy of cfg with one parameter moved by delta: ("ks", capsule, element)
+    for one element's stretching constant, or "g" for the uniform body force
+    (which also sets the initial Poiseuille profile)."""
+    new = dict(cfg)
+    if param == "g":
+        new["body_force_x"] = float(cfg["body_force_x"]) + delta
+        return new
+    _, c, l = param
+    caps = [dict(k) for k in cfg["capsules"]]
+    nv = len(caps[c]["nodes"])
+    ks = np.broadcast_to(np.asarray(caps[c]["ks"], np.float64), (nv,)).copy()
+    ks[l] += delta
+    caps[c]["ks"] = ks
+    new["capsules"] = caps
+    return new
+
+
+def central_difference(cfg: Dict[str, Any], steps: int, param: Any, h: float,
+                       which: str = "D", capsule: int = 0) -> float:
+    """dJ/dparam ~ (J(p + h) - J(p - h)) / (2 h): the definition of the
+    derivative with a symmetric difference, error O(h^2)."""
+    jp = objective(perturbed(cfg, param, h), steps, which, capsule)
+    jm = objective(perturbed(cfg, param, -h), steps, which, capsule)
+    return (jp - jm) / (2.0 * h)

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbib.so")
-SOURCES = ["lbib_kernels.hip", "lbib_api.hip"]
+SOURCES = ["lbib_kernels.hip", "lbib_adjoint.hip", "lbib_api.hip"]
 ARCH = os.environ.get("LBIB_OFFLOAD_ARCH", "gfx950")
 
 

@@ -2,6 +2,7 @@
 // validation, binding of caller-owned device buffers, the per-step launch
 // schedule and state transfers.  Declarations and contracts: include/lbib.h.
 #include "lbib.h"
+#include "lbib_adjoint.h"
 #include "lbib_internal.h"
 
 #include <algorithm>
@@ -52,8 +53,11 @@ struct lbib_ctx {
     void* buf[LBIB_NUM_BUFFERS] = {};
     hipStream_t stream = nullptr;
     int ncap = 0, nodes_used = 0;
-    int patch_cap = 0;
-    size_t lds_bytes = 0;
+    int patch_cap = 0;      // largest patch the on-chip budget allows
+    size_t lds_bytes = 0;   // IB kernel LDS at that patch size
+    int patch_use = 0;      // patch capacity of the launches: what the capsules need
+    size_t lds_use = 0;
+    int lds_ncap = -1;      // capsule count patch_use was computed for
     long long steps = 0;
     int mode = -1;
     std::string err;
@@ -61,6 +65,7 @@ struct lbib_ctx {
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> pool;
     std::vector<int> cap_off, cap_nv, cap_inst;  // host copy of the capsule table layout
+    std::vector<double> cap_kb, cap_P0;
 };
 
 // ----------------------------------------------------------------- helpers
@@ -486,6 +491,8 @@ static lbib_status add_capsule_t(lbib_ctx* c, int inst, const double* xy, int n,
     c->cap_off.push_back(off);
     c->cap_nv.push_back(n);
     c->cap_inst.push_back(inst);
+    c->cap_kb.push_back(kb);
+    c->cap_P0.push_back(P);
     c->ncap++;
     c->nodes_used += n;
     I.ncap++;
@@ -531,6 +538,24 @@ extern "C" lbib_status lbib_add_capsule(lbib_ctx* c, const double* xy, int32_t n
 
 // -------------------------------------------------------------------- step
 
+// Patch capacity of the IB launches: a closed polygon of perimeter P fits in
+// a square of side P / 2, so (P0 + 8)^2 cells hold the patch (bounding box
+// plus the 3-cell halo) of any shape up to twice the stress-free perimeter P0
+// of the largest capsule.  Smaller LDS per block lets more capsules share a
+// compute unit; a capsule that outgrows it raises LBIB_FLAG_PATCH.
+template <typename T>
+static void size_patches(lbib_ctx* c)
+{
+    if (c->lds_ncap == c->ncap) return;
+    double pmax = 0.0;
+    for (double p : c->cap_P0) pmax = std::max(pmax, p);
+    const double side = std::ceil(pmax) + 8.0;
+    const double need = side * side;
+    c->patch_use = need < (double)c->patch_cap ? (int)need : c->patch_cap;
+    c->lds_use = ib_lds_bytes<T>(c->patch_use, c->L.max_nv);
+    c->lds_ncap = c->ncap;
+}
+
 template <typename T>
 static IBArgs<T> ib_args(const lbib_ctx* c, long long n, int phase)
 {
@@ -547,8 +572,10 @@ static IBArgs<T> ib_args(const lbib_ctx* c, long long n, int phase)
     a.node_stride = c->L.max_nodes;
     a.phase = phase;
     a.dynamic = c->mode == LBIB_DYNAMIC;
-    a.patch_cap = c->patch_cap;
+    a.patch_cap = c->patch_use;
     a.max_nv = c->L.max_nv;
+    a.tape_nodes = nullptr;
+    a.tape_ref = nullptr;
     return a;
 }
 
@@ -581,7 +608,7 @@ template <typename T>
 static hipError_t do_ib(lbib_ctx* c, void* p)
 {
     const IBLaunch<T>* q = static_cast<const IBLaunch<T>*>(p);
-    return launch_ib<T>(ib_args<T>(c, q->n, q->phase), c->ncap, c->lds_bytes, c->stream);
+    return launch_ib<T>(ib_args<T>(c, q->n, q->phase), c->ncap, c->lds_use, c->stream);
 }
 
 template <typename T>
@@ -603,6 +630,7 @@ static hipError_t do_grid(lbib_ctx* c, void* p)
 template <typename T>
 static lbib_status step_t(lbib_ctx* c, int nsteps)
 {
+    size_patches<T>(c);
     for (int k = 0; k < nsteps; k++) {
         const long long n = c->steps + k;
         if (c->ncap > 0) {
@@ -704,8 +732,9 @@ static lbib_status get_t(lbib_ctx* c, int what, int cap, void* dst, size_t bytes
     case LBIB_C_DIAG: {
         if (cap < 0 || cap >= c->ncap) return fail(c, LBIB_EINVAL, "bad capsule id");
         if (bytes < kDiagStride * sizeof(double)) return fail(c, LBIB_EINVAL, "dst too small");
+        size_patches<T>(c);
         IBArgs<T> a = ib_args<T>(c, c->steps, PH_DIAG);
-        HIPCHK(c, launch_ib<T>(a, c->ncap, c->lds_bytes, c->stream));
+        HIPCHK(c, launch_ib<T>(a, c->ncap, c->lds_use, c->stream));
         const double* src = reinterpret_cast<const double*>(bufp(c, LBIB_BUF_DIAG)) +
                             (size_t)cap * kDiagStride;
         if (on_dev)
@@ -785,6 +814,248 @@ extern "C" lbib_status lbib_set_state(lbib_ctx* c, int32_t what, int32_t cap, co
     if (!src) return fail(c, LBIB_EINVAL, "src is NULL");
     return c->rb == 4 ? set_t<float>(c, what, cap, src, bytes, on_dev)
                       : set_t<double>(c, what, cap, src, bytes, on_dev);
+}
+
+// ----------------------------------------------------------------- adjoint
+
+// Workspace of lbib_adjoint: a tape slot per time level 0..N (populations
+// P^n, IB force F^{n-1} - g with its flags, node state and reference points),
+// then the reverse-sweep arrays.
+struct AdjLayout {
+    size_t pops = 0, fib = 0, flags = 0, nodes = 0, ref = 0, slot = 0;
+    size_t lam[2] = {0, 0}, lfm = 0, lft = 0, lfm_flags = 0, zero_flags = 0;
+    size_t gacc = 0, lamx = 0, lamd = 0, ksbar = 0, out = 0, total = 0;
+    int blocks = 0;
+};
+
+static bool adj_layout(const lbib_ctx* c, int nsteps, AdjLayout& A)
+{
+    if (!c || c->L.inst.size() != 1 || nsteps < 1) return false;
+    const Inst& I = c->L.inst[0];
+    const size_t cells = (size_t)I.nxp * I.grid.ny;
+    const size_t nseg = I.nseg;
+    A.pops = round256(9 * cells * c->rb);
+    A.fib = round256(2 * cells * sizeof(long long));
+    A.flags = round256((size_t)I.grid.ny * nseg * sizeof(int));
+    A.nodes = round256((size_t)8 * c->L.max_nodes * c->rb);
+    A.ref = round256((size_t)2 * c->L.max_caps * sizeof(double));
+    A.slot = A.pops + A.fib + A.flags + A.nodes + A.ref;
+    size_t o = A.slot * (size_t)(nsteps + 1);
+    A.lam[0] = o;
+    o += A.pops;
+    A.lam[1] = o;
+    o += A.pops;
+    A.lfm = o;
+    o += round256(2 * cells * c->rb);
+    A.lft = o;
+    o += round256(2 * cells * c->rb);
+    A.lfm_flags = o;
+    o += A.flags;
+    A.zero_flags = o;
+    o += A.flags;
+    A.blocks = grid_blocks(I.grid.ny, I.nseg);
+    A.gacc = o;
+    o += round256((size_t)A.blocks * sizeof(double));
+    A.lamx = o;
+    o += round256((size_t)2 * c->L.max_nodes * sizeof(double));
+    A.lamd = o;
+    o += round256((size_t)2 * c->L.max_nodes * sizeof(double));
+    A.ksbar = o;
+    o += round256((size_t)c->L.max_nodes * sizeof(double));
+    A.out = o;
+    o += 256;
+    A.total = o;
+    return true;
+}
+
+extern "C" size_t lbib_adjoint_bytes(const lbib_ctx* c, int32_t nsteps)
+{
+    AdjLayout A;
+    return adj_layout(c, nsteps, A) ? A.total : 0;
+}
+
+template <typename T>
+static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int capid, char* ws,
+                             const AdjLayout& A, double* out_J, double* out_g, double* out_ks)
+{
+    const Inst& I = c->L.inst[0];
+    const GridArgs g = grid_args(I);
+    const hipStream_t st = c->stream;
+    const hipMemcpyKind d2d = hipMemcpyDeviceToDevice;
+    auto slot = [&](int n) { return ws + A.slot * (size_t)n; };
+    auto sP = [&](int n) { return reinterpret_cast<T*>(slot(n)); };
+    auto sF = [&](int n) { return reinterpret_cast<long long*>(slot(n) + A.pops); };
+    auto sFl = [&](int n) { return reinterpret_cast<int*>(slot(n) + A.pops + A.fib); };
+    auto sN = [&](int n) { return reinterpret_cast<T*>(slot(n) + A.pops + A.fib + A.flags); };
+    auto sR = [&](int n) {
+        return reinterpret_cast<double*>(slot(n) + A.pops + A.fib + A.flags + A.nodes);
+    };
+    T* lam[2] = {reinterpret_cast<T*>(ws + A.lam[0]), reinterpret_cast<T*>(ws + A.lam[1])};
+    T* lfm = reinterpret_cast<T*>(ws + A.lfm);
+    T* lft = reinterpret_cast<T*>(ws + A.lft);
+    int* lfm_flags = reinterpret_cast<int*>(ws + A.lfm_flags);
+    int* zero_flags = reinterpret_cast<int*>(ws + A.zero_flags);
+    double* gacc = reinterpret_cast<double*>(ws + A.gacc);
+    double* lamx = reinterpret_cast<double*>(ws + A.lamx);
+    double* lamd = reinterpret_cast<double*>(ws + A.lamd);
+    double* ksbar = reinterpret_cast<double*>(ws + A.ksbar);
+    double* out = reinterpret_cast<double*>(ws + A.out);
+    const size_t pop_bytes = 9 * (size_t)I.nxp * I.grid.ny * sizeof(T);
+
+    // LDS of the IB reverse kernel: FP64 node arrays, the rest holds the patch
+    int dev = 0;
+    hipDeviceProp_t prop;
+    HIPCHK(c, hipGetDevice(&dev));
+    HIPCHK(c, hipGetDeviceProperties(&prop, dev));
+    const size_t budget = (prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536) - 1024;
+    const size_t node_part = ib_adj_lds_bytes<T>(0, c->L.max_nv) + 16;
+    if (node_part + (size_t)1024 * 6 * sizeof(T) > budget)
+        return fail(c, LBIB_ECAPACITY, "capsules too large for the adjoint on-chip memory");
+    const int adj_patch = (int)std::min<size_t>((budget - node_part) / (6 * sizeof(T)),
+                                                (size_t)c->patch_cap);
+    const size_t adj_lds = ib_adj_lds_bytes<T>(adj_patch, c->L.max_nv);
+    HIPCHK(c, ib_adj_set_lds_limit<T>(adj_lds));
+
+    size_patches<T>(c);
+    HIPCHK(c, hipMemsetAsync(ws, 0, A.total, st));
+    HIPCHK(c, hipMemcpyAsync(sP(0), pops(c, 0), pop_bytes, d2d, st));
+    c->mode = mode;
+
+    // ---- forward run, taped
+    for (int n = 0; n < N; n++) {
+        IBArgs<T> a = ib_args<T>(c, n, n == 0 ? (PH_PRIME | PH_A) : (PH_B | PH_A));
+        a.pops = sP(n);
+        a.fib_prev = sF(n);
+        a.fib_next = sF(n + 1);
+        a.flags_next = sFl(n + 1);
+        a.tape_nodes = sN(n);
+        a.tape_ref = sR(n);
+        HIPCHK(c, launch_ib<T>(a, c->ncap, c->lds_use, st));
+        HIPCHK(c, launch_grid_step<T>(sP(n), sP(n + 1), sF(n + 1), sFl(n + 1), sF(n + 1),
+                                      zero_flags, g, st));
+    }
+    {
+        IBArgs<T> a = ib_args<T>(c, N, PH_B);
+        a.pops = sP(N);
+        a.fib_prev = sF(N);
+        a.fib_next = sF(N);
+        a.flags_next = sFl(N);
+        a.tape_nodes = sN(N);
+        a.tape_ref = sR(N);
+        HIPCHK(c, launch_ib<T>(a, c->ncap, c->lds_use, st));
+    }
+    // the context now stands at step N
+    HIPCHK(c, hipMemcpyAsync(pops(c, N), sP(N), pop_bytes, d2d, st));
+    HIPCHK(c, hipMemcpyAsync(fib(c, N + 1), sF(N), 2 * (size_t)I.nxp * I.grid.ny * sizeof(long long),
+                             d2d, st));
+    HIPCHK(c, hipMemcpyAsync(flags(c, N + 1), sFl(N), (size_t)I.grid.ny * I.nseg * sizeof(int),
+                             d2d, st));
+    c->steps = N;
+    int flags_fwd = 0;
+    HIPCHK(c, hipMemcpyAsync(&flags_fwd, status_word(c), sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (flags_fwd)
+        return fail(c, LBIB_ENUMERIC, "device status flags set in the forward run: " +
+                                          std::to_string(flags_fwd));
+
+    // ---- reverse sweep
+    const CapsuleDev* caps = reinterpret_cast<const CapsuleDev*>(bufp(c, LBIB_BUF_CAPS));
+    HIPCHK(c, launch_adj_seed<T>(sN(N), sR(N), caps, capid, c->L.max_nodes, objective, lamx, out,
+                                 st));
+    auto ib_adj = [&](int n, int doA, int doB, int prime) -> hipError_t {
+        IBAdjArgs<T> b;
+        b.pops = sP(n);
+        b.fib_prev = sF(n);
+        b.nodes_n = sN(n);
+        b.ref_n = sR(n);
+        b.nodes_p = doB ? sN(n - 1) : sN(n);
+        b.ref_p = doB ? sR(n - 1) : sR(n);
+        b.consts = reinterpret_cast<const T*>(bufp(c, LBIB_BUF_NODES));
+        b.caps = caps;
+        b.lft = lft;
+        b.lam_p = lam[n & 1];
+        b.lfm = lfm;
+        b.lfm_flags = lfm_flags;
+        b.lamx = lamx;
+        b.lamd = lamd;
+        b.ksbar = ksbar;
+        b.status = status_word(c);
+        b.stride = c->L.max_nodes;
+        b.doA = doA;
+        b.doB = doB;
+        b.prime = prime;
+        b.dynamic = mode == LBIB_DYNAMIC;
+        b.patch_cap = adj_patch;
+        b.max_nv = c->L.max_nv;
+        return launch_ib_adj<T>(b, c->ncap, adj_lds, st);
+    };
+    auto grid_adj_args = [&](int n) {
+        GridAdjArgs<T> ga;
+        ga.pops = sP(n);
+        ga.fib = sF(n + 1);
+        ga.flags = sFl(n + 1);
+        ga.lam_in = lam[(n + 1) & 1];
+        ga.lam_out = lam[n & 1];
+        ga.lfm = lfm;
+        ga.lfm_flags = lfm_flags;
+        ga.lft = lft;
+        ga.gacc = gacc;
+        return ga;
+    };
+    HIPCHK(c, ib_adj(N, 0, 1, 0));
+    for (int n = N - 1; n >= 0; n--) {
+        HIPCHK(c, launch_grid_adj<T>(grid_adj_args(n), g, st));
+        HIPCHK(c, ib_adj(n, 1, n >= 1, n == 0));
+    }
+    {
+        GridAdjArgs<T> ga = grid_adj_args(0);
+        ga.lam_in = lam[0];
+        HIPCHK(c, launch_init_adj<T>(ga, g, I.walls.init_profile, I.nu, st));
+    }
+    HIPCHK(c, launch_reduce_sum(gacc, A.blocks, out, st));
+    double host_out[2] = {0, 0};
+    HIPCHK(c, hipMemcpyAsync(host_out, out, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(out_ks, ksbar, (size_t)c->nodes_used * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+    int flags_rev = 0;
+    HIPCHK(c, hipMemcpyAsync(&flags_rev, status_word(c), sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (flags_rev)
+        return fail(c, LBIB_ENUMERIC, "device status flags set in the reverse sweep: " +
+                                          std::to_string(flags_rev));
+    *out_g = host_out[0];
+    *out_J = host_out[1];
+    return LBIB_OK;
+}
+
+extern "C" lbib_status lbib_adjoint(lbib_ctx* c, int32_t nsteps, lbib_mode mode,
+                                    int32_t objective, int32_t capsule, void* workspace,
+                                    size_t workspace_bytes, double* out_J, double* out_dJ_dg,
+                                    double* out_dJ_dks, int32_t n_ks)
+{
+    if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
+    if (!workspace || !out_J || !out_dJ_dg || !out_dJ_dks)
+        return fail(c, LBIB_EINVAL, "NULL argument");
+    if (c->L.inst.size() != 1) return fail(c, LBIB_EINVAL, "the adjoint needs a single lattice");
+    if (nsteps < 1) return fail(c, LBIB_EINVAL, "nsteps must be >= 1");
+    if (mode != LBIB_KINEMATIC && mode != LBIB_DYNAMIC) return fail(c, LBIB_EINVAL, "bad mode");
+    if (objective != LBIB_OBJ_TAYLOR && objective != LBIB_OBJ_CENTROID_Y)
+        return fail(c, LBIB_EINVAL, "unknown objective");
+    if (capsule < 0 || capsule >= c->ncap) return fail(c, LBIB_EINVAL, "bad capsule id");
+    if (c->steps != 0) return fail(c, LBIB_ESTATE, "the adjoint run starts from step 0");
+    if (c->mode >= 0 && c->mode != (int)mode)
+        return fail(c, LBIB_ESTATE, "the coupling mode is fixed after the first step");
+    for (double kb : c->cap_kb)
+        if (kb != 0.0) return fail(c, LBIB_EINVAL, "the adjoint needs k_b = 0 for every capsule");
+    if (n_ks < c->nodes_used) return fail(c, LBIB_EINVAL, "out_dJ_dks shorter than the node count");
+    AdjLayout A;
+    if (!adj_layout(c, nsteps, A)) return fail(c, LBIB_EINVAL, "invalid adjoint layout");
+    if (workspace_bytes < A.total) return fail(c, LBIB_EINVAL, "workspace too small");
+    char* ws = static_cast<char*>(workspace);
+    return c->rb == 4 ? adjoint_t<float>(c, nsteps, mode, objective, capsule, ws, A, out_J,
+                                         out_dJ_dg, out_dJ_dks)
+                      : adjoint_t<double>(c, nsteps, mode, objective, capsule, ws, A, out_J,
+                                          out_dJ_dg, out_dJ_dks);
 }
 
 // ---------------------------------------------------------- check, timing

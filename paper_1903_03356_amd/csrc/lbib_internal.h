@@ -94,6 +94,8 @@ struct IBArgs {
     int node_stride;
     int phase, dynamic;
     int patch_cap, max_nv;
+    T* tape_nodes;     // if not NULL: node state written here at the end ([8][node_stride])
+    double* tape_ref;  // and the reference points ([max_capsules][2])
 };
 
 // ---- launchers (lbib_kernels.hip) ----

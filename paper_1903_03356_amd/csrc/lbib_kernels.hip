@@ -12,100 +12,11 @@
 // capsule's fluid patch in LDS and runs the Lagrangian part of the step
 // (Secs. 2.2-2.4).  It spreads the force with 64-bit fixed-point atomics, so
 // the force field is bit-reproducible.
-#include "lbib_internal.h"
+#include "lbib_device.h"
 
 #include <math.h>
 
 namespace lbib {
-
-// ------------------------------------------------------------------ lattice
-// Eq. 3 velocities in the order rest, E, N, W, S, NE, NW, SW, SE.
-__device__ constexpr int kEx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-__device__ constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-
-template <typename T>
-__device__ __forceinline__ T lat_w(int i)
-{
-    return i == 0 ? T(4.0 / 9.0) : (i < 5 ? T(1.0 / 9.0) : T(1.0 / 36.0));
-}
-
-template <typename T>
-__device__ __forceinline__ T fix_to_real(long long v)
-{
-    return (T)v * (T)kFixInv;
-}
-
-// First-order weights 3 w_i of the equilibrium and forcing terms.  3 w_axis is
-// the rounded 1/3 and 3 w_diag is chosen as (1 - 2 * 3 w_axis) / 4, so that
-// 2 (3 w_axis) + 4 (3 w_diag) = 1 exactly in binary: the first moment of the
-// equilibrium then returns the momentum exactly instead of (1 + 7e-9) times it,
-// a bias that would otherwise add up coherently over a channel flow in FP32.
-template <typename T>
-struct FirstOrderW {
-    static constexpr T axis = T(1.0 / 3.0);
-    static constexpr T diag = (T(1) - T(2) * axis) / T(4);
-};
-
-// BGK relaxation with the forcing term for one direction, deviation form:
-// s* = s - omega (s - (f_eq - w)) + (1 - omega/2) w [3 (e - u).F + 9 (e.u)(e.F)]
-// with f_eq - w = w (rho - 1) + 3 w (e . m) + w rho (4.5 (e.u)^2 - 1.5 u^2),
-// m = rho u = sum f e + F/2 taken as is, so that rho * (m / rho) rounding does
-// not leak into the momentum.
-template <typename T>
-__device__ __forceinline__ T relax(T s, T w, T w3, T eu, T em, T eF, T drho, T rho, T usq15,
-                                   T uF, T om, T pre)
-{
-    const T seq = w * drho + w3 * em + w * rho * (T(4.5) * eu * eu - usq15);
-    const T src = pre * (w3 * eF + w * (T(9) * eu * eF - T(3) * uF));
-    return s - om * (s - seq) + src;
-}
-
-// Pulls the nine populations arriving at (x, y) from the post-collision field
-// and completes the wall rows with Zou-He (unknowns from the knowns, tangential
-// momentum target rho_w u_w - F_x / 2).
-template <typename T>
-__device__ __forceinline__ void pull(const T* __restrict__ src, int x, int y, const GridArgs& g,
-                                     T Fx, T s[9])
-{
-    const size_t plane = (size_t)g.ny * g.nxp;
-    const int xm = x == 0 ? g.nx - 1 : x - 1;
-    const int xp = x == g.nx - 1 ? 0 : x + 1;
-    int ym, yp;
-    if (g.periodic_y) {
-        ym = y == 0 ? g.ny - 1 : y - 1;
-        yp = y == g.ny - 1 ? 0 : y + 1;
-    } else {  // clamped: the out-of-domain slots are replaced by Zou-He below
-        ym = y == 0 ? 0 : y - 1;
-        yp = y == g.ny - 1 ? y : y + 1;
-    }
-    const size_t r0 = (size_t)y * g.nxp, rm = (size_t)ym * g.nxp, rp = (size_t)yp * g.nxp;
-    s[0] = src[r0 + x];
-    s[1] = src[plane + r0 + xm];
-    s[2] = src[2 * plane + rm + x];
-    s[3] = src[3 * plane + r0 + xp];
-    s[4] = src[4 * plane + rp + x];
-    s[5] = src[5 * plane + rm + xm];
-    s[6] = src[6 * plane + rm + xp];
-    s[7] = src[7 * plane + rp + xp];
-    s[8] = src[8 * plane + rp + xm];
-    if (!g.periodic_y) {
-        if (y == 0) {
-            const T rw = T(1) + s[0] + s[1] + s[3] + T(2) * (s[4] + s[7] + s[8]);
-            const T mx = rw * (T)g.u_bot - T(0.5) * Fx;
-            const T d13 = s[1] - s[3];
-            s[2] = s[4];
-            s[5] = s[7] - T(0.5) * d13 + T(0.5) * mx;
-            s[6] = s[8] + T(0.5) * d13 - T(0.5) * mx;
-        } else if (y == g.ny - 1) {
-            const T rw = T(1) + s[0] + s[1] + s[3] + T(2) * (s[2] + s[5] + s[6]);
-            const T mx = rw * (T)g.u_top - T(0.5) * Fx;
-            const T d13 = s[1] - s[3];
-            s[4] = s[2];
-            s[7] = s[5] + T(0.5) * d13 - T(0.5) * mx;
-            s[8] = s[6] - T(0.5) * d13 + T(0.5) * mx;
-        }
-    }
-}
 
 // ------------------------------------------------------------ grid kernel
 // One lattice node: pull, walls, force-corrected moments, BGK + forcing,
@@ -326,57 +237,6 @@ __device__ __forceinline__ void comp_add(T& hi, T& lo, T d)
     lo = e2;
 }
 
-// Deterministic block reductions over the kIBThreads / 64 wavefronts of the
-// IB kernel: butterfly within each wave, then the wave partials in order.
-constexpr int kIBWaves = kIBThreads / 64;
-
-template <int N>
-__device__ __forceinline__ void block_sum(double (&v)[N], double (*red)[8])
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < N; k++)
-        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < N; k++) red[wave][k] = v[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < N; k++) {
-        double acc = red[0][k];
-        for (int w = 1; w < kIBWaves; w++) acc += red[w][k];
-        v[k] = acc;
-    }
-    __syncthreads();
-}
-
-__device__ __forceinline__ void block_minmax(float (&mn)[2], float (&mx)[2], double (*red)[8])
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int k = 0; k < 2; k++)
-        for (int o = 32; o > 0; o >>= 1) {
-            mn[k] = fminf(mn[k], __shfl_xor(mn[k], o));
-            mx[k] = fmaxf(mx[k], __shfl_xor(mx[k], o));
-        }
-    if (lane == 0) {
-        red[wave][0] = mn[0];
-        red[wave][1] = mn[1];
-        red[wave][2] = mx[0];
-        red[wave][3] = mx[1];
-    }
-    __syncthreads();
-    for (int k = 0; k < 2; k++) {
-        float a = (float)red[0][k], b = (float)red[0][2 + k];
-        for (int w = 1; w < kIBWaves; w++) {
-            a = fminf(a, (float)red[w][k]);
-            b = fmaxf(b, (float)red[w][2 + k]);
-        }
-        mn[k] = a;
-        mx[k] = b;
-    }
-    __syncthreads();
-}
-
 // MLS shape functions of Eq. 9 at p = (px, py), given relative to an integer
 // origin.  Support: the 3x3 nodes around floor(p + 1/2).  Weight
 // exp(-(|x_k - p| / (r_w alpha))^2) with r_w = 2.6, alpha = 0.3.  Linear basis
@@ -425,25 +285,6 @@ __device__ __forceinline__ void mls(T px, T py, int& cx, int& cy, T* phi, T* gx,
             gy[k] = (T)(W * (i02 + i12 * X + i22 * Y));
         }
     }
-}
-
-// Moments of the capsule's fluid patch, staged in LDS: density deviation
-// rho - 1 and the force-corrected velocity.  Cells on a wall row hold NaN
-// and raise ST_WALL if a support touches them.
-template <typename T>
-struct Patch {
-    T* drho;
-    T* ux;
-    T* uy;
-    int ox, oy, W, H;  // origin relative to the capsule reference point, size
-};
-
-template <typename T>
-__device__ __forceinline__ bool patch_index(const Patch<T>& P, int cx, int cy, int k, int& idx)
-{
-    const int lx = cx + k % 3 - 1 - P.ox, ly = cy + k / 3 - 1 - P.oy;
-    idx = ly * P.W + lx;
-    return lx >= 0 && lx < P.W && ly >= 0 && ly < P.H;
 }
 
 // Eq. 8 interpolation of the velocity at p.
@@ -797,37 +638,6 @@ __device__ void diagnostics(const IBArgs<T>& a, const CapsuleDev& cap, int c, do
     }
 }
 
-// Moments of one patch cell from the pulled populations f^n and the force
-// F^{n-1} of the last collision (Eqs. 6-7): rho - 1 and the force-corrected
-// velocity.  Cells on a wall row are marked NaN.
-template <typename T>
-__device__ __forceinline__ void stage_cell(const IBArgs<T>& a, const GridArgs& g, const Patch<T>& P,
-                                           long long refx, long long refy, T gxf, int i)
-{
-    const int lx = i % P.W, ly = i / P.W;
-    long long wy = refy + P.oy + ly;
-    if (g.periodic_y) wy = ((wy % g.ny) + g.ny) % g.ny;
-    else if (wy < 1 || wy > g.ny - 2) {
-        P.drho[i] = T(NAN);
-        P.ux[i] = P.uy[i] = T(0);
-        return;
-    }
-    long long wx = refx + P.ox + lx;
-    wx = ((wx % g.nx) + g.nx) % g.nx;
-    T s[9];
-    pull(a.pops, (int)wx, (int)wy, g, gxf, s);
-    const size_t cell = (size_t)wy * g.nxp + (size_t)wx;
-    const T Fx = gxf + fix_to_real<T>(a.fib_prev[2 * cell]);
-    const T Fy = fix_to_real<T>(a.fib_prev[2 * cell + 1]);
-    const T drho = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])) + s[8];
-    const T jx = (s[1] - s[3]) + (s[5] - s[6]) + (s[8] - s[7]);
-    const T jy = (s[2] - s[4]) + (s[5] + s[6]) - (s[7] + s[8]);
-    const T irho = T(1) / (T(1) + drho);
-    P.drho[i] = drho;
-    P.ux[i] = (jx + T(0.5) * Fx) * irho;
-    P.uy[i] = (jy + T(0.5) * Fy) * irho;
-}
-
 // One block per capsule.  Phases (bit set):
 //   PH_PRIME  start-up of a capsule not yet started: u_v^0 = U(x^0), d^0 = U(x^0)
 //   PH_B      node update closing step n-1 from the fields after its collision:
@@ -1089,6 +899,24 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
         spread_cached(a, g, S, nv, refx, refy, st);
     }
     if (prime && tid == 0) a.caps[c].primed = 1;
+    // trajectory tape (reverse sweeps): the node state of this time level
+    if (a.tape_nodes) {
+        T* TN = a.tape_nodes;
+        for (int v = tid; v < nv; v += nt) {
+            TN[NF_HX * NS + off + v] = S.px[v];
+            TN[NF_HY * NS + off + v] = S.py[v];
+            TN[NF_LX * NS + off + v] = S.qx[v];
+            TN[NF_LY * NS + off + v] = S.qy[v];
+            TN[NF_DX * NS + off + v] = S.dx[v];
+            TN[NF_DY * NS + off + v] = S.dy[v];
+            TN[NF_UX * NS + off + v] = S.ux[v];
+            TN[NF_UY * NS + off + v] = S.uy[v];
+        }
+        if (tid == 0) {
+            a.tape_ref[2 * c] = cap.ref_x;
+            a.tape_ref[2 * c + 1] = cap.ref_y;
+        }
+    }
     if (st) atomicOr(a.status, st);
 }
 

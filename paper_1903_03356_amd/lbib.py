@@ -34,7 +34,8 @@ EXPORTS = ["lbib_required_bytes", "lbib_create", "lbib_add_capsule", "lbib_step"
            "lbib_get_state", "lbib_set_state", "lbib_check", "lbib_set_timing",
            "lbib_get_timing", "lbib_steps_done", "lbib_last_error", "lbib_destroy",
            "lbib_required_bytes_batch", "lbib_create_batch", "lbib_add_capsule_to",
-           "lbib_num_lattices"]
+           "lbib_num_lattices", "lbib_adjoint_bytes", "lbib_adjoint"]
+OBJ_TAYLOR, OBJ_CENTROID_Y = 0, 1
 
 
 class lbib_grid(C.Structure):
@@ -106,6 +107,11 @@ def load() -> C.CDLL:
                                       i32, C.c_double, C.c_double, C.c_double, C.POINTER(i32)]
     L.lbib_num_lattices.restype = i32
     L.lbib_num_lattices.argtypes = [vp]
+    L.lbib_adjoint_bytes.restype = C.c_size_t
+    L.lbib_adjoint_bytes.argtypes = [vp, i32]
+    dp = C.POINTER(C.c_double)
+    L.lbib_adjoint.restype = i32
+    L.lbib_adjoint.argtypes = [vp, i32, i32, i32, i32, vp, C.c_size_t, dp, dp, dp, i32]
     _lib = L
     return L
 
@@ -269,6 +275,34 @@ class Sim:
             _check(load().lbib_get_timing(self.h, out), self.h)
         return {"grid_ms": out[0], "grid_launches": out[1], "ib_ms": out[2],
                 "ib_launches": out[3]}
+
+    def adjoint_bytes(self, nsteps: int) -> int:
+        return int(load().lbib_adjoint_bytes(self.h, int(nsteps)))
+
+    def adjoint(self, nsteps: int, objective: int = OBJ_TAYLOR, capsule: int = 0,
+                mode: Optional[str] = None, workspace=None) -> Dict[str, Any]:
+        """lbib_adjoint: J and dJ/dg, dJ/dk_s (per element, node order) of an
+        nsteps run from step 0.  Allocates the trajectory workspace unless given."""
+        mode = mode or self.cfg.get("mode", "dynamic")
+        m = DYNAMIC if mode == "dynamic" else KINEMATIC
+        nb = self.adjoint_bytes(nsteps)
+        if nb == 0:
+            raise LbibError(EINVAL, "no adjoint layout for this context")
+        with self.torch.cuda.device(self.device):
+            ws = workspace if workspace is not None else self.torch.empty(
+                nb, dtype=self.torch.uint8, device=self.device)
+            nks = max(1, sum(self.nv))
+            ks = np.zeros(nks, np.float64)
+            J, g = C.c_double(), C.c_double()
+            _check(load().lbib_adjoint(self.h, int(nsteps), m, int(objective), int(capsule),
+                                       C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(J),
+                                       C.byref(g), ks.ctypes.data_as(C.POINTER(C.c_double)),
+                                       nks), self.h)
+        caps, o = [], 0
+        for n in self.nv:
+            caps.append(ks[o:o + n].copy())
+            o += n
+        return {"J": J.value, "dJ_dg": g.value, "dJ_dks": caps}
 
     @property
     def steps_done(self) -> int:

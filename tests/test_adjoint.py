@@ -1,0 +1,157 @@
+"""Reverse-mode gradients (lbib_adjoint) against the FP64 oracle.
+
+The oracle of a gradient is the definition of the derivative: the central
+difference (J(p + h) - J(p - h)) / 2h of the oracle's objective after the same
+number of steps.  The CPU test pins that difference (second-order convergence
+in h, so h is in the asymptotic range and the objective is smooth there).
+The GPU tests compare the FP64 adjoint with it (relative 1e-5 of the largest
+component, both schemes, both objectives, k_s of single elements and the body
+force g), the FP32 adjoint with the FP64 adjoint, and check that the taped
+forward run leaves the context exactly where lbib_step would."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1903_03356_amd import lbib
+from paper_1903_03356_amd import workloads as wl
+from tests.parity import log, oracle_threads
+
+
+def ellipse_channel(real_bytes=8, mode="dynamic", nx=64, ny=40, n_nodes=32, ca=0.02,
+                    tau=0.8, a=6.0, b=4.5, centre=(24.0, 17.0), ratio=1.0):
+    """Elliptical capsule (D = (a - b)/(a + b) at rest, so D stays away from
+    its non-smooth zero) in a body-force Poiseuille channel."""
+    ang = 2.0 * math.pi * (np.arange(n_nodes) + 0.5) / n_nodes
+    nodes = np.stack([centre[0] + a * np.cos(ang), centre[1] + b * np.sin(ang)], axis=1)
+    ks = wl.ks_from_ca(tau, 0.02, ca)
+    cfg = wl._base("ellipse", nx, ny, tau, real_bytes, mode, 0,
+                   body_force_x=wl.poiseuille_body_force(tau, ny, 0.02),
+                   init_profile=wl.INIT_POISEUILLE)
+    cfg["capsules"] = [wl.capsule(nodes, ks, 0.0, 1.0, ratio)]
+    return cfg
+
+
+def test_central_difference_is_second_order(orc):
+    """Pins the oracle's gradient.  For an element's k_s the differences with
+    h, h/2, h/4 converge at second order (the gap shrinks about 4x per
+    halving).  The MLS support (floor(x + 1/2)) makes the objective piecewise
+    smooth with small jumps where a node crosses a half-integer, so a
+    difference is only meaningful with h below the distance to the nearest
+    switch: for the body force (which moves every node) h = 1e-4 and 1e-5
+    relative give the same value to 1e-6, while 1e-2 straddles a switch."""
+    oracle_threads(orc)
+    cfg = ellipse_channel(mode="dynamic", nx=48, ny=32, n_nodes=24, centre=(20.0, 13.0))
+    steps = 30
+    ks0 = cfg["capsules"][0]["ks"]
+    h = 0.2 * ks0
+    d1 = orc.central_difference(cfg, steps, ("ks", 0, 3), h, "D")
+    d2 = orc.central_difference(cfg, steps, ("ks", 0, 3), h / 2, "D")
+    d4 = orc.central_difference(cfg, steps, ("ks", 0, 3), h / 4, "D")
+    e1, e2 = abs(d1 - d2), abs(d2 - d4)
+    assert d1 != 0.0 and 0.15 * e1 < e2 < 0.35 * e1, (d1, d2, d4)
+    g0 = cfg["body_force_x"]
+    a = orc.central_difference(cfg, steps, "g", 1e-4 * g0, "D")
+    b = orc.central_difference(cfg, steps, "g", 1e-5 * g0, "D")
+    far = orc.central_difference(cfg, steps, "g", 1e-2 * g0, "D")
+    assert abs(a - b) < 1e-6 * abs(a), (a, b)
+    assert abs(far - a) > 1e-3 * abs(a)  # a support switch inside [g - h, g + h]
+
+
+def _fd(cfg, steps, param, h, which):
+    from oracle import oracle as orc
+    oracle_threads(orc)
+    return orc.central_difference(cfg, steps, param, h, which)
+
+
+def _check_against_fd(mode, which, steps, elements=(0, 7, 19)):
+    cfg = ellipse_channel(real_bytes=8, mode=mode)
+    sim = lbib.Sim(cfg)
+    r = sim.adjoint(steps, lbib.OBJ_TAYLOR if which == "D" else lbib.OBJ_CENTROID_Y, 0, mode)
+    from oracle import oracle as orc
+    J_orc = orc.objective(cfg, steps, which)
+    assert abs(r["J"] - J_orc) < 1e-9 * max(1.0, abs(J_orc)), (r["J"], J_orc)
+    ks0 = cfg["capsules"][0]["ks"]
+    grads, fds = [], []
+    for l in elements:
+        grads.append(r["dJ_dks"][0][l])
+        fds.append(_fd(cfg, steps, ("ks", 0, l), 1e-4 * ks0, which))
+    gg = r["dJ_dg"]
+    # h = 1e-5 g keeps MLS support switches out of [g - h, g + h] (at 1e-4 g the
+    # Dynamic run already crosses one); the difference then carries a rounding
+    # error of up to 2 eps |J| / (2 h), which the g tolerance includes
+    hg = 1e-5 * cfg["body_force_x"]
+    fg = _fd(cfg, steps, "g", hg, which)
+    noise_g = 4.0 * 2.0 * 2.2e-16 * max(1.0, abs(r["J"])) / (2.0 * hg)
+    log(f"{mode} {which} steps={steps}: ks adjoint {grads} fd {fds}; g adjoint {gg} fd {fg}")
+    scale = max(abs(v) for v in fds)
+    for a, f in zip(grads, fds):
+        assert abs(a - f) <= 1e-5 * scale + 1e-12, (a, f)
+    assert abs(gg - fg) <= 1e-5 * abs(fg) + noise_g, (gg, fg, noise_g)
+    return r
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("which", ["D", "yc"])
+def test_adjoint_kinematic_fp64_vs_fd(which):
+    _check_against_fd("kinematic", which, 60)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("which", ["D", "yc"])
+def test_adjoint_dynamic_fp64_vs_fd(which):
+    _check_against_fd("dynamic", which, 60)
+
+
+@pytest.mark.gpu
+def test_adjoint_fp32_vs_fp64():
+    """The FP32 adjoint of the same run, against the FP64 adjoint."""
+    r8 = lbib.Sim(ellipse_channel(real_bytes=8)).adjoint(100, lbib.OBJ_TAYLOR)
+    r4 = lbib.Sim(ellipse_channel(real_bytes=4)).adjoint(100, lbib.OBJ_TAYLOR)
+    k8, k4 = r8["dJ_dks"][0], r4["dJ_dks"][0]
+    err = np.abs(k4 - k8).max() / np.abs(k8).max()
+    log(f"fp32 vs fp64 adjoint: ks rel {err:.2e}, g {r4['dJ_dg']} vs {r8['dJ_dg']}")
+    assert err < 1e-3
+    assert abs(r4["dJ_dg"] - r8["dJ_dg"]) < 1e-3 * abs(r8["dJ_dg"])
+
+
+@pytest.mark.gpu
+def test_adjoint_leaves_the_forward_state():
+    """After lbib_adjoint(N) the context holds exactly the state lbib_step(N)
+    produces (the taped forward run is the same computation)."""
+    cfg = ellipse_channel(real_bytes=4)
+    a = lbib.Sim(cfg)
+    b = lbib.Sim(cfg)
+    a.adjoint(40)
+    b.step(40)
+    assert a.steps_done == 40
+    assert np.array_equal(a.pops_dev(), b.pops_dev())
+    assert np.array_equal(a.force(), b.force())
+    for x, y in zip(a.capsule(0), b.capsule(0)):
+        assert np.array_equal(x, y)
+    a.step(5)
+    b.step(5)
+    assert np.array_equal(a.pops_dev(), b.pops_dev())
+
+
+@pytest.mark.gpu
+def test_adjoint_argument_checks():
+    cfg = ellipse_channel(real_bytes=4)
+    s = lbib.Sim(cfg)
+    for kw, code in (({"objective": 5}, lbib.EINVAL), ({"capsule": 1}, lbib.EINVAL)):
+        with pytest.raises(lbib.LbibError) as e:
+            s.adjoint(10, **kw)
+        assert e.value.code == code
+    s.step(1)
+    with pytest.raises(lbib.LbibError) as e:
+        s.adjoint(10)
+    assert e.value.code == lbib.ESTATE
+    bent = ellipse_channel(real_bytes=4)
+    bent["capsules"][0]["kb"] = 0.01
+    with pytest.raises(lbib.LbibError) as e:
+        lbib.Sim(bent).adjoint(10)
+    assert e.value.code == lbib.EINVAL
+    bat = lbib.Batch([cfg, cfg])
+    with pytest.raises(lbib.LbibError) as e:
+        bat.adjoint(10)
+    assert e.value.code == lbib.EINVAL
