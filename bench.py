@@ -15,6 +15,8 @@ Prints one JSON line:
             recorded around every launch of the timed region, against 8 TB/s
   cpu_baseline  the FP64 oracle on the host cores, a bounded sample of steps of
             the same workload
+  adjoint   side measurement: time of one gradient (lbib_adjoint: taped forward
+            run + reverse sweep) over the plain forward run, 512 x 128 channel
   batched   side measurement: 256 independent channels (seeded ensemble, about
             8.0 M cells, 388 capsules) stepped as one batch context, against one
             context per simulation stepped in turn; speedup = loop time / batch
@@ -151,6 +153,42 @@ def bench_ensemble(steps: int, warmup: int, loop_steps: int):
     }
 
 
+def bench_adjoint(mode: str, steps: int):
+    """Cost of one gradient (taped forward run + reverse sweep, lbib_adjoint)
+    against the plain forward run of the same steps, on the 512 x 128 channel
+    with one circular capsule (R = 10, 96 nodes at 0.4 H, Ca = 1e-2, FP32)."""
+    import torch
+    from paper_1903_03356_amd import lbib
+    from paper_1903_03356_amd import workloads as wl
+
+    cfg = wl.adjoint_channel()
+    cfg["mode"] = mode
+    warm = lbib.Sim(cfg)
+    warm.adjoint(10, lbib.OBJ_TAYLOR, 0, mode)  # first-call set-up outside the timing
+    del warm
+    fwd = lbib.Sim(cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fwd.step(steps, mode)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    if fwd.check():
+        raise RuntimeError("device flags in the forward run")
+    del fwd
+    adj = lbib.Sim(cfg)
+    ws = torch.empty(adj.adjoint_bytes(steps), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = adj.adjoint(steps, lbib.OBJ_TAYLOR, 0, mode, workspace=ws)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    del adj, ws
+    return {"workload": f"512x128 channel, 1 capsule (96 nodes), Ca 1e-2, FP32, {mode}",
+            "mode": mode, "steps": steps, "forward_ms": round(t_fwd * 1e3, 2),
+            "gradient_ms": round(t_adj * 1e3, 2), "adjoint_over_forward": round(t_adj / t_fwd, 2),
+            "J": r["J"], "dJ_dg": r["dJ_dg"]}
+
+
 def cpu_baseline(cfg, budget_s: float = 20.0):
     from oracle import oracle as orc
 
@@ -183,6 +221,8 @@ def main() -> int:
                          "(profiling runs)")
     ap.add_argument("--only-ensemble", action="store_true",
                     help="only the batched ensemble against the per-simulation loop")
+    ap.add_argument("--only-adjoint", action="store_true",
+                    help="only the gradient cost against the forward run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 20 device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -208,6 +248,10 @@ def main() -> int:
     if args.only_ensemble:
         ens = bench_ensemble(min(args.steps, 400), args.warmup, 20)
         print(json.dumps({"batched": ens}), flush=True)
+        return 0
+    if args.only_adjoint:
+        adj = [bench_adjoint("dynamic", 500), bench_adjoint("kinematic", 5000)]
+        print(json.dumps({"adjoint": adj}), flush=True)
         return 0
     cfg = wl.fused_bench(seed=0, n=args.n, steps=args.steps)
     nodes = sum(len(c["nodes"]) for c in cfg["capsules"])
@@ -240,6 +284,11 @@ def main() -> int:
             f"per-simulation loop {ens['loop_ms_per_step']:.3f} ms/step, "
             f"speedup {ens['speedup']:.1f}x")
         side["batched"] = ens
+        adj = [bench_adjoint("dynamic", 500), bench_adjoint("kinematic", 5000)]
+        for a in adj:
+            log(f"adjoint ({a['mode']}, {a['steps']} steps): forward {a['forward_ms']:.1f} ms, "
+                f"gradient {a['gradient_ms']:.1f} ms, ratio {a['adjoint_over_forward']:.2f}")
+        side["adjoint"] = adj
 
     sha = kernel_sha()
     traffic = traffic_from_profile(sha)
