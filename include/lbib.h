@@ -61,7 +61,8 @@ enum lbib_device_flags {
     LBIB_FLAG_NONFINITE = 2,  /* a node position or staged density is NaN/Inf */
     LBIB_FLAG_PATCH = 4,      /* a capsule's fluid patch exceeded the on-chip capacity */
     LBIB_FLAG_OVERFLOW = 8,   /* a spread force left the fixed-point range (|f| >= 2^14) */
-    LBIB_FLAG_MOVE = 16       /* a node moved one lattice unit or more in one step */
+    LBIB_FLAG_MOVE = 16,      /* a node moved one lattice unit or more in one step */
+    LBIB_FLAG_NEAR = 32       /* overlapped schedule: an IB force outside the near regions */
 };
 
 typedef struct {
@@ -165,6 +166,12 @@ lbib_status lbib_add_capsule(lbib_ctx* ctx, const double* nodes_xy, int32_t n, c
  * with the forcing of this step) and one fused collide-stream kernel launch.
  * The call ends with the node update of the last step, so between calls the
  * state is the complete state at time n.
+ * With lbib_set_overlap(ctx, 1), a single lattice with 1..64 capsules splits
+ * the collide-stream pass: a near kernel covers each capsule's near region
+ * (the bounding box of its nodes at n-1 and n plus 5 cells), a far kernel the
+ * rest on a second stream of the library's own, beside the next IB launch.
+ * The results are bit-identical to the single pass; the call still returns
+ * with all work ordered on the bound stream.
  * Errors: EINVAL (nsteps < 0, bad mode), ESTATE (mode differs from the first
  * step's), EDEVICE.  Device-side problems raise status flags (lbib_check). */
 lbib_status lbib_step(lbib_ctx* ctx, int32_t nsteps, lbib_mode mode);
@@ -189,12 +196,18 @@ lbib_status lbib_set_state(lbib_ctx* ctx, int32_t what, int32_t capsule_id, cons
  * is not NULL.  The word is not cleared. */
 lbib_status lbib_check(lbib_ctx* ctx, int32_t* flags_out);
 
-/* Timing of the kernels with HIP events on the bound stream.  enable = 1 starts
- * recording an event before and after every kernel of lbib_step, enable = 0
- * stops.  lbib_get_timing waits for the stream and returns out[6] = {grid kernel
- * total ms, grid launches, IB kernel total ms, IB launches, 0, 0}.  It then
- * resets the counters. */
+/* Timing of the kernels with HIP events on the stream each runs on.  enable = 1
+ * starts recording an event before and after every kernel of lbib_step,
+ * enable = 0 stops.  lbib_get_timing waits for the stream and returns
+ * out[6] = {grid (or far) kernel total ms, its launches, IB kernel total ms,
+ * IB launches, near kernel total ms, near launches}.  It then resets the
+ * counters. */
 lbib_status lbib_set_timing(lbib_ctx* ctx, int32_t enable);
+
+/* enable = 1 selects the overlapped near / far schedule of lbib_step (see
+ * there); enable = 0, the default, keeps the single-pass schedule on one
+ * stream. */
+lbib_status lbib_set_overlap(lbib_ctx* ctx, int32_t enable);
 lbib_status lbib_get_timing(lbib_ctx* ctx, double* out6);
 
 /* Number of completed steps n, or -1 for a NULL context. */

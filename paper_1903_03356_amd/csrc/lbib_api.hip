@@ -43,7 +43,7 @@ struct Layout {
     int max_caps = 0, max_nodes = 0, max_nv = 0;
     int grid_blocks = 0;
     size_t plane_max = 0;
-    size_t inst_table = 0, round_table = 0;  // byte offsets in BUF_CAPS
+    size_t inst_table = 0, round_table = 0, rect_table = 0, near_map = 0;  // offsets in BUF_CAPS
 };
 
 struct lbib_ctx {
@@ -66,6 +66,10 @@ struct lbib_ctx {
     std::vector<hipEvent_t> pool;
     std::vector<int> cap_off, cap_nv, cap_inst;  // host copy of the capsule table layout
     std::vector<double> cap_kb, cap_P0;
+    // overlapped schedule: far part of the grid step on a second stream (opt-in)
+    bool overlap = false;
+    hipStream_t s_far = nullptr;
+    hipEvent_t e_near = nullptr, e_far = nullptr;
 };
 
 // ----------------------------------------------------------------- helpers
@@ -108,6 +112,7 @@ static bool grid_ok(const lbib_grid* g)
 }
 
 constexpr int kMaxInstances = 1 << 16;
+constexpr int kMaxOverlapCapsules = 64;  // the far kernel tests every near region
 
 // Fills L from the lattices' sizes and capacities; false if any is invalid or
 // the totals leave the supported range.
@@ -148,6 +153,8 @@ static bool make_layout(const lbib_grid* grids, int n, Layout& L)
     L.grid_blocks = (int)blocks;
     L.inst_table = round256((size_t)L.max_caps * sizeof(CapsuleDev));
     L.round_table = L.inst_table + round256((size_t)n * sizeof(InstDev));
+    L.rect_table = L.round_table + round256((size_t)(L.grid_blocks / kNumXcd) * sizeof(int));
+    L.near_map = L.rect_table + round256((size_t)2 * L.max_caps * sizeof(NearRect));
     return true;
 }
 
@@ -165,7 +172,7 @@ static size_t layout_bytes(const Layout& L, int id)
     case LBIB_BUF_FLAGS: return round256(2 * L.flag_level * sizeof(int));
     case LBIB_BUF_NODES: return round256((size_t)NF_COUNT * L.max_nodes * L.rb);
     case LBIB_BUF_CAPS:
-        return L.round_table + round256((size_t)(L.grid_blocks / kNumXcd) * sizeof(int));
+        return L.near_map + round256((size_t)2 * L.flag_level * sizeof(int));
     case LBIB_BUF_DIAG: return round256(status_offset(L) + 64);
     case LBIB_BUF_STAGE: {
         size_t n = 3 * L.plane_max;
@@ -241,6 +248,22 @@ static const int* round_table(const lbib_ctx* c)
 {
     return reinterpret_cast<const int*>(bufp(c, LBIB_BUF_CAPS) + c->L.round_table);
 }
+
+static NearRect* rect_table(const lbib_ctx* c, long long parity)
+{
+    return reinterpret_cast<NearRect*>(bufp(c, LBIB_BUF_CAPS) + c->L.rect_table) +
+           (parity & 1) * c->L.max_caps;
+}
+
+// Near map of step n: (row, segment) -> stamp n + 1 where the step's near
+// regions lie (two parities, so IB(n+1) never writes the map far(n) reads).
+static int* near_map(const lbib_ctx* c, long long parity)
+{
+    return reinterpret_cast<int*>(bufp(c, LBIB_BUF_CAPS) + c->L.near_map) +
+           (parity & 1) * c->L.flag_level;
+}
+
+static int step_stamp(long long n) { return (int)((n + 1) & 0x7fffffff); }
 
 static hipEvent_t take_event(lbib_ctx* c)
 {
@@ -576,23 +599,27 @@ static IBArgs<T> ib_args(const lbib_ctx* c, long long n, int phase)
     a.max_nv = c->L.max_nv;
     a.tape_nodes = nullptr;
     a.tape_ref = nullptr;
+    a.rects = nullptr;
+    a.near_map = nullptr;
+    a.stamp = 0;
     return a;
 }
 
 template <typename T>
 static lbib_status launch_timed(lbib_ctx* c, int kind, hipError_t (*fn)(lbib_ctx*, void*),
-                                void* arg)
+                                void* arg, hipStream_t on = nullptr)
 {
+    const hipStream_t st = on ? on : c->stream;
     TimedLaunch t{kind, nullptr, nullptr};
     if (c->timing) {
         t.start = take_event(c);
         t.stop = take_event(c);
         if (!t.start || !t.stop) return fail(c, LBIB_EDEVICE, "hipEventCreate failed");
-        HIPCHK(c, hipEventRecord(t.start, c->stream));
+        HIPCHK(c, hipEventRecord(t.start, st));
     }
     HIPCHK(c, fn(c, arg));
     if (c->timing) {
-        HIPCHK(c, hipEventRecord(t.stop, c->stream));
+        HIPCHK(c, hipEventRecord(t.stop, st));
         c->timed.push_back(t);
     }
     return LBIB_OK;
@@ -602,13 +629,20 @@ template <typename T>
 struct IBLaunch {
     long long n;
     int phase;
+    bool rects;
 };
 
 template <typename T>
 static hipError_t do_ib(lbib_ctx* c, void* p)
 {
     const IBLaunch<T>* q = static_cast<const IBLaunch<T>*>(p);
-    return launch_ib<T>(ib_args<T>(c, q->n, q->phase), c->ncap, c->lds_use, c->stream);
+    IBArgs<T> a = ib_args<T>(c, q->n, q->phase);
+    if (q->rects) {
+        a.rects = rect_table(c, q->n);
+        a.near_map = near_map(c, q->n);
+        a.stamp = step_stamp(q->n);
+    }
+    return launch_ib<T>(a, c->ncap, c->lds_use, c->stream);
 }
 
 template <typename T>
@@ -628,13 +662,79 @@ static hipError_t do_grid(lbib_ctx* c, void* p)
 }
 
 template <typename T>
+static hipError_t do_far(lbib_ctx* c, void* p)
+{
+    const long long n = *static_cast<const long long*>(p);
+    const GridArgs g = grid_args(c->L.inst[0]);
+    return launch_grid_far<T>(static_cast<const T*>(pops(c, n)), static_cast<T*>(pops(c, n + 1)),
+                              flags(c, n), flags(c, n + 1), near_map(c, n), step_stamp(n),
+                              status_word(c), g, c->s_far);
+}
+
+template <typename T>
+static hipError_t do_near(lbib_ctx* c, void* p)
+{
+    const long long n = *static_cast<const long long*>(p);
+    const GridArgs g = grid_args(c->L.inst[0]);
+    return launch_grid_near<T>(static_cast<const T*>(pops(c, n)), static_cast<T*>(pops(c, n + 1)),
+                               fib(c, n), flags(c, n), fib(c, n + 1), flags(c, n + 1),
+                               rect_table(c, n), c->ncap, g, c->stream);
+}
+
+// Overlapped schedule of a single lattice with capsules.  Per step n:
+//   main stream: [IB(n)] -> wait far(n-1) -> near(n) -> IB(n+1) ...
+//   far stream:  wait near(n) -> far(n)
+// IB(n) writes the near regions R_n and stamps them into the near map.
+// near(n) computes R_n with the IB force; far(n) the rest with the body force
+// only.  IB(n+1), queued right behind near(n) on an otherwise idle device,
+// takes its compute units before far(n) floods them and then runs beside
+// far(n): it reads only populations near(n) wrote and force levels far(n)
+// never touches.  The call ends with the main stream waiting for the last far
+// part.
+template <typename T>
+static lbib_status step_overlap_t(lbib_ctx* c, int nsteps)
+{
+    if (!c->s_far) {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->s_far, hipStreamNonBlocking));
+        HIPCHK(c, hipEventCreateWithFlags(&c->e_near, hipEventDisableTiming));
+        HIPCHK(c, hipEventCreateWithFlags(&c->e_far, hipEventDisableTiming));
+    }
+    for (int k = 0; k < nsteps; k++) {
+        const long long n = c->steps + k;
+        if (k == 0) {
+            IBLaunch<T> q{n, n == 0 ? (PH_PRIME | PH_A) : PH_A, true};
+            lbib_status s = launch_timed<T>(c, 1, do_ib<T>, &q);
+            if (s != LBIB_OK) return s;
+        } else {
+            HIPCHK(c, hipStreamWaitEvent(c->stream, c->e_far, 0));  // far(n-1)
+        }
+        long long nn = n;
+        lbib_status s = launch_timed<T>(c, 2, do_near<T>, &nn);
+        if (s != LBIB_OK) return s;
+        HIPCHK(c, hipEventRecord(c->e_near, c->stream));  // near(n), after IB(n)
+        IBLaunch<T> q{n + 1, k + 1 < nsteps ? (PH_B | PH_A) : PH_B, k + 1 < nsteps};
+        s = launch_timed<T>(c, 1, do_ib<T>, &q);
+        if (s != LBIB_OK) return s;
+        HIPCHK(c, hipStreamWaitEvent(c->s_far, c->e_near, 0));
+        s = launch_timed<T>(c, 0, do_far<T>, &nn, c->s_far);
+        if (s != LBIB_OK) return s;
+        HIPCHK(c, hipEventRecord(c->e_far, c->s_far));
+    }
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->e_far, 0));
+    c->steps += nsteps;
+    return LBIB_OK;
+}
+
+template <typename T>
 static lbib_status step_t(lbib_ctx* c, int nsteps)
 {
     size_patches<T>(c);
+    if (c->overlap && c->L.inst.size() == 1 && c->ncap > 0 && c->ncap <= kMaxOverlapCapsules)
+        return step_overlap_t<T>(c, nsteps);
     for (int k = 0; k < nsteps; k++) {
         const long long n = c->steps + k;
         if (c->ncap > 0) {
-            IBLaunch<T> q{n, k == 0 ? (n == 0 ? (PH_PRIME | PH_A) : PH_A) : (PH_B | PH_A)};
+            IBLaunch<T> q{n, k == 0 ? (n == 0 ? (PH_PRIME | PH_A) : PH_A) : (PH_B | PH_A), false};
             lbib_status s = launch_timed<T>(c, 1, do_ib<T>, &q);
             if (s != LBIB_OK) return s;
         }
@@ -643,7 +743,7 @@ static lbib_status step_t(lbib_ctx* c, int nsteps)
         if (s != LBIB_OK) return s;
     }
     if (c->ncap > 0) {
-        IBLaunch<T> q{c->steps + nsteps, PH_B};
+        IBLaunch<T> q{c->steps + nsteps, PH_B, false};
         lbib_status s = launch_timed<T>(c, 1, do_ib<T>, &q);
         if (s != LBIB_OK) return s;
     }
@@ -1071,6 +1171,13 @@ extern "C" lbib_status lbib_check(lbib_ctx* c, int32_t* flags_out)
     return LBIB_OK;
 }
 
+extern "C" lbib_status lbib_set_overlap(lbib_ctx* c, int32_t enable)
+{
+    if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
+    c->overlap = enable != 0;
+    return LBIB_OK;
+}
+
 extern "C" lbib_status lbib_set_timing(lbib_ctx* c, int32_t enable)
 {
     if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
@@ -1083,7 +1190,7 @@ extern "C" lbib_status lbib_get_timing(lbib_ctx* c, double* out)
     if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
     if (!out) return fail(c, LBIB_EINVAL, "out is NULL");
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    double t[2] = {0, 0}, cnt[2] = {0, 0};
+    double t[3] = {0, 0, 0}, cnt[3] = {0, 0, 0};
     for (const TimedLaunch& tl : c->timed) {
         float ms = 0;
         HIPCHK(c, hipEventElapsedTime(&ms, tl.start, tl.stop));
@@ -1097,7 +1204,8 @@ extern "C" lbib_status lbib_get_timing(lbib_ctx* c, double* out)
     out[1] = cnt[0];
     out[2] = t[1];
     out[3] = cnt[1];
-    out[4] = out[5] = 0;
+    out[4] = t[2];
+    out[5] = cnt[2];
     return LBIB_OK;
 }
 
@@ -1117,5 +1225,11 @@ extern "C" void lbib_destroy(lbib_ctx* c)
         (void)hipEventDestroy(tl.stop);
     }
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    if (c->s_far) {
+        (void)hipStreamSynchronize(c->s_far);
+        (void)hipStreamDestroy(c->s_far);
+        (void)hipEventDestroy(c->e_near);
+        (void)hipEventDestroy(c->e_far);
+    }
     delete c;
 }

@@ -69,7 +69,16 @@ static_assert(sizeof(CapsuleDev) == 144, "CapsuleDev layout");
 
 constexpr int kDiagStride = 16;  // doubles per capsule in BUF_DIAG
 
-enum StatusBits { ST_WALL = 1, ST_NONFINITE = 2, ST_PATCH = 4, ST_OVERFLOW = 8, ST_MOVE = 16 };
+enum StatusBits {
+    ST_WALL = 1, ST_NONFINITE = 2, ST_PATCH = 4, ST_OVERFLOW = 8, ST_MOVE = 16, ST_NEAR = 32
+};
+
+// Near region of one capsule for the overlapped grid step: world cells,
+// inclusive, x unwrapped (taken modulo nx), y clamped to the lattice or
+// wrapped when y is periodic.
+struct NearRect {
+    int x0, y0, x1, y1;
+};
 
 enum Phase { PH_PRIME = 1, PH_B = 2, PH_A = 4, PH_DIAG = 8 };
 
@@ -96,6 +105,9 @@ struct IBArgs {
     int patch_cap, max_nv;
     T* tape_nodes;     // if not NULL: node state written here at the end ([8][node_stride])
     double* tape_ref;  // and the reference points ([max_capsules][2])
+    NearRect* rects;   // if not NULL: near region of this step, one per capsule,
+    int* near_map;     // its (row, segment) units stamped with `stamp` ([ny][nseg])
+    int stamp;
 };
 
 // ---- launchers (lbib_kernels.hip) ----
@@ -110,6 +122,14 @@ hipError_t launch_grid_step_batch(const T* src, T* dst, const long long* fib_now
                                   const int* flags_now, long long* fib_old, int* flags_old,
                                   const InstDev* inst, const int* round_inst, int blocks,
                                   hipStream_t s);
+template <typename T>
+hipError_t launch_grid_far(const T* src, T* dst, const int* flags_now, const int* flags_old,
+                           const int* near_map, int stamp, int* status, const GridArgs& g,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_grid_near(const T* src, T* dst, const long long* fib_now, const int* flags_now,
+                            long long* fib_old, int* flags_old, const NearRect* rects, int ncap,
+                            const GridArgs& g, hipStream_t s);
 // Blocks of the grid kernel for one lattice (a multiple of kNumXcd).
 int grid_blocks(int ny, int nseg);
 template <typename T>

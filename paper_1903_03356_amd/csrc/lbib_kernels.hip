@@ -19,11 +19,46 @@
 namespace lbib {
 
 // ------------------------------------------------------------ grid kernel
-// One lattice node: pull, walls, force-corrected moments, BGK + forcing,
-// store.  The wave that owns the node's 64-cell row segment also clears the
-// force accumulator of the previous time level there (if that segment was
-// active), so the next IB launch finds it zeroed; each segment has exactly one
-// owning wave, which reads its two activity flags before clearing one.
+// One lattice node with total force (Fx, Fy): pull, walls, force-corrected
+// moments, BGK + forcing, store.
+template <typename T>
+__device__ __forceinline__ void collide_store(const T* __restrict__ src, T* __restrict__ dst,
+                                              const GridArgs& g, int x, int y, T Fx, T Fy)
+{
+    const size_t cell = (size_t)y * g.nxp + x;
+    T s[9];
+    pull(src, x, y, g, Fx, s);
+    const T drho = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])) + s[8];
+    const T rho = T(1) + drho;
+    const T jx = (s[1] - s[3]) + (s[5] - s[6]) + (s[8] - s[7]);
+    const T jy = (s[2] - s[4]) + (s[5] + s[6]) - (s[7] + s[8]);
+    const T irho = T(1) / rho;
+    const T mx = jx + T(0.5) * Fx, my = jy + T(0.5) * Fy;  // rho u (Eq. 7)
+    const T ux = mx * irho, uy = my * irho;
+    const T om = (T)g.omega;
+    const T pre = T(1) - T(0.5) * om;
+    const T usq15 = T(1.5) * (ux * ux + uy * uy);
+    const T uF = ux * Fx + uy * Fy;
+    const T wa = T(1.0 / 9.0), wd = T(1.0 / 36.0);
+    const T w3a = FirstOrderW<T>::axis, w3d = FirstOrderW<T>::diag;
+    const size_t plane = (size_t)g.ny * g.nxp;
+    T* o = dst + cell;
+    o[0] = relax(s[0], T(4.0 / 9.0), T(0), T(0), T(0), T(0), drho, rho, usq15, uF, om, pre);
+    o[plane] = relax(s[1], wa, w3a, ux, mx, Fx, drho, rho, usq15, uF, om, pre);
+    o[2 * plane] = relax(s[2], wa, w3a, uy, my, Fy, drho, rho, usq15, uF, om, pre);
+    o[3 * plane] = relax(s[3], wa, w3a, -ux, -mx, -Fx, drho, rho, usq15, uF, om, pre);
+    o[4 * plane] = relax(s[4], wa, w3a, -uy, -my, -Fy, drho, rho, usq15, uF, om, pre);
+    o[5 * plane] = relax(s[5], wd, w3d, ux + uy, mx + my, Fx + Fy, drho, rho, usq15, uF, om, pre);
+    o[6 * plane] = relax(s[6], wd, w3d, uy - ux, my - mx, Fy - Fx, drho, rho, usq15, uF, om, pre);
+    o[7 * plane] = relax(s[7], wd, w3d, -ux - uy, -mx - my, -Fx - Fy, drho, rho, usq15, uF, om, pre);
+    o[8 * plane] = relax(s[8], wd, w3d, ux - uy, mx - my, Fx - Fy, drho, rho, usq15, uF, om, pre);
+}
+
+// One lattice node with the IB force of this step.  The wave that owns the
+// node's 64-cell row segment also clears the force accumulator of the
+// previous time level there (if that segment was active), so the next IB
+// launch finds it zeroed; each segment has exactly one owning wave, which
+// reads its two activity flags before clearing one.
 template <typename T>
 __device__ __forceinline__ void grid_cell(const T* __restrict__ src, T* __restrict__ dst,
                                           const long long* __restrict__ fib_now,
@@ -44,36 +79,99 @@ __device__ __forceinline__ void grid_cell(const T* __restrict__ src, T* __restri
             Fx += fix_to_real<T>(f.x);
             Fy += fix_to_real<T>(f.y);
         }
-        T s[9];
-        pull(src, x, y, g, Fx, s);
-        const T drho = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])) + s[8];
-        const T rho = T(1) + drho;
-        const T jx = (s[1] - s[3]) + (s[5] - s[6]) + (s[8] - s[7]);
-        const T jy = (s[2] - s[4]) + (s[5] + s[6]) - (s[7] + s[8]);
-        const T irho = T(1) / rho;
-        const T mx = jx + T(0.5) * Fx, my = jy + T(0.5) * Fy;  // rho u (Eq. 7)
-        const T ux = mx * irho, uy = my * irho;
-        const T om = (T)g.omega;
-        const T pre = T(1) - T(0.5) * om;
-        const T usq15 = T(1.5) * (ux * ux + uy * uy);
-        const T uF = ux * Fx + uy * Fy;
-        const T wa = T(1.0 / 9.0), wd = T(1.0 / 36.0);
-        const T w3a = FirstOrderW<T>::axis, w3d = FirstOrderW<T>::diag;
-        const size_t plane = (size_t)g.ny * g.nxp;
-        T* o = dst + cell;
-        o[0] = relax(s[0], T(4.0 / 9.0), T(0), T(0), T(0), T(0), drho, rho, usq15, uF, om, pre);
-        o[plane] = relax(s[1], wa, w3a, ux, mx, Fx, drho, rho, usq15, uF, om, pre);
-        o[2 * plane] = relax(s[2], wa, w3a, uy, my, Fy, drho, rho, usq15, uF, om, pre);
-        o[3 * plane] = relax(s[3], wa, w3a, -ux, -mx, -Fx, drho, rho, usq15, uF, om, pre);
-        o[4 * plane] = relax(s[4], wa, w3a, -uy, -my, -Fy, drho, rho, usq15, uF, om, pre);
-        o[5 * plane] = relax(s[5], wd, w3d, ux + uy, mx + my, Fx + Fy, drho, rho, usq15, uF, om, pre);
-        o[6 * plane] = relax(s[6], wd, w3d, uy - ux, my - mx, Fy - Fx, drho, rho, usq15, uF, om, pre);
-        o[7 * plane] = relax(s[7], wd, w3d, -ux - uy, -mx - my, -Fx - Fy, drho, rho, usq15, uF, om, pre);
-        o[8 * plane] = relax(s[8], wd, w3d, ux - uy, mx - my, Fx - Fy, drho, rho, usq15, uF, om, pre);
+        collide_store(src, dst, g, x, y, Fx, Fy);
     }
     if (old) {
         *reinterpret_cast<longlong2*>(fib_old + 2 * cell) = make_longlong2(0, 0);
         if (lane == 0) flags_old[fidx] = 0;
+    }
+}
+
+// ---- near / far split of a grid step (IB launch hidden behind the far part)
+// Rows and 64-cell segments of a capsule's near region (rect in world cells,
+// x unwrapped).  The IB kernel stamps exactly these (row, segment) units into
+// the near map and the near kernel computes exactly these, so near and far
+// cover the lattice once.
+struct RectUnits {
+    int ry0, nrows;  // first row (wrapped) and row count
+    int sa, nA, nsegs;  // segments: sa .. sa + nA - 1, then 0 .. (nsegs - nA) - 1
+};
+
+__device__ __forceinline__ RectUnits rect_units(const NearRect& r, const GridArgs& g)
+{
+    RectUnits u;
+    if (g.periodic_y) {
+        u.nrows = min(r.y1 - r.y0 + 1, g.ny);
+        u.ry0 = ((r.y0 % g.ny) + g.ny) % g.ny;
+    } else {
+        u.ry0 = max(0, r.y0);
+        u.nrows = max(0, min(g.ny - 1, r.y1) - u.ry0 + 1);
+    }
+    const int w = r.x1 - r.x0 + 1;
+    if (w >= g.nx) {
+        u.sa = 0;
+        u.nA = g.nseg;
+        u.nsegs = g.nseg;
+    } else {
+        const int a = ((r.x0 % g.nx) + g.nx) % g.nx;
+        const int b = a + w - 1;
+        u.sa = a / kSegW;
+        if (b < g.nx) {
+            u.nA = b / kSegW - u.sa + 1;
+            u.nsegs = u.nA;
+        } else {
+            u.nA = g.nseg - u.sa;
+            u.nsegs = u.nA + (b - g.nx) / kSegW + 1;
+        }
+    }
+    return u;
+}
+
+// Far part: every (row, segment) outside all near regions, i.e. whose entry
+// in this step's near map does not carry this step's stamp.  The IB force is
+// zero there (its supports lie inside the near regions), so the node sees the
+// body force only and no force level is read or cleared.  An active force
+// flag found here means the near regions were too small: ST_NEAR.
+template <typename T>
+__global__ __launch_bounds__(kSegW * 4) void k_grid_far(
+    const T* __restrict__ src, T* __restrict__ dst, const int* __restrict__ flags_now,
+    const int* __restrict__ flags_old, const int* __restrict__ near_map, int stamp, int* status,
+    GridArgs g)
+{
+    const int b = blockIdx.x;
+    const int j = b / kNumXcd;
+    const int group = j / g.nseg;
+    const int band = group * kNumXcd + (b - j * kNumXcd);
+    const int seg = j - group * g.nseg;
+    const int lane = threadIdx.x & (kSegW - 1);
+    const int y = band * 4 + (threadIdx.x >> 6);
+    if (y >= g.ny) return;
+    const int fidx = y * g.nseg + seg;
+    if (near_map[fidx] == stamp) return;
+    if ((flags_now[fidx] | flags_old[fidx]) && lane == 0) atomicOr(status, ST_NEAR);
+    const int x = seg * kSegW + lane;
+    if (x < g.nx) collide_store(src, dst, g, x, y, (T)g.gx, T(0));
+}
+
+// Near part: the (row, segment) units of every capsule's near region, with
+// the IB force; `per_cap` blocks of 4 waves share one capsule's units.  Units
+// in several regions are computed more than once, with identical results.
+template <typename T>
+__global__ __launch_bounds__(kSegW * 4) void k_grid_near(
+    const T* __restrict__ src, T* __restrict__ dst, const long long* __restrict__ fib_now,
+    const int* __restrict__ flags_now, long long* __restrict__ fib_old,
+    int* __restrict__ flags_old, const NearRect* __restrict__ rects, int per_cap, GridArgs g)
+{
+    const int c = blockIdx.x / per_cap, kb = blockIdx.x - c * per_cap;
+    const RectUnits u = rect_units(rects[c], g);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kSegW - 1);
+    const int units = u.nrows * u.nsegs;
+    for (int q = kb * 4 + wave; q < units; q += per_cap * 4) {
+        const int ri = q / u.nsegs, si = q - ri * u.nsegs;
+        int y = u.ry0 + ri;
+        if (y >= g.ny) y -= g.ny;
+        const int seg = si < u.nA ? u.sa + si : si - u.nA;
+        grid_cell(src, dst, fib_now, flags_now, fib_old, flags_old, g, y, seg, lane);
     }
 }
 
@@ -121,6 +219,29 @@ hipError_t launch_grid_step(const T* src, T* dst, const long long* fib_now, cons
     const int blocks = grid_blocks(g.ny, g.nseg);
     hipLaunchKernelGGL((k_grid_step<T, R>), dim3((unsigned)blocks), dim3(kSegW * 4), 0, s, src, dst,
                        fib_now, flags_now, fib_old, flags_old, g);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_grid_far(const T* src, T* dst, const int* flags_now, const int* flags_old,
+                           const int* near_map, int stamp, int* status, const GridArgs& g,
+                           hipStream_t s)
+{
+    const int blocks = grid_blocks(g.ny, g.nseg);
+    hipLaunchKernelGGL(k_grid_far<T>, dim3((unsigned)blocks), dim3(kSegW * 4), 0, s, src, dst,
+                       flags_now, flags_old, near_map, stamp, status, g);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_grid_near(const T* src, T* dst, const long long* fib_now, const int* flags_now,
+                            long long* fib_old, int* flags_old, const NearRect* rects, int ncap,
+                            const GridArgs& g, hipStream_t s)
+{
+    constexpr int per_cap = 16;
+    if (ncap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grid_near<T>, dim3((unsigned)(ncap * per_cap)), dim3(kSegW * 4), 0, s,
+                       src, dst, fib_now, flags_now, fib_old, flags_old, rects, per_cap, g);
     return hipGetLastError();
 }
 
@@ -857,6 +978,37 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
         __syncthreads();
     }
 
+    // ---- near region of this step's grid update (overlapped schedule): the
+    // bounding box of x^n and x^{n-1} = x^n - d^n plus 5 cells covers the
+    // supports of F^n and F^{n-1} and the patch the next IB launch stages
+    if (a.rects) {
+        float nmn[2] = {3e38f, 3e38f}, nmx[2] = {-3e38f, -3e38f};
+        for (int v = tid; v < nv; v += nt) {
+            const float x = (float)S.px[v], y = (float)S.py[v];
+            const float xo = (float)(S.px[v] - S.dx[v]), yo = (float)(S.py[v] - S.dy[v]);
+            nmn[0] = fminf(nmn[0], fminf(x, xo));
+            nmn[1] = fminf(nmn[1], fminf(y, yo));
+            nmx[0] = fmaxf(nmx[0], fmaxf(x, xo));
+            nmx[1] = fmaxf(nmx[1], fmaxf(y, yo));
+        }
+        block_minmax(nmn, nmx, red);
+        NearRect r;
+        r.x0 = (int)(refx + (long long)floorf(nmn[0])) - 5;
+        r.x1 = (int)(refx + (long long)floorf(nmx[0])) + 5;
+        r.y0 = (int)(refy + (long long)floorf(nmn[1])) - 5;
+        r.y1 = (int)(refy + (long long)floorf(nmx[1])) + 5;
+        if (tid == 0) a.rects[c] = r;
+        const RectUnits u = rect_units(r, g);
+        const int units = u.nrows * u.nsegs;
+        for (int q = tid; q < units; q += nt) {
+            const int ri = q / u.nsegs, si = q - ri * u.nsegs;
+            int y = u.ry0 + ri;
+            if (y >= g.ny) y -= g.ny;
+            const int seg = si < u.nA ? u.sa + si : si - u.nA;
+            a.near_map[y * g.nseg + seg] = a.stamp;
+        }
+    }
+
     // ---- forcing of the new step
     if (doA) {
         if (a.dynamic) {
@@ -1111,6 +1263,11 @@ hipError_t launch_set_nodes(T* nodes, CapsuleDev* caps, int cap, int nv, int nod
     template hipError_t launch_grid_step_batch<T>(const T*, T*, const long long*, const int*,     \
                                                   long long*, int*, const InstDev*, const int*,   \
                                                   int, hipStream_t);                              \
+    template hipError_t launch_grid_far<T>(const T*, T*, const int*, const int*, const int*, int, \
+                                           int*, const GridArgs&, hipStream_t);                   \
+    template hipError_t launch_grid_near<T>(const T*, T*, const long long*, const int*,           \
+                                            long long*, int*, const NearRect*, int,               \
+                                            const GridArgs&, hipStream_t);                        \
     template hipError_t launch_ib<T>(const IBArgs<T>&, int, size_t, hipStream_t);                 \
     template size_t ib_lds_bytes<T>(int, int);                                                    \
     template hipError_t ib_set_lds_limit<T>(size_t);                                              \

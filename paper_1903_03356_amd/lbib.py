@@ -21,7 +21,7 @@ OK, EINVAL, ECAPACITY, EDEVICE, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ECAPACITY", -3: "EDEVICE", -4: "ESTATE",
                 -5: "ENUMERIC"}
 KINEMATIC, DYNAMIC = 0, 1
-FLAG_WALL, FLAG_NONFINITE, FLAG_PATCH, FLAG_OVERFLOW, FLAG_MOVE = 1, 2, 4, 8, 16
+FLAG_WALL, FLAG_NONFINITE, FLAG_PATCH, FLAG_OVERFLOW, FLAG_MOVE, FLAG_NEAR = 1, 2, 4, 8, 16, 32
 NUM_BUFFERS = 8
 BUFFER_NAMES = ["pops_a", "pops_b", "force", "flags", "nodes", "caps", "diag", "stage"]
 # lbib_state_id
@@ -34,7 +34,7 @@ EXPORTS = ["lbib_required_bytes", "lbib_create", "lbib_add_capsule", "lbib_step"
            "lbib_get_state", "lbib_set_state", "lbib_check", "lbib_set_timing",
            "lbib_get_timing", "lbib_steps_done", "lbib_last_error", "lbib_destroy",
            "lbib_required_bytes_batch", "lbib_create_batch", "lbib_add_capsule_to",
-           "lbib_num_lattices", "lbib_adjoint_bytes", "lbib_adjoint"]
+           "lbib_num_lattices", "lbib_adjoint_bytes", "lbib_adjoint", "lbib_set_overlap"]
 OBJ_TAYLOR, OBJ_CENTROID_Y = 0, 1
 
 
@@ -88,6 +88,8 @@ def load() -> C.CDLL:
     L.lbib_check.argtypes = [vp, C.POINTER(i32)]
     L.lbib_set_timing.restype = i32
     L.lbib_set_timing.argtypes = [vp, i32]
+    L.lbib_set_overlap.restype = i32
+    L.lbib_set_overlap.argtypes = [vp, i32]
     L.lbib_get_timing.restype = i32
     L.lbib_get_timing.argtypes = [vp, C.POINTER(C.c_double)]
     L.lbib_steps_done.restype = C.c_int64
@@ -274,7 +276,10 @@ class Sim:
         with self.torch.cuda.device(self.device):
             _check(load().lbib_get_timing(self.h, out), self.h)
         return {"grid_ms": out[0], "grid_launches": out[1], "ib_ms": out[2],
-                "ib_launches": out[3]}
+                "ib_launches": out[3], "near_ms": out[4], "near_launches": out[5]}
+
+    def set_overlap(self, enable: bool) -> None:
+        _check(load().lbib_set_overlap(self.h, 1 if enable else 0), self.h)
 
     def adjoint_bytes(self, nsteps: int) -> int:
         return int(load().lbib_adjoint_bytes(self.h, int(nsteps)))
