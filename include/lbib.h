@@ -166,7 +166,8 @@ lbib_status lbib_add_capsule(lbib_ctx* ctx, const double* nodes_xy, int32_t n, c
  * with the forcing of this step) and one fused collide-stream kernel launch.
  * The call ends with the node update of the last step, so between calls the
  * state is the complete state at time n.
- * With lbib_set_overlap(ctx, 1), a single lattice with 1..64 capsules splits
+ * With lbib_set_overlap(ctx, 1), a single lattice with 1..64 capsules and no
+ * contact force splits
  * the collide-stream pass: a near kernel covers each capsule's near region
  * (the bounding box of its nodes at n-1 and n plus 5 cells), a far kernel the
  * rest on a second stream of the library's own, beside the next IB launch.
@@ -203,6 +204,20 @@ lbib_status lbib_check(lbib_ctx* ctx, int32_t* flags_out);
  * IB launches, near kernel total ms, near launches}.  It then resets the
  * counters. */
 lbib_status lbib_set_timing(lbib_ctx* ctx, int32_t enable);
+
+/* Contact force between capsules (Sec. 3.4, Eq. 27).  cutoff > 0 switches it
+ * on: a node at distance d < cutoff (lattice units) from a node of another
+ * capsule of the same lattice receives (1e-4 / (8 sqrt 2)) sqrt(1 / d^5) along
+ * its inward normal (minus the normalized sum of the outward normals of its
+ * two elements), summed over such nodes, nearest periodic image.  The paper
+ * gives no cutoff; 2 is the reading the workloads use.  cutoff = 0 (the
+ * default) switches it off.  The force joins the total nodal force of the
+ * Dynamic update (step 7) and the internal force of the Kinematic forcing
+ * (step i), at the positions those use.  Contacts cost one bounds and one
+ * contact kernel per force evaluation; the Kinematic scheme then takes
+ * separate launches for the node update and the forcing.
+ * Errors: EINVAL (cutoff not in [0, 16]), EDEVICE. */
+lbib_status lbib_set_contact(lbib_ctx* ctx, double cutoff);
 
 /* enable = 1 selects the overlapped near / far schedule of lbib_step (see
  * there); enable = 0, the default, keeps the single-pass schedule on one
@@ -292,7 +307,8 @@ size_t lbib_adjoint_bytes(const lbib_ctx* ctx, int32_t nsteps);
  * positions); the fixed-point rounding of the spread force is not
  * differentiated.
  * Errors: EINVAL (batch context, nsteps < 1, bad mode, objective or capsule
- * id, a capsule with k_b != 0, workspace or n_ks too small, NULL pointers),
+ * id, a capsule with k_b != 0, the contact force on, workspace or n_ks too
+ * small, NULL pointers),
  * ESTATE (context not at step 0, or its mode differs), ECAPACITY (capsules too
  * large for the on-chip memory of the reverse IB kernel), ENUMERIC (a device
  * status flag in the forward run or the reverse sweep), EDEVICE.

@@ -64,6 +64,7 @@ typedef struct {
     double kb, ka, mass, mv, A0, P0;
     double *ftot;   /* last total nodal force (Dynamic) or internal force (Kinematic) */
     double *fext;   /* last hydrodynamic nodal force (Dynamic) */
+    double *fc;     /* contact force of the current positions (Eq. 27) */
     int primed;
 } orc_capsule;
 
@@ -80,6 +81,7 @@ typedef struct {
     long steps;
     int mode;                  /* -1 until the first step */
     int status;
+    double contact_cutoff;     /* Eq. 27 repulsion acts below this distance; 0 = off */
 } orc_sim;
 
 static inline size_t cid(const orc_sim *s, int x, int y) { return (size_t)x * s->ny + y; }
@@ -585,7 +587,7 @@ void orc_destroy(orc_sim *s)
     for (int c = 0; c < s->ncap; c++) {
         orc_capsule *k = &s->caps[c];
         free(k->x); free(k->xm1); free(k->uv); free(k->l0); free(k->theta0);
-        free(k->ks); free(k->ftot); free(k->fext);
+        free(k->ks); free(k->ftot); free(k->fext); free(k->fc);
     }
     free(s->caps);
     free(s->f); free(s->ftmp); free(s->F); free(s->fib);
@@ -615,6 +617,7 @@ int orc_add_capsule(orc_sim *s, int nv, const double *nodes, const double *ks, i
     k->ks = (double *)xcalloc(nv, sizeof(double));
     k->ftot = (double *)xcalloc(2 * nv, sizeof(double));
     k->fext = (double *)xcalloc(2 * nv, sizeof(double));
+    k->fc = (double *)xcalloc(2 * nv, sizeof(double));
     memcpy(k->x, nodes, sizeof(double) * 2 * nv);
     double P = 0;
     for (int l = 0; l < nv; l++) {
@@ -633,6 +636,59 @@ int orc_add_capsule(orc_sim *s, int nv, const double *nodes, const double *ks, i
     k->P0 = P;
     k->primed = 0;
     return s->ncap++;
+}
+
+/* Eq. 27: repulsion between the vertices of different capsules (Sec. 3.4).
+ * Vertex i of capsule a, at distance d < cutoff from vertex j of capsule b,
+ * receives (1e-4 / (8 sqrt 2)) sqrt(dx / d^5) along its inward normal n-,
+ * summed over all such j; dx = 1.  Readings: the cutoff is not printed (the
+ * caller sets it, 2 dx by default in the workloads); the vertex normal is the
+ * normalized sum of the outward normals of its two elements.  Distances take
+ * the nearest periodic image.  Evaluated at the current positions of every
+ * capsule, before any of them moves. */
+static void contact_forces(orc_sim *s)
+{
+    const double C = 1e-4 / (8.0 * sqrt(2.0));
+    for (int a = 0; a < s->ncap; a++)
+        memset(s->caps[a].fc, 0, sizeof(double) * 2 * s->caps[a].nv);
+    if (!(s->contact_cutoff > 0.0)) return;
+    for (int a = 0; a < s->ncap; a++) {
+        orc_capsule *ka = &s->caps[a];
+        int nv = ka->nv;
+        for (int i = 0; i < nv; i++) {
+            int il = (i + nv - 1) % nv, ir = (i + 1) % nv;
+            double ax = ka->x[2 * i] - ka->x[2 * il], ay = ka->x[2 * i + 1] - ka->x[2 * il + 1];
+            double bx = ka->x[2 * ir] - ka->x[2 * i], by = ka->x[2 * ir + 1] - ka->x[2 * i + 1];
+            double la = hypot(ax, ay), lb = hypot(bx, by);
+            /* outward element normals (t_y, -t_x)/|t| of elements i-1 and i */
+            double nx = ay / la + by / lb, ny = -ax / la - bx / lb;
+            double nn = hypot(nx, ny);
+            double inx = -nx / nn, iny = -ny / nn;
+            for (int b = 0; b < s->ncap; b++) {
+                if (b == a) continue;
+                orc_capsule *kb = &s->caps[b];
+                for (int j = 0; j < kb->nv; j++) {
+                    double dx = kb->x[2 * j] - ka->x[2 * i];
+                    double dy = kb->x[2 * j + 1] - ka->x[2 * i + 1];
+                    dx -= s->nx * nearbyint(dx / s->nx);
+                    if (s->periodic_y) dy -= s->ny * nearbyint(dy / s->ny);
+                    double d = hypot(dx, dy);
+                    if (d < s->contact_cutoff && d > 0.0) {
+                        double mag = C * sqrt(1.0 / (d * d * d * d * d));
+                        ka->fc[2 * i] += mag * inx;
+                        ka->fc[2 * i + 1] += mag * iny;
+                    }
+                }
+            }
+        }
+    }
+}
+
+void orc_set_contact(orc_sim *s, double cutoff) { s->contact_cutoff = cutoff > 0.0 ? cutoff : 0.0; }
+
+void orc_get_contact(const orc_sim *s, int c, double *fc)
+{
+    memcpy(fc, s->caps[c].fc, sizeof(double) * 2 * s->caps[c].nv);
 }
 
 /* Start-up (reading: the paper gives no history at n = 0): the node velocity
@@ -693,7 +749,9 @@ static void step_dynamic(orc_sim *s)
     /* steps 7-8: total nodal force at x^n (internal Eqs. 11, 13, 14 plus
      * hydrodynamic Eqs. 15-16 from the new moments), Verlet position update
      * (Eq. 23) with the tentative velocity interpolated from u^{n+1}
-     * (reading), BDF2 node velocity (Eq. 24). */
+     * (reading), BDF2 node velocity (Eq. 24).  The contact force (Eq. 27) of
+     * x^n joins the total force. */
+    contact_forces(s);
     for (int c = 0; c < s->ncap; c++) {
         orc_capsule *k = &s->caps[c];
         int nv = k->nv;
@@ -708,7 +766,7 @@ static void step_dynamic(orc_sim *s)
             interpolate_u(s, k->x[2 * v], k->x[2 * v + 1], U);
             for (int d = 0; d < 2; d++) {
                 int j = 2 * v + d;
-                k->ftot[j] = fs[j] + fb[j] + fa[j] + k->fext[j];
+                k->ftot[j] = fs[j] + fb[j] + fa[j] + k->fext[j] + k->fc[j];
                 xn[j] = k->x[j] + U[d] * 1.0 + 0.5 * k->ftot[j] / k->mv * 1.0;
                 k->uv[j] = (1.5 * xn[j] - 2.0 * k->x[j] + 0.5 * k->xm1[j]) / 1.0;
             }
@@ -724,8 +782,9 @@ static void step_kinematic(orc_sim *s)
 {
     size_t n = (size_t)s->nx * s->ny;
     memset(s->fib, 0, sizeof(double) * 2 * n);
-    /* i-iii: internal forces only, spread with c_v = 1 (reading: F_v is a
-     * nodal force, so c_v = 1 / dx^2) */
+    /* i-iii: internal forces (and the contact force of Eq. 27 at x^n), spread
+     * with c_v = 1 (reading: F_v is a nodal force, so c_v = 1 / dx^2) */
+    contact_forces(s);
     for (int c = 0; c < s->ncap; c++) {
         orc_capsule *k = &s->caps[c];
         int nv = k->nv;
@@ -734,8 +793,8 @@ static void step_kinematic(orc_sim *s)
         double *fa = (double *)xcalloc(2 * nv, sizeof(double));
         orc_internal_forces(nv, k->x, k->l0, k->theta0, k->ks, k->kb, k->ka, k->A0, fs, fb, fa);
         for (int v = 0; v < nv; v++) {
-            k->ftot[2 * v] = fs[2 * v] + fb[2 * v] + fa[2 * v];
-            k->ftot[2 * v + 1] = fs[2 * v + 1] + fb[2 * v + 1] + fa[2 * v + 1];
+            k->ftot[2 * v] = fs[2 * v] + fb[2 * v] + fa[2 * v] + k->fc[2 * v];
+            k->ftot[2 * v + 1] = fs[2 * v + 1] + fb[2 * v + 1] + fa[2 * v + 1] + k->fc[2 * v + 1];
             spread(s, k->x[2 * v], k->x[2 * v + 1], 1.0, k->ftot[2 * v], k->ftot[2 * v + 1]);
         }
         free(fs); free(fb); free(fa);

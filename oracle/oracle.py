@@ -71,6 +71,8 @@ def lib() -> C.CDLL:
     L.orc_external_forces.argtypes = [vp, C.c_int, _dp, _dp]
     L.orc_interpolate.argtypes = [vp, C.c_int, _dp, _dp]
     L.orc_spread.argtypes = [vp, C.c_int, _dp, _dp, _dp, _dp]
+    L.orc_set_contact.argtypes = [vp, C.c_double]
+    L.orc_get_contact.argtypes = [vp, C.c_int, _dp]
     L.orc_set_threads.argtypes = [C.c_int]
     L.orc_get_threads.restype = C.c_int
     _lib = L
@@ -148,6 +150,8 @@ class Sim:
             L.orc_add_capsule(self.h, nodes.shape[0], nodes, ks, ks.size, float(cap["kb"]),
                               float(cap["ka"]), float(cap["mass"]))
             self.nodes.append(nodes.shape[0])
+        if cfg.get("contact_cutoff", 0.0):
+            L.orc_set_contact(self.h, float(cfg["contact_cutoff"]))
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -203,6 +207,12 @@ class Sim:
 
     def set_capsule(self, c: int, x, xm1, uv) -> None:
         lib().orc_set_capsule(self.h, c, *(np.ascontiguousarray(a, np.float64) for a in (x, xm1, uv)))
+
+    def contact(self, c: int) -> np.ndarray:
+        """Contact forces (Eq. 27) of the positions at the last force evaluation."""
+        out = np.zeros((self.nodes[c], 2))
+        lib().orc_get_contact(self.h, c, out)
+        return out
 
     def capsule_forces(self, c: int):
         nv = self.nodes[c]

@@ -43,7 +43,7 @@ struct Layout {
     int max_caps = 0, max_nodes = 0, max_nv = 0;
     int grid_blocks = 0;
     size_t plane_max = 0;
-    size_t inst_table = 0, round_table = 0, rect_table = 0, near_map = 0;  // offsets in BUF_CAPS
+    size_t inst_table = 0, round_table = 0, rect_table = 0, near_map = 0, bounds = 0;  // in BUF_CAPS
 };
 
 struct lbib_ctx {
@@ -68,6 +68,7 @@ struct lbib_ctx {
     std::vector<double> cap_kb, cap_P0;
     // overlapped schedule: far part of the grid step on a second stream (opt-in)
     bool overlap = false;
+    double contact_cutoff = 0.0;  // Eq. 27 contact force below this node distance; 0 = off
     hipStream_t s_far = nullptr;
     hipEvent_t e_near = nullptr, e_far = nullptr;
 };
@@ -155,6 +156,7 @@ static bool make_layout(const lbib_grid* grids, int n, Layout& L)
     L.round_table = L.inst_table + round256((size_t)n * sizeof(InstDev));
     L.rect_table = L.round_table + round256((size_t)(L.grid_blocks / kNumXcd) * sizeof(int));
     L.near_map = L.rect_table + round256((size_t)2 * L.max_caps * sizeof(NearRect));
+    L.bounds = L.near_map + round256((size_t)2 * L.flag_level * sizeof(int));
     return true;
 }
 
@@ -172,7 +174,7 @@ static size_t layout_bytes(const Layout& L, int id)
     case LBIB_BUF_FLAGS: return round256(2 * L.flag_level * sizeof(int));
     case LBIB_BUF_NODES: return round256((size_t)NF_COUNT * L.max_nodes * L.rb);
     case LBIB_BUF_CAPS:
-        return L.near_map + round256((size_t)2 * L.flag_level * sizeof(int));
+        return L.bounds + round256((size_t)L.max_caps * sizeof(float4));
     case LBIB_BUF_DIAG: return round256(status_offset(L) + 64);
     case LBIB_BUF_STAGE: {
         size_t n = 3 * L.plane_max;
@@ -602,6 +604,7 @@ static IBArgs<T> ib_args(const lbib_ctx* c, long long n, int phase)
     a.rects = nullptr;
     a.near_map = nullptr;
     a.stamp = 0;
+    a.contact = c->contact_cutoff > 0.0;
     return a;
 }
 
@@ -659,6 +662,21 @@ static hipError_t do_grid(lbib_ctx* c, void* p)
                                      static_cast<T*>(pops(c, n + 1)), fib(c, n), flags(c, n),
                                      fib(c, n + 1), flags(c, n + 1), inst_table(c), round_table(c),
                                      c->L.grid_blocks, c->stream);
+}
+
+template <typename T>
+static lbib_status launch_contact_t(lbib_ctx* c)
+{
+    ContactArgs<T> a;
+    a.nodes = reinterpret_cast<T*>(bufp(c, LBIB_BUF_NODES));
+    a.caps = reinterpret_cast<const CapsuleDev*>(bufp(c, LBIB_BUF_CAPS));
+    a.bounds = reinterpret_cast<float4*>(bufp(c, LBIB_BUF_CAPS) + c->L.bounds);
+    a.node_stride = c->L.max_nodes;
+    a.ncap = c->ncap;
+    a.max_nv = c->L.max_nv;
+    a.cutoff = c->contact_cutoff;
+    HIPCHK(c, launch_contact<T>(a, c->stream));
+    return LBIB_OK;
 }
 
 template <typename T>
@@ -725,17 +743,44 @@ static lbib_status step_overlap_t(lbib_ctx* c, int nsteps)
     return LBIB_OK;
 }
 
+// Single-pass schedule.  With the contact force on, its kernel runs on the
+// positions the next force evaluation uses: before every launch with a
+// Dynamic node update (x^n of step 7), and, for the Kinematic scheme, between
+// the node update and the forcing (x^n of step i), which then take separate
+// launches.
 template <typename T>
 static lbib_status step_t(lbib_ctx* c, int nsteps)
 {
     size_patches<T>(c);
-    if (c->overlap && c->L.inst.size() == 1 && c->ncap > 0 && c->ncap <= kMaxOverlapCapsules)
+    const bool contact = c->contact_cutoff > 0.0 && c->ncap > 1;
+    const bool dyn = c->mode == LBIB_DYNAMIC;
+    if (c->overlap && !contact && c->L.inst.size() == 1 && c->ncap > 0 &&
+        c->ncap <= kMaxOverlapCapsules)
         return step_overlap_t<T>(c, nsteps);
     for (int k = 0; k < nsteps; k++) {
         const long long n = c->steps + k;
         if (c->ncap > 0) {
-            IBLaunch<T> q{n, k == 0 ? (n == 0 ? (PH_PRIME | PH_A) : PH_A) : (PH_B | PH_A), false};
-            lbib_status s = launch_timed<T>(c, 1, do_ib<T>, &q);
+            const int pb = k == 0 ? 0 : PH_B;
+            const int pa = n == 0 ? (PH_PRIME | PH_A) : PH_A;
+            lbib_status s = LBIB_OK;
+            if (contact && !dyn) {
+                if (pb) {
+                    IBLaunch<T> qb{n, pb, false};
+                    s = launch_timed<T>(c, 1, do_ib<T>, &qb);
+                    if (s != LBIB_OK) return s;
+                }
+                s = launch_contact_t<T>(c);
+                if (s != LBIB_OK) return s;
+                IBLaunch<T> qa{n, pa, false};
+                s = launch_timed<T>(c, 1, do_ib<T>, &qa);
+            } else {
+                if (contact && pb) {
+                    s = launch_contact_t<T>(c);
+                    if (s != LBIB_OK) return s;
+                }
+                IBLaunch<T> q{n, pb | pa, false};
+                s = launch_timed<T>(c, 1, do_ib<T>, &q);
+            }
             if (s != LBIB_OK) return s;
         }
         long long nn = n;
@@ -743,6 +788,10 @@ static lbib_status step_t(lbib_ctx* c, int nsteps)
         if (s != LBIB_OK) return s;
     }
     if (c->ncap > 0) {
+        if (contact && dyn) {
+            lbib_status s = launch_contact_t<T>(c);
+            if (s != LBIB_OK) return s;
+        }
         IBLaunch<T> q{c->steps + nsteps, PH_B, false};
         lbib_status s = launch_timed<T>(c, 1, do_ib<T>, &q);
         if (s != LBIB_OK) return s;
@@ -1147,6 +1196,8 @@ extern "C" lbib_status lbib_adjoint(lbib_ctx* c, int32_t nsteps, lbib_mode mode,
         return fail(c, LBIB_ESTATE, "the coupling mode is fixed after the first step");
     for (double kb : c->cap_kb)
         if (kb != 0.0) return fail(c, LBIB_EINVAL, "the adjoint needs k_b = 0 for every capsule");
+    if (c->contact_cutoff > 0.0 && c->ncap > 1)
+        return fail(c, LBIB_EINVAL, "the adjoint does not differentiate the contact force");
     if (n_ks < c->nodes_used) return fail(c, LBIB_EINVAL, "out_dJ_dks shorter than the node count");
     AdjLayout A;
     if (!adj_layout(c, nsteps, A)) return fail(c, LBIB_EINVAL, "invalid adjoint layout");
@@ -1168,6 +1219,21 @@ extern "C" lbib_status lbib_check(lbib_ctx* c, int32_t* flags_out)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (flags_out) *flags_out = st;
     if (st) return fail(c, LBIB_ENUMERIC, "device status flags set: " + std::to_string(st));
+    return LBIB_OK;
+}
+
+extern "C" lbib_status lbib_set_contact(lbib_ctx* c, double cutoff)
+{
+    if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
+    if (!std::isfinite(cutoff) || cutoff < 0.0 || cutoff > 16.0)
+        return fail(c, LBIB_EINVAL, "cutoff must be in [0, 16]");
+    if (cutoff > 0.0) {
+        hipError_t e = c->rb == 4 ? contact_set_lds_limit<float>(c->L.max_nv)
+                                  : contact_set_lds_limit<double>(c->L.max_nv);
+        if (e != hipSuccess)
+            return fail(c, LBIB_EDEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+    }
+    c->contact_cutoff = cutoff;
     return LBIB_OK;
 }
 

@@ -32,6 +32,7 @@ enum NodeField {
     NF_FX, NF_FY,       // last nodal force (total Dynamic / internal Kinematic)
     NF_EX, NF_EY,       // last hydrodynamic nodal force (Dynamic)
     NF_L0L,             // low part of the stress-free length (l0 = NF_L0 + NF_L0L)
+    NF_CX, NF_CY,       // contact force (Eq. 27) of the current positions
     NF_COUNT
 };
 
@@ -108,6 +109,17 @@ struct IBArgs {
     NearRect* rects;   // if not NULL: near region of this step, one per capsule,
     int* near_map;     // its (row, segment) units stamped with `stamp` ([ny][nseg])
     int stamp;
+    int contact;       // add the contact force NF_CX/NF_CY (Dynamic B, Kinematic A)
+};
+
+// Contact forces (Eq. 27) of the current node positions.
+template <typename T>
+struct ContactArgs {
+    T* nodes;                 // reads positions, writes NF_CX / NF_CY
+    const CapsuleDev* caps;
+    float4* bounds;           // per capsule: world bounding box (x0, y0, x1, y1)
+    int node_stride, ncap, max_nv;
+    double cutoff;
 };
 
 // ---- launchers (lbib_kernels.hip) ----
@@ -130,6 +142,10 @@ template <typename T>
 hipError_t launch_grid_near(const T* src, T* dst, const long long* fib_now, const int* flags_now,
                             long long* fib_old, int* flags_old, const NearRect* rects, int ncap,
                             const GridArgs& g, hipStream_t s);
+template <typename T>
+hipError_t launch_contact(const ContactArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t contact_set_lds_limit(int max_nv);
 // Blocks of the grid kernel for one lattice (a multiple of kNumXcd).
 int grid_blocks(int ny, int nseg);
 template <typename T>

@@ -911,7 +911,11 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
             const T dox = S.dx[v], doy = S.dy[v];
             T dx, dy;
             if (a.dynamic) {
-                const T fx = S.t[8][v] + S.t[2][v], fy = S.t[9][v] + S.t[3][v];
+                T fx = S.t[8][v] + S.t[2][v], fy = S.t[9][v] + S.t[3][v];
+                if (a.contact) {
+                    fx += N[NF_CX * NS + off + v];
+                    fy += N[NF_CY * NS + off + v];
+                }
                 dx = Ux + half_inv_m * fx;  // Eq. 23
                 dy = Uy + half_inv_m * fy;
                 const T uvx = T(1.5) * dx - T(0.5) * dox, uvy = T(1.5) * dy - T(0.5) * doy;  // Eq. 24
@@ -1039,6 +1043,10 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
         } else {
             internal_forces(S, nv, cap.kb, cap.ka, cap.A0, red);  // -> t8, t9
             for (int v = tid; v < nv; v += nt) {
+                if (a.contact) {
+                    S.t[8][v] += N[NF_CX * NS + off + v];
+                    S.t[9][v] += N[NF_CY * NS + off + v];
+                }
                 N[NF_FX * NS + off + v] = S.t[8][v];
                 N[NF_FY * NS + off + v] = S.t[9][v];
                 int cx, cy;
@@ -1090,6 +1098,139 @@ hipError_t launch_ib(const IBArgs<T>& a, int ncap, size_t lds_bytes, hipStream_t
 {
     if (ncap <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_ib<T>, dim3(ncap), dim3(kIBThreads), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- contact
+// World bounding box of each capsule's current nodes (one block per capsule).
+template <typename T>
+__global__ __launch_bounds__(kIBThreads) void k_bounds(ContactArgs<T> a)
+{
+    __shared__ double red[kIBThreads / 64][8];
+    const int c = blockIdx.x;
+    const CapsuleDev cap = a.caps[c];
+    const size_t NS = a.node_stride;
+    const T* N = a.nodes;
+    float mn[2] = {3e38f, 3e38f}, mx[2] = {-3e38f, -3e38f};
+    for (int v = threadIdx.x; v < cap.nv; v += blockDim.x) {
+        const float x = (float)N[NF_HX * NS + cap.node_offset + v];
+        const float y = (float)N[NF_HY * NS + cap.node_offset + v];
+        mn[0] = fminf(mn[0], x);
+        mn[1] = fminf(mn[1], y);
+        mx[0] = fmaxf(mx[0], x);
+        mx[1] = fmaxf(mx[1], y);
+    }
+    block_minmax(mn, mx, red);
+    if (threadIdx.x == 0)
+        a.bounds[c] = make_float4((float)cap.ref_x + mn[0], (float)cap.ref_y + mn[1],
+                                  (float)cap.ref_x + mx[0], (float)cap.ref_y + mx[1]);
+}
+
+// Eq. 27 (Sec. 3.4): node v of capsule c, at distance d < cutoff from a node
+// of another capsule of the same lattice, receives (1e-4 / (8 sqrt 2))
+// sqrt(1 / d^5) (dx = 1) along its inward normal, summed over those nodes.
+// The inward normal is minus the normalized sum of the outward normals of the
+// node's two elements.  Distances take the nearest periodic image.  One
+// block per capsule; capsules whose boxes (grown by the cutoff) miss this
+// one's are skipped, the others are staged in LDS.  FP64.
+template <typename T>
+__global__ __launch_bounds__(kIBThreads) void k_contact(ContactArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int c = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const CapsuleDev cap = a.caps[c];
+    const int nv = cap.nv, off = cap.node_offset;
+    const size_t NS = a.node_stride;
+    const T* N = a.nodes;
+    double* X = reinterpret_cast<double*>(smem);
+    double* Y = X + a.max_nv;
+    double* IX = Y + a.max_nv;  // inward normal
+    double* IY = IX + a.max_nv;
+    double* FX = IY + a.max_nv;
+    double* FY = FX + a.max_nv;
+    double* BX = FY + a.max_nv;  // the other capsule, in this capsule's frame
+    double* BY = BX + a.max_nv;
+    for (int v = tid; v < nv; v += nt) {
+        X[v] = (double)N[NF_HX * NS + off + v] + (double)N[NF_LX * NS + off + v];
+        Y[v] = (double)N[NF_HY * NS + off + v] + (double)N[NF_LY * NS + off + v];
+        FX[v] = FY[v] = 0.0;
+    }
+    __syncthreads();
+    for (int v = tid; v < nv; v += nt) {
+        const int vl = v == 0 ? nv - 1 : v - 1, vr = v + 1 == nv ? 0 : v + 1;
+        const double ax = X[v] - X[vl], ay = Y[v] - Y[vl];
+        const double bx = X[vr] - X[v], by = Y[vr] - Y[v];
+        const double la = sqrt(ax * ax + ay * ay), lb = sqrt(bx * bx + by * by);
+        const double nx = ay / la + by / lb, ny = -ax / la - bx / lb;
+        const double nn = sqrt(nx * nx + ny * ny);
+        IX[v] = -nx / nn;
+        IY[v] = -ny / nn;
+    }
+    const float4 me = a.bounds[c];
+    const double Lx = cap.nx, Ly = cap.ny;
+    const double C = 1e-4 / (8.0 * sqrt(2.0));
+    const float cut = (float)a.cutoff;
+    for (int o = 0; o < a.ncap; o++) {
+        if (o == c) continue;
+        const CapsuleDev oc = a.caps[o];
+        if (oc.inst != cap.inst) continue;
+        const float4 ob = a.bounds[o];
+        // box test with the nearest periodic image in x (and y when periodic)
+        float sx = (0.5f * (ob.x + ob.z)) - (0.5f * (me.x + me.z));
+        sx -= (float)Lx * rintf(sx / (float)Lx);
+        float sy = (0.5f * (ob.y + ob.w)) - (0.5f * (me.y + me.w));
+        if (cap.periodic_y) sy -= (float)Ly * rintf(sy / (float)Ly);
+        const float hx = 0.5f * ((ob.z - ob.x) + (me.z - me.x)) + cut;
+        const float hy = 0.5f * ((ob.w - ob.y) + (me.w - me.y)) + cut;
+        if (fabsf(sx) > hx || fabsf(sy) > hy) continue;
+        __syncthreads();
+        const double rx = oc.ref_x - cap.ref_x, ry = oc.ref_y - cap.ref_y;
+        for (int j = tid; j < oc.nv; j += nt) {
+            BX[j] = rx + (double)N[NF_HX * NS + oc.node_offset + j] +
+                    (double)N[NF_LX * NS + oc.node_offset + j];
+            BY[j] = ry + (double)N[NF_HY * NS + oc.node_offset + j] +
+                    (double)N[NF_LY * NS + oc.node_offset + j];
+        }
+        __syncthreads();
+        for (int v = tid; v < nv; v += nt) {
+            double fx = 0.0, fy = 0.0;
+            for (int j = 0; j < oc.nv; j++) {
+                double dx = BX[j] - X[v], dy = BY[j] - Y[v];
+                dx -= Lx * rint(dx / Lx);
+                if (cap.periodic_y) dy -= Ly * rint(dy / Ly);
+                const double d = sqrt(dx * dx + dy * dy);
+                if (d < a.cutoff && d > 0.0) {
+                    const double mag = C * sqrt(1.0 / (d * d * d * d * d));
+                    fx += mag * IX[v];
+                    fy += mag * IY[v];
+                }
+            }
+            FX[v] += fx;
+            FY[v] += fy;
+        }
+    }
+    T* W = a.nodes;
+    for (int v = tid; v < nv; v += nt) {
+        W[NF_CX * NS + off + v] = (T)FX[v];
+        W[NF_CY * NS + off + v] = (T)FY[v];
+    }
+}
+
+template <typename T>
+hipError_t contact_set_lds_limit(int max_nv)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_contact<T>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(8 * sizeof(double) * (size_t)max_nv));
+}
+
+template <typename T>
+hipError_t launch_contact(const ContactArgs<T>& a, hipStream_t s)
+{
+    if (a.ncap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bounds<T>, dim3(a.ncap), dim3(kIBThreads), 0, s, a);
+    hipLaunchKernelGGL(k_contact<T>, dim3(a.ncap), dim3(kIBThreads),
+                       8 * sizeof(double) * (size_t)a.max_nv, s, a);
     return hipGetLastError();
 }
 
@@ -1268,6 +1409,8 @@ hipError_t launch_set_nodes(T* nodes, CapsuleDev* caps, int cap, int nv, int nod
     template hipError_t launch_grid_near<T>(const T*, T*, const long long*, const int*,           \
                                             long long*, int*, const NearRect*, int,               \
                                             const GridArgs&, hipStream_t);                        \
+    template hipError_t launch_contact<T>(const ContactArgs<T>&, hipStream_t);                   \
+    template hipError_t contact_set_lds_limit<T>(int);                                            \
     template hipError_t launch_ib<T>(const IBArgs<T>&, int, size_t, hipStream_t);                 \
     template size_t ib_lds_bytes<T>(int, int);                                                    \
     template hipError_t ib_set_lds_limit<T>(size_t);                                              \

@@ -34,7 +34,8 @@ EXPORTS = ["lbib_required_bytes", "lbib_create", "lbib_add_capsule", "lbib_step"
            "lbib_get_state", "lbib_set_state", "lbib_check", "lbib_set_timing",
            "lbib_get_timing", "lbib_steps_done", "lbib_last_error", "lbib_destroy",
            "lbib_required_bytes_batch", "lbib_create_batch", "lbib_add_capsule_to",
-           "lbib_num_lattices", "lbib_adjoint_bytes", "lbib_adjoint", "lbib_set_overlap"]
+           "lbib_num_lattices", "lbib_adjoint_bytes", "lbib_adjoint", "lbib_set_overlap",
+           "lbib_set_contact"]
 OBJ_TAYLOR, OBJ_CENTROID_Y = 0, 1
 
 
@@ -90,6 +91,8 @@ def load() -> C.CDLL:
     L.lbib_set_timing.argtypes = [vp, i32]
     L.lbib_set_overlap.restype = i32
     L.lbib_set_overlap.argtypes = [vp, i32]
+    L.lbib_set_contact.restype = i32
+    L.lbib_set_contact.argtypes = [vp, C.c_double]
     L.lbib_get_timing.restype = i32
     L.lbib_get_timing.argtypes = [vp, C.POINTER(C.c_double)]
     L.lbib_steps_done.restype = C.c_int64
@@ -189,6 +192,8 @@ class Sim:
         for cap in caps:
             self.add_capsule(cap["nodes"], cap["ks"], cap["kb"], cap["ka"], cap["mass"])
         self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
+        if cfg.get("contact_cutoff", 0.0):
+            self.set_contact(float(cfg["contact_cutoff"]))
 
     # -- ABI wrappers with the same names ------------------------------------
     def add_capsule(self, nodes, ks, kb: float, ka: float, mass: float) -> int:
@@ -277,6 +282,10 @@ class Sim:
             _check(load().lbib_get_timing(self.h, out), self.h)
         return {"grid_ms": out[0], "grid_launches": out[1], "ib_ms": out[2],
                 "ib_launches": out[3], "near_ms": out[4], "near_launches": out[5]}
+
+    def set_contact(self, cutoff: float) -> None:
+        with self.torch.cuda.device(self.device):
+            _check(load().lbib_set_contact(self.h, float(cutoff)), self.h)
 
     def set_overlap(self, enable: bool) -> None:
         _check(load().lbib_set_overlap(self.h, 1 if enable else 0), self.h)
@@ -400,3 +409,6 @@ class Batch(Sim):
                                        cap["mass"]) for cap in c.get("capsules", [])]
             self.cap_ids.append(ids)
         self.nx, self.ny = self.dims[0]
+        cut = max(float(c.get("contact_cutoff", 0.0)) for c in cfgs)
+        if cut:
+            self.set_contact(cut)

@@ -26,7 +26,7 @@ def test_required_bytes_batch_is_the_sum_of_the_lattices():
                                                             for g in grids)
     assert lbib.required_bytes_batch(grids, 3) >= sum(2 * g.ny * 2 * 4 for g in grids)
     assert lbib.required_bytes_batch(grids, 4) == \
-        -(-16 * (200 + 128 + 3) * 4 // 256) * 256
+        -(-18 * (200 + 128 + 3) * 4 // 256) * 256
     assert lbib.required_bytes_batch(grids, 5) >= 4 * 144 + 3 * 96
     assert lbib.required_bytes_batch(grids, 7) >= 3 * 1024 * 9 * 8
     assert lbib.required_bytes_batch(grids[:1], 0) == lbib.required_bytes(grids[0], 0)

@@ -264,6 +264,38 @@ def test_overlapped_schedule_is_bit_identical():
                 assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("mode", ["dynamic", "kinematic"])
+@pytest.mark.parametrize("real_bytes", [8, 4])
+def test_contact_pair(mode, real_bytes):
+    """Two capsules 1.65 lu apart in a Couette channel with the Eq. 27 contact
+    force (cutoff 2): fields, nodes and the last nodal force (which carries the
+    contact term) against the oracle."""
+    n = 150
+    log(f"contact pair {mode} real_bytes={real_bytes} steps={n}")
+    cfg = wl._base("contact", 64, 48, 0.9, real_bytes, mode, 0, u_bottom=-0.005, u_top=0.005,
+                   init_profile=wl.INIT_COUETTE)
+    cfg["capsules"] = [wl.capsule(wl.circle_nodes(24.0, 23.0, 6.0, 48), 0.02, 0.0, 1.0, 1.0),
+                       wl.capsule(wl.circle_nodes(37.5, 25.0, 6.0, 48), 0.02, 0.0, 1.0, 1.3)]
+    cfg["contact_cutoff"] = 2.0
+    g, o = pair(cfg)
+    g.step(n)
+    o.step(n)
+    assert np.abs(o.contact(0)).max() > 0 and np.abs(o.contact(1)).max() > 0
+    if real_bytes == 8:
+        compare_fields(g, o, 1e-10, 1e-12)
+        compare_capsules(g, o, 1e-10, 1e-10)
+        ftol = 1e-12
+    else:
+        compare_fields(g, o, 1e-5, 1e-6)
+        compare_capsules(g, o, 1e-4, 1e-4)
+        ftol = 1e-6
+    for c in range(2):
+        fg = g.capsule_force(c)
+        fo = o.capsule_forces(c)[0]
+        assert np.abs(fg - fo).max() <= ftol * max(1.0, np.abs(fo).max() * 1e3), (c, np.abs(fg - fo).max())
+    assert g.check() == 0
+
+
 # ------------------------------------------------------------ error paths --
 
 def test_add_capsule_validation():

@@ -495,3 +495,46 @@ def test_p15_kinematic_deformation_grows_with_g(orc):
         d.append(sim.diag(0)["D"])
         assert sim.status == 0
     assert d[0] < d[1] < d[2], d
+
+
+# ---- Eq. 27: contact repulsion between capsules ------------------------------
+
+def _diamond(cx, cy, h=2.0):
+    """Counter-clockwise square rotated 45 degrees: right, top, left, bottom
+    vertices; the outward vertex normal of the right vertex is +x."""
+    return np.array([[cx + h, cy], [cx, cy + h], [cx - h, cy], [cx, cy - h]])
+
+
+@pytest.mark.parametrize("d,shift", [(0.8, False), (1.5, False), (2.5, False), (1.0, True)])
+def test_contact_force_formula(orc, d, shift):
+    """Two diamonds whose facing vertices are d apart (one pair inside the
+    2 dx cutoff, every other pair beyond it): each of the two vertices gets
+    (1e-4 / (8 sqrt 2)) d^(-5/2) along its own inward normal, nothing beyond
+    the cutoff, and no other vertex is pushed.  With shift the pair faces
+    across the periodic x boundary."""
+    from paper_1903_03356_amd import workloads as wl
+    nx = 40
+    cfg = wl.periodic_box(nx, 24, 0.8, real_bytes=8, mode="kinematic")
+    if shift:
+        a, b = _diamond(nx - 2.0 - d / 2, 12.0), _diamond(2.0 + d / 2, 12.0)
+    else:
+        a, b = _diamond(16.0, 12.0), _diamond(16.0 + 4.0 + d, 12.0)
+    cfg["capsules"] = [wl.capsule(a, 0.0, 0.0, 0.0), wl.capsule(b, 0.0, 0.0, 0.0)]
+    cfg["contact_cutoff"] = 2.0
+    s = orc.Sim(cfg)
+    s.step(1)
+    fa, fb = s.contact(0), s.contact(1)
+    mag = 1e-4 / (8.0 * math.sqrt(2.0)) * d ** -2.5 if d < 2.0 else 0.0
+    np.testing.assert_allclose(fa[0], [-mag, 0.0], rtol=1e-12, atol=1e-20)
+    np.testing.assert_allclose(fb[2], [mag, 0.0], rtol=1e-12, atol=1e-20)
+    assert np.all(fa[1:] == 0.0) and np.all(fb[[0, 1, 3]] == 0.0)
+
+
+def test_contact_force_off_by_default(orc):
+    from paper_1903_03356_amd import workloads as wl
+    cfg = wl.periodic_box(40, 24, 0.8, real_bytes=8, mode="kinematic")
+    cfg["capsules"] = [wl.capsule(_diamond(16.0, 12.0), 0.0, 0.0, 0.0),
+                       wl.capsule(_diamond(21.0, 12.0), 0.0, 0.0, 0.0)]
+    s = orc.Sim(cfg)
+    s.step(1)
+    assert np.all(s.contact(0) == 0.0)
