@@ -57,7 +57,8 @@ typedef enum { LBIB_KINEMATIC = 0, LBIB_DYNAMIC = 1 } lbib_mode;
 /* Status bits raised by the device.  lbib_check returns LBIB_ENUMERIC if any
  * is set: */
 enum lbib_device_flags {
-    LBIB_FLAG_WALL = 1,       /* an MLS support touched a wall row (needs 1 <= y <= ny-2) */
+    LBIB_FLAG_WALL = 1,       /* an MLS support touched a wall row (needs 1 <= y <= ny-2) or an
+                                 open-channel inlet / outlet column */
     LBIB_FLAG_NONFINITE = 2,  /* a node position or staged density is NaN/Inf */
     LBIB_FLAG_PATCH = 4,      /* a capsule's fluid patch exceeded the on-chip capacity */
     LBIB_FLAG_OVERFLOW = 8,   /* a spread force left the fixed-point range (|f| >= 2^14) */
@@ -74,14 +75,22 @@ typedef struct {
 } lbib_grid;
 
 typedef struct {
-    int32_t periodic_x;     /* must be 1: x is periodic */
+    int32_t periodic_x;     /* 1: x is periodic; 0: open channel (Sec. 3.2): Zou-He velocity inlet at
+                               x = 0 with u_x = 4 inlet_umax y (H - y) / H^2, u_y = 0, and Zou-He
+                               pressure outlet at x = nx-1 with rho = outlet_rho; needs stationary
+                               walls (periodic_y = 0, wall speeds 0) and body_force_x = 0.  Corner
+                               nodes: bounce-back of the non-equilibrium part, the two buried
+                               populations share the mass deficit with the density of the inner
+                               diagonal neighbour.  Capsule nodes must keep 3 <= x <= nx - 4 */
     int32_t periodic_y;     /* 1: fully periodic box; 0: Zou-He walls at y = 0, ny-1 (Sec. 2.1, ref. [36]) */
     double u_bottom, u_top; /* tangential wall speeds (lattice units) */
     double body_force_x;    /* uniform body force g added to the IB force everywhere (0 for none) */
     int32_t init_profile;   /* initial velocity: 0 rest, 1 linear between the wall speeds,
                                2 body-force Poiseuille g/(2 nu) y (H - y), H = ny - 1,
-                               3 uniform (init_ux, init_uy) */
+                               3 uniform (init_ux, init_uy), 4 the inlet parabola (open channel) */
     double init_ux, init_uy;
+    double inlet_umax;      /* open channel: peak inlet speed */
+    double outlet_rho;      /* open channel: outlet density, (0.5, 2) */
 } lbib_walls;
 
 /* Caller-owned device buffers, bound at lbib_create in this order. */
@@ -139,7 +148,8 @@ size_t lbib_required_bytes(const lbib_grid* grid, int32_t buffer_id);
  * hipStream_t (NULL = the default stream).
  * The call zeroes the force and flag buffers and writes the initial
  * populations f^0 = f^eq(1, u_init) (Eq. 2), queued on the stream.
- * Errors: EINVAL (nx or ny < 8, tau <= 1/2, periodic_x != 1, real_bytes not 4 or 8,
+ * Errors: EINVAL (nx or ny < 8, tau <= 1/2, periodic_x not 0 or 1, an open channel
+ * with moving or periodic walls or a body force, real_bytes not 4 or 8,
  * non-finite values, NULL buffers), ECAPACITY (capacities out of range),
  * EDEVICE (HIP failure).  *out is set only on success. */
 lbib_status lbib_create(const lbib_grid* grid, double tau, const lbib_walls* walls,
@@ -307,8 +317,8 @@ size_t lbib_adjoint_bytes(const lbib_ctx* ctx, int32_t nsteps);
  * positions); the fixed-point rounding of the spread force is not
  * differentiated.
  * Errors: EINVAL (batch context, nsteps < 1, bad mode, objective or capsule
- * id, a capsule with k_b != 0, the contact force on, workspace or n_ks too
- * small, NULL pointers),
+ * id, a capsule with k_b != 0, the contact force on, an open channel,
+ * workspace or n_ks too small, NULL pointers),
  * ESTATE (context not at step 0, or its mode differs), ECAPACITY (capsules too
  * large for the on-chip memory of the reverse IB kernel), ENUMERIC (a device
  * status flag in the forward run or the reverse sweep), EDEVICE.

@@ -70,6 +70,8 @@ typedef struct {
 
 typedef struct {
     int nx, ny, periodic_y;
+    int periodic_x;            /* 0: velocity inlet at x = 0, pressure outlet at x = nx-1 */
+    double u_in, rho_out;      /* inlet peak speed (parabolic profile), outlet density */
     double tau, nu;
     double u_bot, u_top, gx, gy;
     double *f, *ftmp;          /* [nx][ny][9] */
@@ -337,28 +339,79 @@ static void *xcalloc(size_t n, size_t sz)
  * (Sec. 2.1, ref. [36]); the wall moves along x at u_w.  Reading: with a body
  * force F at the wall node the tangential momentum target is rho u_w - F_x / 2,
  * so that the force-corrected velocity (Eq. 7) equals the wall speed; the wall
- * normal force is zero in every configuration here. */
+ * normal force is zero in every configuration here.
+ * Open channel (periodic_x = 0, Sec. 3.2): Zou-He velocity inlet at x = 0 with
+ * the parabolic profile u_x = -u_max((1 - y/(H/2))^2 - 1) = 4 u_max y (H - y) / H^2,
+ * u_y = 0, and Zou-He pressure outlet at x = nx-1 with rho = rho_out, u_y = 0
+ * (stationary walls and no body force there).  Corner nodes (u = 0): the
+ * unknowns opposite a known population take it (bounce-back of the
+ * non-equilibrium part), the two remaining "buried" populations share the
+ * mass deficit, with the corner density read from the inner diagonal
+ * neighbour at the same time level (reading: the paper does not treat the
+ * corners). */
+static void corner(orc_sim *s, double *f, int x, int y, int nbx, int nby, const int pair[3][2],
+                   int b1, int b2)
+{
+    double *g = f + cid(s, x, y) * 9;
+    const double *h = f + cid(s, nbx, nby) * 9;
+    double rho = 0.0;
+    for (int i = 0; i < 9; i++) rho += h[i];
+    for (int p = 0; p < 3; p++) g[pair[p][0]] = g[pair[p][1]];
+    double known = 0.0;
+    for (int i = 0; i < 9; i++)
+        if (i != b1 && i != b2) known += g[i];
+    g[b1] = g[b2] = 0.5 * (rho - known);
+}
+
 static void zou_he(orc_sim *s, double *f, const double *F)
 {
-    if (s->periodic_y) return;
-    for (int x = 0; x < s->nx; x++) {
-        /* bottom wall: f2, f5, f6 unknown */
-        double *g = f + cid(s, x, 0) * 9;
-        double Fx = F[cid(s, x, 0) * 2];
-        double rw = g[0] + g[1] + g[3] + 2.0 * (g[4] + g[7] + g[8]);
-        double mx = rw * s->u_bot - 0.5 * Fx;
-        g[2] = g[4];
-        g[5] = g[7] - 0.5 * (g[1] - g[3]) + 0.5 * mx;
-        g[6] = g[8] + 0.5 * (g[1] - g[3]) - 0.5 * mx;
-        /* top wall: f4, f7, f8 unknown */
-        g = f + cid(s, x, s->ny - 1) * 9;
-        Fx = F[cid(s, x, s->ny - 1) * 2];
-        rw = g[0] + g[1] + g[3] + 2.0 * (g[2] + g[5] + g[6]);
-        mx = rw * s->u_top - 0.5 * Fx;
-        g[4] = g[2];
-        g[7] = g[5] + 0.5 * (g[1] - g[3]) - 0.5 * mx;
-        g[8] = g[6] - 0.5 * (g[1] - g[3]) + 0.5 * mx;
+    if (!s->periodic_y) {
+        int xa = s->periodic_x ? 0 : 1, xb = s->periodic_x ? s->nx : s->nx - 1;
+        for (int x = xa; x < xb; x++) {
+            /* bottom wall: f2, f5, f6 unknown */
+            double *g = f + cid(s, x, 0) * 9;
+            double Fx = F[cid(s, x, 0) * 2];
+            double rw = g[0] + g[1] + g[3] + 2.0 * (g[4] + g[7] + g[8]);
+            double mx = rw * s->u_bot - 0.5 * Fx;
+            g[2] = g[4];
+            g[5] = g[7] - 0.5 * (g[1] - g[3]) + 0.5 * mx;
+            g[6] = g[8] + 0.5 * (g[1] - g[3]) - 0.5 * mx;
+            /* top wall: f4, f7, f8 unknown */
+            g = f + cid(s, x, s->ny - 1) * 9;
+            Fx = F[cid(s, x, s->ny - 1) * 2];
+            rw = g[0] + g[1] + g[3] + 2.0 * (g[2] + g[5] + g[6]);
+            mx = rw * s->u_top - 0.5 * Fx;
+            g[4] = g[2];
+            g[7] = g[5] + 0.5 * (g[1] - g[3]) - 0.5 * mx;
+            g[8] = g[6] - 0.5 * (g[1] - g[3]) + 0.5 * mx;
+        }
     }
+    if (s->periodic_x) return;
+    const double H = s->ny - 1;
+    for (int y = 1; y < s->ny - 1; y++) {
+        /* inlet x = 0: velocity (u_in(y), 0) known, f1, f5, f8 unknown */
+        double *g = f + cid(s, 0, y) * 9;
+        double ux = 4.0 * s->u_in * y * (H - y) / (H * H);
+        double rho = (g[0] + g[2] + g[4] + 2.0 * (g[3] + g[6] + g[7])) / (1.0 - ux);
+        g[1] = g[3] + 2.0 / 3.0 * rho * ux;
+        g[5] = g[7] - 0.5 * (g[2] - g[4]) + rho * ux / 6.0;
+        g[8] = g[6] + 0.5 * (g[2] - g[4]) + rho * ux / 6.0;
+        /* outlet x = nx-1: density rho_out known, f3, f6, f7 unknown */
+        g = f + cid(s, s->nx - 1, y) * 9;
+        double uo = (g[0] + g[2] + g[4] + 2.0 * (g[1] + g[5] + g[8])) / s->rho_out - 1.0;
+        g[3] = g[1] - 2.0 / 3.0 * s->rho_out * uo;
+        g[7] = g[5] + 0.5 * (g[2] - g[4]) - s->rho_out * uo / 6.0;
+        g[6] = g[8] - 0.5 * (g[2] - g[4]) - s->rho_out * uo / 6.0;
+    }
+    const int nx = s->nx, ny = s->ny;
+    static const int bl[3][2] = {{1, 3}, {2, 4}, {5, 7}};
+    static const int tl[3][2] = {{1, 3}, {4, 2}, {8, 6}};
+    static const int br[3][2] = {{3, 1}, {2, 4}, {6, 8}};
+    static const int tr[3][2] = {{3, 1}, {4, 2}, {7, 5}};
+    corner(s, f, 0, 0, 1, 1, bl, 6, 8);
+    corner(s, f, 0, ny - 1, 1, ny - 2, tl, 5, 7);
+    corner(s, f, nx - 1, 0, nx - 2, 1, br, 5, 7);
+    corner(s, f, nx - 1, ny - 1, nx - 2, ny - 2, tr, 6, 8);
 }
 
 /* Eqs. 6-7: rho = sum f, rho u = sum f e + F/2 (reading: the half term is the
@@ -406,7 +459,9 @@ static void collide_stream(orc_sim *s)
             orc_forcing(s->tau, ux, uy, F[c * 2], F[c * 2 + 1], src);
             for (int i = 0; i < 9; i++) {
                 double post = g[i] - (g[i] - feq[i]) / s->tau + src[i];
-                int xd = wrap(x + EX[i], s->nx), yd = y + EY[i];
+                int xd = x + EX[i], yd = y + EY[i];
+                if (s->periodic_x) xd = wrap(xd, s->nx);
+                else if (xd < 0 || xd >= s->nx) continue;
                 if (s->periodic_y) yd = wrap(yd, s->ny);
                 else if (yd < 0 || yd >= s->ny) continue;
                 s->ftmp[cid(s, xd, yd) * 9 + i] = post;
@@ -423,6 +478,10 @@ static void collide_stream(orc_sim *s)
 static int field_index(orc_sim *s, int cx, int cy, size_t *out)
 {
     int x = wrap(cx, s->nx), y = cy;
+    if (!s->periodic_x && (cx < 1 || cx > s->nx - 2)) {
+        s->status |= ORC_E_WALL;
+        return 0;
+    }
     if (s->periodic_y) y = wrap(cy, s->ny);
     else if (cy < 1 || cy > s->ny - 2) {
         s->status |= ORC_E_WALL;
@@ -544,12 +603,16 @@ int orc_get_threads(void)
  * f^0 = f^eq(1, u_init); the wall condition is then applied with F = g and the
  * moments are taken with half of F^{-1} = g. */
 orc_sim *orc_create(int nx, int ny, double tau, int periodic_y, double u_bot, double u_top,
-                    double gx, double gy, int init_profile, double u0x, double u0y)
+                    double gx, double gy, int init_profile, double u0x, double u0y, int periodic_x,
+                    double u_in, double rho_out)
 {
     orc_sim *s = (orc_sim *)xcalloc(1, sizeof(orc_sim));
     s->nx = nx;
     s->ny = ny;
     s->periodic_y = periodic_y;
+    s->periodic_x = periodic_x;
+    s->u_in = u_in;
+    s->rho_out = rho_out;
     s->tau = tau;
     s->nu = CS2 * (tau - 0.5); /* Sec. 2.1, dt = 1 */
     s->u_bot = u_bot;
@@ -572,6 +635,7 @@ orc_sim *orc_create(int nx, int ny, double tau, int periodic_y, double u_bot, do
             if (init_profile == 1) ux = u_bot + (u_top - u_bot) * y / H;
             else if (init_profile == 2) ux = gx / (2.0 * s->nu) * y * (H - y);
             else if (init_profile == 3) { ux = u0x; uy = u0y; }
+            else if (init_profile == 4) ux = 4.0 * u_in * y * (H - y) / (H * H);
             orc_equilibrium(1.0, ux, uy, s->f + cid(s, x, y) * 9);
             s->F[cid(s, x, y) * 2] = gx;
             s->F[cid(s, x, y) * 2 + 1] = gy;
@@ -670,7 +734,7 @@ static void contact_forces(orc_sim *s)
                 for (int j = 0; j < kb->nv; j++) {
                     double dx = kb->x[2 * j] - ka->x[2 * i];
                     double dy = kb->x[2 * j + 1] - ka->x[2 * i + 1];
-                    dx -= s->nx * nearbyint(dx / s->nx);
+                    if (s->periodic_x) dx -= s->nx * nearbyint(dx / s->nx);
                     if (s->periodic_y) dy -= s->ny * nearbyint(dy / s->ny);
                     double d = hypot(dx, dy);
                     if (d < s->contact_cutoff && d > 0.0) {

@@ -53,7 +53,8 @@ def lib() -> C.CDLL:
     L.orc_polygon_diag.argtypes = [C.c_int, _dp, _dp]
     L.orc_create.restype = vp
     L.orc_create.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_double, C.c_double,
-                             C.c_double, C.c_double, C.c_int, C.c_double, C.c_double]
+                             C.c_double, C.c_double, C.c_int, C.c_double, C.c_double, C.c_int,
+                             C.c_double, C.c_double]
     L.orc_destroy.argtypes = [vp]
     L.orc_add_capsule.argtypes = [vp, C.c_int, _dp, _dp, C.c_int, C.c_double, C.c_double,
                                   C.c_double]
@@ -142,7 +143,9 @@ class Sim:
         self.h = L.orc_create(self.nx, self.ny, float(cfg["tau"]), int(cfg.get("periodic_y", 0)),
                               float(cfg.get("u_bottom", 0.0)), float(cfg.get("u_top", 0.0)),
                               float(cfg.get("body_force_x", 0.0)), 0.0,
-                              int(cfg.get("init_profile", 0)), float(ux0), float(uy0))
+                              int(cfg.get("init_profile", 0)), float(ux0), float(uy0),
+                              int(cfg.get("periodic_x", 1)), float(cfg.get("inlet_umax", 0.0)),
+                              float(cfg.get("outlet_rho", 1.0)))
         self.nodes = []
         for cap in cfg.get("capsules", []):
             nodes = np.ascontiguousarray(cap["nodes"], np.float64)

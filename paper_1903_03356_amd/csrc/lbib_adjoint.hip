@@ -779,9 +779,12 @@ __global__ __launch_bounds__(kIBThreads) void k_ib_adj(IBAdjArgs<T> a)
     g.nxp = cap.nxp;
     g.nseg = cap.nseg;
     g.periodic_y = cap.periodic_y;
+    g.periodic_x = cap.periodic_x;
     g.omega = 0.0;
     g.gx = cap.gx;
     g.u_bot = g.u_top = 0.0;
+    g.u_in = 0.0;
+    g.rho_out = 1.0;
     const size_t plane = (size_t)g.ny * g.nxp;
     T* lam_p = a.lam_p + cap.pop_off;
     T* lfm = a.lfm + cap.fib_off;

@@ -210,6 +210,9 @@ static GridArgs grid_args(const Inst& I)
     g.gx = I.walls.body_force_x;
     g.u_bot = I.walls.periodic_y ? 0.0 : I.walls.u_bottom;
     g.u_top = I.walls.periodic_y ? 0.0 : I.walls.u_top;
+    g.periodic_x = I.walls.periodic_x;
+    g.u_in = I.walls.periodic_x ? 0.0 : I.walls.inlet_umax;
+    g.rho_out = I.walls.periodic_x ? 1.0 : I.walls.outlet_rho;
     return g;
 }
 
@@ -288,15 +291,28 @@ static lbib_status check_lattice(const lbib_grid* grid, double tau, const lbib_w
         return fail(nullptr, LBIB_EINVAL, "real_bytes must be 4 or 8");
     if (!grid_ok(grid)) return fail(nullptr, LBIB_ECAPACITY, "grid capacities out of range");
     if (!(std::isfinite(tau) && tau > 0.5)) return fail(nullptr, LBIB_EINVAL, "tau must be > 1/2");
-    if (walls->periodic_x != 1) return fail(nullptr, LBIB_EINVAL, "periodic_x must be 1");
+    if (walls->periodic_x != 0 && walls->periodic_x != 1)
+        return fail(nullptr, LBIB_EINVAL, "periodic_x must be 0 or 1");
     if (walls->periodic_y != 0 && walls->periodic_y != 1)
         return fail(nullptr, LBIB_EINVAL, "periodic_y must be 0 or 1");
     if (!(std::isfinite(walls->u_bottom) && std::isfinite(walls->u_top) &&
           std::isfinite(walls->body_force_x) && std::isfinite(walls->init_ux) &&
-          std::isfinite(walls->init_uy)))
+          std::isfinite(walls->init_uy) && std::isfinite(walls->inlet_umax) &&
+          std::isfinite(walls->outlet_rho)))
         return fail(nullptr, LBIB_EINVAL, "non-finite wall or profile value");
-    if (walls->init_profile < 0 || walls->init_profile > 3)
-        return fail(nullptr, LBIB_EINVAL, "init_profile must be 0..3");
+    if (walls->init_profile < 0 || walls->init_profile > 4)
+        return fail(nullptr, LBIB_EINVAL, "init_profile must be 0..4");
+    if (!walls->periodic_x) {
+        if (walls->periodic_y || walls->u_bottom != 0.0 || walls->u_top != 0.0 ||
+            walls->body_force_x != 0.0)
+            return fail(nullptr, LBIB_EINVAL,
+                        "an open channel (periodic_x = 0) needs stationary walls and no body force");
+        if (!(walls->outlet_rho > 0.5 && walls->outlet_rho < 2.0) ||
+            !(std::fabs(walls->inlet_umax) < 0.3))
+            return fail(nullptr, LBIB_EINVAL, "outlet_rho must be in (0.5, 2), |inlet_umax| < 0.3");
+    } else if (walls->init_profile == 4) {
+        return fail(nullptr, LBIB_EINVAL, "init_profile 4 (inlet parabola) needs periodic_x = 0");
+    }
     return LBIB_OK;
 }
 
@@ -379,6 +395,9 @@ static lbib_status create_common(const lbib_grid* grids, const double* taus,
         d.nxp = g.nxp;
         d.nseg = g.nseg;
         d.periodic_y = g.periodic_y;
+        d.periodic_x = g.periodic_x;
+        d.u_in = g.u_in;
+        d.rho_out = g.rho_out;
         d.block0 = I.block0;
         d.pop_off = (int64_t)I.pop_off;
         d.fib_off = (int64_t)I.fib_off;
@@ -504,6 +523,7 @@ static lbib_status add_capsule_t(lbib_ctx* c, int inst, const double* xy, int n,
     cd.nxp = g.nxp;
     cd.nseg = g.nseg;
     cd.periodic_y = g.periodic_y;
+    cd.periodic_x = g.periodic_x;
     cd.pop_off = (int64_t)I.pop_off;
     cd.fib_off = (int64_t)I.fib_off;
     cd.flag_off = (int64_t)I.flag_off;
@@ -550,6 +570,10 @@ extern "C" lbib_status lbib_add_capsule_to(lbib_ctx* c, int32_t inst, const doub
         for (int v = 0; v < n; v++)
             if (xy[2 * v + 1] < 3.0 || xy[2 * v + 1] > I.grid.ny - 4.0)
                 return fail(c, LBIB_EINVAL, "nodes must satisfy 3 <= y <= ny - 4");
+    if (!I.walls.periodic_x)
+        for (int v = 0; v < n; v++)
+            if (xy[2 * v] < 3.0 || xy[2 * v] > I.grid.nx - 4.0)
+                return fail(c, LBIB_EINVAL, "open channel: nodes must satisfy 3 <= x <= nx - 4");
     return c->rb == 4 ? add_capsule_t<float>(c, inst, xy, n, ks, n_ks, kb, ka, mass, id)
                       : add_capsule_t<double>(c, inst, xy, n, ks, n_ks, kb, ka, mass, id);
 }
@@ -1198,6 +1222,8 @@ extern "C" lbib_status lbib_adjoint(lbib_ctx* c, int32_t nsteps, lbib_mode mode,
         if (kb != 0.0) return fail(c, LBIB_EINVAL, "the adjoint needs k_b = 0 for every capsule");
     if (c->contact_cutoff > 0.0 && c->ncap > 1)
         return fail(c, LBIB_EINVAL, "the adjoint does not differentiate the contact force");
+    if (!c->L.inst[0].walls.periodic_x)
+        return fail(c, LBIB_EINVAL, "the adjoint needs a periodic channel (periodic_x = 1)");
     if (n_ks < c->nodes_used) return fail(c, LBIB_EINVAL, "out_dJ_dks shorter than the node count");
     AdjLayout A;
     if (!adj_layout(c, nsteps, A)) return fail(c, LBIB_EINVAL, "invalid adjoint layout");

@@ -51,16 +51,97 @@ __device__ __forceinline__ T relax(T s, T w, T w3, T eu, T em, T eF, T drho, T r
     return s - om * (s - seq) + src;
 }
 
+// Raw pull of the nine populations arriving at an interior node.
+template <typename T>
+__device__ __forceinline__ void pull_interior(const T* __restrict__ src, int x, int y,
+                                              const GridArgs& g, T s[9])
+{
+    const size_t plane = (size_t)g.ny * g.nxp;
+    const size_t r0 = (size_t)y * g.nxp, rm = (size_t)(y - 1) * g.nxp, rp = (size_t)(y + 1) * g.nxp;
+    s[0] = src[r0 + x];
+    s[1] = src[plane + r0 + x - 1];
+    s[2] = src[2 * plane + rm + x];
+    s[3] = src[3 * plane + r0 + x + 1];
+    s[4] = src[4 * plane + rp + x];
+    s[5] = src[5 * plane + rm + x - 1];
+    s[6] = src[6 * plane + rm + x + 1];
+    s[7] = src[7 * plane + rp + x + 1];
+    s[8] = src[8 * plane + rp + x - 1];
+}
+
+// Open channel (Sec. 3.2): Zou-He velocity inlet at x = 0 with the parabolic
+// profile u_x = 4 u_max y (H - y) / H^2, u_y = 0 (f1, f5, f8 unknown), and
+// Zou-He pressure outlet at x = nx - 1 with rho = rho_out, u_y = 0 (f3, f6, f7
+// unknown); no force acts on these columns.  Corners (u = 0): each unknown
+// opposite a known population takes it, the two buried diagonal populations
+// share the mass deficit, with the density of the inner diagonal neighbour at
+// this time level.  Deviation form: the known weights sum to 1, so the
+// textbook formulas keep their shape with 1 + sum(s) for sum(f).
+template <typename T>
+__device__ __forceinline__ void open_boundary(const T* __restrict__ src, int x, int y,
+                                              const GridArgs& g, T s[9])
+{
+    const bool bot = y == 0, top = y == g.ny - 1;
+    if (bot || top) {
+        T h[9];
+        pull_interior(src, x == 0 ? 1 : g.nx - 2, bot ? 1 : g.ny - 2, g, h);
+        const T drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+        if (x == 0 && bot) {
+            s[1] = s[3];
+            s[2] = s[4];
+            s[5] = s[7];
+            s[6] = s[8] = T(0.5) * (drho - (s[0] + s[1] + s[2] + s[3] + s[4] + s[5] + s[7]));
+        } else if (x == 0) {
+            s[1] = s[3];
+            s[4] = s[2];
+            s[8] = s[6];
+            s[5] = s[7] = T(0.5) * (drho - (s[0] + s[1] + s[2] + s[3] + s[4] + s[6] + s[8]));
+        } else if (bot) {
+            s[3] = s[1];
+            s[2] = s[4];
+            s[6] = s[8];
+            s[5] = s[7] = T(0.5) * (drho - (s[0] + s[1] + s[2] + s[3] + s[4] + s[6] + s[8]));
+        } else {
+            s[3] = s[1];
+            s[4] = s[2];
+            s[7] = s[5];
+            s[6] = s[8] = T(0.5) * (drho - (s[0] + s[1] + s[2] + s[3] + s[4] + s[5] + s[7]));
+        }
+        return;
+    }
+    const T H = (T)(g.ny - 1);
+    if (x == 0) {
+        const T ux = T(4) * (T)g.u_in * (T)y * (H - (T)y) / (H * H);
+        const T rho = (T(1) + s[0] + s[2] + s[4] + T(2) * (s[3] + s[6] + s[7])) / (T(1) - ux);
+        const T m = rho * ux;
+        s[1] = s[3] + T(2.0 / 3.0) * m;
+        s[5] = s[7] - T(0.5) * (s[2] - s[4]) + m * T(1.0 / 6.0);
+        s[8] = s[6] + T(0.5) * (s[2] - s[4]) + m * T(1.0 / 6.0);
+    } else {
+        const T ro = (T)g.rho_out;
+        const T uo = (T(1) + s[0] + s[2] + s[4] + T(2) * (s[1] + s[5] + s[8])) / ro - T(1);
+        const T m = ro * uo;
+        s[3] = s[1] - T(2.0 / 3.0) * m;
+        s[7] = s[5] + T(0.5) * (s[2] - s[4]) - m * T(1.0 / 6.0);
+        s[6] = s[8] - T(0.5) * (s[2] - s[4]) - m * T(1.0 / 6.0);
+    }
+}
+
 // Pulls the nine populations arriving at (x, y) from the post-collision field
 // and completes the wall rows with Zou-He (unknowns from the knowns, tangential
-// momentum target rho_w u_w - F_x / 2).
+// momentum target rho_w u_w - F_x / 2) and, in an open channel, the inlet and
+// outlet columns.
 template <typename T>
 __device__ __forceinline__ void pull(const T* __restrict__ src, int x, int y, const GridArgs& g,
                                      T Fx, T s[9])
 {
     const size_t plane = (size_t)g.ny * g.nxp;
-    const int xm = x == 0 ? g.nx - 1 : x - 1;
-    const int xp = x == g.nx - 1 ? 0 : x + 1;
+    int xm = x == 0 ? g.nx - 1 : x - 1;
+    int xp = x == g.nx - 1 ? 0 : x + 1;
+    if (!g.periodic_x) {  // clamped: the unknown slots are replaced below
+        xm = x == 0 ? 0 : xm;
+        xp = x == g.nx - 1 ? x : xp;
+    }
     int ym, yp;
     if (g.periodic_y) {
         ym = y == 0 ? g.ny - 1 : y - 1;
@@ -79,6 +160,10 @@ __device__ __forceinline__ void pull(const T* __restrict__ src, int x, int y, co
     s[6] = src[6 * plane + rm + xp];
     s[7] = src[7 * plane + rp + xp];
     s[8] = src[8 * plane + rp + xm];
+    if (!g.periodic_x && (x == 0 || x == g.nx - 1)) {
+        open_boundary(src, x, y, g, s);
+        return;
+    }
     if (!g.periodic_y) {
         if (y == 0) {
             const T rw = T(1) + s[0] + s[1] + s[3] + T(2) * (s[4] + s[7] + s[8]);
@@ -133,7 +218,12 @@ __device__ __forceinline__ void stage_cell(const IBArgs<T>& a, const GridArgs& g
         return;
     }
     long long wx = refx + P.ox + lx;
-    wx = ((wx % g.nx) + g.nx) % g.nx;
+    if (g.periodic_x) wx = ((wx % g.nx) + g.nx) % g.nx;
+    else if (wx < 1 || wx > g.nx - 2) {
+        P.drho[i] = T(NAN);
+        P.ux[i] = P.uy[i] = T(0);
+        return;
+    }
     T s[9];
     pull(a.pops, (int)wx, (int)wy, g, gxf, s);
     const size_t cell = (size_t)wy * g.nxp + (size_t)wx;

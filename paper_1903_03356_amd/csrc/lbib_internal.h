@@ -42,14 +42,15 @@ enum NodeField {
 struct InstDev {
     int32_t nx, ny, nxp, nseg;
     int32_t periodic_y, block0;  // block0: first block of the lattice in a batched grid launch
-    int32_t pad0, pad1;
+    int32_t periodic_x, pad1;    // periodic_x = 0: velocity inlet x = 0, pressure outlet x = nx-1
     int64_t pop_off;   // offset of the lattice's planes in a population buffer (elements)
     int64_t fib_off;   // offset in one time level of the force field (long long elements)
     int64_t flag_off;  // offset in one time level of the segment flags (ints)
     int64_t pad2;
     double omega, gx, u_bot, u_top;
+    double u_in, rho_out;        // inlet peak speed, outlet density (open channel)
 };
-static_assert(sizeof(InstDev) == 96, "InstDev layout");
+static_assert(sizeof(InstDev) == 112, "InstDev layout");
 
 struct CapsuleDev {
     int32_t node_offset;
@@ -61,7 +62,7 @@ struct CapsuleDev {
     // the capsule's lattice, copied from its InstDev so that the IB kernel
     // needs no second dependent load
     int32_t nx, ny, nxp, nseg;
-    int32_t periodic_y, pad0;
+    int32_t periodic_y, periodic_x;
     int64_t pop_off, fib_off, flag_off;
     double gx, nu;
     double pad1;
@@ -85,9 +86,11 @@ enum Phase { PH_PRIME = 1, PH_B = 2, PH_A = 4, PH_DIAG = 8 };
 
 struct GridArgs {
     int nx, ny, nxp, nseg, periodic_y;
-    double omega;  // 1 / tau
-    double gx;     // uniform body force
+    int periodic_x;  // 0: Zou-He velocity inlet at x = 0, pressure outlet at x = nx - 1
+    double omega;    // 1 / tau
+    double gx;       // uniform body force
     double u_bot, u_top;
+    double u_in, rho_out;  // inlet peak speed (parabolic profile), outlet density
 };
 
 // Buffer bases of an IB launch; each block adds its capsule's lattice offsets.

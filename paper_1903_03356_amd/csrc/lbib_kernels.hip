@@ -264,10 +264,13 @@ __global__ __launch_bounds__(kSegW * 4) void k_grid_step_batch(
     g.nxp = I.nxp;
     g.nseg = I.nseg;
     g.periodic_y = I.periodic_y;
+    g.periodic_x = I.periodic_x;
     g.omega = I.omega;
     g.gx = I.gx;
     g.u_bot = I.u_bot;
     g.u_top = I.u_top;
+    g.u_in = I.u_in;
+    g.rho_out = I.rho_out;
     const int lb = b - I.block0;
     const int j = lb / kNumXcd;
     const int group = j / g.nseg;
@@ -317,6 +320,7 @@ __global__ void k_init(T* pops, GridArgs g, int profile, double ux0, double uy0,
         if (profile == 1) ux = g.u_bot + (g.u_top - g.u_bot) * yd / H;
         else if (profile == 2) ux = g.gx / (2.0 * nu) * yd * (H - yd);
         else if (profile == 3) { ux = ux0; uy = uy0; }
+        else if (profile == 4) ux = 4.0 * g.u_in * yd * (H - yd) / (H * H);
         const double eu = kEx[i] * ux + kEy[i] * uy;
         const double w = i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
         const double dev = w * (3.0 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy));
@@ -667,7 +671,8 @@ __device__ __forceinline__ void spread_one(const IBArgs<T>& a, const GridArgs& g
     if (g.periodic_y) gy = ((gy % g.ny) + g.ny) % g.ny;
     else if (gy < 1 || gy > g.ny - 2) { st |= ST_WALL; return; }
     long long gx = refx + cx + k % 3 - 1;
-    gx = ((gx % g.nx) + g.nx) % g.nx;
+    if (g.periodic_x) gx = ((gx % g.nx) + g.nx) % g.nx;
+    else if (gx < 1 || gx > g.nx - 2) { st |= ST_WALL; return; }
     const long long fx = to_fix(vx, st), fy = to_fix(vy, st);
     const size_t cell = (size_t)gy * g.nxp + (size_t)gx;
     unsigned long long* dst = reinterpret_cast<unsigned long long*>(a.fib_next + 2 * cell);
@@ -787,9 +792,12 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
     g.nxp = cap.nxp;
     g.nseg = cap.nseg;
     g.periodic_y = cap.periodic_y;
+    g.periodic_x = cap.periodic_x;
     g.omega = 0.0;
     g.gx = cap.gx;
-    g.u_bot = g.u_top = 0.0;  // wall rows are never staged
+    g.u_bot = g.u_top = 0.0;  // wall rows and open-channel columns are never staged
+    g.u_in = 0.0;
+    g.rho_out = 1.0;
     const int nv = cap.nv, off = cap.node_offset;
     const size_t NS = a.node_stride;
     T* N = a.nodes;
@@ -1177,7 +1185,7 @@ __global__ __launch_bounds__(kIBThreads) void k_contact(ContactArgs<T> a)
         const float4 ob = a.bounds[o];
         // box test with the nearest periodic image in x (and y when periodic)
         float sx = (0.5f * (ob.x + ob.z)) - (0.5f * (me.x + me.z));
-        sx -= (float)Lx * rintf(sx / (float)Lx);
+        if (cap.periodic_x) sx -= (float)Lx * rintf(sx / (float)Lx);
         float sy = (0.5f * (ob.y + ob.w)) - (0.5f * (me.y + me.w));
         if (cap.periodic_y) sy -= (float)Ly * rintf(sy / (float)Ly);
         const float hx = 0.5f * ((ob.z - ob.x) + (me.z - me.x)) + cut;
@@ -1196,7 +1204,7 @@ __global__ __launch_bounds__(kIBThreads) void k_contact(ContactArgs<T> a)
             double fx = 0.0, fy = 0.0;
             for (int j = 0; j < oc.nv; j++) {
                 double dx = BX[j] - X[v], dy = BY[j] - Y[v];
-                dx -= Lx * rint(dx / Lx);
+                if (cap.periodic_x) dx -= Lx * rint(dx / Lx);
                 if (cap.periodic_y) dy -= Ly * rint(dy / Ly);
                 const double d = sqrt(dx * dx + dy * dy);
                 if (d < a.cutoff && d > 0.0) {

@@ -49,7 +49,8 @@ class lbib_walls(C.Structure):
     _fields_ = [("periodic_x", C.c_int32), ("periodic_y", C.c_int32),
                 ("u_bottom", C.c_double), ("u_top", C.c_double),
                 ("body_force_x", C.c_double), ("init_profile", C.c_int32),
-                ("init_ux", C.c_double), ("init_uy", C.c_double)]
+                ("init_ux", C.c_double), ("init_uy", C.c_double),
+                ("inlet_umax", C.c_double), ("outlet_rho", C.c_double)]
 
 
 class LbibError(RuntimeError):
@@ -154,9 +155,11 @@ def grid_of(cfg: Dict[str, Any], max_capsules: int = 0, max_nodes_total: int = 0
 
 def walls_of(cfg: Dict[str, Any]) -> lbib_walls:
     ux0, uy0 = cfg.get("init_u", (0.0, 0.0))
-    return lbib_walls(1, int(cfg.get("periodic_y", 0)), float(cfg.get("u_bottom", 0.0)),
-                      float(cfg.get("u_top", 0.0)), float(cfg.get("body_force_x", 0.0)),
-                      int(cfg.get("init_profile", 0)), float(ux0), float(uy0))
+    return lbib_walls(int(cfg.get("periodic_x", 1)), int(cfg.get("periodic_y", 0)),
+                      float(cfg.get("u_bottom", 0.0)), float(cfg.get("u_top", 0.0)),
+                      float(cfg.get("body_force_x", 0.0)), int(cfg.get("init_profile", 0)),
+                      float(ux0), float(uy0), float(cfg.get("inlet_umax", 0.0)),
+                      float(cfg.get("outlet_rho", 1.0)))
 
 
 class Sim:

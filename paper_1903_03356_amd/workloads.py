@@ -25,6 +25,7 @@ INIT_REST = 0
 INIT_COUETTE = 1      # linear profile between the two wall speeds
 INIT_POISEUILLE = 2   # u(y) = g/(2 nu) * y * (H - y), H = ny - 1
 INIT_UNIFORM = 3      # uniform (ux, uy) everywhere (fully periodic boxes)
+INIT_INLET = 4        # the inlet parabola 4 u_max y (H - y) / H^2 everywhere (open channels)
 
 
 def viscosity(tau: float) -> float:
@@ -318,6 +319,16 @@ def adjoint_channel(nx: int = 512, ny: int = 128, tau: float = 0.8, u_max: float
     caps = [capsule(circle_nodes(128.0, 0.4 * H, radius, n_nodes), ks, 0.0, 1.0, 1.0)]
     return _base("adjoint512x128", nx, ny, tau, 4, "dynamic", steps,
                  body_force_x=g, init_profile=INIT_POISEUILLE, capsules=caps)
+
+
+def open_channel(nx: int, ny: int, tau: float, u_max: float, real_bytes: int = 8,
+                 mode: str = "dynamic", steps: int = 0, init_profile: int = INIT_REST,
+                 outlet_rho: float = 1.0) -> Dict[str, Any]:
+    """Open channel of Sec. 3.2: stationary walls, parabolic velocity inlet
+    u_x(0, y) = 4 u_max y (H - y) / H^2 and outlet density outlet_rho; no body
+    force; the flow starts at rest (or from the inlet parabola)."""
+    return _base(f"open{nx}x{ny}", nx, ny, tau, real_bytes, mode, steps, periodic_x=0,
+                 inlet_umax=float(u_max), outlet_rho=float(outlet_rho), init_profile=init_profile)
 
 
 def periodic_box(nx: int, ny: int, tau: float, u0=(0.0, 0.0), real_bytes: int = 8,

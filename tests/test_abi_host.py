@@ -75,9 +75,20 @@ def test_create_rejects_invalid_arguments(L):
     assert rc == lbib.EINVAL
     rc, _ = _create(L, lbib.make_grid(64, 64, 4, 1, 64, 5000), 0.8, w)
     assert rc == lbib.ECAPACITY
-    w0 = lbib.lbib_walls(0, 0, 0.0, 0.0, 0.0, 0, 0.0, 0.0)
-    rc, _ = _create(L, g, 0.8, w0)
+    w2 = lbib.lbib_walls(2, 0, 0.0, 0.0, 0.0, 0, 0.0, 0.0)
+    rc, _ = _create(L, g, 0.8, w2)
     assert rc == lbib.EINVAL and b"periodic_x" in L.lbib_last_error(None)
+    # open channel: outlet density, stationary walls, no body force, no periodic y
+    for args in ((0, 0, 0.0, 0.0, 0.0, 0, 0.0, 0.0, 0.01, 0.0),
+                 (0, 0, 0.0, 0.01, 0.0, 0, 0.0, 0.0, 0.01, 1.0),
+                 (0, 0, 0.0, 0.0, 1e-6, 0, 0.0, 0.0, 0.01, 1.0),
+                 (0, 1, 0.0, 0.0, 0.0, 0, 0.0, 0.0, 0.01, 1.0),
+                 (0, 0, 0.0, 0.0, 0.0, 0, 0.0, 0.0, 0.5, 1.0)):
+        rc, _ = _create(L, g, 0.8, lbib.lbib_walls(*args))
+        assert rc == lbib.EINVAL, args
+    # the inlet parabola as initial state needs an open channel
+    rc, _ = _create(L, g, 0.8, lbib.lbib_walls(1, 0, 0.0, 0.0, 0.0, 4, 0.0, 0.0, 0.0, 1.0))
+    assert rc == lbib.EINVAL
     wbad = lbib.lbib_walls(1, 0, float("inf"), 0.0, 0.0, 0, 0.0, 0.0)
     rc, _ = _create(L, g, 0.8, wbad)
     assert rc == lbib.EINVAL

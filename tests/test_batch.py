@@ -66,7 +66,7 @@ def test_create_batch_rejects_invalid_arguments():
     assert rc == lbib.EINVAL
     rc, _ = _create_batch([g4], [0.8], [w], null_taus=True)
     assert rc == lbib.EINVAL
-    w0 = lbib.lbib_walls(0, 0, 0.0, 0.0, 0.0, 0, 0.0, 0.0)
+    w0 = lbib.lbib_walls(2, 0, 0.0, 0.0, 0.0, 0, 0.0, 0.0)
     rc, _ = _create_batch([g4, g4], [0.8, 0.8], [w, w0])
     assert rc == lbib.EINVAL and b"periodic_x" in L.lbib_last_error(None)
     assert L.lbib_num_lattices(None) == -1

@@ -296,6 +296,59 @@ def test_contact_pair(mode, real_bytes):
     assert g.check() == 0
 
 
+@pytest.mark.parametrize("real_bytes", [8, 4])
+def test_open_channel_random_state(real_bytes):
+    """Open channel (velocity inlet, pressure outlet, four corners) from random
+    non-equilibrium populations, ragged sizes."""
+    log(f"open channel random real_bytes={real_bytes}")
+    cfg = wl.open_channel(70, 33, 0.75, 0.02, real_bytes=real_bytes)
+    g, o = pair(cfg)
+    f0 = wl.random_populations(70, 33, seed=21)
+    g.set_pops(f0)
+    o.set_pops(f0)
+    if real_bytes == 8:
+        compare_fields(g, o, 1e-13, 1e-14, pop_tol=1e-15)
+    g.step(80)
+    o.step(80)
+    if real_bytes == 8:
+        compare_fields(g, o, 1e-12, 1e-13, pop_tol=1e-13)
+    else:
+        compare_fields(g, o, 1e-5, 1e-6, pop_tol=1e-6)
+    assert g.check() == 0
+
+
+@pytest.mark.parametrize("real_bytes", [8, 4])
+def test_open_channel_capsule(real_bytes):
+    """Dynamic IB capsule carried by the inlet-driven flow of an open channel
+    started from the inlet parabola (Sec. 3.2 set-up)."""
+    n = 300
+    log(f"open channel capsule real_bytes={real_bytes} steps={n}")
+    cfg = wl.open_channel(160, 48, 0.8, 0.02, real_bytes=real_bytes, mode="dynamic",
+                          init_profile=wl.INIT_INLET)
+    ks = wl.ks_from_ca(0.8, 0.02, 1e-2)
+    cfg["capsules"] = [wl.capsule(wl.circle_nodes(50.0, 21.0, 7.0, 64), ks, 0.0, 1.0, 1.0)]
+    g, o = pair(cfg)
+    g.step(n)
+    o.step(n)
+    if real_bytes == 8:
+        compare_fields(g, o, 1e-10, 1e-12)
+        compare_capsules(g, o, 1e-10, 1e-10)
+    else:
+        compare_fields(g, o, 1e-5, 1e-6)
+        compare_capsules(g, o, 1e-4, 1e-4)
+    assert g.check() == 0
+
+
+def test_open_channel_rejects_nodes_near_the_ends():
+    from paper_1903_03356_amd import lbib
+    cfg = wl.open_channel(64, 40, 0.8, 0.02, real_bytes=4)
+    g = lbib.Sim(cfg, max_capsules=2, max_nodes_total=64, max_nodes_capsule=32)
+    with pytest.raises(lbib.LbibError) as e:
+        g.add_capsule(wl.circle_nodes(6.0, 20.0, 4.0, 24), 0.01, 0.0, 1.0, 1.0)  # x = 2 node
+    assert e.value.code == lbib.EINVAL
+    assert g.add_capsule(wl.circle_nodes(20.0, 20.0, 4.0, 24), 0.01, 0.0, 1.0, 1.0) == 0
+
+
 # ------------------------------------------------------------ error paths --
 
 def test_add_capsule_validation():

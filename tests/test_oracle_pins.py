@@ -538,3 +538,38 @@ def test_contact_force_off_by_default(orc):
     s = orc.Sim(cfg)
     s.step(1)
     assert np.all(s.contact(0) == 0.0)
+
+
+# ---- open channel: Zou-He velocity inlet and pressure outlet (Sec. 3.2) ---
+
+def test_open_channel_poiseuille(orc):
+    """Channel driven by the parabolic inlet profile and the outlet density,
+    started at rest (Sec. 3.2).  The inlet velocity and the outlet density are
+    imposed exactly; at steady state the mid-channel profile is the parabola
+    and the pressure gradient is the plane-Poiseuille one, dp/dx = -8 nu rho
+    u_max / H^2 (closed forms); the corner density is the inner diagonal
+    neighbour's."""
+    from paper_1903_03356_amd import workloads as wl
+    orc.set_threads(4)
+    nx, ny, umax, tau = 60, 21, 0.01, 1.0
+    cfg = wl.open_channel(nx, ny, tau, umax, real_bytes=8, mode="kinematic")
+    s = orc.Sim(cfg)
+    s.step(19000)
+    m0 = s.moments()
+    s.step(1000)
+    rho, ux, uy = s.moments()
+    assert np.abs(np.stack([rho, ux, uy]) - m0).max() < 1e-12  # steady
+    H = ny - 1
+    y = np.arange(ny)
+    prof = 4.0 * umax * y * (H - y) / H ** 2
+    assert np.abs(ux[:, 0] - prof).max() < 1e-14
+    assert np.abs(rho[1:-1, -1] - 1.0).max() < 1e-14
+    mid = nx // 2
+    assert np.abs(ux[:, mid] / ux[H // 2, mid] - prof / umax).max() < 1e-4
+    nu = (tau - 0.5) / 3.0
+    dpdx = np.polyfit(np.arange(10, nx - 10), rho[H // 2, 10:nx - 10] / 3.0, 1)[0]
+    theory = -8.0 * nu * umax / H ** 2 * rho.mean()
+    assert abs(dpdx / theory - 1.0) < 0.01, (dpdx, theory)
+    for (cx, cy), (nbx, nby) in (((0, 0), (1, 1)), ((0, H), (1, H - 1)),
+                                 ((nx - 1, 0), (nx - 2, 1)), ((nx - 1, H), (nx - 2, H - 1))):
+        assert abs(rho[cy, cx] - rho[nby, nbx]) < 1e-15
