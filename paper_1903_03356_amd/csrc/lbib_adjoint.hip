@@ -318,7 +318,7 @@ __global__ __launch_bounds__(kSegW * 4) void k_grid_adj(GridAdjArgs<T> a, GridAr
                 Fy += fix_to_real<T>(a.fib[2 * cell + 1]);
             }
             T s[9], lo[9], sb[9];
-            pull(a.pops, x, y, g, Fx, s);
+            pull<T, false>(a.pops, x, y, g, Fx, s);  // the adjoint needs periodic x
 #pragma unroll
             for (int i = 0; i < 9; i++) lo[i] = a.lam_in[i * plane + cell];
             T Fbx, Fby;

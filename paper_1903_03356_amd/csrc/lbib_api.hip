@@ -249,6 +249,13 @@ static const InstDev* inst_table(const lbib_ctx* c)
     return reinterpret_cast<const InstDev*>(bufp(c, LBIB_BUF_CAPS) + c->L.inst_table);
 }
 
+static bool any_open(const lbib_ctx* c)
+{
+    for (const Inst& I : c->L.inst)
+        if (!I.walls.periodic_x) return true;
+    return false;
+}
+
 static const int* round_table(const lbib_ctx* c)
 {
     return reinterpret_cast<const int*>(bufp(c, LBIB_BUF_CAPS) + c->L.round_table);
@@ -685,7 +692,7 @@ static hipError_t do_grid(lbib_ctx* c, void* p)
     return launch_grid_step_batch<T>(static_cast<const T*>(pops(c, n)),
                                      static_cast<T*>(pops(c, n + 1)), fib(c, n), flags(c, n),
                                      fib(c, n + 1), flags(c, n + 1), inst_table(c), round_table(c),
-                                     c->L.grid_blocks, c->stream);
+                                     c->L.grid_blocks, any_open(c), c->stream);
 }
 
 template <typename T>
@@ -778,8 +785,8 @@ static lbib_status step_t(lbib_ctx* c, int nsteps)
     size_patches<T>(c);
     const bool contact = c->contact_cutoff > 0.0 && c->ncap > 1;
     const bool dyn = c->mode == LBIB_DYNAMIC;
-    if (c->overlap && !contact && c->L.inst.size() == 1 && c->ncap > 0 &&
-        c->ncap <= kMaxOverlapCapsules)
+    if (c->overlap && !contact && c->L.inst.size() == 1 && c->L.inst[0].walls.periodic_x &&
+        c->ncap > 0 && c->ncap <= kMaxOverlapCapsules)
         return step_overlap_t<T>(c, nsteps);
     for (int k = 0; k < nsteps; k++) {
         const long long n = c->steps + k;

@@ -130,15 +130,16 @@ __device__ __forceinline__ void open_boundary(const T* __restrict__ src, int x, 
 // Pulls the nine populations arriving at (x, y) from the post-collision field
 // and completes the wall rows with Zou-He (unknowns from the knowns, tangential
 // momentum target rho_w u_w - F_x / 2) and, in an open channel, the inlet and
-// outlet columns.
-template <typename T>
+// outlet columns.  OPEN = false compiles the periodic-x lattice only (the hot
+// path, and callers that never reach the end columns of an open channel).
+template <typename T, bool OPEN = true>
 __device__ __forceinline__ void pull(const T* __restrict__ src, int x, int y, const GridArgs& g,
                                      T Fx, T s[9])
 {
     const size_t plane = (size_t)g.ny * g.nxp;
     int xm = x == 0 ? g.nx - 1 : x - 1;
     int xp = x == g.nx - 1 ? 0 : x + 1;
-    if (!g.periodic_x) {  // clamped: the unknown slots are replaced below
+    if (OPEN && !g.periodic_x) {  // clamped: the unknown slots are replaced below
         xm = x == 0 ? 0 : xm;
         xp = x == g.nx - 1 ? x : xp;
     }
@@ -160,7 +161,7 @@ __device__ __forceinline__ void pull(const T* __restrict__ src, int x, int y, co
     s[6] = src[6 * plane + rm + xp];
     s[7] = src[7 * plane + rp + xp];
     s[8] = src[8 * plane + rp + xm];
-    if (!g.periodic_x && (x == 0 || x == g.nx - 1)) {
+    if (OPEN && !g.periodic_x && (x == 0 || x == g.nx - 1)) {
         open_boundary(src, x, y, g, s);
         return;
     }
@@ -225,7 +226,7 @@ __device__ __forceinline__ void stage_cell(const IBArgs<T>& a, const GridArgs& g
         return;
     }
     T s[9];
-    pull(a.pops, (int)wx, (int)wy, g, gxf, s);
+    pull<T, false>(a.pops, (int)wx, (int)wy, g, gxf, s);  // never an end column
     const size_t cell = (size_t)wy * g.nxp + (size_t)wx;
     const T Fx = gxf + fix_to_real<T>(a.fib_prev[2 * cell]);
     const T Fy = fix_to_real<T>(a.fib_prev[2 * cell + 1]);

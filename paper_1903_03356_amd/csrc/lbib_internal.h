@@ -136,7 +136,7 @@ template <typename T>
 hipError_t launch_grid_step_batch(const T* src, T* dst, const long long* fib_now,
                                   const int* flags_now, long long* fib_old, int* flags_old,
                                   const InstDev* inst, const int* round_inst, int blocks,
-                                  hipStream_t s);
+                                  bool any_open, hipStream_t s);
 template <typename T>
 hipError_t launch_grid_far(const T* src, T* dst, const int* flags_now, const int* flags_old,
                            const int* near_map, int stamp, int* status, const GridArgs& g,

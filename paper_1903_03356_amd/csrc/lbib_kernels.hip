@@ -21,13 +21,13 @@ namespace lbib {
 // ------------------------------------------------------------ grid kernel
 // One lattice node with total force (Fx, Fy): pull, walls, force-corrected
 // moments, BGK + forcing, store.
-template <typename T>
+template <typename T, bool OPEN>
 __device__ __forceinline__ void collide_store(const T* __restrict__ src, T* __restrict__ dst,
                                               const GridArgs& g, int x, int y, T Fx, T Fy)
 {
     const size_t cell = (size_t)y * g.nxp + x;
     T s[9];
-    pull(src, x, y, g, Fx, s);
+    pull<T, OPEN>(src, x, y, g, Fx, s);
     const T drho = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])) + s[8];
     const T rho = T(1) + drho;
     const T jx = (s[1] - s[3]) + (s[5] - s[6]) + (s[8] - s[7]);
@@ -59,7 +59,7 @@ __device__ __forceinline__ void collide_store(const T* __restrict__ src, T* __re
 // previous time level there (if that segment was active), so the next IB
 // launch finds it zeroed; each segment has exactly one owning wave, which
 // reads its two activity flags before clearing one.
-template <typename T>
+template <bool OPEN, typename T>
 __device__ __forceinline__ void grid_cell(const T* __restrict__ src, T* __restrict__ dst,
                                           const long long* __restrict__ fib_now,
                                           const int* __restrict__ flags_now,
@@ -79,7 +79,7 @@ __device__ __forceinline__ void grid_cell(const T* __restrict__ src, T* __restri
             Fx += fix_to_real<T>(f.x);
             Fy += fix_to_real<T>(f.y);
         }
-        collide_store(src, dst, g, x, y, Fx, Fy);
+        collide_store<T, OPEN>(src, dst, g, x, y, Fx, Fy);
     }
     if (old) {
         *reinterpret_cast<longlong2*>(fib_old + 2 * cell) = make_longlong2(0, 0);
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kSegW * 4) void k_grid_far(
     if (near_map[fidx] == stamp) return;
     if ((flags_now[fidx] | flags_old[fidx]) && lane == 0) atomicOr(status, ST_NEAR);
     const int x = seg * kSegW + lane;
-    if (x < g.nx) collide_store(src, dst, g, x, y, (T)g.gx, T(0));
+    if (x < g.nx) collide_store<T, false>(src, dst, g, x, y, (T)g.gx, T(0));
 }
 
 // Near part: the (row, segment) units of every capsule's near region, with
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kSegW * 4) void k_grid_near(
         int y = u.ry0 + ri;
         if (y >= g.ny) y -= g.ny;
         const int seg = si < u.nA ? u.sa + si : si - u.nA;
-        grid_cell(src, dst, fib_now, flags_now, fib_old, flags_old, g, y, seg, lane);
+        grid_cell<false>(src, dst, fib_now, flags_now, fib_old, flags_old, g, y, seg, lane);
     }
 }
 
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kSegW * 4) void k_grid_near(
 // (accesses spread over all HBM channels), and the cache lines that the
 // x-shifted pulls share between neighbouring segments of a band stay in the L2
 // of the XCD that owns the band.
-template <typename T, int ROWS>
+template <typename T, int ROWS, bool OPEN>
 __global__ __launch_bounds__(kSegW * 4) void k_grid_step(
     const T* __restrict__ src, T* __restrict__ dst, const long long* __restrict__ fib_now,
     const int* __restrict__ flags_now, long long* __restrict__ fib_old,
@@ -199,7 +199,8 @@ __global__ __launch_bounds__(kSegW * 4) void k_grid_step(
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
         const int y = y0 + 4 * r;
-        if (y < g.ny) grid_cell(src, dst, fib_now, flags_now, fib_old, flags_old, g, y, seg, lane);
+        if (y < g.ny)
+            grid_cell<OPEN>(src, dst, fib_now, flags_now, fib_old, flags_old, g, y, seg, lane);
     }
 }
 
@@ -217,8 +218,12 @@ hipError_t launch_grid_step(const T* src, T* dst, const long long* fib_now, cons
 {
     constexpr int R = kGridRowsPerThread;
     const int blocks = grid_blocks(g.ny, g.nseg);
-    hipLaunchKernelGGL((k_grid_step<T, R>), dim3((unsigned)blocks), dim3(kSegW * 4), 0, s, src, dst,
-                       fib_now, flags_now, fib_old, flags_old, g);
+    if (g.periodic_x)
+        hipLaunchKernelGGL((k_grid_step<T, R, false>), dim3((unsigned)blocks), dim3(kSegW * 4), 0, s,
+                           src, dst, fib_now, flags_now, fib_old, flags_old, g);
+    else
+        hipLaunchKernelGGL((k_grid_step<T, R, true>), dim3((unsigned)blocks), dim3(kSegW * 4), 0, s,
+                           src, dst, fib_now, flags_now, fib_old, flags_old, g);
     return hipGetLastError();
 }
 
@@ -249,7 +254,7 @@ hipError_t launch_grid_near(const T* src, T* dst, const long long* fib_now, cons
 // starts at a multiple of kNumXcd, so block b still lands on XCD b % 8 and the
 // band-to-XCD mapping above holds inside each lattice.  round_inst[b / 8]
 // names the lattice of block b.
-template <typename T, int ROWS>
+template <typename T, int ROWS, bool OPEN>
 __global__ __launch_bounds__(kSegW * 4) void k_grid_step_batch(
     const T* __restrict__ src, T* __restrict__ dst, const long long* __restrict__ fib_now,
     const int* __restrict__ flags_now, long long* __restrict__ fib_old,
@@ -282,9 +287,9 @@ __global__ __launch_bounds__(kSegW * 4) void k_grid_step_batch(
     for (int r = 0; r < ROWS; r++) {
         const int y = y0 + 4 * r;
         if (y < g.ny)
-            grid_cell(src + I.pop_off, dst + I.pop_off, fib_now + I.fib_off,
-                      flags_now + I.flag_off, fib_old + I.fib_off, flags_old + I.flag_off, g, y,
-                      seg, lane);
+            grid_cell<OPEN>(src + I.pop_off, dst + I.pop_off, fib_now + I.fib_off,
+                            flags_now + I.flag_off, fib_old + I.fib_off, flags_old + I.flag_off, g,
+                            y, seg, lane);
     }
 }
 
@@ -292,12 +297,18 @@ template <typename T>
 hipError_t launch_grid_step_batch(const T* src, T* dst, const long long* fib_now,
                                   const int* flags_now, long long* fib_old, int* flags_old,
                                   const InstDev* inst, const int* round_inst, int blocks,
-                                  hipStream_t s)
+                                  bool any_open, hipStream_t s)
 {
     constexpr int R = kGridRowsPerThread;
     if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_grid_step_batch<T, R>), dim3((unsigned)blocks), dim3(kSegW * 4), 0, s,
-                       src, dst, fib_now, flags_now, fib_old, flags_old, inst, round_inst);
+    if (any_open)
+        hipLaunchKernelGGL((k_grid_step_batch<T, R, true>), dim3((unsigned)blocks),
+                           dim3(kSegW * 4), 0, s, src, dst, fib_now, flags_now, fib_old, flags_old,
+                           inst, round_inst);
+    else
+        hipLaunchKernelGGL((k_grid_step_batch<T, R, false>), dim3((unsigned)blocks),
+                           dim3(kSegW * 4), 0, s, src, dst, fib_now, flags_now, fib_old, flags_old,
+                           inst, round_inst);
     return hipGetLastError();
 }
 
@@ -1411,7 +1422,7 @@ hipError_t launch_set_nodes(T* nodes, CapsuleDev* caps, int cap, int nv, int nod
                                             long long*, int*, const GridArgs&, hipStream_t);      \
     template hipError_t launch_grid_step_batch<T>(const T*, T*, const long long*, const int*,     \
                                                   long long*, int*, const InstDev*, const int*,   \
-                                                  int, hipStream_t);                              \
+                                                  int, bool, hipStream_t);                        \
     template hipError_t launch_grid_far<T>(const T*, T*, const int*, const int*, const int*, int, \
                                            int*, const GridArgs&, hipStream_t);                   \
     template hipError_t launch_grid_near<T>(const T*, T*, const long long*, const int*,           \
