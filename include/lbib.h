@@ -118,7 +118,9 @@ typedef enum {
     LBIB_C_FORCE = 7,     /* last nodal force: total (Dynamic) or internal (Kinematic) [nv][2] (get) */
     LBIB_C_STATE = 8,     /* x^n, x^{n-1}, u_v^n stacked, [3][nv][2]                           (get, set) */
     LBIB_C_DIAG = 9,      /* 16 FP64 values, see lbib_diag_index                              (get) */
-    LBIB_STATUS = 10      /* int32 device status word (lbib_device_flags)                     (get) */
+    LBIB_STATUS = 10,     /* int32 device status word (lbib_device_flags)                     (get) */
+    LBIB_C_RIGID = 11     /* rigid particle: 10 FP64 values X, Y, theta, u_x, u_y, omega, F_x, F_y,
+                             M (last load), rigid flag; host memory only                       (get) */
 } lbib_state_id;
 
 /* Layout of the LBIB_C_DIAG record (Sec. 3.1-3.2 diagnostics, all FP64). */
@@ -170,6 +172,22 @@ lbib_status lbib_create(const lbib_grid* grid, double tau, const lbib_walls* wal
 lbib_status lbib_add_capsule(lbib_ctx* ctx, const double* nodes_xy, int32_t n, const double* ks,
                              int32_t n_ks, double kb, double ka, double mass_total,
                              int32_t* capsule_id);
+
+/* Adds a rigid particle (Sec. 2.3.1) to lattice `lattice`: nodes_xy [n][2]
+ * FP64 counter-clockwise outline; mass and moment of inertia about its area
+ * centroid (the caller's choice, e.g. (rho_s/rho_f) times the area and the
+ * polar second moment of area).  The nodes are driven towards the rigid-body
+ * velocity u + omega x r by direct forcing (Dynamic steps 1-3, spreading with
+ * c_v = arc length); force and torque come from the stresses at the outer
+ * probes x_c + 1.2 n+ (Eqs. 17-18) plus any contact forces on the nodes; the
+ * velocities follow Eqs. 19-20; (reading: the paper prints no position
+ * update) X += u dt, theta += omega dt, and the nodes are placed at
+ * X + R(theta) r0.  Start-up (reading): u and omega are the mean and the
+ * least-squares rotation of the interpolated fluid velocity at the nodes.
+ * Dynamic scheme only: EINVAL from lbib_step in KINEMATIC mode.  Checks and
+ * errors as for lbib_add_capsule_to, plus EINVAL for inertia <= 0. */
+lbib_status lbib_add_rigid_to(lbib_ctx* ctx, int32_t lattice, const double* nodes_xy, int32_t n,
+                              double mass, double inertia, int32_t* capsule_id);
 
 /* Queues nsteps >= 0 time steps of the chosen scheme on the bound stream.
  * Each step is one IB kernel launch (node update of the previous step fused
@@ -317,7 +335,7 @@ size_t lbib_adjoint_bytes(const lbib_ctx* ctx, int32_t nsteps);
  * positions); the fixed-point rounding of the spread force is not
  * differentiated.
  * Errors: EINVAL (batch context, nsteps < 1, bad mode, objective or capsule
- * id, a capsule with k_b != 0, the contact force on, an open channel,
+ * id, a capsule with k_b != 0, a rigid particle, the contact force on, an open channel,
  * workspace or n_ks too small, NULL pointers),
  * ESTATE (context not at step 0, or its mode differs), ECAPACITY (capsules too
  * large for the on-chip memory of the reverse IB kernel), ENUMERIC (a device

@@ -66,6 +66,14 @@ typedef struct {
     double *fext;   /* last hydrodynamic nodal force (Dynamic) */
     double *fc;     /* contact force of the current positions (Eq. 27) */
     int primed;
+    /* rigid particle (Sec. 2.3.1): nodes x_v = X + R(theta) r0_v */
+    int rigid;
+    double *r0;               /* body-frame offsets from the area centroid, [2 nv] */
+    double X[2], theta;       /* centroid and rotation angle */
+    double u[2], um1[2];      /* velocity at n and n-1 (Eq. 19) */
+    double w, wm1;            /* angular velocity at n and n-1 (Eq. 20) */
+    double I;                 /* moment of inertia about the centroid */
+    double Ftot[2], Mtot;     /* last hydrodynamic force and torque (Eqs. 17-18) */
 } orc_capsule;
 
 typedef struct {
@@ -651,7 +659,7 @@ void orc_destroy(orc_sim *s)
     for (int c = 0; c < s->ncap; c++) {
         orc_capsule *k = &s->caps[c];
         free(k->x); free(k->xm1); free(k->uv); free(k->l0); free(k->theta0);
-        free(k->ks); free(k->ftot); free(k->fext); free(k->fc);
+        free(k->ks); free(k->ftot); free(k->fext); free(k->fc); free(k->r0);
     }
     free(s->caps);
     free(s->f); free(s->ftmp); free(s->F); free(s->fib);
@@ -748,6 +756,108 @@ static void contact_forces(orc_sim *s)
     }
 }
 
+/* Adds a rigid particle (Sec. 2.3.1) with the given node outline (counter-
+ * clockwise), total mass m and moment of inertia I about the area centroid.
+ * It moves with the Dynamic scheme only: direct forcing towards the rigid-body
+ * velocity of each node, force and torque from the outer probes (Eqs. 17-18),
+ * velocities by Eqs. 19-20. */
+int orc_add_rigid(orc_sim *s, int nv, const double *nodes, double mass, double inertia)
+{
+    double ks = 0.0;
+    int c = orc_add_capsule(s, nv, nodes, &ks, 1, 0.0, 0.0, mass);
+    orc_capsule *k = &s->caps[c];
+    k->rigid = 1;
+    k->I = inertia;
+    double A2 = 0, cx = 0, cy = 0;
+    for (int l = 0; l < nv; l++) {
+        int m = (l + 1) % nv;
+        double cr = nodes[2 * l] * nodes[2 * m + 1] - nodes[2 * m] * nodes[2 * l + 1];
+        A2 += cr;
+        cx += (nodes[2 * l] + nodes[2 * m]) * cr;
+        cy += (nodes[2 * l + 1] + nodes[2 * m + 1]) * cr;
+    }
+    k->X[0] = cx / (3.0 * A2);
+    k->X[1] = cy / (3.0 * A2);
+    k->theta = 0.0;
+    k->r0 = (double *)xcalloc(2 * nv, sizeof(double));
+    for (int v = 0; v < nv; v++) {
+        k->r0[2 * v] = nodes[2 * v] - k->X[0];
+        k->r0[2 * v + 1] = nodes[2 * v + 1] - k->X[1];
+    }
+    return c;
+}
+
+void orc_get_rigid(const orc_sim *s, int c, double out[10])
+{
+    const orc_capsule *k = &s->caps[c];
+    out[0] = k->X[0]; out[1] = k->X[1]; out[2] = k->theta;
+    out[3] = k->u[0]; out[4] = k->u[1]; out[5] = k->w;
+    out[6] = k->Ftot[0]; out[7] = k->Ftot[1]; out[8] = k->Mtot; out[9] = k->rigid;
+}
+
+/* Eqs. 17-18: force and torque of the fluid on a rigid particle from the
+ * stresses at the outer probes x_c + 1.2 n+ of every element (pressure as the
+ * deviation c_s^2 (rho - 1): a uniform pressure gives no net force or torque
+ * on a closed polygon).  Torque about the centroid X with the element
+ * centroid as lever point.  The contact forces of Eq. 27 on its nodes add to
+ * both. */
+static void rigid_loads(orc_sim *s, orc_capsule *k)
+{
+    int nv = k->nv;
+    const double *x = k->x;
+    k->Ftot[0] = k->Ftot[1] = k->Mtot = 0.0;
+    for (int l = 0; l < nv; l++) {
+        int v1 = l, v2 = (l + 1) % nv;
+        double tx = x[2 * v2] - x[2 * v1], ty = x[2 * v2 + 1] - x[2 * v1 + 1];
+        double len = sqrt(tx * tx + ty * ty);
+        double npx = ty / len, npy = -tx / len;
+        double xc = 0.5 * (x[2 * v1] + x[2 * v2]), yc = 0.5 * (x[2 * v1 + 1] + x[2 * v2 + 1]);
+        double pp, Gp[2][2];
+        probe_state(s, xc + PROBE_LEN * npx, yc + PROBE_LEN * npy, &pp, Gp);
+        pp -= CS2;
+        double t00 = s->nu * 2.0 * Gp[0][0], t11 = s->nu * 2.0 * Gp[1][1];
+        double t01 = s->nu * (Gp[0][1] + Gp[1][0]);
+        double fx = (t00 * npx + t01 * npy - pp * npx) * len;
+        double fy = (t01 * npx + t11 * npy - pp * npy) * len;
+        k->Ftot[0] += fx;
+        k->Ftot[1] += fy;
+        k->Mtot += (xc - k->X[0]) * fy - (yc - k->X[1]) * fx;
+    }
+    /* contact forces on the nodes (Eq. 27) act on the body as a whole */
+    for (int v = 0; v < nv; v++) {
+        k->Ftot[0] += k->fc[2 * v];
+        k->Ftot[1] += k->fc[2 * v + 1];
+        k->Mtot += (x[2 * v] - k->X[0]) * k->fc[2 * v + 1] - (x[2 * v + 1] - k->X[1]) * k->fc[2 * v];
+    }
+}
+
+/* Eqs. 19-20 and the rigid-body kinematics: new velocities from the
+ * accelerations F/m and M/I, then (reading: the paper prints no position
+ * update) X^{n+1} = X^n + u^{n+1} dt, theta^{n+1} = theta^n + w^{n+1} dt and
+ * x_v = X + R(theta) r0_v.  uv holds the nodes' rigid-body velocities. */
+static void rigid_update(orc_capsule *k)
+{
+    double ax = k->Ftot[0] / k->mass, ay = k->Ftot[1] / k->mass, aw = k->Mtot / k->I;
+    double ux = 2.0 / 3.0 * (2.0 * k->u[0] - 0.5 * k->um1[0] + ax * 1.0);
+    double uy = 2.0 / 3.0 * (2.0 * k->u[1] - 0.5 * k->um1[1] + ay * 1.0);
+    double w = 2.0 / 3.0 * (2.0 * k->w - 0.5 * k->wm1 + aw * 1.0);
+    k->um1[0] = k->u[0]; k->um1[1] = k->u[1]; k->wm1 = k->w;
+    k->u[0] = ux; k->u[1] = uy; k->w = w;
+    k->X[0] += ux * 1.0;
+    k->X[1] += uy * 1.0;
+    k->theta += w * 1.0;
+    double c = cos(k->theta), sn = sin(k->theta);
+    memcpy(k->xm1, k->x, sizeof(double) * 2 * k->nv);
+    for (int v = 0; v < k->nv; v++) {
+        double rx = c * k->r0[2 * v] - sn * k->r0[2 * v + 1];
+        double ry = sn * k->r0[2 * v] + c * k->r0[2 * v + 1];
+        k->x[2 * v] = k->X[0] + rx;
+        k->x[2 * v + 1] = k->X[1] + ry;
+        k->uv[2 * v] = ux - w * ry;
+        k->uv[2 * v + 1] = uy + w * rx;
+    }
+}
+
 void orc_set_contact(orc_sim *s, double cutoff) { s->contact_cutoff = cutoff > 0.0 ? cutoff : 0.0; }
 
 void orc_get_contact(const orc_sim *s, int c, double *fc)
@@ -760,6 +870,32 @@ void orc_get_contact(const orc_sim *s, int c, double *fc)
  * so the first direct-forcing term vanishes and uniform motion is exact. */
 static void prime(orc_sim *s, orc_capsule *k)
 {
+    if (k->rigid) {
+        /* reading: u^0 = u^{-1} = mean node velocity of the fluid, w^0 = w^{-1}
+         * = the least-squares rigid rotation of the interpolated velocities */
+        double su[2] = {0, 0}, num = 0, den = 0;
+        for (int v = 0; v < k->nv; v++) {
+            double U[2];
+            interpolate_u(s, k->x[2 * v], k->x[2 * v + 1], U);
+            double rx = k->x[2 * v] - k->X[0], ry = k->x[2 * v + 1] - k->X[1];
+            su[0] += U[0];
+            su[1] += U[1];
+            num += rx * U[1] - ry * U[0];
+            den += rx * rx + ry * ry;
+        }
+        k->u[0] = k->um1[0] = su[0] / k->nv;
+        k->u[1] = k->um1[1] = su[1] / k->nv;
+        k->w = k->wm1 = num / den;
+        for (int v = 0; v < k->nv; v++) {
+            double rx = k->x[2 * v] - k->X[0], ry = k->x[2 * v + 1] - k->X[1];
+            k->uv[2 * v] = k->u[0] - k->w * ry;
+            k->uv[2 * v + 1] = k->u[1] + k->w * rx;
+            k->xm1[2 * v] = k->x[2 * v] - k->uv[2 * v];
+            k->xm1[2 * v + 1] = k->x[2 * v + 1] - k->uv[2 * v + 1];
+        }
+        k->primed = 1;
+        return;
+    }
     for (int v = 0; v < k->nv; v++) {
         double U[2];
         interpolate_u(s, k->x[2 * v], k->x[2 * v + 1], U);
@@ -819,6 +955,11 @@ static void step_dynamic(orc_sim *s)
     for (int c = 0; c < s->ncap; c++) {
         orc_capsule *k = &s->caps[c];
         int nv = k->nv;
+        if (k->rigid) {  /* Sec. 2.3.1 */
+            rigid_loads(s, k);
+            rigid_update(k);
+            continue;
+        }
         double *fs = (double *)xcalloc(2 * nv, sizeof(double));
         double *fb = (double *)xcalloc(2 * nv, sizeof(double));
         double *fa = (double *)xcalloc(2 * nv, sizeof(double));
@@ -895,6 +1036,8 @@ static void step_kinematic(orc_sim *s)
 int orc_step(orc_sim *s, int nsteps, int mode)
 {
     if (s->mode >= 0 && s->mode != mode) return -4;
+    for (int c = 0; c < s->ncap; c++)
+        if (s->caps[c].rigid && mode != ORC_DYNAMIC) return -5;  /* rigid: Dynamic only */
     s->mode = mode;
     for (int t = 0; t < nsteps; t++) {
         for (int c = 0; c < s->ncap; c++)

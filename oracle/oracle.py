@@ -73,6 +73,8 @@ def lib() -> C.CDLL:
     L.orc_interpolate.argtypes = [vp, C.c_int, _dp, _dp]
     L.orc_spread.argtypes = [vp, C.c_int, _dp, _dp, _dp, _dp]
     L.orc_set_contact.argtypes = [vp, C.c_double]
+    L.orc_add_rigid.argtypes = [vp, C.c_int, _dp, C.c_double, C.c_double]
+    L.orc_get_rigid.argtypes = [vp, C.c_int, _dp]
     L.orc_get_contact.argtypes = [vp, C.c_int, _dp]
     L.orc_set_threads.argtypes = [C.c_int]
     L.orc_get_threads.restype = C.c_int
@@ -149,9 +151,13 @@ class Sim:
         self.nodes = []
         for cap in cfg.get("capsules", []):
             nodes = np.ascontiguousarray(cap["nodes"], np.float64)
-            ks = np.atleast_1d(np.asarray(cap["ks"], np.float64)).copy()
-            L.orc_add_capsule(self.h, nodes.shape[0], nodes, ks, ks.size, float(cap["kb"]),
-                              float(cap["ka"]), float(cap["mass"]))
+            if cap.get("rigid"):
+                L.orc_add_rigid(self.h, nodes.shape[0], nodes, float(cap["mass"]),
+                                float(cap["inertia"]))
+            else:
+                ks = np.atleast_1d(np.asarray(cap["ks"], np.float64)).copy()
+                L.orc_add_capsule(self.h, nodes.shape[0], nodes, ks, ks.size, float(cap["kb"]),
+                                  float(cap["ka"]), float(cap["mass"]))
             self.nodes.append(nodes.shape[0])
         if cfg.get("contact_cutoff", 0.0):
             L.orc_set_contact(self.h, float(cfg["contact_cutoff"]))
@@ -210,6 +216,14 @@ class Sim:
 
     def set_capsule(self, c: int, x, xm1, uv) -> None:
         lib().orc_set_capsule(self.h, c, *(np.ascontiguousarray(a, np.float64) for a in (x, xm1, uv)))
+
+    def rigid(self, c: int) -> Dict[str, float]:
+        """Rigid particle state: centroid, angle, velocity, angular velocity, last
+        hydrodynamic force and torque."""
+        out = np.zeros(10)
+        lib().orc_get_rigid(self.h, c, out)
+        return dict(zip(["X", "Y", "theta", "ux", "uy", "w", "Fx", "Fy", "M", "rigid"],
+                        out.tolist()))
 
     def contact(self, c: int) -> np.ndarray:
         """Contact forces (Eq. 27) of the positions at the last force evaluation."""

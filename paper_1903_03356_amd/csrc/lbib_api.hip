@@ -66,6 +66,7 @@ struct lbib_ctx {
     std::vector<hipEvent_t> pool;
     std::vector<int> cap_off, cap_nv, cap_inst;  // host copy of the capsule table layout
     std::vector<double> cap_kb, cap_P0;
+    std::vector<int> cap_rigid;
     // overlapped schedule: far part of the grid step on a second stream (opt-in)
     bool overlap = false;
     double contact_cutoff = 0.0;  // Eq. 27 contact force below this node distance; 0 = off
@@ -461,7 +462,8 @@ extern "C" int32_t lbib_num_lattices(const lbib_ctx* c)
 
 template <typename T>
 static lbib_status add_capsule_t(lbib_ctx* c, int inst, const double* xy, int n, const double* ks,
-                                 int n_ks, double kb, double ka, double mass, int32_t* id)
+                                 int n_ks, double kb, double ka, double mass, int32_t* id,
+                                 bool rigid = false, double inertia = 0.0)
 {
     Inst& I = c->L.inst[inst];
     // stress-free shape (Sec. 2.2.1): element lengths, turning angles, area, perimeter
@@ -507,6 +509,24 @@ static lbib_status add_capsule_t(lbib_ctx* c, int inst, const double* xy, int n,
         f[NF_TH0 * n + v] = (T)th0[v];
         f[NF_KS * n + v] = (T)(n_ks == 1 ? ks[0] : ks[v]);
     }
+    // rigid particle: area centroid and body-frame offsets of the nodes
+    double rcx = 0.0, rcy = 0.0;
+    if (rigid) {
+        double a2 = 0.0;
+        for (int v = 0; v < n; v++) {
+            const int m = (v + 1) % n;
+            const double cr = xy[2 * v] * xy[2 * m + 1] - xy[2 * m] * xy[2 * v + 1];
+            a2 += cr;
+            rcx += (xy[2 * v] + xy[2 * m]) * cr;
+            rcy += (xy[2 * v + 1] + xy[2 * m + 1]) * cr;
+        }
+        rcx /= 3.0 * a2;
+        rcy /= 3.0 * a2;
+        for (int v = 0; v < n; v++) {
+            f[NF_R0X * n + v] = (T)(xy[2 * v] - rcx);
+            f[NF_R0Y * n + v] = (T)(xy[2 * v + 1] - rcy);
+        }
+    }
     for (int k = 0; k < NF_COUNT; k++)
         HIPCHK(c, hipMemcpyAsync(bufp(c, LBIB_BUF_NODES) + (k * S + off) * sizeof(T),
                                  f.data() + (size_t)k * n, n * sizeof(T), hipMemcpyHostToDevice,
@@ -536,6 +556,13 @@ static lbib_status add_capsule_t(lbib_ctx* c, int inst, const double* xy, int n,
     cd.flag_off = (int64_t)I.flag_off;
     cd.gx = g.gx;
     cd.nu = I.nu;
+    if (rigid) {
+        cd.rigid = 1;
+        cd.rX = rcx;
+        cd.rY = rcy;
+        cd.rI = inertia;
+        cd.rm = mass;
+    }
     HIPCHK(c, hipMemcpyAsync(bufp(c, LBIB_BUF_CAPS) + (size_t)c->ncap * sizeof(CapsuleDev), &cd,
                              sizeof(cd), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -545,6 +572,7 @@ static lbib_status add_capsule_t(lbib_ctx* c, int inst, const double* xy, int n,
     c->cap_inst.push_back(inst);
     c->cap_kb.push_back(kb);
     c->cap_P0.push_back(P);
+    c->cap_rigid.push_back(rigid ? 1 : 0);
     c->ncap++;
     c->nodes_used += n;
     I.ncap++;
@@ -583,6 +611,41 @@ extern "C" lbib_status lbib_add_capsule_to(lbib_ctx* c, int32_t inst, const doub
                 return fail(c, LBIB_EINVAL, "open channel: nodes must satisfy 3 <= x <= nx - 4");
     return c->rb == 4 ? add_capsule_t<float>(c, inst, xy, n, ks, n_ks, kb, ka, mass, id)
                       : add_capsule_t<double>(c, inst, xy, n, ks, n_ks, kb, ka, mass, id);
+}
+
+extern "C" lbib_status lbib_add_rigid_to(lbib_ctx* c, int32_t inst, const double* xy, int32_t n,
+                                         double mass, double inertia, int32_t* id)
+{
+    if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
+    if (!xy || !id) return fail(c, LBIB_EINVAL, "NULL argument");
+    if (!(std::isfinite(inertia) && inertia > 0))
+        return fail(c, LBIB_EINVAL, "inertia must be finite and > 0");
+    if (c->mode == LBIB_KINEMATIC)
+        return fail(c, LBIB_ESTATE, "rigid particles move with the Dynamic scheme only");
+    const double ks = 0.0;
+    // the checks of lbib_add_capsule_to, then the rigid record
+    if (inst < 0 || inst >= (int)c->L.inst.size()) return fail(c, LBIB_EINVAL, "bad lattice index");
+    if (c->steps > 0) return fail(c, LBIB_ESTATE, "capsules must be added before the first step");
+    const Inst& I = c->L.inst[inst];
+    if (n < 3) return fail(c, LBIB_EINVAL, "a capsule needs at least 3 nodes");
+    if (n > I.grid.max_nodes_capsule)
+        return fail(c, LBIB_ECAPACITY, "n exceeds max_nodes_capsule");
+    if (I.ncap >= I.grid.max_capsules) return fail(c, LBIB_ECAPACITY, "capsule table full");
+    if (I.nodes + n > I.grid.max_nodes_total) return fail(c, LBIB_ECAPACITY, "node arrays full");
+    if (!(std::isfinite(mass) && mass > 0)) return fail(c, LBIB_EINVAL, "mass must be > 0");
+    for (int v = 0; v < 2 * n; v++)
+        if (!std::isfinite(xy[v])) return fail(c, LBIB_EINVAL, "non-finite node coordinate");
+    if (!I.walls.periodic_y)
+        for (int v = 0; v < n; v++)
+            if (xy[2 * v + 1] < 3.0 || xy[2 * v + 1] > I.grid.ny - 4.0)
+                return fail(c, LBIB_EINVAL, "nodes must satisfy 3 <= y <= ny - 4");
+    if (!I.walls.periodic_x)
+        for (int v = 0; v < n; v++)
+            if (xy[2 * v] < 3.0 || xy[2 * v] > I.grid.nx - 4.0)
+                return fail(c, LBIB_EINVAL, "open channel: nodes must satisfy 3 <= x <= nx - 4");
+    return c->rb == 4 ? add_capsule_t<float>(c, inst, xy, n, &ks, 1, 0.0, 0.0, mass, id, true, inertia)
+                      : add_capsule_t<double>(c, inst, xy, n, &ks, 1, 0.0, 0.0, mass, id, true,
+                                              inertia);
 }
 
 extern "C" lbib_status lbib_add_capsule(lbib_ctx* c, const double* xy, int32_t n, const double* ks,
@@ -838,6 +901,9 @@ extern "C" lbib_status lbib_step(lbib_ctx* c, int32_t nsteps, lbib_mode mode)
     if (mode != LBIB_KINEMATIC && mode != LBIB_DYNAMIC) return fail(c, LBIB_EINVAL, "bad mode");
     if (c->mode >= 0 && c->mode != (int)mode)
         return fail(c, LBIB_ESTATE, "the coupling mode is fixed after the first step");
+    if (mode == LBIB_KINEMATIC)
+        for (int r : c->cap_rigid)
+            if (r) return fail(c, LBIB_EINVAL, "rigid particles move with the Dynamic scheme only");
     if (nsteps == 0) return LBIB_OK;
     c->mode = mode;
     return c->rb == 4 ? step_t<float>(c, nsteps) : step_t<double>(c, nsteps);
@@ -921,6 +987,27 @@ static lbib_status get_t(lbib_ctx* c, int what, int cap, void* dst, size_t bytes
             HIPCHK(c, hipMemcpyAsync(dst, src, kDiagStride * sizeof(double),
                                      hipMemcpyDeviceToDevice, c->stream));
         return finish(src, kDiagStride);
+    }
+    case LBIB_C_RIGID: {
+        if (cap < 0 || cap >= c->ncap) return fail(c, LBIB_EINVAL, "bad capsule id");
+        if (on_dev) return fail(c, LBIB_EINVAL, "LBIB_C_RIGID is copied to host memory only");
+        if (bytes < 10 * sizeof(double)) return fail(c, LBIB_EINVAL, "dst too small");
+        CapsuleDev cd;
+        HIPCHK(c, hipMemcpyAsync(&cd, bufp(c, LBIB_BUF_CAPS) + (size_t)cap * sizeof(CapsuleDev),
+                                 sizeof(cd), d2h, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        double* o = static_cast<double*>(dst);
+        o[0] = cd.rX;
+        o[1] = cd.rY;
+        o[2] = cd.rth;
+        o[3] = cd.ru[0];
+        o[4] = cd.ru[1];
+        o[5] = cd.rw;
+        o[6] = cd.rF[0];
+        o[7] = cd.rF[1];
+        o[8] = cd.rM;
+        o[9] = cd.rigid;
+        return LBIB_OK;
     }
     case LBIB_STATUS: {
         if (bytes < sizeof(int)) return fail(c, LBIB_EINVAL, "dst too small");
@@ -1231,6 +1318,8 @@ extern "C" lbib_status lbib_adjoint(lbib_ctx* c, int32_t nsteps, lbib_mode mode,
         return fail(c, LBIB_EINVAL, "the adjoint does not differentiate the contact force");
     if (!c->L.inst[0].walls.periodic_x)
         return fail(c, LBIB_EINVAL, "the adjoint needs a periodic channel (periodic_x = 1)");
+    for (int r : c->cap_rigid)
+        if (r) return fail(c, LBIB_EINVAL, "the adjoint does not differentiate rigid particles");
     if (n_ks < c->nodes_used) return fail(c, LBIB_EINVAL, "out_dJ_dks shorter than the node count");
     AdjLayout A;
     if (!adj_layout(c, nsteps, A)) return fail(c, LBIB_EINVAL, "invalid adjoint layout");

@@ -33,6 +33,7 @@ enum NodeField {
     NF_EX, NF_EY,       // last hydrodynamic nodal force (Dynamic)
     NF_L0L,             // low part of the stress-free length (l0 = NF_L0 + NF_L0L)
     NF_CX, NF_CY,       // contact force (Eq. 27) of the current positions
+    NF_R0X, NF_R0Y,     // rigid particle: body-frame offset of the node from the centroid
     NF_COUNT
 };
 
@@ -66,8 +67,16 @@ struct CapsuleDev {
     int64_t pop_off, fib_off, flag_off;
     double gx, nu;
     double pad1;
+    // rigid particle (Sec. 2.3.1): nodes x_v = X + R(theta) r0_v
+    int32_t rigid, pad2;
+    double rX, rY, rth;        // centroid (world coordinates) and angle
+    double ru[2], rum1[2];     // velocity at n and n-1 (Eq. 19)
+    double rw, rwm1;           // angular velocity at n and n-1 (Eq. 20)
+    double rI, rm;             // moment of inertia about the centroid, mass
+    double rF[2], rM;          // last hydrodynamic (+ contact) force and torque (Eqs. 17-18)
+    double pad3;
 };
-static_assert(sizeof(CapsuleDev) == 144, "CapsuleDev layout");
+static_assert(sizeof(CapsuleDev) == 272, "CapsuleDev layout");
 
 constexpr int kDiagStride = 16;  // doubles per capsule in BUF_DIAG
 

@@ -775,6 +775,155 @@ __device__ void diagnostics(const IBArgs<T>& a, const CapsuleDev& cap, int c, do
     }
 }
 
+// Rigid particle start-up (reading, as for membranes): u^0 = u^{-1} = mean of
+// the interpolated fluid velocity at the nodes, w^0 = w^{-1} = the
+// least-squares rigid rotation of those velocities about the centroid; the
+// nodes take the rigid-body velocity, and d^0 = u_v^0.
+template <typename T>
+__device__ void rigid_prime(const IBArgs<T>& a, const Scratch<T>& S, const Patch<T>& P,
+                            CapsuleDev& cap, int c, int& st, double (*red)[8])
+{
+    const int tid = threadIdx.x, nt = blockDim.x, nv = cap.nv, off = cap.node_offset;
+    const size_t NS = a.node_stride;
+    T* N = a.nodes;
+    const double Xr = cap.rX - cap.ref_x, Yr = cap.rY - cap.ref_y;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int v = tid; v < nv; v += nt) {
+        T Ux, Uy;
+        interp_u(P, S.px[v], S.py[v], Ux, Uy, st);
+        const double rx = (double)S.px[v] + (double)S.qx[v] - Xr;
+        const double ry = (double)S.py[v] + (double)S.qy[v] - Yr;
+        acc[0] += (double)Ux;
+        acc[1] += (double)Uy;
+        acc[2] += rx * (double)Uy - ry * (double)Ux;
+        acc[3] += rx * rx + ry * ry;
+    }
+    block_sum<4>(acc, red);
+    const double ux = acc[0] / nv, uy = acc[1] / nv, w = acc[2] / acc[3];
+    for (int v = tid; v < nv; v += nt) {
+        const double rx = (double)S.px[v] + (double)S.qx[v] - Xr;
+        const double ry = (double)S.py[v] + (double)S.qy[v] - Yr;
+        const T vx = (T)(ux - w * ry), vy = (T)(uy + w * rx);
+        N[NF_UX * NS + cap.node_offset + v] = vx;
+        N[NF_UY * NS + cap.node_offset + v] = vy;
+        N[NF_DX * NS + off + v] = vx;
+        N[NF_DY * NS + off + v] = vy;
+        S.ux[v] = vx;
+        S.uy[v] = vy;
+        S.dx[v] = vx;
+        S.dy[v] = vy;
+    }
+    cap.ru[0] = cap.rum1[0] = ux;
+    cap.ru[1] = cap.rum1[1] = uy;
+    cap.rw = cap.rwm1 = w;
+    if (tid == 0) {
+        a.caps[c].ru[0] = a.caps[c].rum1[0] = ux;
+        a.caps[c].ru[1] = a.caps[c].rum1[1] = uy;
+        a.caps[c].rw = a.caps[c].rwm1 = w;
+    }
+}
+
+// Rigid particle update closing step n-1 (Sec. 2.3.1): force and torque from
+// the stresses at the outer probes x_c + 1.2 n+ (Eqs. 17-18; pressure as the
+// deviation c_s^2 (rho - 1), torque about the centroid with the element
+// centroid as lever point) plus the contact forces on the nodes; velocities by
+// Eqs. 19-20 from F/m and M/I; (reading) X += u dt, theta += w dt; the nodes
+// go to X + R(theta) r0 with the rigid-body velocity.  New positions are left
+// in S.t[4..7] with their sum in csum, for the common re-basing.
+template <typename T>
+__device__ void rigid_update(const IBArgs<T>& a, const Scratch<T>& S, const Patch<T>& P,
+                             CapsuleDev& cap, int c, int& st, double (*red)[8], double (&csum)[2])
+{
+    const int tid = threadIdx.x, nt = blockDim.x, nv = cap.nv, off = cap.node_offset;
+    const size_t NS = a.node_stride;
+    T* N = a.nodes;
+    const double Xr = cap.rX - cap.ref_x, Yr = cap.rY - cap.ref_y;
+    const T nu = (T)cap.nu;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int l = tid; l < nv; l += nt) {
+        const int m = l + 1 == nv ? 0 : l + 1;
+        T tx, ty;
+        edge(S, l, m, tx, ty);
+        const T len = sqrt(tx * tx + ty * ty);
+        const T nx = ty / len, ny = -tx / len;
+        const T xc = T(0.5) * (S.px[l] + S.px[m]), yc = T(0.5) * (S.py[l] + S.py[m]);
+        T dp, G[2][2];
+        probe(P, xc + T(1.2) * nx, yc + T(1.2) * ny, dp, G, st);
+        const T t00 = nu * T(2) * G[0][0], t11 = nu * T(2) * G[1][1];
+        const T t01 = nu * (G[0][1] + G[1][0]);
+        const double fx = (double)((t00 * nx + t01 * ny - dp * nx) * len);
+        const double fy = (double)((t01 * nx + t11 * ny - dp * ny) * len);
+        acc[0] += fx;
+        acc[1] += fy;
+        acc[2] += ((double)xc - Xr) * fy - ((double)yc - Yr) * fx;
+    }
+    if (a.contact) {
+        for (int v = tid; v < nv; v += nt) {
+            const double fx = (double)N[NF_CX * NS + off + v], fy = (double)N[NF_CY * NS + off + v];
+            const double rx = (double)S.px[v] + (double)S.qx[v] - Xr;
+            const double ry = (double)S.py[v] + (double)S.qy[v] - Yr;
+            acc[0] += fx;
+            acc[1] += fy;
+            acc[2] += rx * fy - ry * fx;
+        }
+    }
+    block_sum<3>(acc, red);
+    const double ux = 2.0 / 3.0 * (2.0 * cap.ru[0] - 0.5 * cap.rum1[0] + acc[0] / cap.rm);
+    const double uy = 2.0 / 3.0 * (2.0 * cap.ru[1] - 0.5 * cap.rum1[1] + acc[1] / cap.rm);
+    const double w = 2.0 / 3.0 * (2.0 * cap.rw - 0.5 * cap.rwm1 + acc[2] / cap.rI);
+    const double Xn = Xr + ux, Yn = Yr + uy, th = cap.rth + w;
+    const double cs = cos(th), sn = sin(th);
+    for (int v = tid; v < nv; v += nt) {
+        const double r0x = (double)N[NF_R0X * NS + off + v], r0y = (double)N[NF_R0Y * NS + off + v];
+        const double rx = cs * r0x - sn * r0y, ry = sn * r0x + cs * r0y;
+        const double x = Xn + rx, y = Yn + ry;
+        const T hx = (T)x, hy = (T)y;
+        const T lx = (T)(x - (double)hx), ly = (T)(y - (double)hy);
+        const T dx = (T)(x - ((double)S.px[v] + (double)S.qx[v]));
+        const T dy = (T)(y - ((double)S.py[v] + (double)S.qy[v]));
+        if (!(fabs(dx) < T(1) && fabs(dy) < T(1))) st |= ST_MOVE;
+        const T vx = (T)(ux - w * ry), vy = (T)(uy + w * rx);
+        N[NF_DX * NS + off + v] = dx;
+        N[NF_DY * NS + off + v] = dy;
+        N[NF_UX * NS + off + v] = vx;
+        N[NF_UY * NS + off + v] = vy;
+        S.dx[v] = dx;
+        S.dy[v] = dy;
+        S.ux[v] = vx;
+        S.uy[v] = vy;
+        S.t[4][v] = hx;
+        S.t[5][v] = hy;
+        S.t[6][v] = lx;
+        S.t[7][v] = ly;
+        csum[0] += (double)hx;
+        csum[1] += (double)hy;
+    }
+    cap.rum1[0] = cap.ru[0];
+    cap.rum1[1] = cap.ru[1];
+    cap.rwm1 = cap.rw;
+    cap.ru[0] = ux;
+    cap.ru[1] = uy;
+    cap.rw = w;
+    cap.rX = cap.ref_x + Xn;
+    cap.rY = cap.ref_y + Yn;
+    cap.rth = th;
+    if (tid == 0) {
+        CapsuleDev& o = a.caps[c];
+        o.rum1[0] = cap.rum1[0];
+        o.rum1[1] = cap.rum1[1];
+        o.rwm1 = cap.rwm1;
+        o.ru[0] = ux;
+        o.ru[1] = uy;
+        o.rw = w;
+        o.rX = cap.rX;
+        o.rY = cap.rY;
+        o.rth = th;
+        o.rF[0] = acc[0];
+        o.rF[1] = acc[1];
+        o.rM = acc[2];
+    }
+}
+
 // One block per capsule.  Phases (bit set):
 //   PH_PRIME  start-up of a capsule not yet started: u_v^0 = U(x^0), d^0 = U(x^0)
 //   PH_B      node update closing step n-1 from the fields after its collision:
@@ -901,7 +1050,9 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
     }
 
     // ---- start-up (reading: u_v^0 = U(x^0), x^{-1} = x^0 - U(x^0))
-    if (prime) {
+    if (prime && cap.rigid) {
+        rigid_prime(a, S, P, cap, c, st, red);
+    } else if (prime) {
         for (int v = tid; v < nv; v += nt) {
             T Ux, Uy;
             interp_u(P, S.px[v], S.py[v], Ux, Uy, st);
@@ -918,13 +1069,14 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
 
     // ---- node update closing the previous step
     if (doB) {
-        if (a.dynamic) {
+        double csum[2] = {0.0, 0.0};
+        if (cap.rigid) rigid_update(a, S, P, cap, c, st, red, csum);
+        if (a.dynamic && !cap.rigid) {
             internal_forces(S, nv, cap.kb, cap.ka, cap.A0, red);  // -> t8, t9
             external_forces(S, P, nv, (T)cap.nu, st);                            // -> t2, t3
         }
         const T half_inv_m = (T)(0.5 / cap.mv);
-        double csum[2] = {0.0, 0.0};
-        for (int v = tid; v < nv; v += nt) {
+        for (int v = cap.rigid ? nv : tid; v < nv; v += nt) {
             T Ux, Uy;
             interp_u(P, S.px[v], S.py[v], Ux, Uy, st);  // tentative velocity, Eq. 23
             const T dox = S.dx[v], doy = S.dy[v];

@@ -26,7 +26,7 @@ NUM_BUFFERS = 8
 BUFFER_NAMES = ["pops_a", "pops_b", "force", "flags", "nodes", "caps", "diag", "stage"]
 # lbib_state_id
 F_POPS, F_POPS_DEV, F_MOMENTS, F_FORCE = 0, 1, 2, 3
-C_NODES, C_PREV, C_VEL, C_FORCE, C_STATE, C_DIAG, STATUS = 4, 5, 6, 7, 8, 9, 10
+C_NODES, C_PREV, C_VEL, C_FORCE, C_STATE, C_DIAG, STATUS, C_RIGID = 4, 5, 6, 7, 8, 9, 10, 11
 DIAG_KEYS = ["area", "perimeter", "cx", "cy", "D", "Sw", "dp", "dA", "Jxx", "Jyy", "Jxy", "A0",
              "P0"]
 
@@ -35,7 +35,7 @@ EXPORTS = ["lbib_required_bytes", "lbib_create", "lbib_add_capsule", "lbib_step"
            "lbib_get_timing", "lbib_steps_done", "lbib_last_error", "lbib_destroy",
            "lbib_required_bytes_batch", "lbib_create_batch", "lbib_add_capsule_to",
            "lbib_num_lattices", "lbib_adjoint_bytes", "lbib_adjoint", "lbib_set_overlap",
-           "lbib_set_contact"]
+           "lbib_set_contact", "lbib_add_rigid_to"]
 OBJ_TAYLOR, OBJ_CENTROID_Y = 0, 1
 
 
@@ -94,6 +94,9 @@ def load() -> C.CDLL:
     L.lbib_set_overlap.argtypes = [vp, i32]
     L.lbib_set_contact.restype = i32
     L.lbib_set_contact.argtypes = [vp, C.c_double]
+    L.lbib_add_rigid_to.restype = i32
+    L.lbib_add_rigid_to.argtypes = [vp, i32, C.POINTER(C.c_double), i32, C.c_double, C.c_double,
+                                    C.POINTER(i32)]
     L.lbib_get_timing.restype = i32
     L.lbib_get_timing.argtypes = [vp, C.POINTER(C.c_double)]
     L.lbib_steps_done.restype = C.c_int64
@@ -193,7 +196,10 @@ class Sim:
         self.nv: List[int] = []
         self.dims = [(int(cfg["nx"]), int(cfg["ny"]))]
         for cap in caps:
-            self.add_capsule(cap["nodes"], cap["ks"], cap["kb"], cap["ka"], cap["mass"])
+            if cap.get("rigid"):
+                self.add_rigid_to(0, cap["nodes"], cap["mass"], cap["inertia"])
+            else:
+                self.add_capsule(cap["nodes"], cap["ks"], cap["kb"], cap["ka"], cap["mass"])
         self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
         if cfg.get("contact_cutoff", 0.0):
             self.set_contact(float(cfg["contact_cutoff"]))
@@ -223,6 +229,27 @@ class Sim:
                    self.h)
         self.nv.append(nodes.shape[0])
         return cid.value
+
+    def add_rigid_to(self, lattice: int, nodes, mass: float, inertia: float) -> int:
+        nodes = np.ascontiguousarray(nodes, np.float64)
+        cid = C.c_int32()
+        with self.torch.cuda.device(self.device):
+            _check(load().lbib_add_rigid_to(self.h, int(lattice),
+                                            nodes.ctypes.data_as(C.POINTER(C.c_double)),
+                                            nodes.shape[0], float(mass), float(inertia),
+                                            C.byref(cid)), self.h)
+        self.nv.append(nodes.shape[0])
+        return cid.value
+
+    def rigid(self, c: int) -> Dict[str, float]:
+        """Rigid particle state: centroid, angle, velocity, angular velocity and
+        the last force and torque (LBIB_C_RIGID)."""
+        out = np.zeros(10)
+        with self.torch.cuda.device(self.device):
+            _check(load().lbib_get_state(self.h, C_RIGID, int(c), out.ctypes.data_as(C.c_void_p),
+                                         out.nbytes, 0), self.h)
+        return dict(zip(["X", "Y", "theta", "ux", "uy", "w", "Fx", "Fy", "M", "rigid"],
+                        out.tolist()))
 
     @property
     def num_lattices(self) -> int:
@@ -408,7 +435,9 @@ class Batch(Sim):
         self.dims = [(int(c["nx"]), int(c["ny"])) for c in cfgs]
         self.cap_ids: List[List[int]] = []
         for i, c in enumerate(cfgs):
-            ids = [self.add_capsule_to(i, cap["nodes"], cap["ks"], cap["kb"], cap["ka"],
+            ids = [self.add_rigid_to(i, cap["nodes"], cap["mass"], cap["inertia"])
+                   if cap.get("rigid") else
+                   self.add_capsule_to(i, cap["nodes"], cap["ks"], cap["kb"], cap["ka"],
                                        cap["mass"]) for cap in c.get("capsules", [])]
             self.cap_ids.append(ids)
         self.nx, self.ny = self.dims[0]

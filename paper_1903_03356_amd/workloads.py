@@ -115,6 +115,25 @@ def capsule(nodes: np.ndarray, ks: float, kb: float = 0.0, ka: float = 1.0,
     }
 
 
+def rigid_particle(nodes: np.ndarray, density_ratio: float = 1.0) -> Dict[str, Any]:
+    """Rigid particle record (Sec. 2.3.1): outline (n, 2) counter-clockwise,
+    mass m = (rho_s / rho_f) A and moment of inertia I = (rho_s / rho_f) J about
+    the area centroid, with A and J (polar second moment of area) from the
+    polygon by Green's theorem."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    x, y = nodes[:, 0], nodes[:, 1]
+    xn, yn = np.roll(x, -1), np.roll(y, -1)
+    cr = x * yn - xn * y
+    A = 0.5 * cr.sum()
+    cx = ((x + xn) * cr).sum() / (6.0 * A)
+    cy = ((y + yn) * cr).sum() / (6.0 * A)
+    Jxx = ((y * y + y * yn + yn * yn) * cr).sum() / 12.0 - A * cy * cy
+    Jyy = ((x * x + x * xn + xn * xn) * cr).sum() / 12.0 - A * cx * cx
+    return {"nodes": nodes, "rigid": True, "ks": 0.0, "kb": 0.0, "ka": 0.0,
+            "mass": float(density_ratio * A), "inertia": float(density_ratio * (Jxx + Jyy)),
+            "density_ratio": float(density_ratio)}
+
+
 def _base(name: str, nx: int, ny: int, tau: float, real_bytes: int, mode: str, steps: int,
           **kw: Any) -> Dict[str, Any]:
     cfg = {

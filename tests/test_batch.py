@@ -26,8 +26,8 @@ def test_required_bytes_batch_is_the_sum_of_the_lattices():
                                                             for g in grids)
     assert lbib.required_bytes_batch(grids, 3) >= sum(2 * g.ny * 2 * 4 for g in grids)
     assert lbib.required_bytes_batch(grids, 4) == \
-        -(-18 * (200 + 128 + 3) * 4 // 256) * 256
-    assert lbib.required_bytes_batch(grids, 5) >= 4 * 144 + 3 * 96
+        -(-20 * (200 + 128 + 3) * 4 // 256) * 256
+    assert lbib.required_bytes_batch(grids, 5) >= 4 * 272 + 3 * 112
     assert lbib.required_bytes_batch(grids, 7) >= 3 * 1024 * 9 * 8
     assert lbib.required_bytes_batch(grids[:1], 0) == lbib.required_bytes(grids[0], 0)
     for bid in range(8):

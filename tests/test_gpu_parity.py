@@ -349,6 +349,87 @@ def test_open_channel_rejects_nodes_near_the_ends():
     assert g.add_capsule(wl.circle_nodes(20.0, 20.0, 4.0, 24), 0.01, 0.0, 1.0, 1.0) == 0
 
 
+def _compare_rigid(g, o, c, tol):
+    rg, ro = g.rigid(c), o.rigid(c)
+    for k in ("X", "Y", "theta", "ux", "uy", "w", "Fx", "Fy", "M"):
+        assert abs(rg[k] - ro[k]) <= tol * max(1.0, abs(ro[k])), (k, rg[k], ro[k])
+
+
+def test_rigid_particle_uniform_flow_fp64():
+    """Rigid particle (Sec. 2.3.1) in a uniform periodic flow: translates
+    exactly, like the oracle."""
+    u0 = (0.02, -0.01)
+    cfg = wl.periodic_box(48, 32, 0.8, u0=u0, real_bytes=8, mode="dynamic")
+    nodes = wl.circle_nodes(20.0, 15.0, 5.0, 40)
+    cfg["capsules"] = [wl.rigid_particle(nodes, 1.5)]
+    g, o = pair(cfg)
+    g.step(100)
+    o.step(100)
+    _compare_rigid(g, o, 0, 1e-12)
+    xg, _, _ = g.capsule(0)
+    np.testing.assert_allclose(xg, nodes + 100 * np.array(u0), atol=1e-11)
+    assert g.check() == 0
+
+
+@pytest.mark.parametrize("real_bytes", [8, 4])
+def test_rigid_disc_in_couette(real_bytes):
+    """Free rigid disc at the centre of a Couette flow (it spins up to about
+    -gamma/2): fields, nodes, force, torque and velocities against the oracle."""
+    n = 500
+    log(f"rigid disc couette real_bytes={real_bytes} steps={n}")
+    cfg = wl._base("rot", 64, 48, 0.9, real_bytes, "dynamic", 0, u_bottom=-0.01, u_top=0.01,
+                   init_profile=wl.INIT_COUETTE)
+    cfg["capsules"] = [wl.rigid_particle(wl.circle_nodes(31.5, 23.5, 5.0, 40), 1.3)]
+    g, o = pair(cfg)
+    g.step(n)
+    o.step(n)
+    if real_bytes == 8:
+        compare_fields(g, o, 1e-10, 1e-12)
+        compare_capsules(g, o, 1e-10, 1e-10)
+        _compare_rigid(g, o, 0, 1e-9)
+    else:
+        compare_fields(g, o, 1e-5, 1e-6)
+        compare_capsules(g, o, 1e-4, 1e-4)
+        rg, ro = g.rigid(0), o.rigid(0)
+        assert abs(rg["w"] - ro["w"]) < 1e-4 * abs(ro["w"]), (rg["w"], ro["w"])
+    assert g.check() == 0
+
+
+def test_rigid_and_membrane_in_contact_fp64():
+    """A rigid particle and a membrane capsule close enough for the Eq. 27
+    contact force, in a Poiseuille channel, Dynamic scheme."""
+    cfg = wl._base("mix", 96, 48, 0.8, 8, "dynamic", 0,
+                   body_force_x=wl.poiseuille_body_force(0.8, 48, 0.02),
+                   init_profile=wl.INIT_POISEUILLE)
+    ks = wl.ks_from_ca(0.8, 0.02, 1e-2)
+    cfg["capsules"] = [wl.rigid_particle(wl.circle_nodes(30.0, 22.0, 6.0, 48), 1.2),
+                       wl.capsule(wl.circle_nodes(43.7, 24.0, 6.0, 48), ks, 0.0, 1.0, 1.0)]
+    cfg["contact_cutoff"] = 2.0
+    g, o = pair(cfg)
+    g.step(200)
+    o.step(200)
+    assert np.abs(o.contact(0)).max() > 0
+    compare_fields(g, o, 1e-10, 1e-12)
+    compare_capsules(g, o, 1e-10, 1e-10)
+    _compare_rigid(g, o, 0, 1e-9)
+    assert g.check() == 0
+
+
+def test_rigid_particle_needs_the_dynamic_scheme():
+    from paper_1903_03356_amd import lbib
+    cfg = wl.periodic_box(48, 32, 0.8, real_bytes=4, mode="kinematic")
+    cfg["capsules"] = [wl.rigid_particle(wl.circle_nodes(20.0, 15.0, 5.0, 24), 1.0)]
+    g = lbib.Sim(cfg)
+    with pytest.raises(lbib.LbibError) as e:
+        g.step(1, "kinematic")
+    assert e.value.code == lbib.EINVAL
+    with pytest.raises(lbib.LbibError) as e:
+        g.add_rigid_to(0, wl.circle_nodes(35.0, 15.0, 3.0, 16), 1.0, 0.0)  # inertia 0
+    assert e.value.code == lbib.EINVAL
+    g.step(2, "dynamic")
+    assert g.check() == 0
+
+
 # ------------------------------------------------------------ error paths --
 
 def test_add_capsule_validation():

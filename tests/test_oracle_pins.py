@@ -573,3 +573,59 @@ def test_open_channel_poiseuille(orc):
     for (cx, cy), (nbx, nby) in (((0, 0), (1, 1)), ((0, H), (1, H - 1)),
                                  ((nx - 1, 0), (nx - 2, 1)), ((nx - 1, H), (nx - 2, H - 1))):
         assert abs(rho[cy, cx] - rho[nby, nbx]) < 1e-15
+
+
+# ---- rigid particles (Sec. 2.3.1, Eqs. 17-20) --------------------------------
+
+def test_rigid_mass_and_inertia_of_a_regular_polygon():
+    """Regular N-gon of circumradius R: A = N R^2 sin(2 pi / N) / 2 and polar
+    moment J = A R^2 (2 + cos(2 pi / N)) / 6 about its centre (-> pi R^4 / 2)."""
+    from paper_1903_03356_amd import workloads as wl
+    for n in (6, 40):
+        R = 5.0
+        p = wl.rigid_particle(wl.circle_nodes(3.0, 4.0, R, n), density_ratio=1.5)
+        A = n * R * R * math.sin(2 * math.pi / n) / 2.0
+        J = A * R * R * (2.0 + math.cos(2 * math.pi / n)) / 6.0
+        assert p["mass"] == pytest.approx(1.5 * A, rel=1e-13)
+        assert p["inertia"] == pytest.approx(1.5 * J, rel=1e-12)
+
+
+def test_rigid_particle_translates_with_uniform_flow(orc):
+    """Uniform flow in a periodic box: the start-up takes the flow's velocity,
+    the direct forcing and the outer-probe loads vanish (uniform pressure gives
+    no net force or torque on a closed polygon), so the particle translates
+    exactly and does not turn."""
+    from paper_1903_03356_amd import workloads as wl
+    u0 = (0.02, -0.01)
+    cfg = wl.periodic_box(48, 32, 0.8, u0=u0, real_bytes=8, mode="dynamic")
+    nodes = wl.circle_nodes(20.0, 15.0, 5.0, 40)
+    cfg["capsules"] = [wl.rigid_particle(nodes, 1.5)]
+    s = orc.Sim(cfg)
+    r0 = s.rigid(0)
+    s.step(100)
+    r = s.rigid(0)
+    assert abs(r["X"] - (r0["X"] + 100 * u0[0])) < 1e-11
+    assert abs(r["Y"] - (r0["Y"] + 100 * u0[1])) < 1e-11
+    assert abs(r["w"]) < 1e-14 and abs(r["theta"]) < 1e-12
+    x, _, _ = s.capsule(0)
+    np.testing.assert_allclose(x, nodes + 100 * np.array(u0), atol=1e-11)
+
+
+def test_rigid_disc_rotates_at_half_the_shear_rate(orc):
+    """A free disc at the centre of a Couette flow turns at -gamma/2 in the
+    unconfined Stokes limit (the fluid's local angular velocity); confinement
+    R/H = 5/47 slows it by a few per cent.  The steady rate must lie in
+    (0.95, 1.0) x (-gamma / 2)."""
+    from paper_1903_03356_amd import workloads as wl
+    orc.set_threads(4)
+    nx, ny = 64, 48
+    H = ny - 1
+    cfg = wl._base("rot", nx, ny, 0.9, 8, "dynamic", 0, u_bottom=-0.01, u_top=0.01,
+                   init_profile=wl.INIT_COUETTE)
+    cfg["capsules"] = [wl.rigid_particle(wl.circle_nodes(0.5 * (nx - 1), 0.5 * H, 5.0, 40), 1.0)]
+    s = orc.Sim(cfg)
+    s.step(4000)
+    r = s.rigid(0)
+    ratio = r["w"] / (-0.5 * 0.02 / H)
+    assert 0.95 < ratio < 1.0, ratio
+    assert abs(r["X"] - 0.5 * (nx - 1)) < 1e-4 and abs(r["Y"] - 0.5 * H) < 1e-4
