@@ -15,6 +15,8 @@ Prints one JSON line:
             recorded around every launch of the timed region, against 8 TB/s
   cpu_baseline  the FP64 oracle on the host cores, a bounded sample of steps of
             the same workload
+  multi_body_open_channel  side measurement: MLUPS of a 1536 x 256 open channel
+            with 14 capsules and 2 rigid discs in contact range
   adjoint   side measurement: time of one gradient (lbib_adjoint: taped forward
             run + reverse sweep) over the plain forward run, 512 x 128 channel
   batched   side measurement: 256 independent channels (seeded ensemble, about
@@ -224,6 +226,18 @@ def bench_adjoint(mode: str, steps: int):
             "J": r["J"], "dJ_dg": r["dJ_dg"]}
 
 
+def bench_multi(steps: int, warmup: int):
+    """The paper's remaining physics at scale: 1536 x 256 open channel
+    (velocity inlet, pressure outlet), 14 biconcave capsules and 2 rigid
+    discs, contact force on, Dynamic, FP32."""
+    from paper_1903_03356_amd import workloads as wl
+    cfg = wl.multi_capsule_channel(steps=steps)
+    r = time_gpu(cfg, steps, warmup, timing=False)
+    del r["sim"]
+    return {"workload": "1536x256 open channel, 14 capsules + 2 rigid discs, contact on, FP32",
+            "mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4)}
+
+
 def cpu_baseline(cfg, budget_s: float = 20.0):
     from oracle import oracle as orc
 
@@ -327,6 +341,9 @@ def main() -> int:
             f"per-simulation loop {ens['loop_ms_per_step']:.3f} ms/step, "
             f"speedup {ens['speedup']:.1f}x")
         side["batched"] = ens
+        mc = bench_multi(min(args.steps, 400), args.warmup)
+        log(f"multi-body open channel: {mc['mlups']:.0f} MLUPS ({mc['ms_per_step']:.3f} ms/step)")
+        side["multi_body_open_channel"] = mc
         adj = [bench_adjoint("dynamic", 500), bench_adjoint("kinematic", 5000)]
         for a in adj:
             log(f"adjoint ({a['mode']}, {a['steps']} steps): forward {a['forward_ms']:.1f} ms, "

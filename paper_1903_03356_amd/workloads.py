@@ -350,6 +350,42 @@ def open_channel(nx: int, ny: int, tau: float, u_max: float, real_bytes: int = 8
                  inlet_umax=float(u_max), outlet_rho=float(outlet_rho), init_profile=init_profile)
 
 
+def multi_capsule_channel(seed: int = 0, nx: int = 1536, ny: int = 256, tau: float = 0.8,
+                          u_max: float = 0.02, n_caps: int = 16, n_rigid: int = 2,
+                          length: float = 30.0, ca: float = 1e-2, gap: float = 0.5,
+                          real_bytes: int = 4, steps: int = 1000) -> Dict[str, Any]:
+    """Open channel (velocity inlet, pressure outlet, Sec. 3.2) carrying a
+    4 x 4 block of bodies a few lattice units apart, the Sec. 3.4 set-up: 16
+    biconcave capsules of the given length (Ca from u_max), of which the first
+    ``n_rigid`` are replaced by rigid discs of the same length; contact force
+    (Eq. 27, cutoff 2).  Draws from default_rng(seed): per body, orientation
+    U[-0.3, 0.3] rad and a centre jitter U[-1, 1] lu in x and y.  The flow starts
+    from the inlet parabola everywhere."""
+    rng = np.random.default_rng(seed)
+    H = ny - 1
+    ks = ks_from_ca(tau, u_max, ca)
+    pitch_x = length + gap + 2.0
+    pitch_y = 0.5 * length + gap + 2.0
+    x0 = 0.25 * nx
+    y0 = 0.5 * H - 1.5 * pitch_y
+    caps: List[Dict[str, Any]] = []
+    for k in range(n_caps):
+        i, j = k % 4, k // 4
+        angle = float(rng.uniform(-0.3, 0.3))
+        jx, jy = rng.uniform(-1.0, 1.0, 2)
+        cx, cy = x0 + i * pitch_x + jx, y0 + j * pitch_y + jy
+        if k < n_rigid:
+            caps.append(rigid_particle(circle_nodes(cx, cy, 0.25 * length, 64), 1.0))
+        else:
+            caps.append(capsule(biconcave_nodes(cx, cy, length, 96, angle), ks, 0.0, 1.0, 1.0))
+    cfg = open_channel(nx, ny, tau, u_max, real_bytes=real_bytes, mode="dynamic", steps=steps,
+                       init_profile=INIT_INLET)
+    cfg["name"] = f"multi{n_caps}_{nx}x{ny}"
+    cfg["capsules"] = caps
+    cfg["contact_cutoff"] = 2.0
+    return cfg
+
+
 def periodic_box(nx: int, ny: int, tau: float, u0=(0.0, 0.0), real_bytes: int = 8,
                  mode: str = "dynamic", steps: int = 10) -> Dict[str, Any]:
     """Fully periodic box at uniform velocity u0 (no walls, no body force)."""

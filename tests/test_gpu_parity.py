@@ -430,6 +430,26 @@ def test_rigid_particle_needs_the_dynamic_scheme():
     assert g.check() == 0
 
 
+def test_multi_capsule_open_channel_full_size():
+    """The multi-body benchmark case at full size (1536 x 256 open channel, 14
+    biconcave capsules and 2 rigid discs, contact force on, FP32): fields,
+    nodes and rigid states against the oracle after 60 steps."""
+    n = 60
+    cfg = wl.multi_capsule_channel()
+    log(f"multi-capsule open channel 1536x256 steps={n}")
+    g, o = pair(cfg)
+    g.step(n)
+    o.step(n)
+    assert any(np.abs(o.contact(c)).max() > 0 for c in range(len(cfg["capsules"])))
+    compare_fields(g, o, 1e-5, 1e-6)
+    compare_capsules(g, o, 1e-4, 1e-4)
+    for c in range(2):
+        rg, ro = g.rigid(c), o.rigid(c)
+        assert abs(rg["X"] - ro["X"]) < 1e-4 and abs(rg["Y"] - ro["Y"]) < 1e-4
+        assert abs(rg["theta"] - ro["theta"]) < 1e-5
+    assert g.check() == 0
+
+
 # ------------------------------------------------------------ error paths --
 
 def test_add_capsule_validation():
