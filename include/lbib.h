@@ -194,13 +194,15 @@ lbib_status lbib_add_rigid_to(lbib_ctx* ctx, int32_t lattice, const double* node
  * with the forcing of this step) and one fused collide-stream kernel launch.
  * The call ends with the node update of the last step, so between calls the
  * state is the complete state at time n.
- * With lbib_set_overlap(ctx, 1), a single lattice with 1..64 capsules and no
- * contact force splits
- * the collide-stream pass: a near kernel covers each capsule's near region
- * (the bounding box of its nodes at n-1 and n plus 5 cells), a far kernel the
- * rest on a second stream of the library's own, beside the next IB launch.
- * The results are bit-identical to the single pass; the call still returns
- * with all work ordered on the bound stream.
+ * Overlapped schedule (lbib_set_overlap): a periodic single lattice with
+ * 1..64 capsules and no contact force can split the collide-stream pass.  A
+ * near kernel covers each capsule's near region (the bounding box of its
+ * nodes at n-1 and n plus 5 cells) on the bound stream, and the next IB launch
+ * follows it there; a far kernel covers the rest on a second stream of the
+ * library's own, so the IB work runs beside it.  The results are
+ * bit-identical to the single pass, and the call still returns with all work
+ * ordered on the bound stream.  By default the split is used from 2^23
+ * lattice cells on, where it pays.
  * Errors: EINVAL (nsteps < 0, bad mode), ESTATE (mode differs from the first
  * step's), EDEVICE.  Device-side problems raise status flags (lbib_check). */
 lbib_status lbib_step(lbib_ctx* ctx, int32_t nsteps, lbib_mode mode);
@@ -247,9 +249,9 @@ lbib_status lbib_set_timing(lbib_ctx* ctx, int32_t enable);
  * Errors: EINVAL (cutoff not in [0, 16]), EDEVICE. */
 lbib_status lbib_set_contact(lbib_ctx* ctx, double cutoff);
 
-/* enable = 1 selects the overlapped near / far schedule of lbib_step (see
- * there); enable = 0, the default, keeps the single-pass schedule on one
- * stream. */
+/* Schedule of lbib_step: enable = 1 always uses the overlapped near / far
+ * schedule where it applies (see lbib_step), 0 never, -1 (the default) from
+ * 2^23 lattice cells on.  Errors: EINVAL (other values). */
 lbib_status lbib_set_overlap(lbib_ctx* ctx, int32_t enable);
 lbib_status lbib_get_timing(lbib_ctx* ctx, double* out6);
 

@@ -317,8 +317,11 @@ class Sim:
         with self.torch.cuda.device(self.device):
             _check(load().lbib_set_contact(self.h, float(cutoff)), self.h)
 
-    def set_overlap(self, enable: bool) -> None:
-        _check(load().lbib_set_overlap(self.h, 1 if enable else 0), self.h)
+    def set_overlap(self, enable) -> None:
+        """True / False force the overlapped schedule on / off; None restores
+        the automatic choice (large lattices only)."""
+        v = -1 if enable is None else (1 if enable else 0)
+        _check(load().lbib_set_overlap(self.h, v), self.h)
 
     def adjoint_bytes(self, nsteps: int) -> int:
         return int(load().lbib_adjoint_bytes(self.h, int(nsteps)))

@@ -107,4 +107,6 @@ def test_null_context_calls(L):
     assert L.lbib_steps_done(None) == -1
     assert L.lbib_get_state(None, 0, 0, None, 0, 0) == lbib.EINVAL
     assert L.lbib_set_timing(None, 1) == lbib.EINVAL
+    assert L.lbib_set_overlap(None, 1) == lbib.EINVAL
+    assert L.lbib_set_contact(None, 2.0) == lbib.EINVAL
     L.lbib_destroy(None)

@@ -253,6 +253,7 @@ def test_overlapped_schedule_is_bit_identical():
         a = lbib.Sim(cfg)
         b = lbib.Sim(cfg)
         a.set_overlap(True)
+        b.set_overlap(False)
         for chunk in (1, 25, 34):
             a.step(chunk)
             b.step(chunk)
