@@ -21,6 +21,10 @@
 
 namespace lbib {
 
+// The reverse IB kernel runs 256 threads per capsule: one wave per SIMD, so
+// its dual-number MLS work gets the whole register file instead of spilling.
+constexpr int kAdjThreads = 256;
+
 // ------------------------------------------------------------ dual numbers
 template <int N>
 struct Dual {
@@ -765,7 +769,7 @@ __device__ void external_vjp(const AdjScratch<T>& S, const Patch<T>& P, int nv, 
 // of x^{n-1}, d^{n-1}.  The adjoint of the moments M^n goes into lambda P^n
 // (transpose of the pull) and lambda F^{n-1} (its half-force term).
 template <typename T>
-__global__ __launch_bounds__(kIBThreads) void k_ib_adj(IBAdjArgs<T> a)
+__global__ __launch_bounds__(kAdjThreads) void k_ib_adj(IBAdjArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[kIBThreads / 64][8];
@@ -1139,7 +1143,7 @@ template <typename T>
 hipError_t launch_ib_adj(const IBAdjArgs<T>& a, int ncap, size_t lds_bytes, hipStream_t s)
 {
     if (ncap <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ib_adj<T>, dim3(ncap), dim3(kIBThreads), lds_bytes, s, a);
+    hipLaunchKernelGGL(k_ib_adj<T>, dim3(ncap), dim3(kAdjThreads), lds_bytes, s, a);
     return hipGetLastError();
 }
 

@@ -239,9 +239,8 @@ __device__ __forceinline__ void stage_cell(const IBArgs<T>& a, const GridArgs& g
     P.uy[i] = (jy + T(0.5) * Fy) * irho;
 }
 
-// Deterministic block reductions over the kIBThreads / 64 wavefronts of the
-// IB kernel: butterfly within each wave, then the wave partials in order.
-constexpr int kIBWaves = kIBThreads / 64;
+// Deterministic block reductions over the wavefronts of a block (at most
+// kIBThreads / 64): butterfly within each wave, then the wave partials in order.
 
 template <int N>
 __device__ __forceinline__ void block_sum(double (&v)[N], double (*red)[8])
@@ -254,10 +253,11 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double (*red)[8])
 #pragma unroll
         for (int k = 0; k < N; k++) red[wave][k] = v[k];
     __syncthreads();
+    const int nw = (int)(blockDim.x >> 6);
 #pragma unroll
     for (int k = 0; k < N; k++) {
         double acc = red[0][k];
-        for (int w = 1; w < kIBWaves; w++) acc += red[w][k];
+        for (int w = 1; w < nw; w++) acc += red[w][k];
         v[k] = acc;
     }
     __syncthreads();
@@ -278,9 +278,10 @@ __device__ __forceinline__ void block_minmax(float (&mn)[2], float (&mx)[2], dou
         red[wave][3] = mx[1];
     }
     __syncthreads();
+    const int nw = (int)(blockDim.x >> 6);
     for (int k = 0; k < 2; k++) {
         float a = (float)red[0][k], b = (float)red[0][2 + k];
-        for (int w = 1; w < kIBWaves; w++) {
+        for (int w = 1; w < nw; w++) {
             a = fminf(a, (float)red[w][k]);
             b = fmaxf(b, (float)red[w][2 + k]);
         }
