@@ -219,11 +219,30 @@ def bench_adjoint(mode: str, steps: int):
     r = adj.adjoint(steps, lbib.OBJ_TAYLOR, 0, mode, workspace=ws)
     torch.cuda.synchronize()
     t_adj = time.perf_counter() - t0
+    full_bytes = ws.numel()
     del adj, ws
+    # the same gradient with a checkpoint every 70 steps (segments recomputed)
+    ck = lbib.Sim(cfg)
+    ws = torch.empty(ck.adjoint_bytes(steps, 70), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc = ck.adjoint(steps, lbib.OBJ_TAYLOR, 0, mode, workspace=ws, checkpoint_every=70)
+    torch.cuda.synchronize()
+    t_ck = time.perf_counter() - t0
+    # the recomputed forward steps are exact; the reverse kernel's atomics sum
+    # in a free order, so the gradients agree to rounding
+    if rc["J"] != r["J"] or abs(rc["dJ_dg"] - r["dJ_dg"]) > 1e-3 * abs(r["dJ_dg"]):
+        raise RuntimeError("checkpointed gradient differs from the whole-trajectory tape")
+    ck_bytes = ws.numel()
+    del ck, ws
     return {"workload": f"512x128 channel, 1 capsule (96 nodes), Ca 1e-2, FP32, {mode}",
             "mode": mode, "steps": steps, "forward_ms": round(t_fwd * 1e3, 2),
             "gradient_ms": round(t_adj * 1e3, 2), "adjoint_over_forward": round(t_adj / t_fwd, 2),
-            "J": r["J"], "dJ_dg": r["dJ_dg"]}
+            "workspace_gb": round(full_bytes / 1e9, 3),
+            "gradient_ckpt70_ms": round(t_ck * 1e3, 2),
+            "ckpt70_over_forward": round(t_ck / t_fwd, 2),
+            "ckpt70_workspace_gb": round(ck_bytes / 1e9, 3),
+            "J": r["J"], "dJ_dg": r["dJ_dg"], "dJ_dg_ckpt70": rc["dJ_dg"]}
 
 
 def bench_multi(steps: int, warmup: int):
@@ -347,7 +366,10 @@ def main() -> int:
         adj = [bench_adjoint("dynamic", 500), bench_adjoint("kinematic", 5000)]
         for a in adj:
             log(f"adjoint ({a['mode']}, {a['steps']} steps): forward {a['forward_ms']:.1f} ms, "
-                f"gradient {a['gradient_ms']:.1f} ms, ratio {a['adjoint_over_forward']:.2f}")
+                f"gradient {a['gradient_ms']:.1f} ms, ratio {a['adjoint_over_forward']:.2f}; "
+                f"checkpoint every 70: {a['gradient_ckpt70_ms']:.1f} ms, ratio "
+                f"{a['ckpt70_over_forward']:.2f}, workspace {a['ckpt70_workspace_gb']:.3f} GB "
+                f"against {a['workspace_gb']:.2f} GB")
         side["adjoint"] = adj
 
     sha = kernel_sha()

@@ -312,19 +312,33 @@ enum lbib_objective {
     LBIB_OBJ_CENTROID_Y = 1  /* area-centroid height y_c (LBIB_D_CY) */
 };
 
-/* Workspace bytes lbib_adjoint needs for nsteps steps of this context, or 0
- * if the context is not a single lattice or nsteps < 1.  The workspace holds
- * the whole forward trajectory (populations, IB force field and node state of
- * every time level: about (36 + 16) B per cell per step in FP32), so it grows
- * linearly in nsteps. */
-size_t lbib_adjoint_bytes(const lbib_ctx* ctx, int32_t nsteps);
+/* Workspace bytes lbib_adjoint needs for nsteps steps of this context with
+ * the given checkpoint interval, or 0 if the context is not a single lattice,
+ * nsteps < 1 or checkpoint_every < 0.
+ *   checkpoint_every == 0 or >= nsteps: the whole forward trajectory is taped
+ *     (populations, IB force field and node state of every time level: about
+ *     (36 + 16) B per cell per step in FP32, linear in nsteps).
+ *   0 < checkpoint_every = K < nsteps: the grid state is kept at every K-th
+ *     level only (ceil(nsteps / K) checkpoints) plus a tape of K + 1 levels
+ *     that the reverse sweep refills segment by segment; the node state of
+ *     every level is still taped (a few kB per level). */
+size_t lbib_adjoint_bytes(const lbib_ctx* ctx, int32_t nsteps, int32_t checkpoint_every);
 
 /* Runs nsteps time steps of the chosen scheme from the initial state (the
  * context must be at step 0), taping the trajectory into `workspace` (device
- * memory, caller-owned, lbib_adjoint_bytes long), evaluates
- * J = objective(capsule) at step nsteps, then runs the reverse sweep: the exact
- * discrete adjoint of the executed step (Secs. 2.1-2.4), one reverse grid
- * launch and one reverse IB launch per step.  Outputs (host):
+ * memory, caller-owned, lbib_adjoint_bytes(ctx, nsteps, checkpoint_every)
+ * long), evaluates J = objective(capsule) at step nsteps, then runs the reverse
+ * sweep: the exact discrete adjoint of the executed step (Secs. 2.1-2.4), one
+ * reverse grid launch and one reverse IB launch per step.  With a checkpoint
+ * interval K (0 < K < nsteps) the reverse sweep goes segment by segment, last
+ * first: it restores the segment's checkpoint, runs its K forward steps again
+ * into the short tape, and reverses them.  The recomputed steps repeat the
+ * first run bit for bit (the forward kernels sum in a fixed order), so J and
+ * the final state equal those of the full tape exactly and the gradients
+ * equal them up to the summation order of the reverse IB kernel's
+ * floating-point atomics (which also varies between two full-tape runs); the
+ * price is one more forward run.
+ * Outputs (host):
  *   *out_J       J
  *   *out_dJ_dg   dJ/dg for the uniform body force g (the walls' body_force_x),
  *                including its use in the initial Poiseuille profile
@@ -336,16 +350,17 @@ size_t lbib_adjoint_bytes(const lbib_ctx* ctx, int32_t nsteps);
  * The MLS supports are held fixed (they are piecewise constant in the
  * positions); the fixed-point rounding of the spread force is not
  * differentiated.
- * Errors: EINVAL (batch context, nsteps < 1, bad mode, objective or capsule
- * id, a capsule with k_b != 0, a rigid particle, the contact force on, an open channel,
- * workspace or n_ks too small, NULL pointers),
- * ESTATE (context not at step 0, or its mode differs), ECAPACITY (capsules too
- * large for the on-chip memory of the reverse IB kernel), ENUMERIC (a device
- * status flag in the forward run or the reverse sweep), EDEVICE.
- * Waits for the stream. */
-lbib_status lbib_adjoint(lbib_ctx* ctx, int32_t nsteps, lbib_mode mode, int32_t objective,
-                         int32_t capsule, void* workspace, size_t workspace_bytes, double* out_J,
-                         double* out_dJ_dg, double* out_dJ_dks, int32_t n_ks);
+ * Errors: EINVAL (batch context, nsteps < 1, checkpoint_every < 0, bad mode,
+ * objective or capsule id, a capsule with k_b != 0, a rigid particle, the
+ * contact force on, an open channel, workspace or n_ks too small, NULL
+ * pointers), ESTATE (context not at step 0, or its mode differs), ECAPACITY
+ * (capsules too large for the on-chip memory of the reverse IB kernel),
+ * ENUMERIC (a device status flag in the forward run or the reverse sweep),
+ * EDEVICE.  Waits for the stream. */
+lbib_status lbib_adjoint(lbib_ctx* ctx, int32_t nsteps, int32_t checkpoint_every, lbib_mode mode,
+                         int32_t objective, int32_t capsule, void* workspace,
+                         size_t workspace_bytes, double* out_J, double* out_dJ_dg,
+                         double* out_dJ_dks, int32_t n_ks);
 
 /* Frees the host-side context.  Device buffers stay with the caller.  Waits for
  * the stream first. */

@@ -1094,29 +1094,55 @@ extern "C" lbib_status lbib_set_state(lbib_ctx* c, int32_t what, int32_t cap, co
 
 // ----------------------------------------------------------------- adjoint
 
-// Workspace of lbib_adjoint: a tape slot per time level 0..N (populations
-// P^n, IB force F^{n-1} - g with its flags, node state and reference points),
+// Workspace of lbib_adjoint.  Segments of K = `every` steps (the last one
+// may be shorter); segment s covers time levels sK .. min(sK + K, N).
+//   grid tape   K + 1 slots, slot r = level sK + r of the current segment:
+//               populations P, IB force F - g and its segment flags
+//   node tape   N + 1 slots: node state and reference points of every level
+//   checkpoints one per segment when there are several: the grid slot of
+//               level sK plus the node buffer, capsule table and diagnostics
+//               the forward run carries; one more node part keeps the state
+//               at level N while the reverse sweep recomputes segments
 // then the reverse-sweep arrays.
 struct AdjLayout {
-    size_t pops = 0, fib = 0, flags = 0, nodes = 0, ref = 0, slot = 0;
+    size_t pops = 0, fib = 0, flags = 0, gslot = 0;
+    size_t nodes = 0, ref = 0, nslot = 0;
+    size_t ck_nodes = 0, ck_caps = 0, ck_diag = 0, ck_live = 0, ckslot = 0;
+    size_t ntape = 0, ckpt = 0, fin = 0;
     size_t lam[2] = {0, 0}, lfm = 0, lft = 0, lfm_flags = 0, zero_flags = 0;
     size_t gacc = 0, lamx = 0, lamd = 0, ksbar = 0, out = 0, total = 0;
-    int blocks = 0;
+    int every = 0, nseg = 0, blocks = 0;
 };
 
-static bool adj_layout(const lbib_ctx* c, int nsteps, AdjLayout& A)
+static bool adj_layout(const lbib_ctx* c, int nsteps, int every, AdjLayout& A)
 {
-    if (!c || c->L.inst.size() != 1 || nsteps < 1) return false;
+    if (!c || c->L.inst.size() != 1 || nsteps < 1 || every < 0) return false;
     const Inst& I = c->L.inst[0];
     const size_t cells = (size_t)I.nxp * I.grid.ny;
     const size_t nseg = I.nseg;
+    A.every = (every == 0 || every >= nsteps) ? nsteps : every;
+    A.nseg = (nsteps + A.every - 1) / A.every;
     A.pops = round256(9 * cells * c->rb);
     A.fib = round256(2 * cells * sizeof(long long));
     A.flags = round256((size_t)I.grid.ny * nseg * sizeof(int));
+    A.gslot = A.pops + A.fib + A.flags;
     A.nodes = round256((size_t)8 * c->L.max_nodes * c->rb);
     A.ref = round256((size_t)2 * c->L.max_caps * sizeof(double));
-    A.slot = A.pops + A.fib + A.flags + A.nodes + A.ref;
-    size_t o = A.slot * (size_t)(nsteps + 1);
+    A.nslot = A.nodes + A.ref;
+    A.ck_nodes = round256((size_t)NF_COUNT * c->L.max_nodes * c->rb);
+    A.ck_caps = round256((size_t)c->L.max_caps * sizeof(CapsuleDev));
+    A.ck_diag = round256(status_offset(c->L));
+    A.ck_live = A.ck_nodes + A.ck_caps + A.ck_diag;
+    A.ckslot = A.gslot + A.ck_live;
+    size_t o = A.gslot * (size_t)(A.every + 1);
+    A.ntape = o;
+    o += A.nslot * (size_t)(nsteps + 1);
+    A.ckpt = o;
+    if (A.nseg > 1) {
+        o += A.ckslot * (size_t)A.nseg;
+        A.fin = o;
+        o += A.ck_live;
+    }
     A.lam[0] = o;
     o += A.pops;
     A.lam[1] = o;
@@ -1144,10 +1170,10 @@ static bool adj_layout(const lbib_ctx* c, int nsteps, AdjLayout& A)
     return true;
 }
 
-extern "C" size_t lbib_adjoint_bytes(const lbib_ctx* c, int32_t nsteps)
+extern "C" size_t lbib_adjoint_bytes(const lbib_ctx* c, int32_t nsteps, int32_t checkpoint_every)
 {
     AdjLayout A;
-    return adj_layout(c, nsteps, A) ? A.total : 0;
+    return adj_layout(c, nsteps, checkpoint_every, A) ? A.total : 0;
 }
 
 template <typename T>
@@ -1158,14 +1184,17 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
     const GridArgs g = grid_args(I);
     const hipStream_t st = c->stream;
     const hipMemcpyKind d2d = hipMemcpyDeviceToDevice;
-    auto slot = [&](int n) { return ws + A.slot * (size_t)n; };
-    auto sP = [&](int n) { return reinterpret_cast<T*>(slot(n)); };
-    auto sF = [&](int n) { return reinterpret_cast<long long*>(slot(n) + A.pops); };
-    auto sFl = [&](int n) { return reinterpret_cast<int*>(slot(n) + A.pops + A.fib); };
-    auto sN = [&](int n) { return reinterpret_cast<T*>(slot(n) + A.pops + A.fib + A.flags); };
+    const int K = A.every;
+    // grid tape, by slot; node tape, by level; checkpoints, by segment
+    auto gslot = [&](int r) { return ws + A.gslot * (size_t)r; };
+    auto gP = [&](int r) { return reinterpret_cast<T*>(gslot(r)); };
+    auto gF = [&](int r) { return reinterpret_cast<long long*>(gslot(r) + A.pops); };
+    auto gFl = [&](int r) { return reinterpret_cast<int*>(gslot(r) + A.pops + A.fib); };
+    auto sN = [&](int n) { return reinterpret_cast<T*>(ws + A.ntape + A.nslot * (size_t)n); };
     auto sR = [&](int n) {
-        return reinterpret_cast<double*>(slot(n) + A.pops + A.fib + A.flags + A.nodes);
+        return reinterpret_cast<double*>(ws + A.ntape + A.nslot * (size_t)n + A.nodes);
     };
+    auto ck = [&](int seg) { return ws + A.ckpt + A.ckslot * (size_t)seg; };
     T* lam[2] = {reinterpret_cast<T*>(ws + A.lam[0]), reinterpret_cast<T*>(ws + A.lam[1])};
     T* lfm = reinterpret_cast<T*>(ws + A.lfm);
     T* lft = reinterpret_cast<T*>(ws + A.lft);
@@ -1177,6 +1206,9 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
     double* ksbar = reinterpret_cast<double*>(ws + A.ksbar);
     double* out = reinterpret_cast<double*>(ws + A.out);
     const size_t pop_bytes = 9 * (size_t)I.nxp * I.grid.ny * sizeof(T);
+    char* live_nodes = bufp(c, LBIB_BUF_NODES);
+    char* live_caps = bufp(c, LBIB_BUF_CAPS);  // the capsule table leads the buffer
+    char* live_diag = bufp(c, LBIB_BUF_DIAG);  // per-capsule rows, then the status word
 
     // LDS of the IB reverse kernel: FP64 node arrays, the rest holds the patch
     int dev = 0;
@@ -1192,40 +1224,87 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
     const size_t adj_lds = ib_adj_lds_bytes<T>(adj_patch, c->L.max_nv);
     HIPCHK(c, ib_adj_set_lds_limit<T>(adj_lds));
 
+    // node buffer, capsule table and diagnostics rows: the state the IB kernel
+    // carries from step to step besides the grid
+    auto save_live = [&](char* dst) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(dst, live_nodes, A.ck_nodes, d2d, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(dst + A.ck_nodes, live_caps, A.ck_caps, d2d, st);
+        if (e == hipSuccess && A.ck_diag)
+            e = hipMemcpyAsync(dst + A.ck_nodes + A.ck_caps, live_diag, A.ck_diag, d2d, st);
+        return e;
+    };
+    auto load_live = [&](const char* src) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(live_nodes, src, A.ck_nodes, d2d, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(live_caps, src + A.ck_nodes, A.ck_caps, d2d, st);
+        if (e == hipSuccess && A.ck_diag)
+            e = hipMemcpyAsync(live_diag, src + A.ck_nodes + A.ck_caps, A.ck_diag, d2d, st);
+        return e;
+    };
+    // forward steps c0 .. e0-1 of one segment; the grid slot 0 holds level c0
+    // and the force accumulators of slots 1 .. e0-c0 are zero
+    auto run_segment = [&](int c0, int e0) -> lbib_status {
+        for (int n = c0; n < e0; n++) {
+            const int r = n - c0;
+            IBArgs<T> a = ib_args<T>(c, n, n == 0 ? (PH_PRIME | PH_A) : (PH_B | PH_A));
+            a.pops = gP(r);
+            a.fib_prev = gF(r);
+            a.fib_next = gF(r + 1);
+            a.flags_next = gFl(r + 1);
+            a.tape_nodes = sN(n);
+            a.tape_ref = sR(n);
+            HIPCHK(c, launch_ib<T>(a, c->ncap, c->lds_use, st));
+            HIPCHK(c, launch_grid_step<T>(gP(r), gP(r + 1), gF(r + 1), gFl(r + 1), gF(r + 1),
+                                          zero_flags, g, st));
+        }
+        return LBIB_OK;
+    };
+    // zero the force accumulators and flags of grid slots 1 .. m
+    auto clear_slots = [&](int m) -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int r = 1; r <= m && e == hipSuccess; r++)
+            e = hipMemsetAsync(gF(r), 0, A.fib + A.flags, st);
+        return e;
+    };
+    auto seg_lo = [&](int s) { return s * K; };
+    auto seg_hi = [&](int s) { return std::min(s * K + K, N); };
+
     size_patches<T>(c);
     HIPCHK(c, hipMemsetAsync(ws, 0, A.total, st));
-    HIPCHK(c, hipMemcpyAsync(sP(0), pops(c, 0), pop_bytes, d2d, st));
+    HIPCHK(c, hipMemcpyAsync(gP(0), pops(c, 0), pop_bytes, d2d, st));
     c->mode = mode;
 
-    // ---- forward run, taped
-    for (int n = 0; n < N; n++) {
-        IBArgs<T> a = ib_args<T>(c, n, n == 0 ? (PH_PRIME | PH_A) : (PH_B | PH_A));
-        a.pops = sP(n);
-        a.fib_prev = sF(n);
-        a.fib_next = sF(n + 1);
-        a.flags_next = sFl(n + 1);
-        a.tape_nodes = sN(n);
-        a.tape_ref = sR(n);
-        HIPCHK(c, launch_ib<T>(a, c->ncap, c->lds_use, st));
-        HIPCHK(c, launch_grid_step<T>(sP(n), sP(n + 1), sF(n + 1), sFl(n + 1), sF(n + 1),
-                                      zero_flags, g, st));
+    // ---- forward run, taped segment by segment
+    for (int s = 0; s < A.nseg; s++) {
+        const int c0 = seg_lo(s), e0 = seg_hi(s);
+        if (s > 0) {
+            HIPCHK(c, hipMemcpyAsync(gslot(0), gslot(K), A.gslot, d2d, st));
+            HIPCHK(c, clear_slots(e0 - c0));
+        }
+        if (A.nseg > 1) {
+            HIPCHK(c, hipMemcpyAsync(ck(s), gslot(0), A.gslot, d2d, st));
+            HIPCHK(c, save_live(ck(s) + A.gslot));
+        }
+        lbib_status e = run_segment(c0, e0);
+        if (e != LBIB_OK) return e;
     }
+    const int cl = seg_lo(A.nseg - 1), rN = N - cl;
     {
         IBArgs<T> a = ib_args<T>(c, N, PH_B);
-        a.pops = sP(N);
-        a.fib_prev = sF(N);
-        a.fib_next = sF(N);
-        a.flags_next = sFl(N);
+        a.pops = gP(rN);
+        a.fib_prev = gF(rN);
+        a.fib_next = gF(rN);
+        a.flags_next = gFl(rN);
         a.tape_nodes = sN(N);
         a.tape_ref = sR(N);
         HIPCHK(c, launch_ib<T>(a, c->ncap, c->lds_use, st));
     }
     // the context now stands at step N
-    HIPCHK(c, hipMemcpyAsync(pops(c, N), sP(N), pop_bytes, d2d, st));
-    HIPCHK(c, hipMemcpyAsync(fib(c, N + 1), sF(N), 2 * (size_t)I.nxp * I.grid.ny * sizeof(long long),
+    HIPCHK(c, hipMemcpyAsync(pops(c, N), gP(rN), pop_bytes, d2d, st));
+    HIPCHK(c, hipMemcpyAsync(fib(c, N + 1), gF(rN), 2 * (size_t)I.nxp * I.grid.ny * sizeof(long long),
                              d2d, st));
-    HIPCHK(c, hipMemcpyAsync(flags(c, N + 1), sFl(N), (size_t)I.grid.ny * I.nseg * sizeof(int),
+    HIPCHK(c, hipMemcpyAsync(flags(c, N + 1), gFl(rN), (size_t)I.grid.ny * I.nseg * sizeof(int),
                              d2d, st));
+    if (A.nseg > 1) HIPCHK(c, save_live(ws + A.fin));
     c->steps = N;
     int flags_fwd = 0;
     HIPCHK(c, hipMemcpyAsync(&flags_fwd, status_word(c), sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1238,10 +1317,11 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
     const CapsuleDev* caps = reinterpret_cast<const CapsuleDev*>(bufp(c, LBIB_BUF_CAPS));
     HIPCHK(c, launch_adj_seed<T>(sN(N), sR(N), caps, capid, c->L.max_nodes, objective, lamx, out,
                                  st));
-    auto ib_adj = [&](int n, int doA, int doB, int prime) -> hipError_t {
+    // slot r of the grid tape holds level n (the segment starts at n - r)
+    auto ib_adj = [&](int n, int r, int doA, int doB, int prime) -> hipError_t {
         IBAdjArgs<T> b;
-        b.pops = sP(n);
-        b.fib_prev = sF(n);
+        b.pops = gP(r);
+        b.fib_prev = gF(r);
         b.nodes_n = sN(n);
         b.ref_n = sR(n);
         b.nodes_p = doB ? sN(n - 1) : sN(n);
@@ -1265,11 +1345,11 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
         b.max_nv = c->L.max_nv;
         return launch_ib_adj<T>(b, c->ncap, adj_lds, st);
     };
-    auto grid_adj_args = [&](int n) {
+    auto grid_adj_args = [&](int n, int r) {
         GridAdjArgs<T> ga;
-        ga.pops = sP(n);
-        ga.fib = sF(n + 1);
-        ga.flags = sFl(n + 1);
+        ga.pops = gP(r);
+        ga.fib = gF(r + 1);
+        ga.flags = gFl(r + 1);
         ga.lam_in = lam[(n + 1) & 1];
         ga.lam_out = lam[n & 1];
         ga.lfm = lfm;
@@ -1278,16 +1358,29 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
         ga.gacc = gacc;
         return ga;
     };
-    HIPCHK(c, ib_adj(N, 0, 1, 0));
-    for (int n = N - 1; n >= 0; n--) {
-        HIPCHK(c, launch_grid_adj<T>(grid_adj_args(n), g, st));
-        HIPCHK(c, ib_adj(n, 1, n >= 1, n == 0));
+    HIPCHK(c, ib_adj(N, rN, 0, 1, 0));
+    for (int s = A.nseg - 1; s >= 0; s--) {
+        const int c0 = seg_lo(s), e0 = seg_hi(s);
+        if (s < A.nseg - 1) {
+            // the constant node fields the reverse kernel reads (stiffness,
+            // rest lengths) are the same in every checkpoint
+            HIPCHK(c, hipMemcpyAsync(gslot(0), ck(s), A.gslot, d2d, st));
+            HIPCHK(c, load_live(ck(s) + A.gslot));
+            HIPCHK(c, clear_slots(e0 - c0));
+            lbib_status e = run_segment(c0, e0);
+            if (e != LBIB_OK) return e;
+        }
+        for (int n = e0 - 1; n >= c0; n--) {
+            HIPCHK(c, launch_grid_adj<T>(grid_adj_args(n, n - c0), g, st));
+            HIPCHK(c, ib_adj(n, n - c0, 1, n >= 1, n == 0));
+        }
     }
     {
-        GridAdjArgs<T> ga = grid_adj_args(0);
+        GridAdjArgs<T> ga = grid_adj_args(0, 0);
         ga.lam_in = lam[0];
         HIPCHK(c, launch_init_adj<T>(ga, g, I.walls.init_profile, I.nu, st));
     }
+    if (A.nseg > 1) HIPCHK(c, load_live(ws + A.fin));
     HIPCHK(c, launch_reduce_sum(gacc, A.blocks, out, st));
     double host_out[2] = {0, 0};
     HIPCHK(c, hipMemcpyAsync(host_out, out, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1304,16 +1397,17 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
     return LBIB_OK;
 }
 
-extern "C" lbib_status lbib_adjoint(lbib_ctx* c, int32_t nsteps, lbib_mode mode,
-                                    int32_t objective, int32_t capsule, void* workspace,
-                                    size_t workspace_bytes, double* out_J, double* out_dJ_dg,
-                                    double* out_dJ_dks, int32_t n_ks)
+extern "C" lbib_status lbib_adjoint(lbib_ctx* c, int32_t nsteps, int32_t checkpoint_every,
+                                    lbib_mode mode, int32_t objective, int32_t capsule,
+                                    void* workspace, size_t workspace_bytes, double* out_J,
+                                    double* out_dJ_dg, double* out_dJ_dks, int32_t n_ks)
 {
     if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
     if (!workspace || !out_J || !out_dJ_dg || !out_dJ_dks)
         return fail(c, LBIB_EINVAL, "NULL argument");
     if (c->L.inst.size() != 1) return fail(c, LBIB_EINVAL, "the adjoint needs a single lattice");
     if (nsteps < 1) return fail(c, LBIB_EINVAL, "nsteps must be >= 1");
+    if (checkpoint_every < 0) return fail(c, LBIB_EINVAL, "checkpoint_every must be >= 0");
     if (mode != LBIB_KINEMATIC && mode != LBIB_DYNAMIC) return fail(c, LBIB_EINVAL, "bad mode");
     if (objective != LBIB_OBJ_TAYLOR && objective != LBIB_OBJ_CENTROID_Y)
         return fail(c, LBIB_EINVAL, "unknown objective");
@@ -1331,7 +1425,8 @@ extern "C" lbib_status lbib_adjoint(lbib_ctx* c, int32_t nsteps, lbib_mode mode,
         if (r) return fail(c, LBIB_EINVAL, "the adjoint does not differentiate rigid particles");
     if (n_ks < c->nodes_used) return fail(c, LBIB_EINVAL, "out_dJ_dks shorter than the node count");
     AdjLayout A;
-    if (!adj_layout(c, nsteps, A)) return fail(c, LBIB_EINVAL, "invalid adjoint layout");
+    if (!adj_layout(c, nsteps, checkpoint_every, A))
+        return fail(c, LBIB_EINVAL, "invalid adjoint layout");
     if (workspace_bytes < A.total) return fail(c, LBIB_EINVAL, "workspace too small");
     char* ws = static_cast<char*>(workspace);
     return c->rb == 4 ? adjoint_t<float>(c, nsteps, mode, objective, capsule, ws, A, out_J,

@@ -117,10 +117,10 @@ def load() -> C.CDLL:
     L.lbib_num_lattices.restype = i32
     L.lbib_num_lattices.argtypes = [vp]
     L.lbib_adjoint_bytes.restype = C.c_size_t
-    L.lbib_adjoint_bytes.argtypes = [vp, i32]
+    L.lbib_adjoint_bytes.argtypes = [vp, i32, i32]
     dp = C.POINTER(C.c_double)
     L.lbib_adjoint.restype = i32
-    L.lbib_adjoint.argtypes = [vp, i32, i32, i32, i32, vp, C.c_size_t, dp, dp, dp, i32]
+    L.lbib_adjoint.argtypes = [vp, i32, i32, i32, i32, i32, vp, C.c_size_t, dp, dp, dp, i32]
     _lib = L
     return L
 
@@ -323,16 +323,19 @@ class Sim:
         v = -1 if enable is None else (1 if enable else 0)
         _check(load().lbib_set_overlap(self.h, v), self.h)
 
-    def adjoint_bytes(self, nsteps: int) -> int:
-        return int(load().lbib_adjoint_bytes(self.h, int(nsteps)))
+    def adjoint_bytes(self, nsteps: int, checkpoint_every: int = 0) -> int:
+        return int(load().lbib_adjoint_bytes(self.h, int(nsteps), int(checkpoint_every)))
 
     def adjoint(self, nsteps: int, objective: int = OBJ_TAYLOR, capsule: int = 0,
-                mode: Optional[str] = None, workspace=None) -> Dict[str, Any]:
+                mode: Optional[str] = None, workspace=None,
+                checkpoint_every: int = 0) -> Dict[str, Any]:
         """lbib_adjoint: J and dJ/dg, dJ/dk_s (per element, node order) of an
-        nsteps run from step 0.  Allocates the trajectory workspace unless given."""
+        nsteps run from step 0.  checkpoint_every = 0 tapes the whole
+        trajectory; K > 0 keeps every K-th grid state and recomputes the
+        segments in the reverse sweep.  Allocates the workspace unless given."""
         mode = mode or self.cfg.get("mode", "dynamic")
         m = DYNAMIC if mode == "dynamic" else KINEMATIC
-        nb = self.adjoint_bytes(nsteps)
+        nb = self.adjoint_bytes(nsteps, checkpoint_every)
         if nb == 0:
             raise LbibError(EINVAL, "no adjoint layout for this context")
         with self.torch.cuda.device(self.device):
@@ -341,7 +344,8 @@ class Sim:
             nks = max(1, sum(self.nv))
             ks = np.zeros(nks, np.float64)
             J, g = C.c_double(), C.c_double()
-            _check(load().lbib_adjoint(self.h, int(nsteps), m, int(objective), int(capsule),
+            _check(load().lbib_adjoint(self.h, int(nsteps), int(checkpoint_every), m,
+                                       int(objective), int(capsule),
                                        C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(J),
                                        C.byref(g), ks.ctypes.data_as(C.POINTER(C.c_double)),
                                        nks), self.h)
@@ -447,3 +451,62 @@ class Batch(Sim):
         cut = max(float(c.get("contact_cutoff", 0.0)) for c in cfgs)
         if cut:
             self.set_contact(cut)
+
+
+def capsule_objectives(ks, u_max, build, nsteps: int, capsule: int = 0,
+                       mode: Optional[str] = None, checkpoint_every: int = 0):
+    """Differentiable (D, y_c) of one capsule after ``nsteps`` steps from the
+    initial state, as a function of the per-element stretching constants
+    ``ks`` (1-D tensor) and the channel's peak speed ``u_max`` (0-D tensor).
+
+    ``build(ks_array, u_max_float)`` returns the workload dictionary; its body
+    force must be linear in u_max (g = 8 nu u_max / H^2, as the channel
+    builders set it).  Forward: two lbib_adjoint runs (objectives D and y_c),
+    whose gradients the backward combines with the incoming weights; dJ/du_max =
+    dJ/dg * g / u_max.  ``checkpoint_every`` as in Sim.adjoint."""
+    return _CapsuleObjectives.apply(ks, u_max, build, int(nsteps), int(capsule), mode,
+                                    int(checkpoint_every))
+
+
+def _make_objectives_function():
+    import torch
+
+    class CapsuleObjectives(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, ks, u_max, build, nsteps, capsule, mode, every):
+            ks_np = ks.detach().cpu().double().numpy()
+            um = float(u_max.detach().cpu())
+            cfg = build(ks_np, um)
+            g = float(cfg["body_force_x"])
+            out, gks, gum = [], [], []
+            for obj in (OBJ_TAYLOR, OBJ_CENTROID_Y):
+                r = Sim(cfg).adjoint(nsteps, obj, capsule, mode, checkpoint_every=every)
+                out.append(r["J"])
+                gks.append(torch.as_tensor(r["dJ_dks"][capsule], dtype=ks.dtype))
+                gum.append(r["dJ_dg"] * g / um if um != 0.0 else 0.0)
+            ctx.save_for_backward(torch.stack(gks))
+            ctx.gum = gum
+            return torch.tensor(out, dtype=ks.dtype)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (gks,) = ctx.saved_tensors
+            w = grad_out.to(gks.dtype)
+            grad_ks = w[0] * gks[0] + w[1] * gks[1]
+            grad_um = (w[0] * ctx.gum[0] + w[1] * ctx.gum[1]).reshape(())
+            return grad_ks, grad_um, None, None, None, None, None
+
+    return CapsuleObjectives
+
+
+class _LazyFunction:
+    def __init__(self):
+        self.fn = None
+
+    def apply(self, *args):
+        if self.fn is None:
+            self.fn = _make_objectives_function()
+        return self.fn.apply(*args)
+
+
+_CapsuleObjectives = _LazyFunction()

@@ -109,4 +109,8 @@ def test_null_context_calls(L):
     assert L.lbib_set_timing(None, 1) == lbib.EINVAL
     assert L.lbib_set_overlap(None, 1) == lbib.EINVAL
     assert L.lbib_set_contact(None, 2.0) == lbib.EINVAL
+    assert L.lbib_adjoint_bytes(None, 10, 0) == 0
+    d = C.c_double()
+    ks = (C.c_double * 4)()
+    assert L.lbib_adjoint(None, 10, 0, 1, 0, 0, None, 0, C.byref(d), C.byref(d), ks, 4) == lbib.EINVAL
     L.lbib_destroy(None)

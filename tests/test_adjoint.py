@@ -135,6 +135,52 @@ def test_adjoint_leaves_the_forward_state():
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("mode,rb,every", [("dynamic", 8, 7), ("dynamic", 4, 1),
+                                           ("kinematic", 4, 7), ("kinematic", 8, 29)])
+def test_checkpointed_adjoint_equals_full_tape(mode, rb, every):
+    """Checkpoints every K steps with recomputed segments (K = 7 over 30 steps:
+    four full segments and a ragged one of 2; K = 1; K = N - 1) against the
+    whole-trajectory tape: J and the state left behind are bit-identical (the
+    recomputed forward steps repeat the first run exactly); the gradients agree
+    to the rounding of the reverse kernel's floating-point atomics, whose
+    summation order is free (relative 1e-4 in FP32, 1e-11 in FP64 of the
+    largest component)."""
+    steps = 30
+    full = lbib.Sim(ellipse_channel(real_bytes=rb, mode=mode))
+    ck = lbib.Sim(ellipse_channel(real_bytes=rb, mode=mode))
+    r0 = full.adjoint(steps, lbib.OBJ_CENTROID_Y, 0, mode)
+    r1 = ck.adjoint(steps, lbib.OBJ_CENTROID_Y, 0, mode, checkpoint_every=every)
+    tol = 1e-4 if rb == 4 else 1e-11
+    assert r1["J"] == r0["J"]
+    assert abs(r1["dJ_dg"] - r0["dJ_dg"]) <= tol * abs(r0["dJ_dg"])
+    k0, k1 = r0["dJ_dks"][0], r1["dJ_dks"][0]
+    assert np.abs(k1 - k0).max() <= tol * np.abs(k0).max()
+    assert np.array_equal(ck.pops_dev(), full.pops_dev())
+    assert np.array_equal(ck.force(), full.force())
+    for x, y in zip(ck.capsule(0), full.capsule(0)):
+        assert np.array_equal(x, y)
+    ck.step(3)
+    full.step(3)
+    assert np.array_equal(ck.pops_dev(), full.pops_dev())
+
+
+@pytest.mark.gpu
+def test_checkpoint_workspace_size():
+    """The checkpointed workspace of the 512 x 128 gradient channel (5000
+    steps, a checkpoint every 70) against the whole-trajectory tape."""
+    s = lbib.Sim(wl.adjoint_channel())
+    full = s.adjoint_bytes(5000, 0)
+    ck = s.adjoint_bytes(5000, 70)
+    cells = 512 * 128
+    log(f"adjoint workspace: full {full / 1e9:.2f} GB, checkpoint 70 {ck / 1e9:.3f} GB")
+    assert full > 5000 * 52 * cells
+    per_level = full / 5001  # one grid slot and one node slot (padded rows)
+    assert ck < (72 + 71 + 3) * per_level + 5001 * 8192
+    assert s.adjoint_bytes(5000, 5000) == full == s.adjoint_bytes(5000, 9999)
+    assert s.adjoint_bytes(5000, -1) == 0
+
+
+@pytest.mark.gpu
 def test_adjoint_argument_checks():
     cfg = ellipse_channel(real_bytes=4)
     s = lbib.Sim(cfg)
@@ -155,3 +201,52 @@ def test_adjoint_argument_checks():
     with pytest.raises(lbib.LbibError) as e:
         bat.adjoint(10)
     assert e.value.code == lbib.EINVAL
+    with pytest.raises(lbib.LbibError) as e:
+        lbib.Sim(cfg).adjoint(10, checkpoint_every=-1)
+    assert e.value.code == lbib.EINVAL
+
+
+@pytest.mark.gpu
+def test_autograd_function_chain_rule():
+    """torch.autograd through lbib.capsule_objectives: the forward values
+    against the oracle's objectives, and the gradient of a D + b y_c with
+    respect to the per-element k_s and the peak speed u_max against central
+    differences of the oracle (FP64)."""
+    import torch
+    from oracle import oracle as orc
+    oracle_threads(orc)
+    steps = 40
+    base = ellipse_channel(real_bytes=8)
+    nv = len(base["capsules"][0]["nodes"])
+    ks0 = base["capsules"][0]["ks"]
+    u0 = 0.02
+
+    def build(ks, um):
+        cfg = ellipse_channel(real_bytes=8)
+        cfg["body_force_x"] = wl.poiseuille_body_force(cfg["tau"], cfg["ny"], um)
+        cfg["capsules"][0]["ks"] = np.asarray(ks, np.float64)
+        return cfg
+
+    ks = torch.full((nv,), ks0, dtype=torch.float64, requires_grad=True)
+    um = torch.tensor(u0, dtype=torch.float64, requires_grad=True)
+    out = lbib.capsule_objectives(ks, um, build, steps)
+    a, b = 1.0, 0.3
+    (a * out[0] + b * out[1]).backward()
+
+    def f(ks_np, u):
+        cfg = build(ks_np, u)
+        return a * orc.objective(cfg, steps, "D") + b * orc.objective(cfg, steps, "yc")
+
+    k = np.full(nv, ks0)
+    cfg0 = build(k, u0)
+    out = out.detach()
+    assert abs(float(out[0]) - orc.objective(cfg0, steps, "D")) < 1e-9
+    assert abs(float(out[1]) - orc.objective(cfg0, steps, "yc")) < 1e-9
+    h = 2e-7  # 1e-5 relative: clear of MLS support switches
+    fd_um = (f(k, u0 + h) - f(k, u0 - h)) / (2 * h)
+    e = np.zeros(nv)
+    e[5] = 1e-4 * ks0
+    fd_k5 = (f(k + e, u0) - f(k - e, u0)) / (2 * e[5])
+    log(f"autograd: du_max {float(um.grad)} fd {fd_um}; dks[5] {float(ks.grad[5])} fd {fd_k5}")
+    assert abs(float(um.grad) - fd_um) <= 1e-5 * abs(fd_um)
+    assert abs(float(ks.grad[5]) - fd_k5) <= 1e-5 * abs(fd_k5)
