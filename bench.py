@@ -146,14 +146,19 @@ def bench_ensemble(steps: int, warmup: int, loop_steps: int):
     bat = lbib.Batch(cfgs)
     bat.step(warmup)
     torch.cuda.synchronize()
-    bat.set_timing(True)
-    bat.get_timing()
+    tune = bat.autotune(20)  # tile shape of the batched grid pass
+    log(f"ensemble autotune: rows {tune['rows']}, resident {tune['resident']}; {tune['us']}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     bat.step(steps)
     torch.cuda.synchronize()
     t_bat = (time.perf_counter() - t0) / steps
+    # per-kernel durations from a shorter run with timing events
+    bat.set_timing(True)
+    bat.get_timing()
+    bat.step(max(20, steps // 4))
     tm = bat.get_timing()
+    bat.set_timing(False)
     flags = bat.check()
     if flags:
         raise RuntimeError(f"device flags {flags} in the batched ensemble")
@@ -187,6 +192,8 @@ def bench_ensemble(steps: int, warmup: int, loop_steps: int):
         "grid_kernel_us": round(grid_us, 2),
         "grid_kernel_frac": round(BYTES_PER_CELL * cells / (grid_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
         "ib_kernel_us": round(ib_us, 2),
+        "tile": {"rows": tune["rows"], "resident": tune["resident"]},
+        "tile_candidates_us": tune["us"],
     }
 
 

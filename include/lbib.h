@@ -203,6 +203,13 @@ lbib_status lbib_add_rigid_to(lbib_ctx* ctx, int32_t lattice, const double* node
  * bit-identical to the single pass, and the call still returns with all work
  * ordered on the bound stream.  By default the split is used from 2^23
  * lattice cells on, where it pays.
+ * Captured steps (lbib_set_graph(ctx, 1)): otherwise, unless kernel timing is
+ * on, the inner steps of a call go in blocks of 16 steps captured once into a
+ * HIP graph (one for blocks that start on an even step, one for odd) and
+ * replayed with one launch per block; the first step of a call and the
+ * remainder launch directly.  The graphs hold kernel launches only and are captured
+ * again after the capsule count, the contact cutoff or the mode changed.
+ * Replays run the very launches of the direct path (bit-identical results).
  * Errors: EINVAL (nsteps < 0, bad mode), ESTATE (mode differs from the first
  * step's), EDEVICE.  Device-side problems raise status flags (lbib_check). */
 lbib_status lbib_step(lbib_ctx* ctx, int32_t nsteps, lbib_mode mode);
@@ -253,6 +260,38 @@ lbib_status lbib_set_contact(lbib_ctx* ctx, double cutoff);
  * schedule where it applies (see lbib_step), 0 never, -1 (the default) from
  * 2^23 lattice cells on.  Errors: EINVAL (other values). */
 lbib_status lbib_set_overlap(lbib_ctx* ctx, int32_t enable);
+
+/* Captured step blocks of lbib_step: enable = 1 replays them; 0 and -1 (the
+ * default, automatic) launch every step directly (on MI355X the replays
+ * measure no faster: the direct dispatch keeps pace with these kernels).
+ * Errors: EINVAL (other values). */
+lbib_status lbib_set_graph(lbib_ctx* ctx, int32_t enable);
+
+/* Number of captured-block replays lbib_step has queued on this context, or
+ * -1 for a NULL context. */
+int64_t lbib_graph_replays(const lbib_ctx* ctx);
+
+/* Tile shape of the batched grid pass of a batch context (more than one
+ * lattice).  rows = nodes per thread (1, 2 or 4): a block of 4 wavefronts
+ * covers a 64-cell segment of a band of 4 * rows rows.  resident = 0 launches
+ * one block per tile; k in 1..64 launches k blocks per compute unit (rounded
+ * to a multiple of 8) that loop over the tiles (a persistent launch).  Every
+ * shape computes the same bits.  The default is rows 1, resident 0.
+ * Errors: EINVAL (other values). */
+lbib_status lbib_set_tile(lbib_ctx* ctx, int32_t rows, int32_t resident);
+
+/* Autotuner of the batched grid pass: times every tile shape (rows 1, 2, 4 x
+ * resident 0, 2, 4, 8, in that order: out_us[4 * shape + resident index]) over
+ * `launches` grid passes each on the context's own lattices and current state,
+ * with HIP events on the bound stream, and keeps the fastest for lbib_step.
+ * The trial passes read no IB force and leave the state unchanged (they write
+ * only the population buffer the next step overwrites).  Call it between
+ * lbib_step calls.  Outputs (host, each may be NULL): the chosen rows and
+ * resident count, and up to n_us of the 12 mean times per pass in us.
+ * Waits for the stream.  Errors: EINVAL (single-lattice context, launches not
+ * in [1, 1000]), EDEVICE. */
+lbib_status lbib_autotune(lbib_ctx* ctx, int32_t launches, int32_t* out_rows,
+                          int32_t* out_resident, double* out_us, int32_t n_us);
 lbib_status lbib_get_timing(lbib_ctx* ctx, double* out6);
 
 /* Number of completed steps n, or -1 for a NULL context. */

@@ -30,8 +30,15 @@ struct Inst {
     size_t fib_off = 0;   // long longs of one force level
     size_t flag_off = 0;  // ints of one flag level
     int block0 = 0, blocks = 0;
+    int tile0[3] = {0, 0, 0};  // first tile of the lattice in the batched pass, per tile shape
     int ncap = 0, nodes = 0;
 };
+
+// Tile shapes of the batched grid pass: nodes per thread (rows of a band / 4)
+constexpr int kTileRows[3] = {1, 2, 4};
+// Candidate resident blocks per compute unit of the persistent launch (0: one
+// block per tile)
+constexpr int kTileResident[4] = {0, 2, 4, 8};
 
 // Buffer layout of a context: the lattices one after the other in every
 // buffer; the capsule table followed by the lattice table and the block-round
@@ -42,8 +49,10 @@ struct Layout {
     size_t pop_elems = 0, fib_level = 0, flag_level = 0;
     int max_caps = 0, max_nodes = 0, max_nv = 0;
     int grid_blocks = 0;
+    int tiles[3] = {0, 0, 0};  // tiles of the batched pass, per tile shape
     size_t plane_max = 0;
     size_t inst_table = 0, round_table = 0, rect_table = 0, near_map = 0, bounds = 0;  // in BUF_CAPS
+    size_t round_off[3] = {0, 0, 0};  // the round table of each tile shape
 };
 
 struct lbib_ctx {
@@ -73,6 +82,22 @@ struct lbib_ctx {
     double contact_cutoff = 0.0;  // Eq. 27 contact force below this node distance; 0 = off
     hipStream_t s_far = nullptr;
     hipEvent_t e_ib = nullptr, e_far[2] = {nullptr, nullptr};
+    // captured step blocks of the direct schedule: kGraphSteps steps from an
+    // even and from an odd step (1 on; 0 and -1, the automatic default, off:
+    // replays measured no faster than direct launches, whose dispatch already
+    // keeps up with the kernels); captured on s_cap, replayed on `stream`; the
+    // key records what they were captured for
+    int graph = -1;
+    hipStream_t s_cap = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int g_ncap = -1, g_mode = -1, g_patch = -1;
+    double g_contact = -1.0;
+    long long graph_replays = 0;
+    // tile shape of the batched grid pass (lbib_set_tile, lbib_autotune):
+    // index into kTileRows and resident blocks per compute unit (0: one block
+    // per tile)
+    int tile_shape = 0, tile_resident = 0;
+    int num_cu = 256;
 };
 
 // ----------------------------------------------------------------- helpers
@@ -139,6 +164,10 @@ static bool make_layout(const lbib_grid* grids, int n, Layout& L)
         I.flag_off = L.flag_level;
         I.block0 = (int)blocks;
         I.blocks = grid_blocks(g->ny, I.nseg);
+        for (int k = 0; k < 3; k++) {
+            I.tile0[k] = L.tiles[k];
+            L.tiles[k] += grid_blocks_rows(g->ny, I.nseg, kTileRows[k]);
+        }
         L.pop_elems += 9 * lc;
         L.fib_level += 2 * lc;
         L.flag_level += ((size_t)g->ny * I.nseg + 63) / 64 * 64;
@@ -157,7 +186,12 @@ static bool make_layout(const lbib_grid* grids, int n, Layout& L)
     L.grid_blocks = (int)blocks;
     L.inst_table = round256((size_t)L.max_caps * sizeof(CapsuleDev));
     L.round_table = L.inst_table + round256((size_t)n * sizeof(InstDev));
-    L.rect_table = L.round_table + round256((size_t)(L.grid_blocks / kNumXcd) * sizeof(int));
+    size_t o = L.round_table;
+    for (int k = 0; k < 3; k++) {
+        L.round_off[k] = o;
+        o += round256((size_t)(L.tiles[k] / kNumXcd) * sizeof(int2));
+    }
+    L.rect_table = o;
     L.near_map = L.rect_table + round256((size_t)2 * L.max_caps * sizeof(NearRect));
     L.bounds = L.near_map + round256((size_t)2 * L.flag_level * sizeof(int));
     return true;
@@ -259,9 +293,9 @@ static bool any_open(const lbib_ctx* c)
     return false;
 }
 
-static const int* round_table(const lbib_ctx* c)
+static const int2* round_table(const lbib_ctx* c, int shape)
 {
-    return reinterpret_cast<const int*>(bufp(c, LBIB_BUF_CAPS) + c->L.round_table);
+    return reinterpret_cast<const int2*>(bufp(c, LBIB_BUF_CAPS) + c->L.round_off[shape]);
 }
 
 static NearRect* rect_table(const lbib_ctx* c, long long parity)
@@ -357,6 +391,7 @@ static lbib_status create_common(const lbib_grid* grids, const double* taus,
 
     lbib_ctx* c = new lbib_ctx();
     c->L = L;
+    if (prop.multiProcessorCount > 0) c->num_cu = prop.multiProcessorCount;
     for (int i = 0; i < n_inst; i++) {
         Inst& I = c->L.inst[i];
         I.walls = walls[i];
@@ -394,7 +429,8 @@ static lbib_status create_common(const lbib_grid* grids, const double* taus,
     }
     // lattice table and block-round table of the batched grid launch
     std::vector<InstDev> tab(n_inst);
-    std::vector<int> rounds(L.grid_blocks / kNumXcd);
+    std::vector<int2> rounds[3];
+    for (int k = 0; k < 3; k++) rounds[k].resize(L.tiles[k] / kNumXcd);
     for (int i = 0; i < n_inst; i++) {
         const Inst& I = c->L.inst[i];
         const GridArgs g = grid_args(I);
@@ -416,13 +452,18 @@ static lbib_status create_common(const lbib_grid* grids, const double* taus,
         d.gx = g.gx;
         d.u_bot = g.u_bot;
         d.u_top = g.u_top;
-        for (int r = I.block0 / kNumXcd; r < (I.block0 + I.blocks) / kNumXcd; r++) rounds[r] = i;
+        for (int k = 0; k < 3; k++) {
+            const int r0 = I.tile0[k] / kNumXcd;
+            const int r1 = r0 + grid_blocks_rows(g.ny, g.nseg, kTileRows[k]) / kNumXcd;
+            for (int r = r0; r < r1; r++) rounds[k][r] = make_int2(i, r0);
+        }
     }
     e = hipMemcpyAsync(bufp(c, LBIB_BUF_CAPS) + L.inst_table, tab.data(),
                        tab.size() * sizeof(InstDev), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess && !rounds.empty())
-        e = hipMemcpyAsync(bufp(c, LBIB_BUF_CAPS) + L.round_table, rounds.data(),
-                           rounds.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    for (int k = 0; k < 3 && e == hipSuccess; k++)
+        if (!rounds[k].empty())
+            e = hipMemcpyAsync(bufp(c, LBIB_BUF_CAPS) + L.round_off[k], rounds[k].data(),
+                               rounds[k].size() * sizeof(int2), hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return bail(LBIB_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
     for (int i = 0; i < n_inst && e == hipSuccess; i++) {
         const Inst& I = c->L.inst[i];
@@ -744,6 +785,28 @@ static hipError_t do_ib(lbib_ctx* c, void* p)
     return launch_ib<T>(a, c->ncap, c->lds_use, c->stream);
 }
 
+// Blocks of a persistent batched launch: `resident` per compute unit, a
+// multiple of 8 (so tile t stays on XCD t % 8), at most one per tile.
+static int batch_grid(const lbib_ctx* c, int shape, int resident)
+{
+    const int tiles = c->L.tiles[shape];
+    if (resident <= 0) return tiles;
+    const long long want = (long long)resident * c->num_cu / kNumXcd * kNumXcd;
+    return (int)std::max<long long>(kNumXcd, std::min<long long>(want, tiles));
+}
+
+template <typename T>
+static hipError_t launch_batch_shape(const lbib_ctx* c, const T* src, T* dst,
+                                     const long long* fib_now, const int* flags_now,
+                                     long long* fib_old, int* flags_old, int shape, int resident,
+                                     hipStream_t st)
+{
+    return launch_grid_step_batch<T>(src, dst, fib_now, flags_now, fib_old, flags_old,
+                                     inst_table(c), round_table(c, shape), c->L.tiles[shape],
+                                     kTileRows[shape], batch_grid(c, shape, resident),
+                                     any_open(c), st);
+}
+
 template <typename T>
 static hipError_t do_grid(lbib_ctx* c, void* p)
 {
@@ -754,10 +817,10 @@ static hipError_t do_grid(lbib_ctx* c, void* p)
                                    static_cast<T*>(pops(c, n + 1)), fib(c, n), flags(c, n),
                                    fib(c, n + 1), flags(c, n + 1), g, c->stream);
     }
-    return launch_grid_step_batch<T>(static_cast<const T*>(pops(c, n)),
-                                     static_cast<T*>(pops(c, n + 1)), fib(c, n), flags(c, n),
-                                     fib(c, n + 1), flags(c, n + 1), inst_table(c), round_table(c),
-                                     c->L.grid_blocks, any_open(c), c->stream);
+    return launch_batch_shape<T>(c, static_cast<const T*>(pops(c, n)),
+                                 static_cast<T*>(pops(c, n + 1)), fib(c, n), flags(c, n),
+                                 fib(c, n + 1), flags(c, n + 1), c->tile_shape, c->tile_resident,
+                                 c->stream);
 }
 
 template <typename T>
@@ -845,6 +908,85 @@ static lbib_status step_overlap_t(lbib_ctx* c, int nsteps)
 // Dynamic node update (x^n of step 7), and, for the Kinematic scheme, between
 // the node update and the forcing (x^n of step i), which then take separate
 // launches.
+// One step of the direct schedule: the IB launch(es) that finish step n - 1
+// (phase B, unless pb = 0) and start step n (phase A), then the grid step.
+// With the contact force (Eq. 27): Dynamic takes it before each launch that
+// holds B; Kinematic splits the launch so that it is added at A.
+template <typename T>
+static lbib_status step_body(lbib_ctx* c, long long n, int pb, int pa, bool contact, bool dyn)
+{
+    if (c->ncap > 0) {
+        lbib_status s = LBIB_OK;
+        if (contact && !dyn) {
+            if (pb) {
+                IBLaunch<T> qb{n, pb, false};
+                s = launch_timed<T>(c, 1, do_ib<T>, &qb);
+                if (s != LBIB_OK) return s;
+            }
+            s = launch_contact_t<T>(c);
+            if (s != LBIB_OK) return s;
+            IBLaunch<T> qa{n, pa, false};
+            s = launch_timed<T>(c, 1, do_ib<T>, &qa);
+        } else {
+            if (contact && pb) {
+                s = launch_contact_t<T>(c);
+                if (s != LBIB_OK) return s;
+            }
+            IBLaunch<T> q{n, pb | pa, false};
+            s = launch_timed<T>(c, 1, do_ib<T>, &q);
+        }
+        if (s != LBIB_OK) return s;
+    }
+    long long nn = n;
+    return launch_timed<T>(c, 0, do_grid<T>, &nn);
+}
+
+// Steps per replay of a captured block (even: a replay leaves the buffer
+// parity as it found it)
+constexpr int kGraphSteps = 16;
+
+static void drop_graphs(lbib_ctx* c)
+{
+    for (hipGraphExec_t& g : c->gexec)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+// Captures steps n0 .. n0 + kGraphSteps - 1 (n0 >= 1, every one a full B + A
+// step) into an executable graph.  Every launch argument depends on the step
+// only through its parity, so the graph serves every later block that starts
+// on a step of the same parity.
+template <typename T>
+static lbib_status capture_steps(lbib_ctx* c, long long n0, bool contact, bool dyn,
+                                 hipGraphExec_t* out)
+{
+    if (!c->s_cap) HIPCHK(c, hipStreamCreateWithFlags(&c->s_cap, hipStreamNonBlocking));
+    HIPCHK(c, hipStreamBeginCapture(c->s_cap, hipStreamCaptureModeThreadLocal));
+    const hipStream_t keep = c->stream;
+    c->stream = c->s_cap;
+    lbib_status s = LBIB_OK;
+    for (int i = 0; i < kGraphSteps && s == LBIB_OK; i++)
+        s = step_body<T>(c, n0 + i, PH_B, PH_A, contact, dyn);
+    c->stream = keep;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->s_cap, &g);
+    if (s != LBIB_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return s != LBIB_OK ? s
+                            : fail(c, LBIB_EDEVICE,
+                                   std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        *out = nullptr;
+        return fail(c, LBIB_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    return LBIB_OK;
+}
+
 template <typename T>
 static lbib_status step_t(lbib_ctx* c, int nsteps)
 {
@@ -860,35 +1002,34 @@ static lbib_status step_t(lbib_ctx* c, int nsteps)
     // cells, -4 % at 4.2 M, -30 % at 0.26 M)
     const bool want = c->overlap == 1 || (c->overlap < 0 && cells >= kOverlapMinCells);
     if (can_overlap && want) return step_overlap_t<T>(c, nsteps);
-    for (int k = 0; k < nsteps; k++) {
+    // replays of captured blocks for the inner steps; timed runs launch directly
+    const bool graphs = c->graph == 1 && !c->timing;
+    if (graphs && (c->g_ncap != c->ncap || c->g_mode != c->mode || c->g_patch != c->patch_use ||
+                   c->g_contact != c->contact_cutoff)) {
+        drop_graphs(c);
+        c->g_ncap = c->ncap;
+        c->g_mode = c->mode;
+        c->g_patch = c->patch_use;
+        c->g_contact = c->contact_cutoff;
+    }
+    for (int k = 0; k < nsteps;) {
         const long long n = c->steps + k;
-        if (c->ncap > 0) {
-            const int pb = k == 0 ? 0 : PH_B;
-            const int pa = n == 0 ? (PH_PRIME | PH_A) : PH_A;
-            lbib_status s = LBIB_OK;
-            if (contact && !dyn) {
-                if (pb) {
-                    IBLaunch<T> qb{n, pb, false};
-                    s = launch_timed<T>(c, 1, do_ib<T>, &qb);
-                    if (s != LBIB_OK) return s;
-                }
-                s = launch_contact_t<T>(c);
+        if (graphs && k >= 1 && nsteps - k >= kGraphSteps) {
+            hipGraphExec_t& ge = c->gexec[n & 1];
+            if (!ge) {
+                lbib_status s = capture_steps<T>(c, n, contact, dyn, &ge);
                 if (s != LBIB_OK) return s;
-                IBLaunch<T> qa{n, pa, false};
-                s = launch_timed<T>(c, 1, do_ib<T>, &qa);
-            } else {
-                if (contact && pb) {
-                    s = launch_contact_t<T>(c);
-                    if (s != LBIB_OK) return s;
-                }
-                IBLaunch<T> q{n, pb | pa, false};
-                s = launch_timed<T>(c, 1, do_ib<T>, &q);
             }
-            if (s != LBIB_OK) return s;
+            HIPCHK(c, hipGraphLaunch(ge, c->stream));
+            c->graph_replays++;
+            k += kGraphSteps;
+            continue;
         }
-        long long nn = n;
-        lbib_status s = launch_timed<T>(c, 0, do_grid<T>, &nn);
+        const int pb = k == 0 ? 0 : PH_B;
+        const int pa = n == 0 ? (PH_PRIME | PH_A) : PH_A;
+        lbib_status s = step_body<T>(c, n, pb, pa, contact, dyn);
         if (s != LBIB_OK) return s;
+        k++;
     }
     if (c->ncap > 0) {
         if (contact && dyn) {
@@ -1471,6 +1612,100 @@ extern "C" lbib_status lbib_set_overlap(lbib_ctx* c, int32_t enable)
     return LBIB_OK;
 }
 
+extern "C" lbib_status lbib_set_graph(lbib_ctx* c, int32_t enable)
+{
+    if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
+    if (enable < -1 || enable > 1) return fail(c, LBIB_EINVAL, "enable must be -1, 0 or 1");
+    c->graph = enable;
+    return LBIB_OK;
+}
+
+extern "C" int64_t lbib_graph_replays(const lbib_ctx* c) { return c ? c->graph_replays : -1; }
+
+extern "C" lbib_status lbib_set_tile(lbib_ctx* c, int32_t rows, int32_t resident)
+{
+    if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
+    int shape = -1;
+    for (int k = 0; k < 3; k++)
+        if (kTileRows[k] == rows) shape = k;
+    if (shape < 0) return fail(c, LBIB_EINVAL, "rows must be 1, 2 or 4");
+    if (resident < 0 || resident > 64) return fail(c, LBIB_EINVAL, "resident must be in [0, 64]");
+    c->tile_shape = shape;
+    c->tile_resident = resident;
+    return LBIB_OK;
+}
+
+// Times every tile-shape candidate of the batched grid pass on the context's
+// own lattices and keeps the fastest.  The pass runs on the current state
+// with the force level of the coming step as both its force input and the
+// level it clears: between calls that level is zero (the last grid pass
+// cleared it), so the trial passes read no force, clear nothing, and write
+// only the other population buffer, which the next step rewrites in full.
+template <typename T>
+static lbib_status autotune_t(lbib_ctx* c, int launches, double* us)
+{
+    const long long n = c->steps;
+    const T* src = static_cast<const T*>(pops(c, n));
+    T* dst = static_cast<T*>(pops(c, n + 1));
+    long long* f = fib(c, n);
+    int* fl = flags(c, n);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(c, LBIB_EDEVICE, "hipEventCreate failed");
+    }
+    lbib_status st = LBIB_OK;
+    double best = 1e300;
+    int best_s = 0, best_r = 0;
+    for (int s = 0; s < 3 && st == LBIB_OK; s++)
+        for (int r = 0; r < 4 && st == LBIB_OK; r++) {
+            hipError_t e = launch_batch_shape<T>(c, src, dst, f, fl, f, fl, s, kTileResident[r],
+                                                 c->stream);
+            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+            for (int i = 0; i < launches && e == hipSuccess; i++)
+                e = launch_batch_shape<T>(c, src, dst, f, fl, f, fl, s, kTileResident[r],
+                                          c->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                st = fail(c, LBIB_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+                break;
+            }
+            const double t = 1e3 * ms / launches;
+            us[s * 4 + r] = t;
+            if (t < best) {
+                best = t;
+                best_s = s;
+                best_r = r;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != LBIB_OK) return st;
+    c->tile_shape = best_s;
+    c->tile_resident = kTileResident[best_r];
+    return LBIB_OK;
+}
+
+extern "C" lbib_status lbib_autotune(lbib_ctx* c, int32_t launches, int32_t* out_rows,
+                                     int32_t* out_resident, double* out_us, int32_t n_us)
+{
+    if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
+    if (launches < 1 || launches > 1000) return fail(c, LBIB_EINVAL, "launches must be in [1, 1000]");
+    if (c->L.inst.size() < 2) return fail(c, LBIB_EINVAL, "tile shapes apply to batch contexts");
+    double us[12];
+    const lbib_status st = c->rb == 4 ? autotune_t<float>(c, launches, us)
+                                      : autotune_t<double>(c, launches, us);
+    if (st != LBIB_OK) return st;
+    if (out_rows) *out_rows = kTileRows[c->tile_shape];
+    if (out_resident) *out_resident = c->tile_resident;
+    for (int i = 0; out_us && i < n_us && i < 12; i++) out_us[i] = us[i];
+    return LBIB_OK;
+}
+
 extern "C" lbib_status lbib_set_timing(lbib_ctx* c, int32_t enable)
 {
     if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
@@ -1518,6 +1753,8 @@ extern "C" void lbib_destroy(lbib_ctx* c)
         (void)hipEventDestroy(tl.stop);
     }
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    drop_graphs(c);
+    if (c->s_cap) (void)hipStreamDestroy(c->s_cap);
     if (c->s_far) {
         (void)hipStreamSynchronize(c->s_far);
         (void)hipStreamDestroy(c->s_far);

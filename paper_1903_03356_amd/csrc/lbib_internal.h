@@ -144,8 +144,8 @@ hipError_t launch_grid_step(const T* src, T* dst, const long long* fib_now, cons
 template <typename T>
 hipError_t launch_grid_step_batch(const T* src, T* dst, const long long* fib_now,
                                   const int* flags_now, long long* fib_old, int* flags_old,
-                                  const InstDev* inst, const int* round_inst, int blocks,
-                                  bool any_open, hipStream_t s);
+                                  const InstDev* inst, const int2* rounds, int tiles, int rows,
+                                  int grid, bool any_open, hipStream_t s);
 template <typename T>
 hipError_t launch_grid_far(const T* src, T* dst, const int* flags_now, const int* flags_old,
                            const int* near_map, int stamp, int* status, const GridArgs& g,
@@ -160,6 +160,9 @@ template <typename T>
 hipError_t contact_set_lds_limit(int max_nv);
 // Blocks of the grid kernel for one lattice (a multiple of kNumXcd).
 int grid_blocks(int ny, int nseg);
+// Blocks of a lattice's grid pass with `rows` nodes per thread (bands of
+// 4 * rows rows, dealt to the XCDs in groups of 8 bands), a multiple of 8.
+int grid_blocks_rows(int ny, int nseg, int rows);
 template <typename T>
 hipError_t launch_ib(const IBArgs<T>& a, int ncap, size_t lds_bytes, hipStream_t s);
 template <typename T>

@@ -250,65 +250,95 @@ hipError_t launch_grid_near(const T* src, T* dst, const long long* fib_now, cons
     return hipGetLastError();
 }
 
-// Ensemble of lattices in one launch.  Every lattice owns a run of blocks that
-// starts at a multiple of kNumXcd, so block b still lands on XCD b % 8 and the
-// band-to-XCD mapping above holds inside each lattice.  round_inst[b / 8]
-// names the lattice of block b.
+// Ensemble of lattices in one launch.  The tiles (a 64-cell segment of a band
+// of 4 * ROWS rows) of every lattice form a run that starts at a multiple of
+// kNumXcd, so tile t, processed by a block on XCD t % 8, keeps the band-to-XCD
+// mapping above inside each lattice.  rounds[t / 8] = (lattice, first round of
+// that lattice).  With gridDim.x < tiles (a multiple of 8) the launch is
+// persistent: each block walks the tiles t = blockIdx.x + k * gridDim.x.
 template <typename T, int ROWS, bool OPEN>
 __global__ __launch_bounds__(kSegW * 4) void k_grid_step_batch(
     const T* __restrict__ src, T* __restrict__ dst, const long long* __restrict__ fib_now,
     const int* __restrict__ flags_now, long long* __restrict__ fib_old,
     int* __restrict__ flags_old, const InstDev* __restrict__ inst,
-    const int* __restrict__ round_inst)
+    const int2* __restrict__ rounds, int tiles)
 {
-    const int b = blockIdx.x;
-    const InstDev& I = inst[round_inst[b / kNumXcd]];
-    GridArgs g;
-    g.nx = I.nx;
-    g.ny = I.ny;
-    g.nxp = I.nxp;
-    g.nseg = I.nseg;
-    g.periodic_y = I.periodic_y;
-    g.periodic_x = I.periodic_x;
-    g.omega = I.omega;
-    g.gx = I.gx;
-    g.u_bot = I.u_bot;
-    g.u_top = I.u_top;
-    g.u_in = I.u_in;
-    g.rho_out = I.rho_out;
-    const int lb = b - I.block0;
-    const int j = lb / kNumXcd;
-    const int group = j / g.nseg;
-    const int band = group * kNumXcd + (lb - j * kNumXcd);
-    const int seg = j - group * g.nseg;
-    const int lane = threadIdx.x & (kSegW - 1);
-    const int y0 = band * (4 * ROWS) + (threadIdx.x >> 6);
+    for (int b = blockIdx.x; b < tiles; b += gridDim.x) {
+        const int2 ri = rounds[b / kNumXcd];
+        const InstDev& I = inst[ri.x];
+        GridArgs g;
+        g.nx = I.nx;
+        g.ny = I.ny;
+        g.nxp = I.nxp;
+        g.nseg = I.nseg;
+        g.periodic_y = I.periodic_y;
+        g.periodic_x = I.periodic_x;
+        g.omega = I.omega;
+        g.gx = I.gx;
+        g.u_bot = I.u_bot;
+        g.u_top = I.u_top;
+        g.u_in = I.u_in;
+        g.rho_out = I.rho_out;
+        const int lb = b - ri.y * kNumXcd;
+        const int j = lb / kNumXcd;
+        const int group = j / g.nseg;
+        const int band = group * kNumXcd + (lb - j * kNumXcd);
+        const int seg = j - group * g.nseg;
+        const int lane = threadIdx.x & (kSegW - 1);
+        const int y0 = band * (4 * ROWS) + (threadIdx.x >> 6);
 #pragma unroll
-    for (int r = 0; r < ROWS; r++) {
-        const int y = y0 + 4 * r;
-        if (y < g.ny)
-            grid_cell<OPEN>(src + I.pop_off, dst + I.pop_off, fib_now + I.fib_off,
-                            flags_now + I.flag_off, fib_old + I.fib_off, flags_old + I.flag_off, g,
-                            y, seg, lane);
+        for (int r = 0; r < ROWS; r++) {
+            const int y = y0 + 4 * r;
+            if (y < g.ny)
+                grid_cell<OPEN>(src + I.pop_off, dst + I.pop_off, fib_now + I.fib_off,
+                                flags_now + I.flag_off, fib_old + I.fib_off,
+                                flags_old + I.flag_off, g, y, seg, lane);
+        }
     }
+}
+
+int grid_blocks_rows(int ny, int nseg, int rows)
+{
+    const int bands = (ny + 4 * rows - 1) / (4 * rows);
+    const int groups = (bands + kNumXcd - 1) / kNumXcd;
+    return groups * nseg * kNumXcd;
+}
+
+template <typename T, int R>
+static void launch_batch_rows(const T* src, T* dst, const long long* fib_now, const int* flags_now,
+                              long long* fib_old, int* flags_old, const InstDev* inst,
+                              const int2* rounds, int tiles, int grid, bool any_open,
+                              hipStream_t s)
+{
+    if (any_open)
+        hipLaunchKernelGGL((k_grid_step_batch<T, R, true>), dim3((unsigned)grid), dim3(kSegW * 4),
+                           0, s, src, dst, fib_now, flags_now, fib_old, flags_old, inst, rounds,
+                           tiles);
+    else
+        hipLaunchKernelGGL((k_grid_step_batch<T, R, false>), dim3((unsigned)grid),
+                           dim3(kSegW * 4), 0, s, src, dst, fib_now, flags_now, fib_old, flags_old,
+                           inst, rounds, tiles);
 }
 
 template <typename T>
 hipError_t launch_grid_step_batch(const T* src, T* dst, const long long* fib_now,
                                   const int* flags_now, long long* fib_old, int* flags_old,
-                                  const InstDev* inst, const int* round_inst, int blocks,
-                                  bool any_open, hipStream_t s)
+                                  const InstDev* inst, const int2* rounds, int tiles, int rows,
+                                  int grid, bool any_open, hipStream_t s)
 {
-    constexpr int R = kGridRowsPerThread;
-    if (blocks <= 0) return hipSuccess;
-    if (any_open)
-        hipLaunchKernelGGL((k_grid_step_batch<T, R, true>), dim3((unsigned)blocks),
-                           dim3(kSegW * 4), 0, s, src, dst, fib_now, flags_now, fib_old, flags_old,
-                           inst, round_inst);
+    if (tiles <= 0) return hipSuccess;
+    if (grid <= 0 || grid > tiles || grid % kNumXcd != 0) return hipErrorInvalidValue;
+    if (rows == 1)
+        launch_batch_rows<T, 1>(src, dst, fib_now, flags_now, fib_old, flags_old, inst, rounds,
+                                tiles, grid, any_open, s);
+    else if (rows == 2)
+        launch_batch_rows<T, 2>(src, dst, fib_now, flags_now, fib_old, flags_old, inst, rounds,
+                                tiles, grid, any_open, s);
+    else if (rows == 4)
+        launch_batch_rows<T, 4>(src, dst, fib_now, flags_now, fib_old, flags_old, inst, rounds,
+                                tiles, grid, any_open, s);
     else
-        hipLaunchKernelGGL((k_grid_step_batch<T, R, false>), dim3((unsigned)blocks),
-                           dim3(kSegW * 4), 0, s, src, dst, fib_now, flags_now, fib_old, flags_old,
-                           inst, round_inst);
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -1573,8 +1603,8 @@ hipError_t launch_set_nodes(T* nodes, CapsuleDev* caps, int cap, int nv, int nod
     template hipError_t launch_grid_step<T>(const T*, T*, const long long*, const int*,           \
                                             long long*, int*, const GridArgs&, hipStream_t);      \
     template hipError_t launch_grid_step_batch<T>(const T*, T*, const long long*, const int*,     \
-                                                  long long*, int*, const InstDev*, const int*,   \
-                                                  int, bool, hipStream_t);                        \
+                                                  long long*, int*, const InstDev*, const int2*,  \
+                                                  int, int, int, bool, hipStream_t);              \
     template hipError_t launch_grid_far<T>(const T*, T*, const int*, const int*, const int*, int, \
                                            int*, const GridArgs&, hipStream_t);                   \
     template hipError_t launch_grid_near<T>(const T*, T*, const long long*, const int*,           \

@@ -35,6 +35,7 @@ EXPORTS = ["lbib_required_bytes", "lbib_create", "lbib_add_capsule", "lbib_step"
            "lbib_get_timing", "lbib_steps_done", "lbib_last_error", "lbib_destroy",
            "lbib_required_bytes_batch", "lbib_create_batch", "lbib_add_capsule_to",
            "lbib_num_lattices", "lbib_adjoint_bytes", "lbib_adjoint", "lbib_set_overlap",
+           "lbib_set_graph", "lbib_graph_replays", "lbib_set_tile", "lbib_autotune",
            "lbib_set_contact", "lbib_add_rigid_to"]
 OBJ_TAYLOR, OBJ_CENTROID_Y = 0, 1
 
@@ -67,6 +68,10 @@ def load() -> C.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    # torch carries its own HIP runtime; loading it first makes the library
+    # bind to that same runtime (one device context, torch's streams and
+    # synchronisation), instead of a second copy from the ROCm install
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_1903_03356_amd.build` (hipcc, gfx950)")
@@ -116,6 +121,14 @@ def load() -> C.CDLL:
                                       i32, C.c_double, C.c_double, C.c_double, C.POINTER(i32)]
     L.lbib_num_lattices.restype = i32
     L.lbib_num_lattices.argtypes = [vp]
+    L.lbib_set_graph.restype = i32
+    L.lbib_set_graph.argtypes = [vp, i32]
+    L.lbib_graph_replays.restype = C.c_int64
+    L.lbib_graph_replays.argtypes = [vp]
+    L.lbib_set_tile.restype = i32
+    L.lbib_set_tile.argtypes = [vp, i32, i32]
+    L.lbib_autotune.restype = i32
+    L.lbib_autotune.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double), i32]
     L.lbib_adjoint_bytes.restype = C.c_size_t
     L.lbib_adjoint_bytes.argtypes = [vp, i32, i32]
     dp = C.POINTER(C.c_double)
@@ -322,6 +335,33 @@ class Sim:
         the automatic choice (large lattices only)."""
         v = -1 if enable is None else (1 if enable else 0)
         _check(load().lbib_set_overlap(self.h, v), self.h)
+
+    def set_graph(self, enable) -> None:
+        """True replays captured 16-step blocks; False and None (the
+        default) launch every step directly."""
+        v = -1 if enable is None else (1 if enable else 0)
+        _check(load().lbib_set_graph(self.h, v), self.h)
+
+    @property
+    def graph_replays(self) -> int:
+        return int(load().lbib_graph_replays(self.h))
+
+    def set_tile(self, rows: int, resident: int = 0) -> None:
+        """Tile shape of the batched grid pass (lbib_set_tile)."""
+        _check(load().lbib_set_tile(self.h, int(rows), int(resident)), self.h)
+
+    def autotune(self, launches: int = 20) -> Dict[str, Any]:
+        """lbib_autotune: times the 12 tile shapes of the batched grid pass and
+        keeps the fastest; returns the choice and the mean time per pass (us)
+        of every (rows, resident) candidate."""
+        rows, res = C.c_int32(), C.c_int32()
+        us = (C.c_double * 12)()
+        with self.torch.cuda.device(self.device):
+            _check(load().lbib_autotune(self.h, int(launches), C.byref(rows), C.byref(res), us,
+                                        12), self.h)
+        cands = [(r, k) for r in (1, 2, 4) for k in (0, 2, 4, 8)]
+        return {"rows": rows.value, "resident": res.value,
+                "us": {f"rows{r}_resident{k}": round(us[i], 2) for i, (r, k) in enumerate(cands)}}
 
     def adjoint_bytes(self, nsteps: int, checkpoint_every: int = 0) -> int:
         return int(load().lbib_adjoint_bytes(self.h, int(nsteps), int(checkpoint_every)))

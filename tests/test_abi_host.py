@@ -110,7 +110,29 @@ def test_null_context_calls(L):
     assert L.lbib_set_overlap(None, 1) == lbib.EINVAL
     assert L.lbib_set_contact(None, 2.0) == lbib.EINVAL
     assert L.lbib_adjoint_bytes(None, 10, 0) == 0
+    assert L.lbib_set_graph(None, 1) == lbib.EINVAL
+    assert L.lbib_graph_replays(None) == -1
+    assert L.lbib_set_tile(None, 1, 0) == lbib.EINVAL
+    assert L.lbib_autotune(None, 5, None, None, None, 0) == lbib.EINVAL
     d = C.c_double()
     ks = (C.c_double * 4)()
     assert L.lbib_adjoint(None, 10, 0, 1, 0, 0, None, 0, C.byref(d), C.byref(d), ks, 4) == lbib.EINVAL
     L.lbib_destroy(None)
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Loading the library before torch must not map a second HIP runtime next
+    to torch's own (two runtimes share no streams or synchronisation)."""
+    import subprocess
+    import sys
+    code = ("from paper_1903_03356_amd import lbib\n"
+            "lbib.load()\n"
+            "import torch\n"
+            "torch.zeros(1)\n"
+            "paths = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(paths))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "1", out.stdout

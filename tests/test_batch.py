@@ -230,3 +230,63 @@ def test_batch_state_transfer_per_lattice():
     dg = bat.pops_dev(1)
     do = o.pops() - W[:, None, None]
     assert np.abs(dg - do).max() < 1e-13
+
+
+def _same_batches(a, b, n_lattices):
+    for i in range(n_lattices):
+        assert np.array_equal(a.pops_dev(i), b.pops_dev(i)), i
+        assert np.array_equal(a.force(i), b.force(i)), i
+        for cid in a.cap_ids[i]:
+            for x, y in zip(a.capsule(cid), b.capsule(cid)):
+                assert np.array_equal(x, y), (i, cid)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("rows", [1, 2, 4])
+def test_every_tile_shape_is_bit_identical(rows):
+    """The tile shapes of the batched grid pass (rows per thread, one block
+    per tile or a persistent launch) compute the same bits as the default, on
+    lattices with ragged rows and segments, walls, a Couette channel and a
+    periodic box."""
+    cfgs = _mixed_lattices() + wl.ensemble(seed=4, n_inst=4)
+    ref = lbib.Batch(cfgs)
+    ref.step(40)
+    for resident in (0, 1, 3, 8):
+        log(f"tile rows={rows} resident={resident}")
+        b = lbib.Batch(cfgs)
+        b.set_tile(rows, resident)
+        b.step(40)
+        assert b.check() == 0
+        _same_batches(b, ref, len(cfgs))
+
+
+@pytest.mark.gpu
+def test_autotune_picks_a_shape_and_keeps_the_state():
+    cfgs = wl.ensemble(seed=5, n_inst=16)
+    a, b = lbib.Batch(cfgs), lbib.Batch(cfgs)
+    a.step(9)
+    b.step(9)
+    r = a.autotune(3)
+    log(f"autotune: {r}")
+    assert r["rows"] in (1, 2, 4) and r["resident"] in (0, 2, 4, 8)
+    assert len(r["us"]) == 12 and all(v > 0 for v in r["us"].values())
+    _same_batches(a, b, len(cfgs))  # tuning leaves the state alone
+    a.step(25)
+    b.step(25)
+    _same_batches(a, b, len(cfgs))
+
+
+@pytest.mark.gpu
+def test_tile_arguments_are_checked():
+    s = lbib.Sim(wl.grid_bench(n=64))
+    with pytest.raises(lbib.LbibError) as e:
+        s.autotune(2)
+    assert e.value.code == lbib.EINVAL
+    b = lbib.Batch(wl.ensemble(seed=5, n_inst=2))
+    for rows, res in ((3, 0), (1, -1), (2, 65)):
+        with pytest.raises(lbib.LbibError) as e:
+            b.set_tile(rows, res)
+        assert e.value.code == lbib.EINVAL
+    with pytest.raises(lbib.LbibError) as e:
+        b.autotune(0)
+    assert e.value.code == lbib.EINVAL
