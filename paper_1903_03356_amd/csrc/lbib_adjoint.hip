@@ -878,10 +878,9 @@ __global__ __launch_bounds__(kAdjThreads) void k_ib_adj(IBAdjArgs<T> a)
         ia.fib_prev = a.fib_prev + cap.fib_off;
         const T gxf = (T)cap.gx;
         const int ncell = P.W * P.H;
-        for (int i = tid; i < ncell; i += nt) {
-            stage_cell(ia, g, P, refx, refy, gxf, i);
-            S.Ld[i] = S.Lu[i] = S.Lv[i] = T(0);
-        }
+        // four cells per thread with all their loads in flight together
+        for (int i = tid; i < ncell; i += 4 * nt) stage_cells<T, 4>(ia, g, P, refx, refy, gxf, i, nt);
+        for (int i = tid; i < ncell; i += nt) S.Ld[i] = S.Lu[i] = S.Lv[i] = T(0);
     }
     __syncthreads();
     int st = 0;

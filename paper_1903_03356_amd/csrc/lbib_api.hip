@@ -51,7 +51,8 @@ struct Layout {
     int grid_blocks = 0;
     int tiles[3] = {0, 0, 0};  // tiles of the batched pass, per tile shape
     size_t plane_max = 0;
-    size_t inst_table = 0, round_table = 0, rect_table = 0, near_map = 0, bounds = 0;  // in BUF_CAPS
+    size_t inst_table = 0, round_table = 0, rect_table = 0, near_map = 0, bounds = 0,
+           hints = 0;  // in BUF_CAPS
     size_t round_off[3] = {0, 0, 0};  // the round table of each tile shape
 };
 
@@ -194,6 +195,7 @@ static bool make_layout(const lbib_grid* grids, int n, Layout& L)
     L.rect_table = o;
     L.near_map = L.rect_table + round256((size_t)2 * L.max_caps * sizeof(NearRect));
     L.bounds = L.near_map + round256((size_t)2 * L.flag_level * sizeof(int));
+    L.hints = L.bounds + round256((size_t)L.max_caps * sizeof(float4));
     return true;
 }
 
@@ -211,7 +213,7 @@ static size_t layout_bytes(const Layout& L, int id)
     case LBIB_BUF_FLAGS: return round256(2 * L.flag_level * sizeof(int));
     case LBIB_BUF_NODES: return round256((size_t)NF_COUNT * L.max_nodes * L.rb);
     case LBIB_BUF_CAPS:
-        return L.bounds + round256((size_t)L.max_caps * sizeof(float4));
+        return L.hints + round256((size_t)L.max_caps * sizeof(int4));
     case LBIB_BUF_DIAG: return round256(status_offset(L) + 64);
     case LBIB_BUF_STAGE: {
         size_t n = 3 * L.plane_max;
@@ -742,6 +744,7 @@ static IBArgs<T> ib_args(const lbib_ctx* c, long long n, int phase)
     a.near_map = nullptr;
     a.stamp = 0;
     a.contact = c->contact_cutoff > 0.0;
+    a.hints = reinterpret_cast<int4*>(bufp(c, LBIB_BUF_CAPS) + c->L.hints);
     return a;
 }
 

@@ -203,33 +203,15 @@ __device__ __forceinline__ bool patch_index(const Patch<T>& P, int cx, int cy, i
     return lx >= 0 && lx < P.W && ly >= 0 && ly < P.H;
 }
 
-// Moments of one patch cell from the pulled populations f^n and the force
-// F^{n-1} of the last collision (Eqs. 6-7): rho - 1 and the force-corrected
-// velocity.  Cells on a wall row are marked NaN.
+// Moments of one patch cell from its pulled populations s (f^n) and the force
+// F^{n-1} of the last collision (Eqs. 6-7, fixed-point force, g added):
+// rho - 1 and the force-corrected velocity.
 template <typename T>
-__device__ __forceinline__ void stage_cell(const IBArgs<T>& a, const GridArgs& g, const Patch<T>& P,
-                                           long long refx, long long refy, T gxf, int i)
+__device__ __forceinline__ void stage_store(const Patch<T>& P, int i, const T (&s)[9],
+                                            long long fx, long long fy, T gxf)
 {
-    const int lx = i % P.W, ly = i / P.W;
-    long long wy = refy + P.oy + ly;
-    if (g.periodic_y) wy = ((wy % g.ny) + g.ny) % g.ny;
-    else if (wy < 1 || wy > g.ny - 2) {
-        P.drho[i] = T(NAN);
-        P.ux[i] = P.uy[i] = T(0);
-        return;
-    }
-    long long wx = refx + P.ox + lx;
-    if (g.periodic_x) wx = ((wx % g.nx) + g.nx) % g.nx;
-    else if (wx < 1 || wx > g.nx - 2) {
-        P.drho[i] = T(NAN);
-        P.ux[i] = P.uy[i] = T(0);
-        return;
-    }
-    T s[9];
-    pull<T, false>(a.pops, (int)wx, (int)wy, g, gxf, s);  // never an end column
-    const size_t cell = (size_t)wy * g.nxp + (size_t)wx;
-    const T Fx = gxf + fix_to_real<T>(a.fib_prev[2 * cell]);
-    const T Fy = fix_to_real<T>(a.fib_prev[2 * cell + 1]);
+    const T Fx = gxf + fix_to_real<T>(fx);
+    const T Fy = fix_to_real<T>(fy);
     const T drho = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])) + s[8];
     const T jx = (s[1] - s[3]) + (s[5] - s[6]) + (s[8] - s[7]);
     const T jy = (s[2] - s[4]) + (s[5] + s[6]) - (s[7] + s[8]);
@@ -237,6 +219,70 @@ __device__ __forceinline__ void stage_cell(const IBArgs<T>& a, const GridArgs& g
     P.drho[i] = drho;
     P.ux[i] = (jx + T(0.5) * Fx) * irho;
     P.uy[i] = (jy + T(0.5) * Fy) * irho;
+}
+
+// K patch cells first, first + stride, ..., with the loads of all of them
+// issued before any is used (one memory latency for K cells).  A cell on a
+// wall row or an open end column is marked NaN; cells past the patch store
+// nothing (both load lattice cell (1, 1) instead).  A staged cell is never on
+// a wall row or an end column, so its pull (the nine source addresses of the
+// grid kernel's pull) needs no boundary rule.
+template <typename T, int K>
+__device__ __forceinline__ void stage_cells(const IBArgs<T>& a, const GridArgs& g,
+                                            const Patch<T>& P, long long refx, long long refy,
+                                            T gxf, int first, int stride)
+{
+    const int ncell = P.W * P.H;
+    const size_t plane = (size_t)g.ny * g.nxp;
+    T s[K][9];
+    long long fx[K], fy[K];
+    int state[K];  // 0: past the patch, 1: off the lattice, 2: staged
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int i = first + k * stride;
+        int x = 1, y = 1;
+        state[k] = 0;
+        if (i < ncell) {
+            const int lx = i % P.W, ly = i / P.W;
+            long long wy = refy + P.oy + ly, wx = refx + P.ox + lx;
+            bool on = true;
+            if (g.periodic_y) wy = ((wy % g.ny) + g.ny) % g.ny;
+            else on = wy >= 1 && wy <= g.ny - 2;
+            if (g.periodic_x) wx = ((wx % g.nx) + g.nx) % g.nx;
+            else on = on && wx >= 1 && wx <= g.nx - 2;
+            state[k] = on ? 2 : 1;
+            if (on) {
+                x = (int)wx;
+                y = (int)wy;
+            }
+        }
+        const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+        const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+        const size_t r0 = (size_t)y * g.nxp, rm = (size_t)ym * g.nxp, rp = (size_t)yp * g.nxp;
+        const T* src = a.pops;
+        s[k][0] = src[r0 + x];
+        s[k][1] = src[plane + r0 + xm];
+        s[k][2] = src[2 * plane + rm + x];
+        s[k][3] = src[3 * plane + r0 + xp];
+        s[k][4] = src[4 * plane + rp + x];
+        s[k][5] = src[5 * plane + rm + xm];
+        s[k][6] = src[6 * plane + rm + xp];
+        s[k][7] = src[7 * plane + rp + xp];
+        s[k][8] = src[8 * plane + rp + xm];
+        const longlong2 f = *reinterpret_cast<const longlong2*>(a.fib_prev + 2 * (r0 + x));
+        fx[k] = f.x;
+        fy[k] = f.y;
+    }
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int i = first + k * stride;
+        if (state[k] == 2) {
+            stage_store(P, i, s[k], fx[k], fy[k], gxf);
+        } else if (state[k] == 1) {
+            P.drho[i] = T(NAN);
+            P.ux[i] = P.uy[i] = T(0);
+        }
+    }
 }
 
 // Deterministic block reductions over the wavefronts of a block (at most

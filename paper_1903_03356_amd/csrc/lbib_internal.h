@@ -122,6 +122,7 @@ struct IBArgs {
     int* near_map;     // its (row, segment) units stamped with `stamp` ([ny][nseg])
     int stamp;
     int contact;       // add the contact force NF_CX/NF_CY (Dynamic B, Kinematic A)
+    int4* hints;       // per capsule: the patch box (ox, oy, W, H) of its last launch, W = 0 none
 };
 
 // Contact forces (Eq. 27) of the current node positions.

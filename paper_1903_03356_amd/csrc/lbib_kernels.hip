@@ -639,12 +639,20 @@ __device__ void internal_forces(const Scratch<T>& S, int nv, double kb, double k
 // (S.t[2], S.t[3]).  One work item per (element, side) evaluates a probe
 // (pressure deviation and the symmetric velocity-gradient terms) into
 // S.t[0..7]; one per element combines both sides into its half force
-// (S.t[10..11]); one per node adds the halves of its two elements.
+// (S.t[10..11]); one per node adds the halves of its two elements.  The
+// same pass also interpolates the fluid velocity at every node (Eq. 8) into
+// (S.t[12], S.t[13]), one more work item per node: it needs the same patch
+// and no force, so it fills threads the probes leave idle.
 template <typename T>
 __device__ void external_forces(const Scratch<T>& S, const Patch<T>& P, int nv, T nu, int& st)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (int w = tid; w < 2 * nv; w += nt) {
+    for (int w = tid; w < 3 * nv; w += nt) {
+        if (w >= 2 * nv) {
+            const int v = w - 2 * nv;
+            interp_u(P, S.px[v], S.py[v], S.t[12][v], S.t[13][v], st);
+            continue;
+        }
         const int l = w >> 1, side = w & 1;
         const int m = l + 1 == nv ? 0 : l + 1;
         T tx, ty;
@@ -969,6 +977,8 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
     __shared__ double red[kIBThreads / 64][8];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int c = blockIdx.x;
+    // the patch box of the last launch (used below) is loaded beside the record
+    const int4 hint0 = a0.hints ? a0.hints[c] : make_int4(0, 0, 0, 0);
     CapsuleDev cap = a0.caps[c];
     // the capsule's lattice: buffer offsets and sizes
     IBArgs<T> a = a0;
@@ -1023,6 +1033,27 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
     const bool doB = (a.phase & PH_B) && cap.primed;
     const bool doA = (a.phase & PH_A) != 0;
     long long refx = (long long)cap.ref_x, refy = (long long)cap.ref_y;
+    const bool need_field = prime || doB || (doA && a.dynamic);
+    const T gxf = (T)cap.gx;
+
+    // The patch box of this capsule's last launch: the waves that hold no node
+    // stage it while the node waves load the node state, so that the two
+    // load latencies overlap.  Below, the box the nodes need is checked
+    // against it; the patch is staged again if it does not fit.  (Each cell's
+    // staged values do not depend on the box, so the results do not either.)
+    const int node_threads = (nv + 63) / 64 * 64;
+    const int4 hint = need_field ? hint0 : make_int4(0, 0, 0, 0);
+    const bool early = hint.z > 0 && hint.w > 0 && (long long)hint.z * hint.w <= a.patch_cap &&
+                       node_threads < nt;
+    if (early && tid >= node_threads) {
+        P.ox = hint.x;
+        P.oy = hint.y;
+        P.W = hint.z;
+        P.H = hint.w;
+        const int ncell = P.W * P.H, ns = nt - node_threads;
+        for (int i = tid - node_threads; i < ncell; i += 3 * ns)
+            stage_cells<T, 3>(a, g, P, refx, refy, gxf, i, ns);
+    }
 
     float mn[2] = {3e38f, 3e38f}, mxv[2] = {-3e38f, -3e38f};
     bool finite = true;
@@ -1050,7 +1081,6 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
     block_minmax(mn, mxv, red);  // ends with a barrier, so S.px/py are visible
 
     // ---- fluid patch: bounding box + 3 cells (probe 1.2 + support 1.5 + motion)
-    const bool need_field = prime || doB || (doA && a.dynamic);
     if (need_field) {
         if (!(mn[0] > -1e30f && mxv[0] < 1e30f && mn[1] > -1e30f && mxv[1] < 1e30f)) {
             if (tid == 0) atomicOr(a.status, ST_NONFINITE);
@@ -1061,20 +1091,30 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
             if (tid == 0) atomicOr(a.status, ST_PATCH);
             return;
         }
-        P.ox = (int)floorf(mn[0]) - 3;
-        P.oy = (int)floorf(mn[1]) - 3;
-        P.W = (int)floorf(mxv[0]) - (int)floorf(mn[0]) + 7;
-        P.H = (int)floorf(mxv[1]) - (int)floorf(mn[1]) + 7;
-        if ((long long)P.W * P.H > a.patch_cap) {
-            if (tid == 0) atomicOr(a.status, ST_PATCH);
-            return;
-        }
-        const T gxf = (T)cap.gx;
-        // two cells per iteration, so that both cells' loads are in flight together
-        const int ncell = P.W * P.H;
-        for (int i = tid; i < ncell; i += 2 * nt) {
-            stage_cell(a, g, P, refx, refy, gxf, i);
-            if (i + nt < ncell) stage_cell(a, g, P, refx, refy, gxf, i + nt);
+        const int ox = (int)floorf(mn[0]) - 3, oy = (int)floorf(mn[1]) - 3;
+        const int W = (int)floorf(mxv[0]) - (int)floorf(mn[0]) + 7;
+        const int H = (int)floorf(mxv[1]) - (int)floorf(mn[1]) + 7;
+        if (early && ox >= hint.x && oy >= hint.y && ox + W <= hint.x + hint.z &&
+            oy + H <= hint.y + hint.w) {
+            P.ox = hint.x;
+            P.oy = hint.y;
+            P.W = hint.z;
+            P.H = hint.w;
+        } else {
+            if ((long long)W * H > a.patch_cap) {
+                if (tid == 0) atomicOr(a.status, ST_PATCH);
+                return;
+            }
+            // one spare cell on every side where it fits, so that the box
+            // serves the next launches while the capsule drifts
+            const bool spare = (long long)(W + 2) * (H + 2) <= a.patch_cap;
+            P.ox = spare ? ox - 1 : ox;
+            P.oy = spare ? oy - 1 : oy;
+            P.W = spare ? W + 2 : W;
+            P.H = spare ? H + 2 : H;
+            // three cells per thread with all their loads in flight together
+            const int ncell = P.W * P.H;
+            for (int i = tid; i < ncell; i += 3 * nt) stage_cells<T, 3>(a, g, P, refx, refy, gxf, i, nt);
         }
         __syncthreads();
     }
@@ -1107,8 +1147,13 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
         }
         const T half_inv_m = (T)(0.5 / cap.mv);
         for (int v = cap.rigid ? nv : tid; v < nv; v += nt) {
-            T Ux, Uy;
-            interp_u(P, S.px[v], S.py[v], Ux, Uy, st);  // tentative velocity, Eq. 23
+            T Ux, Uy;  // tentative velocity, Eq. 23 (Dynamic: interpolated beside the probes)
+            if (a.dynamic) {
+                Ux = S.t[12][v];
+                Uy = S.t[13][v];
+            } else {
+                interp_u(P, S.px[v], S.py[v], Ux, Uy, st);
+            }
             const T dox = S.dx[v], doy = S.dy[v];
             T dx, dy;
             if (a.dynamic) {
@@ -1260,6 +1305,7 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
         spread_cached(a, g, S, nv, refx, refy, st);
     }
     if (prime && tid == 0) a.caps[c].primed = 1;
+    if (need_field && a.hints && tid == 0) a.hints[c] = make_int4(P.ox, P.oy, P.W, P.H);
     // trajectory tape (reverse sweeps): the node state of this time level
     if (a.tape_nodes) {
         T* TN = a.tape_nodes;
