@@ -360,7 +360,8 @@ enum lbib_objective {
  *   0 < checkpoint_every = K < nsteps: the grid state is kept at every K-th
  *     level only (ceil(nsteps / K) checkpoints) plus a tape of K + 1 levels
  *     that the reverse sweep refills segment by segment; the node state of
- *     every level is still taped (a few kB per level). */
+ *     every level, with the force each node spread, is still taped (a few kB
+ *     per level). */
 size_t lbib_adjoint_bytes(const lbib_ctx* ctx, int32_t nsteps, int32_t checkpoint_every);
 
 /* Runs nsteps time steps of the chosen scheme from the initial state (the
@@ -370,13 +371,14 @@ size_t lbib_adjoint_bytes(const lbib_ctx* ctx, int32_t nsteps, int32_t checkpoin
  * sweep: the exact discrete adjoint of the executed step (Secs. 2.1-2.4), one
  * reverse grid launch and one reverse IB launch per step.  With a checkpoint
  * interval K (0 < K < nsteps) the reverse sweep goes segment by segment, last
- * first: it restores the segment's checkpoint, runs its K forward steps again
- * into the short tape, and reverses them.  The recomputed steps repeat the
- * first run bit for bit (the forward kernels sum in a fixed order), so J and
- * the final state equal those of the full tape exactly and the gradients
- * equal them up to the summation order of the reverse IB kernel's
- * floating-point atomics (which also varies between two full-tape runs); the
- * price is one more forward run.
+ * first: it restores the segment's checkpoint and runs its K grid steps
+ * again into the short tape, each fed by the force level that the taped node
+ * forces spread (the same fixed-point contributions as the first run, so the
+ * recomputed levels repeat it bit for bit), then reverses them.  J and the
+ * final state equal those of the full tape exactly; the gradients equal them
+ * up to the summation order of the reverse IB kernel's floating-point
+ * atomics (which also varies between two full-tape runs).  The price is one
+ * more pass of grid steps and light spreading launches.
  * Outputs (host):
  *   *out_J       J
  *   *out_dJ_dg   dJ/dg for the uniform body force g (the walls' body_force_x),

@@ -1242,17 +1242,15 @@ extern "C" lbib_status lbib_set_state(lbib_ctx* c, int32_t what, int32_t cap, co
 // may be shorter); segment s covers time levels sK .. min(sK + K, N).
 //   grid tape   K + 1 slots, slot r = level sK + r of the current segment:
 //               populations P, IB force F - g and its segment flags
-//   node tape   N + 1 slots: node state and reference points of every level
-//   checkpoints one per segment when there are several: the grid slot of
-//               level sK plus the node buffer, capsule table and diagnostics
-//               the forward run carries; one more node part keeps the state
-//               at level N while the reverse sweep recomputes segments
-// then the reverse-sweep arrays.
+//   node tape   N + 1 slots: node state, the force each node spread, and the
+//               reference points of every level
+//   checkpoints one grid slot per segment when there are several (level sK)
+// then the reverse-sweep arrays.  A recomputed segment needs no node state:
+// its force levels come back from the taped node forces (k_spread_tape).
 struct AdjLayout {
     size_t pops = 0, fib = 0, flags = 0, gslot = 0;
     size_t nodes = 0, ref = 0, nslot = 0;
-    size_t ck_nodes = 0, ck_caps = 0, ck_diag = 0, ck_live = 0, ckslot = 0;
-    size_t ntape = 0, ckpt = 0, fin = 0;
+    size_t ntape = 0, ckpt = 0;
     size_t lam[2] = {0, 0}, lfm = 0, lft = 0, lfm_flags = 0, zero_flags = 0;
     size_t gacc = 0, lamx = 0, lamd = 0, ksbar = 0, out = 0, total = 0;
     int every = 0, nseg = 0, blocks = 0;
@@ -1270,23 +1268,14 @@ static bool adj_layout(const lbib_ctx* c, int nsteps, int every, AdjLayout& A)
     A.fib = round256(2 * cells * sizeof(long long));
     A.flags = round256((size_t)I.grid.ny * nseg * sizeof(int));
     A.gslot = A.pops + A.fib + A.flags;
-    A.nodes = round256((size_t)8 * c->L.max_nodes * c->rb);
+    A.nodes = round256((size_t)kTapeFields * c->L.max_nodes * c->rb);
     A.ref = round256((size_t)2 * c->L.max_caps * sizeof(double));
     A.nslot = A.nodes + A.ref;
-    A.ck_nodes = round256((size_t)NF_COUNT * c->L.max_nodes * c->rb);
-    A.ck_caps = round256((size_t)c->L.max_caps * sizeof(CapsuleDev));
-    A.ck_diag = round256(status_offset(c->L));
-    A.ck_live = A.ck_nodes + A.ck_caps + A.ck_diag;
-    A.ckslot = A.gslot + A.ck_live;
     size_t o = A.gslot * (size_t)(A.every + 1);
     A.ntape = o;
     o += A.nslot * (size_t)(nsteps + 1);
     A.ckpt = o;
-    if (A.nseg > 1) {
-        o += A.ckslot * (size_t)A.nseg;
-        A.fin = o;
-        o += A.ck_live;
-    }
+    if (A.nseg > 1) o += A.gslot * (size_t)A.nseg;
     A.lam[0] = o;
     o += A.pops;
     A.lam[1] = o;
@@ -1338,7 +1327,7 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
     auto sR = [&](int n) {
         return reinterpret_cast<double*>(ws + A.ntape + A.nslot * (size_t)n + A.nodes);
     };
-    auto ck = [&](int seg) { return ws + A.ckpt + A.ckslot * (size_t)seg; };
+    auto ck = [&](int seg) { return ws + A.ckpt + A.gslot * (size_t)seg; };
     T* lam[2] = {reinterpret_cast<T*>(ws + A.lam[0]), reinterpret_cast<T*>(ws + A.lam[1])};
     T* lfm = reinterpret_cast<T*>(ws + A.lfm);
     T* lft = reinterpret_cast<T*>(ws + A.lft);
@@ -1350,9 +1339,6 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
     double* ksbar = reinterpret_cast<double*>(ws + A.ksbar);
     double* out = reinterpret_cast<double*>(ws + A.out);
     const size_t pop_bytes = 9 * (size_t)I.nxp * I.grid.ny * sizeof(T);
-    char* live_nodes = bufp(c, LBIB_BUF_NODES);
-    char* live_caps = bufp(c, LBIB_BUF_CAPS);  // the capsule table leads the buffer
-    char* live_diag = bufp(c, LBIB_BUF_DIAG);  // per-capsule rows, then the status word
 
     // LDS of the IB reverse kernel: FP64 node arrays, the rest holds the patch
     int dev = 0;
@@ -1368,35 +1354,33 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
     const size_t adj_lds = ib_adj_lds_bytes<T>(adj_patch, c->L.max_nv);
     HIPCHK(c, ib_adj_set_lds_limit<T>(adj_lds));
 
-    // node buffer, capsule table and diagnostics rows: the state the IB kernel
-    // carries from step to step besides the grid
-    auto save_live = [&](char* dst) -> hipError_t {
-        hipError_t e = hipMemcpyAsync(dst, live_nodes, A.ck_nodes, d2d, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(dst + A.ck_nodes, live_caps, A.ck_caps, d2d, st);
-        if (e == hipSuccess && A.ck_diag)
-            e = hipMemcpyAsync(dst + A.ck_nodes + A.ck_caps, live_diag, A.ck_diag, d2d, st);
-        return e;
-    };
-    auto load_live = [&](const char* src) -> hipError_t {
-        hipError_t e = hipMemcpyAsync(live_nodes, src, A.ck_nodes, d2d, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(live_caps, src + A.ck_nodes, A.ck_caps, d2d, st);
-        if (e == hipSuccess && A.ck_diag)
-            e = hipMemcpyAsync(live_diag, src + A.ck_nodes + A.ck_caps, A.ck_diag, d2d, st);
-        return e;
-    };
     // forward steps c0 .. e0-1 of one segment; the grid slot 0 holds level c0
-    // and the force accumulators of slots 1 .. e0-c0 are zero
-    auto run_segment = [&](int c0, int e0) -> lbib_status {
+    // and the force accumulators of slots 1 .. e0-c0 are zero.  The first run
+    // takes the IB launches and tapes the nodes; a recomputed segment spreads
+    // the taped node forces instead (the same force levels, no node state)
+    auto run_segment = [&](int c0, int e0, bool again) -> lbib_status {
         for (int n = c0; n < e0; n++) {
             const int r = n - c0;
-            IBArgs<T> a = ib_args<T>(c, n, n == 0 ? (PH_PRIME | PH_A) : (PH_B | PH_A));
-            a.pops = gP(r);
-            a.fib_prev = gF(r);
-            a.fib_next = gF(r + 1);
-            a.flags_next = gFl(r + 1);
-            a.tape_nodes = sN(n);
-            a.tape_ref = sR(n);
-            HIPCHK(c, launch_ib<T>(a, c->ncap, c->lds_use, st));
+            if (again) {
+                SpreadTapeArgs<T> sa;
+                sa.fib = gF(r + 1);
+                sa.flags = gFl(r + 1);
+                sa.tape = sN(n);
+                sa.ref = sR(n);
+                sa.caps = reinterpret_cast<const CapsuleDev*>(bufp(c, LBIB_BUF_CAPS));
+                sa.status = status_word(c);
+                sa.node_stride = c->L.max_nodes;
+                HIPCHK(c, launch_spread_tape<T>(sa, c->ncap, st));
+            } else {
+                IBArgs<T> a = ib_args<T>(c, n, n == 0 ? (PH_PRIME | PH_A) : (PH_B | PH_A));
+                a.pops = gP(r);
+                a.fib_prev = gF(r);
+                a.fib_next = gF(r + 1);
+                a.flags_next = gFl(r + 1);
+                a.tape_nodes = sN(n);
+                a.tape_ref = sR(n);
+                HIPCHK(c, launch_ib<T>(a, c->ncap, c->lds_use, st));
+            }
             HIPCHK(c, launch_grid_step<T>(gP(r), gP(r + 1), gF(r + 1), gFl(r + 1), gF(r + 1),
                                           zero_flags, g, st));
         }
@@ -1424,11 +1408,8 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
             HIPCHK(c, hipMemcpyAsync(gslot(0), gslot(K), A.gslot, d2d, st));
             HIPCHK(c, clear_slots(e0 - c0));
         }
-        if (A.nseg > 1) {
-            HIPCHK(c, hipMemcpyAsync(ck(s), gslot(0), A.gslot, d2d, st));
-            HIPCHK(c, save_live(ck(s) + A.gslot));
-        }
-        lbib_status e = run_segment(c0, e0);
+        if (A.nseg > 1) HIPCHK(c, hipMemcpyAsync(ck(s), gslot(0), A.gslot, d2d, st));
+        lbib_status e = run_segment(c0, e0, false);
         if (e != LBIB_OK) return e;
     }
     const int cl = seg_lo(A.nseg - 1), rN = N - cl;
@@ -1448,7 +1429,6 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
                              d2d, st));
     HIPCHK(c, hipMemcpyAsync(flags(c, N + 1), gFl(rN), (size_t)I.grid.ny * I.nseg * sizeof(int),
                              d2d, st));
-    if (A.nseg > 1) HIPCHK(c, save_live(ws + A.fin));
     c->steps = N;
     int flags_fwd = 0;
     HIPCHK(c, hipMemcpyAsync(&flags_fwd, status_word(c), sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1506,12 +1486,9 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
     for (int s = A.nseg - 1; s >= 0; s--) {
         const int c0 = seg_lo(s), e0 = seg_hi(s);
         if (s < A.nseg - 1) {
-            // the constant node fields the reverse kernel reads (stiffness,
-            // rest lengths) are the same in every checkpoint
             HIPCHK(c, hipMemcpyAsync(gslot(0), ck(s), A.gslot, d2d, st));
-            HIPCHK(c, load_live(ck(s) + A.gslot));
             HIPCHK(c, clear_slots(e0 - c0));
-            lbib_status e = run_segment(c0, e0);
+            lbib_status e = run_segment(c0, e0, true);
             if (e != LBIB_OK) return e;
         }
         for (int n = e0 - 1; n >= c0; n--) {
@@ -1524,7 +1501,6 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
         ga.lam_in = lam[0];
         HIPCHK(c, launch_init_adj<T>(ga, g, I.walls.init_profile, I.nu, st));
     }
-    if (A.nseg > 1) HIPCHK(c, load_live(ws + A.fin));
     HIPCHK(c, launch_reduce_sum(gacc, A.blocks, out, st));
     double host_out[2] = {0, 0};
     HIPCHK(c, hipMemcpyAsync(host_out, out, 2 * sizeof(double), hipMemcpyDeviceToHost, st));

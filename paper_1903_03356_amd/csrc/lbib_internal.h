@@ -125,6 +125,23 @@ struct IBArgs {
     int4* hints;       // per capsule: the patch box (ox, oy, W, H) of its last launch, W = 0 none
 };
 
+// Node tape of the gradient runs: per time level, the fields NF_HX .. NF_UY
+// of every node, then the force c_v F_v the node spread in that step.
+constexpr int kTapeFX = 8, kTapeFY = 9;
+constexpr int kTapeFields = 10;
+
+// Spreading of a taped step (recomputed segments of the gradient runs).
+template <typename T>
+struct SpreadTapeArgs {
+    long long* fib;         // force level of the step (accumulated), [ny][nxp][2] per lattice
+    int* flags;             // its segment flags
+    const T* tape;          // node tape of the step, [kTapeFields][node_stride]
+    const double* ref;      // reference points of the step, [max_capsules][2]
+    const CapsuleDev* caps;
+    int* status;
+    int node_stride;
+};
+
 // Contact forces (Eq. 27) of the current node positions.
 template <typename T>
 struct ContactArgs {
@@ -157,6 +174,8 @@ hipError_t launch_grid_near(const T* src, T* dst, const long long* fib_now, cons
                             const GridArgs& g, hipStream_t s);
 template <typename T>
 hipError_t launch_contact(const ContactArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_spread_tape(const SpreadTapeArgs<T>& a, int ncap, hipStream_t s);
 template <typename T>
 hipError_t contact_set_lds_limit(int max_nv);
 // Blocks of the grid kernel for one lattice (a multiple of kNumXcd).

@@ -1318,6 +1318,8 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
             TN[NF_DY * NS + off + v] = S.dy[v];
             TN[NF_UX * NS + off + v] = S.ux[v];
             TN[NF_UY * NS + off + v] = S.uy[v];
+            TN[kTapeFX * NS + off + v] = S.t[8][v];  // c_v F_v spread in phase A
+            TN[kTapeFY * NS + off + v] = S.t[9][v];
         }
         if (tid == 0) {
             a.tape_ref[2 * c] = cap.ref_x;
@@ -1345,6 +1347,51 @@ hipError_t launch_ib(const IBArgs<T>& a, int ncap, size_t lds_bytes, hipStream_t
 {
     if (ncap <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_ib<T>, dim3(ncap), dim3(kIBThreads), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+// Spreading of a taped step: each node's taped force c_v F_v with the MLS
+// weights at its taped position, relative to the taped reference point, into
+// the step's force level.  These are the contributions, in fixed point, of
+// the IB launch that wrote the tape (same weights, same products), so the
+// level matches it bit for bit.  One block per capsule, one thread per node.
+template <typename T>
+__global__ __launch_bounds__(kIBThreads) void k_spread_tape(SpreadTapeArgs<T> a)
+{
+    const int c = blockIdx.x;
+    const CapsuleDev cap = a.caps[c];
+    GridArgs g;
+    g.nx = cap.nx;
+    g.ny = cap.ny;
+    g.nxp = cap.nxp;
+    g.nseg = cap.nseg;
+    g.periodic_y = cap.periodic_y;
+    g.periodic_x = cap.periodic_x;
+    IBArgs<T> ia;
+    ia.fib_next = a.fib + cap.fib_off;
+    ia.flags_next = a.flags + cap.flag_off;
+    const long long refx = (long long)a.ref[2 * c], refy = (long long)a.ref[2 * c + 1];
+    const size_t NS = a.node_stride;
+    const int off = cap.node_offset;
+    const T* TN = a.tape;
+    int st = 0;
+    for (int v = threadIdx.x; v < cap.nv; v += blockDim.x) {
+        int cx, cy;
+        T phi[9];
+        mls<T, false>(TN[NF_HX * NS + off + v], TN[NF_HY * NS + off + v], cx, cy, phi, nullptr,
+                      nullptr);
+        const T fx = TN[kTapeFX * NS + off + v], fy = TN[kTapeFY * NS + off + v];
+#pragma unroll
+        for (int k = 0; k < 9; k++) spread_one(ia, g, refx, refy, cx, cy, k, phi[k] * fx, phi[k] * fy, st);
+    }
+    if (st) atomicOr(a.status, st);
+}
+
+template <typename T>
+hipError_t launch_spread_tape(const SpreadTapeArgs<T>& a, int ncap, hipStream_t s)
+{
+    if (ncap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spread_tape<T>, dim3(ncap), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1657,6 +1704,7 @@ hipError_t launch_set_nodes(T* nodes, CapsuleDev* caps, int cap, int nv, int nod
                                             long long*, int*, const NearRect*, int,               \
                                             const GridArgs&, hipStream_t);                        \
     template hipError_t launch_contact<T>(const ContactArgs<T>&, hipStream_t);                   \
+    template hipError_t launch_spread_tape<T>(const SpreadTapeArgs<T>&, int, hipStream_t);         \
     template hipError_t contact_set_lds_limit<T>(int);                                            \
     template hipError_t launch_ib<T>(const IBArgs<T>&, int, size_t, hipStream_t);                 \
     template size_t ib_lds_bytes<T>(int, int);                                                    \
