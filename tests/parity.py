@@ -2,6 +2,7 @@
 oracle from one workload dictionary and compare their states."""
 from __future__ import annotations
 
+import math
 import os
 import sys
 
@@ -64,3 +65,33 @@ def compare_capsules(g, o, pos_tol, d_tol):
         assert e["x_max_abs"] <= pos_tol and e["xprev_max_abs"] <= pos_tol, e
         assert e["dD"] <= d_tol and e["dSw"] <= d_tol and e["ddp"] <= d_tol, e
     return errs
+
+
+def regular_polygon_force(N, R, R0, ks, ka):
+    """Radial (outward) internal force per node of a regular N-gon of radius R
+    with stress-free radius R0, from the membrane energy: stretch
+    sum 1/2 k_s (l - l0)^2 (Eq. 10) and area k_a p_ref (A - A0)^2 / (2 A0) with
+    p_ref = 1/3 (Eq. 12).  By symmetry each node carries -dE/dR / N."""
+    s1, s2 = math.sin(math.pi / N), math.sin(2.0 * math.pi / N)
+    l, l0 = 2.0 * R * s1, 2.0 * R0 * s1
+    A, A0 = 0.5 * N * R * R * s2, 0.5 * N * R0 * R0 * s2
+    dE_dR = N * ks * (l - l0) * 2.0 * s1 + ka / 3.0 * (A - A0) / A0 * N * R * s2
+    return -dE_dR / N, A0
+
+
+def uneven_polygon(cx, cy, a, b, n, seed):
+    """Counter-clockwise nodes on an ellipse at unevenly spaced angles (seeded
+    jitter of a third of the mean spacing)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    ang = 2.0 * math.pi * (np.arange(n) + 0.5 + rng.uniform(-1 / 3, 1 / 3, n)) / n
+    return np.stack([cx + a * np.cos(ang), cy + b * np.sin(ang)], axis=1)
+
+
+def edge_line_integrals(x):
+    """Perimeter P and the line integral of the position, sum over the
+    straight edges of length * midpoint (exact for a polygon)."""
+    import numpy as np
+    y = np.roll(x, -1, axis=0)
+    l = np.hypot(*(y - x).T)
+    return l.sum(), (l[:, None] * 0.5 * (x + y)).sum(axis=0)

@@ -15,7 +15,10 @@ import numpy as np
 import pytest
 
 from paper_1903_03356_amd import workloads as wl
-from tests.parity import W, compare_capsules, compare_fields, log, pair
+import math
+
+from tests.parity import (W, compare_capsules, compare_fields, edge_line_integrals, log, pair,
+                          regular_polygon_force, uneven_polygon)
 
 pytestmark = pytest.mark.gpu
 
@@ -505,3 +508,56 @@ def test_wall_flag_raised_from_host_state():
     g.step(1)
     flags = g.check()
     assert flags & lbib.FLAG_WALL
+
+
+@pytest.mark.parametrize("real_bytes", [8, 4])
+def test_dynamic_first_step_closed_form_gpu(real_bytes):
+    """The HIP path on the closed form of one Dynamic step (Eqs. 21-24): a
+    stretched regular polygon, nodes and fluid at rest, moves each node by half
+    the internal force over m_v, with node velocity 3/2 of the displacement."""
+    from paper_1903_03356_amd import lbib
+    N, R0, R, ks, ka, ratio = 48, 8.0, 8.4, 0.05, 1.0, 1.3
+    c = (20.0, 20.0)
+    cfg = wl.periodic_box(40, 40, 0.8, real_bytes=real_bytes, mode="dynamic")
+    cfg["capsules"] = [wl.capsule(wl.circle_nodes(c[0], c[1], R0, N), ks, 0.0, ka, ratio)]
+    g = lbib.Sim(cfg)
+    x0 = wl.circle_nodes(c[0], c[1], R, N)
+    g.set_capsule(0, x0, x0, np.zeros_like(x0))
+    g.step(1)
+    x1, _, uv = g.capsule(0)
+    Fr, A0 = regular_polygon_force(N, R, R0, ks, ka)
+    rhat = (x0 - np.array(c)) / R
+    d = x1 - x0
+    radial = np.einsum("va,va->v", d, rhat)
+    expect = 0.5 * Fr / (ratio * A0 / N)
+    rtol = 1e-10 if real_bytes == 8 else 2e-4
+    np.testing.assert_allclose(radial, expect, rtol=rtol)
+    np.testing.assert_allclose(uv, 1.5 * d, rtol=0, atol=1e-12 if real_bytes == 8 else 1e-7)
+    assert g.check() == 0
+
+
+def test_dynamic_forcing_weight_is_arc_length_gpu():
+    """The HIP path injects exactly the membrane line integrals of u0 in one
+    step (momentum P u0, angular momentum (integral of x ds) x u0) from a
+    resting, unevenly spaced polygon whose nodes move at u0 over a fluid at
+    rest (c_v = arc length, partition of unity, linear reproduction, Guo
+    forcing)."""
+    from paper_1903_03356_amd import lbib
+    n = 40
+    u0 = np.array([3e-3, -1e-3])
+    cfg = wl.periodic_box(40, 36, 0.8, real_bytes=8, mode="dynamic")
+    x0 = uneven_polygon(20.0, 18.0, 8.0, 6.0, n, seed=7)
+    cfg["capsules"] = [wl.capsule(x0, 0.02, 0.0, 1.0, 1.0)]
+    g = lbib.Sim(cfg)
+    g.set_capsule(0, x0, x0 - u0, np.tile(u0, (n, 1)))
+    f0 = g.pops_dev()
+    g.step(1)
+    f1 = g.pops_dev()
+    E = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1], [1, 1], [-1, 1], [-1, -1], [1, -1]])
+    P, Ix = edge_line_integrals(x0)
+    ys, xs = np.mgrid[0:36, 0:40].astype(np.float64)
+    j = np.einsum("iyx,ia->ayx", f1 - f0, E)
+    # the spread force is quantised to 2^-48 per contribution (360 of them)
+    np.testing.assert_allclose(j.sum(axis=(1, 2)), P * u0, rtol=0, atol=1e-12)
+    L1 = (xs * j[1] - ys * j[0]).sum()
+    assert abs(L1 - (Ix[0] * u0[1] - Ix[1] * u0[0])) < 5e-11

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 from paper_1903_03356_amd import workloads as wl
+from tests.parity import edge_line_integrals, regular_polygon_force, uneven_polygon
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
 
@@ -390,6 +391,71 @@ def test_p14_point_symmetry_shear(orc, mode):
     x, _, _ = sim.capsule(0)
     np.testing.assert_allclose(x[32:], 63.0 - x[:32], atol=1e-11)
     assert d["D"] > 0 and sim.status == 0
+
+
+@pytest.mark.parametrize("R,ratio", [(8.4, 1.0), (7.7, 1.6)])
+def test_dynamic_first_step_closed_form(orc, R, ratio):
+    """Eqs. 21-24 on one step.  A regular polygon stretched (or squeezed) from
+    its stress-free radius, nodes at rest, fluid at rest: the direct forcing is
+    zero, so the fluid stays at rest, the hydrodynamic force and the
+    interpolated velocity are zero, and the update moves every node by exactly
+    half the internal force over the node mass m_v = (rho_s / rho_f) A0 / N
+    (Eq. 23), with node velocity 3/2 of that displacement (Eq. 24, BDF2 from a
+    node at rest).  The internal force is the energy gradient in closed form."""
+    N, R0, ks, ka = 48, 8.0, 0.05, 1.0
+    c = (20.0, 20.0)
+    cfg = wl.periodic_box(40, 40, 0.8, real_bytes=8, mode="dynamic")
+    cfg["capsules"] = [wl.capsule(wl.circle_nodes(c[0], c[1], R0, N), ks, 0.0, ka, ratio)]
+    o = orc.Sim(cfg)
+    x0 = wl.circle_nodes(c[0], c[1], R, N)
+    o.set_capsule(0, x0, x0, np.zeros_like(x0))
+    o.step(1)
+    x1, _, uv = o.capsule(0)
+    Fr, A0 = regular_polygon_force(N, R, R0, ks, ka)
+    mv = ratio * A0 / N
+    rhat = (x0 - np.array(c)) / R
+    d = x1 - x0
+    radial = np.einsum("va,va->v", d, rhat)
+    tangential = d - radial[:, None] * rhat
+    expect = 0.5 * Fr / mv
+    assert abs(expect) > 1e-4
+    np.testing.assert_allclose(radial, expect, rtol=1e-10)
+    assert np.abs(tangential).max() < 1e-12
+    np.testing.assert_allclose(uv, 1.5 * d, rtol=0, atol=1e-14)
+    assert np.abs(np.einsum("iyx,ia->a", o.pops(), E)).max() < 1e-13  # the fluid is still at rest
+
+
+def test_dynamic_forcing_weight_is_arc_length(orc):
+    """Dyn. steps 1-3 with c_v = the arc length of node v, half of each adjacent
+    element (A11).  The nodes of a resting, unevenly spaced polygon are given a
+    uniform velocity u0 over a fluid at rest, so F_v = c_v u0.  Spreading keeps
+    the total (partition of unity) and its first moment (linear reproduction);
+    one collision adds the force to the momentum (P2), and streaming keeps the
+    angular momentum.  After one step the fluid therefore holds exactly the line
+    integrals of u0 along the membrane: momentum P u0, and angular momentum
+    (integral of x ds) x u0.  Both are exact for a polygon as sums of edge length
+    times midpoint.  Per-node weights 1, or one-sided element lengths, give
+    other values."""
+    n = 40
+    u0 = np.array([3e-3, -1e-3])
+    cfg = wl.periodic_box(40, 36, 0.8, real_bytes=8, mode="dynamic")
+    x0 = uneven_polygon(20.0, 18.0, 8.0, 6.0, n, seed=7)
+    cfg["capsules"] = [wl.capsule(x0, 0.02, 0.0, 1.0, 1.0)]
+    o = orc.Sim(cfg)
+    o.set_capsule(0, x0, x0 - u0, np.tile(u0, (n, 1)))
+    f0 = o.pops()
+    o.step(1)
+    f1 = o.pops()
+    P, Ix = edge_line_integrals(x0)
+    ys, xs = np.mgrid[0:36, 0:40].astype(np.float64)
+    j = np.einsum("iyx,ia->ayx", f1 - f0, E)
+    p1 = j.sum(axis=(1, 2))
+    L1 = (xs * j[1] - ys * j[0]).sum()
+    # sums over 1440 cells of O(0.1) populations: rounding ~1e-13 (x 40 for the moment)
+    np.testing.assert_allclose(p1, P * u0, rtol=0, atol=5e-13)
+    assert abs(L1 - (Ix[0] * u0[1] - Ix[1] * u0[0])) < 2e-11
+    one_sided = (np.hypot(*(np.roll(x0, -1, axis=0) - x0).T)[:, None] * x0).sum(axis=0)
+    assert abs((one_sided[0] - Ix[0]) * u0[1] - (one_sided[1] - Ix[1]) * u0[0]) > 1e-6
 
 
 def test_wall_support_flag(orc):
