@@ -104,6 +104,52 @@ def test_adjoint_dynamic_fp64_vs_fd(which):
 
 
 @pytest.mark.gpu
+def test_adjoint_full_size_channel_vs_fd():
+    """The 512 x 128 gradient channel itself (circle R = 10, 96 nodes at 0.4 H,
+    Ca = 1e-2), FP64, 200 Dynamic steps: dD/dk_s of the element with the
+    largest gradient and of element 37, and dD/dg, against the oracle's
+    central differences; then the FP32 gradient of the same run against the
+    FP64 one, and a 500-step FP32 run with a checkpoint every 70 steps against
+    its whole-tape run.
+
+    At this size the MLS support switches put jumps of about 1e-12 into D, so
+    a difference is only trusted where those stay small against h: k_s with
+    h = 1e-3 k_s (1e-3, 5e-4, 2.5e-4 agree within 2e-5 of the largest
+    component), g with h = 1e-7 g (1e-6 and 1e-7 agree within 2e-6, while 1e-5
+    straddles a switch).  The bar is 1e-4 of the largest k_s component, and
+    1e-5 for g."""
+    from oracle import oracle as orc
+    oracle_threads(orc)
+    steps = 200
+    cfg = wl.adjoint_channel()
+    cfg["real_bytes"] = 8
+    r = lbib.Sim(cfg).adjoint(steps, lbib.OBJ_TAYLOR, 0, "dynamic")
+    assert abs(r["J"] - orc.objective(cfg, steps, "D")) < 1e-9
+    ks0 = cfg["capsules"][0]["ks"]
+    k8 = r["dJ_dks"][0]
+    top = int(np.argmax(np.abs(k8)))
+    fds = {l: orc.central_difference(cfg, steps, ("ks", 0, l), 1e-3 * ks0, "D") for l in (top, 37)}
+    scale = abs(fds[top])
+    for l, fd in fds.items():
+        log(f"512x128 dD/dks[{l}]: adjoint {k8[l]} fd {fd}")
+        assert abs(k8[l] - fd) <= 1e-4 * scale, (l, k8[l], fd)
+    hg = 1e-7 * cfg["body_force_x"]
+    fg = orc.central_difference(cfg, steps, "g", hg, "D")
+    log(f"512x128 dD/dg: adjoint {r['dJ_dg']} fd {fg}")
+    assert abs(r["dJ_dg"] - fg) <= 1e-5 * abs(fg)
+    cfg4 = wl.adjoint_channel()
+    r4 = lbib.Sim(cfg4).adjoint(steps, lbib.OBJ_TAYLOR, 0, "dynamic")
+    k4 = r4["dJ_dks"][0]
+    assert np.abs(k4 - k8).max() <= 1e-3 * np.abs(k8).max()
+    assert abs(r4["dJ_dg"] - r["dJ_dg"]) <= 1e-3 * abs(r["dJ_dg"])
+    full = lbib.Sim(cfg4).adjoint(500, lbib.OBJ_CENTROID_Y, 0, "dynamic")
+    ck = lbib.Sim(cfg4).adjoint(500, lbib.OBJ_CENTROID_Y, 0, "dynamic", checkpoint_every=70)
+    assert ck["J"] == full["J"]
+    assert abs(ck["dJ_dg"] - full["dJ_dg"]) <= 1e-4 * abs(full["dJ_dg"])
+    assert np.abs(ck["dJ_dks"][0] - full["dJ_dks"][0]).max() <= 1e-4 * np.abs(full["dJ_dks"][0]).max()
+
+
+@pytest.mark.gpu
 def test_adjoint_fp32_vs_fp64():
     """The FP32 adjoint of the same run, against the FP64 adjoint."""
     r8 = lbib.Sim(ellipse_channel(real_bytes=8)).adjoint(100, lbib.OBJ_TAYLOR)
