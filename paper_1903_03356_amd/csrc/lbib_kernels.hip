@@ -19,6 +19,15 @@
 namespace lbib {
 
 // ------------------------------------------------------------ grid kernel
+// Population stores: streaming (non-temporal) writes.  Each value is read
+// once, by the next step, so keeping it in L2 buys nothing, and the dirty lines
+// it would leave there lengthen the write-back at the end of every launch.
+template <typename T>
+__device__ __forceinline__ void st_stream(T* p, T v)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
 // One lattice node with total force (Fx, Fy): pull, walls, force-corrected
 // moments, BGK + forcing, store.
 template <typename T, bool OPEN>
@@ -43,15 +52,15 @@ __device__ __forceinline__ void collide_store(const T* __restrict__ src, T* __re
     const T w3a = FirstOrderW<T>::axis, w3d = FirstOrderW<T>::diag;
     const size_t plane = (size_t)g.ny * g.nxp;
     T* o = dst + cell;
-    o[0] = relax(s[0], T(4.0 / 9.0), T(0), T(0), T(0), T(0), drho, rho, usq15, uF, om, pre);
-    o[plane] = relax(s[1], wa, w3a, ux, mx, Fx, drho, rho, usq15, uF, om, pre);
-    o[2 * plane] = relax(s[2], wa, w3a, uy, my, Fy, drho, rho, usq15, uF, om, pre);
-    o[3 * plane] = relax(s[3], wa, w3a, -ux, -mx, -Fx, drho, rho, usq15, uF, om, pre);
-    o[4 * plane] = relax(s[4], wa, w3a, -uy, -my, -Fy, drho, rho, usq15, uF, om, pre);
-    o[5 * plane] = relax(s[5], wd, w3d, ux + uy, mx + my, Fx + Fy, drho, rho, usq15, uF, om, pre);
-    o[6 * plane] = relax(s[6], wd, w3d, uy - ux, my - mx, Fy - Fx, drho, rho, usq15, uF, om, pre);
-    o[7 * plane] = relax(s[7], wd, w3d, -ux - uy, -mx - my, -Fx - Fy, drho, rho, usq15, uF, om, pre);
-    o[8 * plane] = relax(s[8], wd, w3d, ux - uy, mx - my, Fx - Fy, drho, rho, usq15, uF, om, pre);
+    st_stream(&o[0], relax(s[0], T(4.0 / 9.0), T(0), T(0), T(0), T(0), drho, rho, usq15, uF, om, pre));
+    st_stream(&o[plane], relax(s[1], wa, w3a, ux, mx, Fx, drho, rho, usq15, uF, om, pre));
+    st_stream(&o[2 * plane], relax(s[2], wa, w3a, uy, my, Fy, drho, rho, usq15, uF, om, pre));
+    st_stream(&o[3 * plane], relax(s[3], wa, w3a, -ux, -mx, -Fx, drho, rho, usq15, uF, om, pre));
+    st_stream(&o[4 * plane], relax(s[4], wa, w3a, -uy, -my, -Fy, drho, rho, usq15, uF, om, pre));
+    st_stream(&o[5 * plane], relax(s[5], wd, w3d, ux + uy, mx + my, Fx + Fy, drho, rho, usq15, uF, om, pre));
+    st_stream(&o[6 * plane], relax(s[6], wd, w3d, uy - ux, my - mx, Fy - Fx, drho, rho, usq15, uF, om, pre));
+    st_stream(&o[7 * plane], relax(s[7], wd, w3d, -ux - uy, -mx - my, -Fx - Fy, drho, rho, usq15, uF, om, pre));
+    st_stream(&o[8 * plane], relax(s[8], wd, w3d, ux - uy, mx - my, Fx - Fy, drho, rho, usq15, uF, om, pre));
 }
 
 // One lattice node with the IB force of this step.  The wave that owns the
