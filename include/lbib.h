@@ -201,7 +201,7 @@ lbib_status lbib_add_rigid_to(lbib_ctx* ctx, int32_t lattice, const double* node
  * follows it there; a far kernel covers the rest on a second stream of the
  * library's own, so the IB work runs beside it.  The results are
  * bit-identical to the single pass, and the call still returns with all work
- * ordered on the bound stream.  By default the split is used from 2^23
+ * ordered on the bound stream.  By default the split is used from 2^22
  * lattice cells on, where it pays.
  * Captured steps (lbib_set_graph(ctx, 1)): otherwise, unless kernel timing is
  * on, the inner steps of a call go in blocks of 16 steps captured once into a
@@ -258,7 +258,7 @@ lbib_status lbib_set_contact(lbib_ctx* ctx, double cutoff);
 
 /* Schedule of lbib_step: enable = 1 always uses the overlapped near / far
  * schedule where it applies (see lbib_step), 0 never, -1 (the default) from
- * 2^23 lattice cells on.  Errors: EINVAL (other values). */
+ * 2^22 lattice cells on.  Errors: EINVAL (other values). */
 lbib_status lbib_set_overlap(lbib_ctx* ctx, int32_t enable);
 
 /* Captured step blocks of lbib_step: enable = 1 replays them; 0 and -1 (the

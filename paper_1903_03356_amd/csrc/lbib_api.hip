@@ -142,7 +142,7 @@ static bool grid_ok(const lbib_grid* g)
 
 constexpr int kMaxInstances = 1 << 16;
 constexpr int kMaxOverlapCapsules = 64;  // near regions per step (one near-kernel block group each)
-constexpr long long kOverlapMinCells = 1LL << 23;  // automatic overlap from 8.4 M cells
+constexpr long long kOverlapMinCells = 1LL << 22;  // automatic overlap from 4.2 M cells
 
 // Fills L from the lattices' sizes and capacities; false if any is invalid or
 // the totals leave the supported range.
@@ -1001,8 +1001,9 @@ static lbib_status step_t(lbib_ctx* c, int nsteps)
                              c->ncap <= kMaxOverlapCapsules;
     const long long cells = (long long)c->L.inst[0].grid.nx * c->L.inst[0].grid.ny;
     // automatic: the split pays once the grid step clearly outlasts the IB
-    // launch, the near pass and the stream hand-offs (measured: +6 % at 16.8 M
-    // cells, -4 % at 4.2 M, -30 % at 0.26 M)
+    // launch, the near pass and the stream hand-offs (32 capsules, measured:
+    // +7 % at 16.8 M cells, +12 % at 8.4 M, +5.5 % at 4.2 M, -10 % at 2.1 M,
+    // -19 % at 1.0 M)
     const bool want = c->overlap == 1 || (c->overlap < 0 && cells >= kOverlapMinCells);
     if (can_overlap && want) return step_overlap_t<T>(c, nsteps);
     // replays of captured blocks for the inner steps; timed runs launch directly
