@@ -660,59 +660,60 @@ __device__ void internal_fwd(const AdjScratch<T>& S, const double* X, const doub
 // Transpose of the hydrodynamic forces (Eqs. 15-16) at x^{n-1}: element l
 // force f = len (-(p+ - p-) n + (tau+ - tau-) n) split half and half, probes
 // x_c +- 1.2 n.  hE = (lF_l + lF_m) / 2.  Adds to the element arrays and the
-// patch adjoints.
+// patch adjoints.  One lane per (element, side): the two probes of an element
+// sit in neighbouring lanes of one wave (work item 2 l + side) and trade their
+// values with shuffles, so each lane evaluates two MLS fits, not four.
 template <typename T>
 __device__ void external_vjp(const AdjScratch<T>& S, const Patch<T>& P, int nv, double nu, int sx,
                              int sy, int& st)
 {
-    for (int l = threadIdx.x; l < nv; l += blockDim.x) {
+    for (int w = threadIdx.x; w < 2 * nv; w += blockDim.x) {
+        const int l = w >> 1, side = w & 1;
         const int m = l + 1 == nv ? 0 : l + 1;
-        // probe supports exactly as the forward kernel chose them (frame n-1)
+        // probe support exactly as the forward kernel chose it (frame n-1)
         const T txT = (S.hxp[m] - S.hxp[l]) + (S.lxp[m] - S.lxp[l]);
         const T tyT = (S.hyp[m] - S.hyp[l]) + (S.lyp[m] - S.lyp[l]);
         const T lenT = sqrt(txT * txT + tyT * tyT);
         const T nxT = tyT / lenT, nyT = -txT / lenT;
         const T xcT = T(0.5) * (S.hxp[l] + S.hxp[m]), ycT = T(0.5) * (S.hyp[l] + S.hyp[m]);
-        int cxs[2], cys[2];
-        for (int side = 0; side < 2; side++) {
-            const T sg = side ? T(-1.2) : T(1.2);
-            const T px = xcT + sg * nxT, py = ycT + sg * nyT;
-            cxs[side] = (int)floor(px + T(0.5)) + sx;
-            cys[side] = (int)floor(py + T(0.5)) + sy;
-        }
+        const T sgT = side ? T(-1.2) : T(1.2);
+        const T pxT = xcT + sgT * nxT, pyT = ycT + sgT * nyT;
+        const int cx = (int)floor(pxT + T(0.5)) + sx;
+        const int cy = (int)floor(pyT + T(0.5)) + sy;
         // geometry in FP64 (patch frame)
         const double tx = S.Xp[m] - S.Xp[l], ty = S.Yp[m] - S.Yp[l];
         const double len = sqrt(tx * tx + ty * ty);
         const double npx = ty, npy = -tx;  // len * n+
         const double nx = npx / len, ny = npy / len;
         const double xc = 0.5 * (S.Xp[l] + S.Xp[m]), yc = 0.5 * (S.Yp[l] + S.Yp[m]);
-        // forward probe values
-        double dp[2], G[2][4];  // G: 00, 01, 10, 11
-        for (int side = 0; side < 2; side++) {
-            const double sg = side ? -1.2 : 1.2;
-            const double px = xc + sg * nx, py = yc + sg * ny;
-            double r = 0, g00 = 0, g01 = 0, g10 = 0, g11 = 0;
-            mls_dual<true>(px, py, cxs[side], cys[side],
-                           [&](int k, const Dual<2>& phi, const Dual<2>& gx, const Dual<2>& gy) {
-                               const int idx = adj_patch_index(P, cxs[side], cys[side], k);
-                               if (idx < 0) { st |= ST_PATCH; return; }
-                               const double u = S.pu[idx], v = S.pv[idx];
-                               r += phi.v * (double)S.pd[idx];
-                               g00 += gx.v * u;
-                               g01 += gy.v * u;
-                               g10 += gx.v * v;
-                               g11 += gy.v * v;
-                           });
-            dp[side] = r / 3.0;
-            G[side][0] = g00;
-            G[side][1] = g01;
-            G[side][2] = g10;
-            G[side][3] = g11;
+        const double sg = side ? -1.2 : 1.2;
+        const double px = xc + sg * nx, py = yc + sg * ny;
+        // forward value of this lane's probe
+        double r = 0, g00 = 0, g01 = 0, g10 = 0, g11 = 0;
+        mls_dual<true>(px, py, cx, cy,
+                       [&](int k, const Dual<2>& phi, const Dual<2>& gx, const Dual<2>& gy) {
+                           const int idx = adj_patch_index(P, cx, cy, k);
+                           if (idx < 0) { st |= ST_PATCH; return; }
+                           const double u = S.pu[idx], v = S.pv[idx];
+                           r += phi.v * (double)S.pd[idx];
+                           g00 += gx.v * u;
+                           g01 += gy.v * u;
+                           g10 += gx.v * v;
+                           g11 += gy.v * v;
+                       });
+        // both probes of the element: side 0 (outer) and side 1 (inner)
+        const double own[5] = {r / 3.0, g00, g01, g10, g11};
+        double pr[2][5];
+#pragma unroll
+        for (int q = 0; q < 5; q++) {
+            const double other = __shfl_xor(own[q], 1);
+            pr[0][q] = side ? other : own[q];
+            pr[1][q] = side ? own[q] : other;
         }
-        const double dpr = dp[0] - dp[1];
-        const double d00 = 2.0 * (G[0][0] - G[1][0]);
-        const double d11 = 2.0 * (G[0][3] - G[1][3]);
-        const double d01 = (G[0][1] + G[0][2]) - (G[1][1] + G[1][2]);
+        const double dpr = pr[0][0] - pr[1][0];
+        const double d00 = 2.0 * (pr[0][1] - pr[1][1]);
+        const double d11 = 2.0 * (pr[0][4] - pr[1][4]);
+        const double d01 = (pr[0][2] + pr[0][3]) - (pr[1][2] + pr[1][3]);
         const double hx = 0.5 * (S.lFx[l] + S.lFx[m]), hy = 0.5 * (S.lFy[l] + S.lFy[m]);
         // f = -dpr np + nu D np  (np = len n+, D symmetric)
         const double lnpx = -dpr * hx + nu * (d00 * hx + d01 * hy);
@@ -720,34 +721,31 @@ __device__ void external_vjp(const AdjScratch<T>& S, const Patch<T>& P, int nv, 
         const double ldpr = -(npx * hx + npy * hy);
         const double ld00 = nu * hx * npx, ld11 = nu * hy * npy;
         const double ld01 = nu * (hx * npy + hy * npx);
+        // reverse of this lane's probe
+        const double sgn = side ? -1.0 : 1.0;
+        const double lP = sgn * ldpr / 3.0;  // lambda of sum phi rho (p = rho / 3)
+        const double l00 = 2.0 * sgn * ld00, l11 = 2.0 * sgn * ld11, l01 = sgn * ld01;
+        double gpx = 0.0, gpy = 0.0;
+        mls_dual<true>(px, py, cx, cy,
+                       [&](int k, const Dual<2>& phi, const Dual<2>& gx, const Dual<2>& gy) {
+                           const int idx = adj_patch_index(P, cx, cy, k);
+                           if (idx < 0) return;
+                           const double d = S.pd[idx], u = S.pu[idx], v = S.pv[idx];
+                           // G00 = sum gx u, G01 = sum gy u, G10 = sum gx v, G11 = sum gy v
+                           const double cgx = l00 * u + l01 * v;
+                           const double cgy = l01 * u + l11 * v;
+                           gpx += lP * d * phi.d[0] + cgx * gx.d[0] + cgy * gy.d[0];
+                           gpy += lP * d * phi.d[1] + cgx * gx.d[1] + cgy * gy.d[1];
+                           atomicAdd(&S.Ld[idx], (T)(lP * phi.v));
+                           atomicAdd(&S.Lu[idx], (T)(l00 * gx.v + l01 * gy.v));
+                           atomicAdd(&S.Lv[idx], (T)(l01 * gx.v + l11 * gy.v));
+                       });
+        // sums over the two probes (side 0 first)
+        const double ox = __shfl_xor(gpx, 1), oy = __shfl_xor(gpy, 1);
+        if (side) continue;
+        const double lxc = gpx + ox, lyc = gpy + oy;
+        const double lnx = 1.2 * gpx + -1.2 * ox, lny = 1.2 * gpy + -1.2 * oy;
         double ltx = -lnpy, lty = lnpx;  // np = (t_y, -t_x)
-        double lxc = 0.0, lyc = 0.0, lnx = 0.0, lny = 0.0;
-        for (int side = 0; side < 2; side++) {
-            const double sgn = side ? -1.0 : 1.0;
-            const double sg = 1.2 * sgn;
-            const double px = xc + sg * nx, py = yc + sg * ny;
-            const double lP = sgn * ldpr / 3.0;  // lambda of sum phi rho (p = rho / 3)
-            const double l00 = 2.0 * sgn * ld00, l11 = 2.0 * sgn * ld11, l01 = sgn * ld01;
-            double gpx = 0.0, gpy = 0.0;
-            mls_dual<true>(px, py, cxs[side], cys[side],
-                           [&](int k, const Dual<2>& phi, const Dual<2>& gx, const Dual<2>& gy) {
-                               const int idx = adj_patch_index(P, cxs[side], cys[side], k);
-                               if (idx < 0) return;
-                               const double d = S.pd[idx], u = S.pu[idx], v = S.pv[idx];
-                               // G00 = sum gx u, G01 = sum gy u, G10 = sum gx v, G11 = sum gy v
-                               const double cgx = l00 * u + l01 * v;
-                               const double cgy = l01 * u + l11 * v;
-                               gpx += lP * d * phi.d[0] + cgx * gx.d[0] + cgy * gy.d[0];
-                               gpy += lP * d * phi.d[1] + cgx * gx.d[1] + cgy * gy.d[1];
-                               atomicAdd(&S.Ld[idx], (T)(lP * phi.v));
-                               atomicAdd(&S.Lu[idx], (T)(l00 * gx.v + l01 * gy.v));
-                               atomicAdd(&S.Lv[idx], (T)(l01 * gx.v + l11 * gy.v));
-                           });
-            lxc += gpx;
-            lyc += gpy;
-            lnx += sg * gpx;
-            lny += sg * gpy;
-        }
         // n = R t / len: (dn/dt)^T v = ((-v_y, v_x) - t^ (n . v)) / len
         const double ndot = nx * lnx + ny * lny;
         ltx += (-lny - tx / len * ndot) / len;
