@@ -29,8 +29,7 @@ struct Inst {
     size_t pop_off = 0;   // elements of a population buffer
     size_t fib_off = 0;   // long longs of one force level
     size_t flag_off = 0;  // ints of one flag level
-    int block0 = 0, blocks = 0;
-    int tile0[3] = {0, 0, 0};  // first tile of the lattice in the batched pass, per tile shape
+    long long tile0[3] = {0, 0, 0};  // first tile of the lattice in the batched pass, per tile shape
     int ncap = 0, nodes = 0;
 };
 
@@ -48,8 +47,7 @@ struct Layout {
     int rb = 4;
     size_t pop_elems = 0, fib_level = 0, flag_level = 0;
     int max_caps = 0, max_nodes = 0, max_nv = 0;
-    int grid_blocks = 0;
-    int tiles[3] = {0, 0, 0};  // tiles of the batched pass, per tile shape
+    long long tiles[3] = {0, 0, 0};  // tiles of the batched pass, per tile shape
     size_t plane_max = 0;
     size_t inst_table = 0, round_table = 0, rect_table = 0, near_map = 0, bounds = 0,
            hints = 0;  // in BUF_CAPS
@@ -151,7 +149,7 @@ static bool make_layout(const lbib_grid* grids, int n, Layout& L)
     if (!grids || n < 1 || n > kMaxInstances) return false;
     L = Layout();
     L.rb = grids[0].real_bytes;
-    long long caps = 0, nodes = 0, blocks = 0, cells = 0;
+    long long caps = 0, nodes = 0, cells = 0;
     for (int i = 0; i < n; i++) {
         const lbib_grid* g = &grids[i];
         if (!grid_ok(g) || g->real_bytes != L.rb) return false;
@@ -163,8 +161,6 @@ static bool make_layout(const lbib_grid* grids, int n, Layout& L)
         I.pop_off = L.pop_elems;
         I.fib_off = L.fib_level;
         I.flag_off = L.flag_level;
-        I.block0 = (int)blocks;
-        I.blocks = grid_blocks(g->ny, I.nseg);
         for (int k = 0; k < 3; k++) {
             I.tile0[k] = L.tiles[k];
             L.tiles[k] += grid_blocks_rows(g->ny, I.nseg, kTileRows[k]);
@@ -172,7 +168,6 @@ static bool make_layout(const lbib_grid* grids, int n, Layout& L)
         L.pop_elems += 9 * lc;
         L.fib_level += 2 * lc;
         L.flag_level += ((size_t)g->ny * I.nseg + 63) / 64 * 64;
-        blocks += I.blocks;
         caps += g->max_capsules;
         nodes += g->max_nodes_total;
         cells += (long long)g->nx * g->ny;
@@ -180,11 +175,11 @@ static bool make_layout(const lbib_grid* grids, int n, Layout& L)
         L.plane_max = std::max(L.plane_max, (size_t)g->nx * g->ny);
         L.inst.push_back(I);
     }
-    if (caps > (1 << 20) || nodes > (1 << 26) || blocks > (1LL << 30) || cells > (1LL << 33))
+    // one-row tiles are the most numerous shape
+    if (caps > (1 << 20) || nodes > (1 << 26) || L.tiles[0] > (1LL << 30) || cells > (1LL << 33))
         return false;
     L.max_caps = (int)caps;
     L.max_nodes = (int)nodes;
-    L.grid_blocks = (int)blocks;
     L.inst_table = round256((size_t)L.max_caps * sizeof(CapsuleDev));
     L.round_table = L.inst_table + round256((size_t)n * sizeof(InstDev));
     size_t o = L.round_table;
@@ -446,7 +441,6 @@ static lbib_status create_common(const lbib_grid* grids, const double* taus,
         d.periodic_x = g.periodic_x;
         d.u_in = g.u_in;
         d.rho_out = g.rho_out;
-        d.block0 = I.block0;
         d.pop_off = (int64_t)I.pop_off;
         d.fib_off = (int64_t)I.fib_off;
         d.flag_off = (int64_t)I.flag_off;
@@ -455,7 +449,7 @@ static lbib_status create_common(const lbib_grid* grids, const double* taus,
         d.u_bot = g.u_bot;
         d.u_top = g.u_top;
         for (int k = 0; k < 3; k++) {
-            const int r0 = I.tile0[k] / kNumXcd;
+            const int r0 = (int)(I.tile0[k] / kNumXcd);
             const int r1 = r0 + grid_blocks_rows(g.ny, g.nseg, kTileRows[k]) / kNumXcd;
             for (int r = r0; r < r1; r++) rounds[k][r] = make_int2(i, r0);
         }
@@ -792,7 +786,7 @@ static hipError_t do_ib(lbib_ctx* c, void* p)
 // multiple of 8 (so tile t stays on XCD t % 8), at most one per tile.
 static int batch_grid(const lbib_ctx* c, int shape, int resident)
 {
-    const int tiles = c->L.tiles[shape];
+    const int tiles = (int)c->L.tiles[shape];
     if (resident <= 0) return tiles;
     const long long want = (long long)resident * c->num_cu / kNumXcd * kNumXcd;
     return (int)std::max<long long>(kNumXcd, std::min<long long>(want, tiles));
@@ -805,7 +799,7 @@ static hipError_t launch_batch_shape(const lbib_ctx* c, const T* src, T* dst,
                                      hipStream_t st)
 {
     return launch_grid_step_batch<T>(src, dst, fib_now, flags_now, fib_old, flags_old,
-                                     inst_table(c), round_table(c, shape), c->L.tiles[shape],
+                                     inst_table(c), round_table(c, shape), (int)c->L.tiles[shape],
                                      kTileRows[shape], batch_grid(c, shape, resident),
                                      any_open(c), st);
 }

@@ -42,7 +42,7 @@ enum NodeField {
 // buffers, one after the other, and step in lockstep.
 struct InstDev {
     int32_t nx, ny, nxp, nseg;
-    int32_t periodic_y, block0;  // block0: first block of the lattice in a batched grid launch
+    int32_t periodic_y, pad0;
     int32_t periodic_x, pad1;    // periodic_x = 0: velocity inlet x = 0, pressure outlet x = nx-1
     int64_t pop_off;   // offset of the lattice's planes in a population buffer (elements)
     int64_t fib_off;   // offset in one time level of the force field (long long elements)
