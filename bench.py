@@ -313,7 +313,7 @@ def main() -> int:
         return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(this build is single-GPU)", file=sys.stderr)
+              "(the library steps its lattices on a single device)", file=sys.stderr)
         return 2
 
     import torch

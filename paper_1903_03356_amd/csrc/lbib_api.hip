@@ -40,8 +40,9 @@ constexpr int kTileRows[3] = {1, 2, 4};
 constexpr int kTileResident[4] = {0, 2, 4, 8};
 
 // Buffer layout of a context: the lattices one after the other in every
-// buffer; the capsule table followed by the lattice table and the block-round
-// table of the batched grid launch.
+// buffer; the capsule table followed by the lattice table, the round tables
+// of the batched grid launch (one per tile shape), the near-region tables,
+// the capsules' bounding boxes and their patch boxes.
 struct Layout {
     std::vector<Inst> inst;
     int rb = 4;
