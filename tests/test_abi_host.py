@@ -136,3 +136,21 @@ def test_one_hip_runtime_whatever_the_import_order():
                          timeout=300)
     assert out.returncode == 0, out.stderr[-2000:]
     assert out.stdout.strip().splitlines()[-1] == "1", out.stdout
+
+
+def test_missing_library_fails_loudly():
+    """Without the built HIP library the binding raises ImportError: there is
+    no CPU fallback for any step of the path."""
+    import subprocess
+    import sys
+    code = ("from paper_1903_03356_amd import lbib\n"
+            "lbib.LIB_PATH = '/nonexistent/liblbib.so'\n"
+            "try:\n"
+            "    lbib.load()\n"
+            "except ImportError as e:\n"
+            "    print('ImportError', 'build' in str(e))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "ImportError True", out.stdout
