@@ -162,9 +162,25 @@ def bench_ensemble(steps: int, warmup: int, loop_steps: int):
     flags = bat.check()
     if flags:
         raise RuntimeError(f"device flags {flags} in the batched ensemble")
+    del bat
+    # the same steps replayed from captured 16-step graphs (lbib_set_graph), on
+    # a fresh batch over the same stretch of steps (the Dynamic loop's slow
+    # mode sets in later)
+    gb = lbib.Batch(cfgs)
+    gb.set_tile(tune["rows"], tune["resident"])
+    gb.set_graph(True)
+    gb.step(max(1, warmup - 18))
+    gb.step(18)  # the blocks of both step parities are captured here
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gb.step(steps)
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / steps
+    if gb.check():
+        raise RuntimeError("device flags in the graph-replayed ensemble")
+    del gb
     grid_us = tm["grid_ms"] / max(1.0, tm["grid_launches"]) * 1e3
     ib_us = tm["ib_ms"] / max(1.0, tm["ib_launches"]) * 1e3
-    del bat
     sims = [lbib.Sim(c) for c in cfgs]
     for s in sims:
         s.step(2)
@@ -192,6 +208,7 @@ def bench_ensemble(steps: int, warmup: int, loop_steps: int):
         "grid_kernel_us": round(grid_us, 2),
         "grid_kernel_frac": round(BYTES_PER_CELL * cells / (grid_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
         "ib_kernel_us": round(ib_us, 2),
+        "graph_ms_per_step": round(t_graph * 1e3, 4),
         "tile": {"rows": tune["rows"], "resident": tune["resident"]},
         "tile_candidates_us": tune["us"],
     }
@@ -363,6 +380,7 @@ def main() -> int:
         side["biconcave_1024x256_mlups"] = round(c2r["mlups"], 1)
         ens = bench_ensemble(min(args.steps, 400), args.warmup, 20)
         log(f"ensemble: batched {ens['mlups']:.0f} MLUPS ({ens['ms_per_step']:.3f} ms/step, "
+            f"{ens['graph_ms_per_step']:.3f} with graph replays, "
             f"grid {ens['grid_kernel_us']:.1f} us, IB {ens['ib_kernel_us']:.1f} us), "
             f"per-simulation loop {ens['loop_ms_per_step']:.3f} ms/step, "
             f"speedup {ens['speedup']:.1f}x")
