@@ -207,8 +207,9 @@ lbib_status lbib_add_rigid_to(lbib_ctx* ctx, int32_t lattice, const double* node
  * on, the inner steps of a call go in blocks of 16 steps captured once into a
  * HIP graph (one for blocks that start on an even step, one for odd) and
  * replayed with one launch per block; the first step of a call and the
- * remainder launch directly.  The graphs hold kernel launches only and are captured
- * again after the capsule count, the contact cutoff or the mode changed.
+ * remainder launch directly.  The graphs hold kernel launches only and are
+ * captured again after the capsule count, the contact cutoff, the mode or the
+ * batched pass's tile shape changed.
  * Replays run the very launches of the direct path (bit-identical results).
  * Errors: EINVAL (nsteps < 0, bad mode), ESTATE (mode differs from the first
  * step's), EDEVICE.  Device-side problems raise status flags (lbib_check). */

@@ -90,7 +90,7 @@ struct lbib_ctx {
     int graph = -1;
     hipStream_t s_cap = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    int g_ncap = -1, g_mode = -1, g_patch = -1;
+    int g_ncap = -1, g_mode = -1, g_patch = -1, g_tile = -1;
     double g_contact = -1.0;
     long long graph_replays = 0;
     // tile shape of the batched grid pass (lbib_set_tile, lbib_autotune):
@@ -1003,13 +1003,15 @@ static lbib_status step_t(lbib_ctx* c, int nsteps)
     if (can_overlap && want) return step_overlap_t<T>(c, nsteps);
     // replays of captured blocks for the inner steps; timed runs launch directly
     const bool graphs = c->graph == 1 && !c->timing;
+    const int tile = c->tile_shape * 256 + c->tile_resident;
     if (graphs && (c->g_ncap != c->ncap || c->g_mode != c->mode || c->g_patch != c->patch_use ||
-                   c->g_contact != c->contact_cutoff)) {
+                   c->g_contact != c->contact_cutoff || c->g_tile != tile)) {
         drop_graphs(c);
         c->g_ncap = c->ncap;
         c->g_mode = c->mode;
         c->g_patch = c->patch_use;
         c->g_contact = c->contact_cutoff;
+        c->g_tile = tile;
     }
     for (int k = 0; k < nsteps;) {
         const long long n = c->steps + k;

@@ -89,6 +89,12 @@ def test_graph_replays_in_a_batch():
         b.step(chunk)
     assert a.graph_replays == 3
     _same(a, b, sum(len(c["capsules"]) for c in cfgs), lattices=len(cfgs))
+    # a new tile shape is captured again (the replays then launch that shape)
+    a.set_tile(2, 4)
+    a.step(20)
+    b.step(20)
+    assert a.graph_replays == 4
+    _same(a, b, sum(len(c["capsules"]) for c in cfgs), lattices=len(cfgs))
 
 
 def test_timing_runs_launch_directly():
