@@ -281,24 +281,45 @@ def bench_multi(steps: int, warmup: int):
             "mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4)}
 
 
-def cpu_baseline(cfg, budget_s: float = 20.0):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, budget_s: float = 20.0, single_s: float = 10.0):
+    """The FP64 oracle on the host: all threads for about budget_s seconds of
+    steps (the reported value), then one thread for about single_s seconds."""
     from oracle import oracle as orc
 
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    orc.set_threads(threads)
-    sim = orc.Sim(cfg)
-    sim.step(1)  # first touch of the arrays
-    n, t = 0, 0.0
-    while t < budget_s and n < 200:
-        t0 = time.perf_counter()
-        sim.step(1)
-        t += time.perf_counter() - t0
-        n += 1
     cells = cfg["nx"] * cfg["ny"]
-    return {"value": round(cells * n / t / 1e6, 3), "unit": "MLUPS", "cores": orc.get_threads(),
+
+    def timed(nthreads, budget):
+        orc.set_threads(nthreads)
+        sim = orc.Sim(cfg)
+        sim.step(1)  # first touch of the arrays
+        n, t = 0, 0.0
+        while t < budget and n < 200:
+            t0 = time.perf_counter()
+            sim.step(1)
+            t += time.perf_counter() - t0
+            n += 1
+        return n, t, orc.get_threads()
+
+    n, t, used = timed(threads, budget_s)
+    n1, t1, _ = timed(1, single_s)
+    return {"value": round(cells * n / t / 1e6, 3), "unit": "MLUPS", "cores": used,
             "kind": "oracle",
             "sample": f"{n} steps of the same {cfg['nx']}x{cfg['ny']} workload with its "
-                      f"{len(cfg['capsules'])} capsules (FP64 oracle, {t:.1f} s)"}
+                      f"{len(cfg['capsules'])} capsules (FP64 oracle, {t:.1f} s)",
+            "single_thread_mlups": round(cells * n1 / t1 / 1e6, 3),
+            "single_thread_sample": f"{n1} steps on one thread ({t1:.1f} s)",
+            "cpu_model": cpu_model()}
 
 
 def main() -> int:
