@@ -149,6 +149,48 @@ def test_adjoint_full_size_channel_vs_fd():
     assert np.abs(ck["dJ_dks"][0] - full["dJ_dks"][0]).max() <= 1e-4 * np.abs(full["dJ_dks"][0]).max()
 
 
+def two_capsule_channel(real_bytes=8, mode="dynamic"):
+    """Two elliptical capsules one behind the other in a body-force channel:
+    the first acts on the second only through the fluid."""
+    cfg = ellipse_channel(real_bytes=real_bytes, mode=mode, nx=96, ny=40, centre=(22.0, 17.0))
+    ang = 2.0 * math.pi * (np.arange(28) + 0.5) / 28
+    nodes = np.stack([52.0 + 5.0 * np.cos(ang), 21.0 + 4.0 * np.sin(ang)], axis=1)
+    cfg["capsules"].append(wl.capsule(nodes, wl.ks_from_ca(0.8, 0.02, 0.03), 0.0, 1.0, 1.2))
+    return cfg
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("mode", ["dynamic", "kinematic"])
+def test_adjoint_two_capsules_vs_fd(mode):
+    """The objective of the second capsule, differentiated with respect to an
+    element of each capsule and g, against the oracle's central differences
+    (FP64): the cross-capsule term travels through the fluid adjoint."""
+    from oracle import oracle as orc
+    oracle_threads(orc)
+    steps = 50
+    cfg = two_capsule_channel(mode=mode)
+    r = lbib.Sim(cfg).adjoint(steps, lbib.OBJ_TAYLOR, 1, mode)
+    assert abs(r["J"] - orc.objective(cfg, steps, "D", capsule=1)) < 1e-9
+    fds, grads = [], []
+    for c, l in ((0, 5), (1, 3), (1, 17)):
+        ks0 = cfg["capsules"][c]["ks"]
+        # h = 1e-3 k_s: below it the differences of this run carry support-switch
+        # noise (1e-3 and 3e-3 agree within 3e-7; 1e-4 scatters by 1e-4)
+        fds.append(orc.central_difference(cfg, steps, ("ks", c, l), 1e-3 * ks0, "D", capsule=1))
+        grads.append(r["dJ_dks"][c][l])
+    log(f"two capsules {mode}: adjoint {grads} fd {fds}")
+    scale = max(abs(v) for v in fds)
+    assert abs(fds[0]) > 1e-6 * scale  # capsule 0 does move the objective
+    for a, f in zip(grads, fds):
+        assert abs(a - f) <= 1e-5 * scale, (a, f)
+    # 1e-6 g: at 1e-5 g the two-capsule run already straddles a support switch
+    hg = 1e-6 * cfg["body_force_x"]
+    fg = orc.central_difference(cfg, steps, "g", hg, "D", capsule=1)
+    noise = 4.0 * 2.0 * 2.2e-16 * max(1.0, abs(r["J"])) / (2.0 * hg)
+    log(f"two capsules {mode}: dJ/dg adjoint {r['dJ_dg']} fd {fg} (noise {noise:.1e})")
+    assert abs(r["dJ_dg"] - fg) <= 1e-5 * abs(fg) + noise, (r["dJ_dg"], fg)
+
+
 @pytest.mark.gpu
 def test_adjoint_fp32_vs_fp64():
     """The FP32 adjoint of the same run, against the FP64 adjoint."""
