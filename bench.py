@@ -147,7 +147,8 @@ def bench_ensemble(steps: int, warmup: int, loop_steps: int):
     bat.step(warmup)
     torch.cuda.synchronize()
     tune = bat.autotune(20)  # tile shape of the batched grid pass
-    log(f"ensemble autotune: rows {tune['rows']}, resident {tune['resident']}; {tune['us']}")
+    log(f"ensemble autotune: rows {tune['rows']}, linear {tune['linear']}, resident "
+        f"{tune['resident']}; {tune['us']}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     bat.step(steps)
@@ -167,7 +168,7 @@ def bench_ensemble(steps: int, warmup: int, loop_steps: int):
     # a fresh batch over the same stretch of steps (the Dynamic loop's slow
     # mode sets in later)
     gb = lbib.Batch(cfgs)
-    gb.set_tile(tune["rows"], tune["resident"])
+    gb.set_tile(tune["rows"], tune["resident"], tune["linear"])
     gb.set_graph(True)
     gb.step(max(1, warmup - 18))
     gb.step(18)  # the blocks of both step parities are captured here
@@ -209,7 +210,7 @@ def bench_ensemble(steps: int, warmup: int, loop_steps: int):
         "grid_kernel_frac": round(BYTES_PER_CELL * cells / (grid_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
         "ib_kernel_us": round(ib_us, 2),
         "graph_ms_per_step": round(t_graph * 1e3, 4),
-        "tile": {"rows": tune["rows"], "resident": tune["resident"]},
+        "tile": {"rows": tune["rows"], "linear": tune["linear"], "resident": tune["resident"]},
         "tile_candidates_us": tune["us"],
     }
 

@@ -29,15 +29,25 @@ struct Inst {
     size_t pop_off = 0;   // elements of a population buffer
     size_t fib_off = 0;   // long longs of one force level
     size_t flag_off = 0;  // ints of one flag level
-    long long tile0[3] = {0, 0, 0};  // first tile of the lattice in the batched pass, per tile shape
+    long long tile0[6] = {0, 0, 0, 0, 0, 0};  // first tile in the batched pass, per tile shape
     int ncap = 0, nodes = 0;
 };
 
 // Tile shapes of the batched grid pass: nodes per thread (rows of a band / 4)
-constexpr int kTileRows[3] = {1, 2, 4};
+// and the tile order (banded groups of 8 bands, or linear over band and segment)
+constexpr int kTileShapes = 6;
+constexpr int kTileRows[kTileShapes] = {1, 2, 4, 1, 2, 4};
+constexpr bool kTileLinear[kTileShapes] = {false, false, false, true, true, true};
 // Candidate resident blocks per compute unit of the persistent launch (0: one
 // block per tile)
 constexpr int kTileResident[4] = {0, 2, 4, 8};
+
+// Tiles of one lattice in tile shape k.
+static int lattice_tiles(int ny, int nseg, int k)
+{
+    return kTileLinear[k] ? grid_tiles_linear(ny, nseg, kTileRows[k])
+                          : grid_blocks_rows(ny, nseg, kTileRows[k]);
+}
 
 // Buffer layout of a context: the lattices one after the other in every
 // buffer; the capsule table followed by the lattice table, the round tables
@@ -48,11 +58,11 @@ struct Layout {
     int rb = 4;
     size_t pop_elems = 0, fib_level = 0, flag_level = 0;
     int max_caps = 0, max_nodes = 0, max_nv = 0;
-    long long tiles[3] = {0, 0, 0};  // tiles of the batched pass, per tile shape
+    long long tiles[6] = {0, 0, 0, 0, 0, 0};  // tiles of the batched pass, per tile shape
     size_t plane_max = 0;
     size_t inst_table = 0, round_table = 0, rect_table = 0, near_map = 0, bounds = 0,
            hints = 0;  // in BUF_CAPS
-    size_t round_off[3] = {0, 0, 0};  // the round table of each tile shape
+    size_t round_off[6] = {0, 0, 0, 0, 0, 0};  // the round table of each tile shape
 };
 
 struct lbib_ctx {
@@ -162,9 +172,9 @@ static bool make_layout(const lbib_grid* grids, int n, Layout& L)
         I.pop_off = L.pop_elems;
         I.fib_off = L.fib_level;
         I.flag_off = L.flag_level;
-        for (int k = 0; k < 3; k++) {
+        for (int k = 0; k < kTileShapes; k++) {
             I.tile0[k] = L.tiles[k];
-            L.tiles[k] += grid_blocks_rows(g->ny, I.nseg, kTileRows[k]);
+            L.tiles[k] += lattice_tiles(g->ny, I.nseg, k);
         }
         L.pop_elems += 9 * lc;
         L.fib_level += 2 * lc;
@@ -184,7 +194,7 @@ static bool make_layout(const lbib_grid* grids, int n, Layout& L)
     L.inst_table = round256((size_t)L.max_caps * sizeof(CapsuleDev));
     L.round_table = L.inst_table + round256((size_t)n * sizeof(InstDev));
     size_t o = L.round_table;
-    for (int k = 0; k < 3; k++) {
+    for (int k = 0; k < kTileShapes; k++) {
         L.round_off[k] = o;
         o += round256((size_t)(L.tiles[k] / kNumXcd) * sizeof(int2));
     }
@@ -427,8 +437,8 @@ static lbib_status create_common(const lbib_grid* grids, const double* taus,
     }
     // lattice table and block-round table of the batched grid launch
     std::vector<InstDev> tab(n_inst);
-    std::vector<int2> rounds[3];
-    for (int k = 0; k < 3; k++) rounds[k].resize(L.tiles[k] / kNumXcd);
+    std::vector<int2> rounds[kTileShapes];
+    for (int k = 0; k < kTileShapes; k++) rounds[k].resize(L.tiles[k] / kNumXcd);
     for (int i = 0; i < n_inst; i++) {
         const Inst& I = c->L.inst[i];
         const GridArgs g = grid_args(I);
@@ -449,15 +459,15 @@ static lbib_status create_common(const lbib_grid* grids, const double* taus,
         d.gx = g.gx;
         d.u_bot = g.u_bot;
         d.u_top = g.u_top;
-        for (int k = 0; k < 3; k++) {
+        for (int k = 0; k < kTileShapes; k++) {
             const int r0 = (int)(I.tile0[k] / kNumXcd);
-            const int r1 = r0 + grid_blocks_rows(g.ny, g.nseg, kTileRows[k]) / kNumXcd;
+            const int r1 = r0 + lattice_tiles(g.ny, g.nseg, k) / kNumXcd;
             for (int r = r0; r < r1; r++) rounds[k][r] = make_int2(i, r0);
         }
     }
     e = hipMemcpyAsync(bufp(c, LBIB_BUF_CAPS) + L.inst_table, tab.data(),
                        tab.size() * sizeof(InstDev), hipMemcpyHostToDevice, c->stream);
-    for (int k = 0; k < 3 && e == hipSuccess; k++)
+    for (int k = 0; k < kTileShapes && e == hipSuccess; k++)
         if (!rounds[k].empty())
             e = hipMemcpyAsync(bufp(c, LBIB_BUF_CAPS) + L.round_off[k], rounds[k].data(),
                                rounds[k].size() * sizeof(int2), hipMemcpyHostToDevice, c->stream);
@@ -801,7 +811,8 @@ static hipError_t launch_batch_shape(const lbib_ctx* c, const T* src, T* dst,
 {
     return launch_grid_step_batch<T>(src, dst, fib_now, flags_now, fib_old, flags_old,
                                      inst_table(c), round_table(c, shape), (int)c->L.tiles[shape],
-                                     kTileRows[shape], batch_grid(c, shape, resident),
+                                     kTileRows[shape], kTileLinear[shape],
+                                     batch_grid(c, shape, resident),
                                      any_open(c), st);
 }
 
@@ -1599,12 +1610,13 @@ extern "C" lbib_status lbib_set_graph(lbib_ctx* c, int32_t enable)
 
 extern "C" int64_t lbib_graph_replays(const lbib_ctx* c) { return c ? c->graph_replays : -1; }
 
-extern "C" lbib_status lbib_set_tile(lbib_ctx* c, int32_t rows, int32_t resident)
+extern "C" lbib_status lbib_set_tile(lbib_ctx* c, int32_t rows, int32_t linear, int32_t resident)
 {
     if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
+    if (linear != 0 && linear != 1) return fail(c, LBIB_EINVAL, "linear must be 0 or 1");
     int shape = -1;
-    for (int k = 0; k < 3; k++)
-        if (kTileRows[k] == rows) shape = k;
+    for (int k = 0; k < kTileShapes; k++)
+        if (kTileRows[k] == rows && kTileLinear[k] == (linear == 1)) shape = k;
     if (shape < 0) return fail(c, LBIB_EINVAL, "rows must be 1, 2 or 4");
     if (resident < 0 || resident > 64) return fail(c, LBIB_EINVAL, "resident must be in [0, 64]");
     c->tile_shape = shape;
@@ -1635,7 +1647,7 @@ static lbib_status autotune_t(lbib_ctx* c, int launches, double* us)
     lbib_status st = LBIB_OK;
     double best = 1e300;
     int best_s = 0, best_r = 0;
-    for (int s = 0; s < 3 && st == LBIB_OK; s++)
+    for (int s = 0; s < kTileShapes && st == LBIB_OK; s++)
         for (int r = 0; r < 4 && st == LBIB_OK; r++) {
             hipError_t e = launch_batch_shape<T>(c, src, dst, f, fl, f, fl, s, kTileResident[r],
                                                  c->stream);
@@ -1668,18 +1680,20 @@ static lbib_status autotune_t(lbib_ctx* c, int launches, double* us)
 }
 
 extern "C" lbib_status lbib_autotune(lbib_ctx* c, int32_t launches, int32_t* out_rows,
-                                     int32_t* out_resident, double* out_us, int32_t n_us)
+                                     int32_t* out_linear, int32_t* out_resident, double* out_us,
+                                     int32_t n_us)
 {
     if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
     if (launches < 1 || launches > 1000) return fail(c, LBIB_EINVAL, "launches must be in [1, 1000]");
     if (c->L.inst.size() < 2) return fail(c, LBIB_EINVAL, "tile shapes apply to batch contexts");
-    double us[12];
+    double us[kTileShapes * 4];
     const lbib_status st = c->rb == 4 ? autotune_t<float>(c, launches, us)
                                       : autotune_t<double>(c, launches, us);
     if (st != LBIB_OK) return st;
     if (out_rows) *out_rows = kTileRows[c->tile_shape];
+    if (out_linear) *out_linear = kTileLinear[c->tile_shape] ? 1 : 0;
     if (out_resident) *out_resident = c->tile_resident;
-    for (int i = 0; out_us && i < n_us && i < 12; i++) out_us[i] = us[i];
+    for (int i = 0; out_us && i < n_us && i < kTileShapes * 4; i++) out_us[i] = us[i];
     return LBIB_OK;
 }
 

@@ -163,7 +163,7 @@ template <typename T>
 hipError_t launch_grid_step_batch(const T* src, T* dst, const long long* fib_now,
                                   const int* flags_now, long long* fib_old, int* flags_old,
                                   const InstDev* inst, const int2* rounds, int tiles, int rows,
-                                  int grid, bool any_open, hipStream_t s);
+                                  bool linear, int grid, bool any_open, hipStream_t s);
 template <typename T>
 hipError_t launch_grid_far(const T* src, T* dst, const int* flags_now, const int* flags_old,
                            const int* near_map, int stamp, int* status, const GridArgs& g,
@@ -183,6 +183,9 @@ int grid_blocks(int ny, int nseg);
 // Blocks of a lattice's grid pass with `rows` nodes per thread (bands of
 // 4 * rows rows, dealt to the XCDs in groups of 8 bands), a multiple of 8.
 int grid_blocks_rows(int ny, int nseg, int rows);
+// Tiles of a lattice in the linear mapping: bands times segments, rounded up
+// to a multiple of 8.
+int grid_tiles_linear(int ny, int nseg, int rows);
 template <typename T>
 hipError_t launch_ib(const IBArgs<T>& a, int ncap, size_t lds_bytes, hipStream_t s);
 template <typename T>

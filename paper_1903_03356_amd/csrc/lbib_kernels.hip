@@ -261,11 +261,14 @@ hipError_t launch_grid_near(const T* src, T* dst, const long long* fib_now, cons
 
 // Ensemble of lattices in one launch.  The tiles (a 64-cell segment of a band
 // of 4 * ROWS rows) of every lattice form a run that starts at a multiple of
-// kNumXcd, so tile t, processed by a block on XCD t % 8, keeps the band-to-XCD
-// mapping above inside each lattice.  rounds[t / 8] = (lattice, first round of
-// that lattice).  With gridDim.x < tiles (a multiple of 8) the launch is
-// persistent: each block walks the tiles t = blockIdx.x + k * gridDim.x.
-template <typename T, int ROWS, bool OPEN>
+// kNumXcd.  rounds[t / 8] = (lattice, first round of that lattice).  Banded
+// (LIN = false): the lattice's bands go in groups of 8, so tile t, processed by
+// a block on XCD t % 8, keeps the band-to-XCD mapping above.  Linear (LIN =
+// true): tile t covers band t / nseg, segment t % nseg of its lattice, with
+// the run padded only to a multiple of 8 tiles (no empty bands).  With
+// gridDim.x < tiles (a multiple of 8) the launch is persistent: each block
+// walks the tiles t = blockIdx.x + k * gridDim.x.
+template <typename T, int ROWS, bool OPEN, bool LIN>
 __global__ __launch_bounds__(kSegW * 4) void k_grid_step_batch(
     const T* __restrict__ src, T* __restrict__ dst, const long long* __restrict__ fib_now,
     const int* __restrict__ flags_now, long long* __restrict__ fib_old,
@@ -289,10 +292,16 @@ __global__ __launch_bounds__(kSegW * 4) void k_grid_step_batch(
         g.u_in = I.u_in;
         g.rho_out = I.rho_out;
         const int lb = b - ri.y * kNumXcd;
-        const int j = lb / kNumXcd;
-        const int group = j / g.nseg;
-        const int band = group * kNumXcd + (lb - j * kNumXcd);
-        const int seg = j - group * g.nseg;
+        int band, seg;
+        if (LIN) {
+            band = lb / g.nseg;
+            seg = lb - band * g.nseg;
+        } else {
+            const int j = lb / kNumXcd;
+            const int group = j / g.nseg;
+            band = group * kNumXcd + (lb - j * kNumXcd);
+            seg = j - group * g.nseg;
+        }
         const int lane = threadIdx.x & (kSegW - 1);
         const int y0 = band * (4 * ROWS) + (threadIdx.x >> 6);
 #pragma unroll
@@ -313,42 +322,60 @@ int grid_blocks_rows(int ny, int nseg, int rows)
     return groups * nseg * kNumXcd;
 }
 
-template <typename T, int R>
+int grid_tiles_linear(int ny, int nseg, int rows)
+{
+    const int bands = (ny + 4 * rows - 1) / (4 * rows);
+    return (bands * nseg + kNumXcd - 1) / kNumXcd * kNumXcd;
+}
+
+template <typename T, int R, bool LIN>
 static void launch_batch_rows(const T* src, T* dst, const long long* fib_now, const int* flags_now,
                               long long* fib_old, int* flags_old, const InstDev* inst,
                               const int2* rounds, int tiles, int grid, bool any_open,
                               hipStream_t s)
 {
     if (any_open)
-        hipLaunchKernelGGL((k_grid_step_batch<T, R, true>), dim3((unsigned)grid), dim3(kSegW * 4),
-                           0, s, src, dst, fib_now, flags_now, fib_old, flags_old, inst, rounds,
-                           tiles);
-    else
-        hipLaunchKernelGGL((k_grid_step_batch<T, R, false>), dim3((unsigned)grid),
+        hipLaunchKernelGGL((k_grid_step_batch<T, R, true, LIN>), dim3((unsigned)grid),
                            dim3(kSegW * 4), 0, s, src, dst, fib_now, flags_now, fib_old, flags_old,
                            inst, rounds, tiles);
+    else
+        hipLaunchKernelGGL((k_grid_step_batch<T, R, false, LIN>), dim3((unsigned)grid),
+                           dim3(kSegW * 4), 0, s, src, dst, fib_now, flags_now, fib_old, flags_old,
+                           inst, rounds, tiles);
+}
+
+template <typename T, bool LIN>
+static hipError_t launch_batch_lin(const T* src, T* dst, const long long* fib_now,
+                                   const int* flags_now, long long* fib_old, int* flags_old,
+                                   const InstDev* inst, const int2* rounds, int tiles, int rows,
+                                   int grid, bool any_open, hipStream_t s)
+{
+    if (rows == 1)
+        launch_batch_rows<T, 1, LIN>(src, dst, fib_now, flags_now, fib_old, flags_old, inst,
+                                     rounds, tiles, grid, any_open, s);
+    else if (rows == 2)
+        launch_batch_rows<T, 2, LIN>(src, dst, fib_now, flags_now, fib_old, flags_old, inst,
+                                     rounds, tiles, grid, any_open, s);
+    else if (rows == 4)
+        launch_batch_rows<T, 4, LIN>(src, dst, fib_now, flags_now, fib_old, flags_old, inst,
+                                     rounds, tiles, grid, any_open, s);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_grid_step_batch(const T* src, T* dst, const long long* fib_now,
                                   const int* flags_now, long long* fib_old, int* flags_old,
                                   const InstDev* inst, const int2* rounds, int tiles, int rows,
-                                  int grid, bool any_open, hipStream_t s)
+                                  bool linear, int grid, bool any_open, hipStream_t s)
 {
     if (tiles <= 0) return hipSuccess;
     if (grid <= 0 || grid > tiles || grid % kNumXcd != 0) return hipErrorInvalidValue;
-    if (rows == 1)
-        launch_batch_rows<T, 1>(src, dst, fib_now, flags_now, fib_old, flags_old, inst, rounds,
-                                tiles, grid, any_open, s);
-    else if (rows == 2)
-        launch_batch_rows<T, 2>(src, dst, fib_now, flags_now, fib_old, flags_old, inst, rounds,
-                                tiles, grid, any_open, s);
-    else if (rows == 4)
-        launch_batch_rows<T, 4>(src, dst, fib_now, flags_now, fib_old, flags_old, inst, rounds,
-                                tiles, grid, any_open, s);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    return linear ? launch_batch_lin<T, true>(src, dst, fib_now, flags_now, fib_old, flags_old,
+                                              inst, rounds, tiles, rows, grid, any_open, s)
+                  : launch_batch_lin<T, false>(src, dst, fib_now, flags_now, fib_old, flags_old,
+                                               inst, rounds, tiles, rows, grid, any_open, s);
 }
 
 // ------------------------------------------------------------ init kernel
@@ -1706,7 +1733,7 @@ hipError_t launch_set_nodes(T* nodes, CapsuleDev* caps, int cap, int nv, int nod
                                             long long*, int*, const GridArgs&, hipStream_t);      \
     template hipError_t launch_grid_step_batch<T>(const T*, T*, const long long*, const int*,     \
                                                   long long*, int*, const InstDev*, const int2*,  \
-                                                  int, int, int, bool, hipStream_t);              \
+                                                  int, int, bool, int, bool, hipStream_t);        \
     template hipError_t launch_grid_far<T>(const T*, T*, const int*, const int*, const int*, int, \
                                            int*, const GridArgs&, hipStream_t);                   \
     template hipError_t launch_grid_near<T>(const T*, T*, const long long*, const int*,           \

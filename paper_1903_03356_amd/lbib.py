@@ -126,9 +126,10 @@ def load() -> C.CDLL:
     L.lbib_graph_replays.restype = C.c_int64
     L.lbib_graph_replays.argtypes = [vp]
     L.lbib_set_tile.restype = i32
-    L.lbib_set_tile.argtypes = [vp, i32, i32]
+    L.lbib_set_tile.argtypes = [vp, i32, i32, i32]
     L.lbib_autotune.restype = i32
-    L.lbib_autotune.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double), i32]
+    L.lbib_autotune.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                                C.POINTER(C.c_double), i32]
     L.lbib_adjoint_bytes.restype = C.c_size_t
     L.lbib_adjoint_bytes.argtypes = [vp, i32, i32]
     dp = C.POINTER(C.c_double)
@@ -346,22 +347,23 @@ class Sim:
     def graph_replays(self) -> int:
         return int(load().lbib_graph_replays(self.h))
 
-    def set_tile(self, rows: int, resident: int = 0) -> None:
+    def set_tile(self, rows: int, resident: int = 0, linear: bool = False) -> None:
         """Tile shape of the batched grid pass (lbib_set_tile)."""
-        _check(load().lbib_set_tile(self.h, int(rows), int(resident)), self.h)
+        _check(load().lbib_set_tile(self.h, int(rows), 1 if linear else 0, int(resident)), self.h)
 
     def autotune(self, launches: int = 20) -> Dict[str, Any]:
-        """lbib_autotune: times the 12 tile shapes of the batched grid pass and
+        """lbib_autotune: times the 24 tile shapes of the batched grid pass and
         keeps the fastest; returns the choice and the mean time per pass (us)
-        of every (rows, resident) candidate."""
-        rows, res = C.c_int32(), C.c_int32()
-        us = (C.c_double * 12)()
+        of every (order, rows, resident) candidate."""
+        rows, lin, res = C.c_int32(), C.c_int32(), C.c_int32()
+        us = (C.c_double * 24)()
         with self.torch.cuda.device(self.device):
-            _check(load().lbib_autotune(self.h, int(launches), C.byref(rows), C.byref(res), us,
-                                        12), self.h)
-        cands = [(r, k) for r in (1, 2, 4) for k in (0, 2, 4, 8)]
-        return {"rows": rows.value, "resident": res.value,
-                "us": {f"rows{r}_resident{k}": round(us[i], 2) for i, (r, k) in enumerate(cands)}}
+            _check(load().lbib_autotune(self.h, int(launches), C.byref(rows), C.byref(lin),
+                                        C.byref(res), us, 24), self.h)
+        cands = [(o, r, k) for o in ("banded", "linear") for r in (1, 2, 4) for k in (0, 2, 4, 8)]
+        return {"rows": rows.value, "linear": bool(lin.value), "resident": res.value,
+                "us": {f"{o}_rows{r}_resident{k}": round(us[i], 2)
+                       for i, (o, r, k) in enumerate(cands)}}
 
     def adjoint_bytes(self, nsteps: int, checkpoint_every: int = 0) -> int:
         return int(load().lbib_adjoint_bytes(self.h, int(nsteps), int(checkpoint_every)))

@@ -112,8 +112,8 @@ def test_null_context_calls(L):
     assert L.lbib_adjoint_bytes(None, 10, 0) == 0
     assert L.lbib_set_graph(None, 1) == lbib.EINVAL
     assert L.lbib_graph_replays(None) == -1
-    assert L.lbib_set_tile(None, 1, 0) == lbib.EINVAL
-    assert L.lbib_autotune(None, 5, None, None, None, 0) == lbib.EINVAL
+    assert L.lbib_set_tile(None, 1, 0, 0) == lbib.EINVAL
+    assert L.lbib_autotune(None, 5, None, None, None, None, 0) == lbib.EINVAL
     d = C.c_double()
     ks = (C.c_double * 4)()
     assert L.lbib_adjoint(None, 10, 0, 1, 0, 0, None, 0, C.byref(d), C.byref(d), ks, 4) == lbib.EINVAL

@@ -242,19 +242,20 @@ def _same_batches(a, b, n_lattices):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("linear", [False, True])
 @pytest.mark.parametrize("rows", [1, 2, 4])
-def test_every_tile_shape_is_bit_identical(rows):
-    """The tile shapes of the batched grid pass (rows per thread, one block
-    per tile or a persistent launch) compute the same bits as the default, on
-    lattices with ragged rows and segments, walls, a Couette channel and a
-    periodic box."""
+def test_every_tile_shape_is_bit_identical(rows, linear):
+    """The tile shapes of the batched grid pass (rows per thread, banded or
+    linear tile order, one block per tile or a persistent launch) compute the
+    same bits as the default, on lattices with ragged rows and segments, walls,
+    a Couette channel and a periodic box."""
     cfgs = _mixed_lattices() + wl.ensemble(seed=4, n_inst=4)
     ref = lbib.Batch(cfgs)
     ref.step(40)
     for resident in (0, 1, 3, 8):
-        log(f"tile rows={rows} resident={resident}")
+        log(f"tile rows={rows} linear={linear} resident={resident}")
         b = lbib.Batch(cfgs)
-        b.set_tile(rows, resident)
+        b.set_tile(rows, resident, linear)
         b.step(40)
         assert b.check() == 0
         _same_batches(b, ref, len(cfgs))
@@ -269,7 +270,7 @@ def test_autotune_picks_a_shape_and_keeps_the_state():
     r = a.autotune(3)
     log(f"autotune: {r}")
     assert r["rows"] in (1, 2, 4) and r["resident"] in (0, 2, 4, 8)
-    assert len(r["us"]) == 12 and all(v > 0 for v in r["us"].values())
+    assert len(r["us"]) == 24 and all(v > 0 for v in r["us"].values())
     _same_batches(a, b, len(cfgs))  # tuning leaves the state alone
     a.step(25)
     b.step(25)
