@@ -113,7 +113,6 @@ def near_cells(sim, cfg) -> int:
     and x^n), i.e. the cells the far kernel skipped."""
     import math
     nx, ny = cfg["nx"], cfg["ny"]
-    nseg = -(-nx // 64)
     units = set()
     for c in range(len(cfg["capsules"])):
         x, xp, _ = sim.capsule(c)
@@ -164,22 +163,28 @@ def bench_ensemble(steps: int, warmup: int, loop_steps: int):
     if flags:
         raise RuntimeError(f"device flags {flags} in the batched ensemble")
     del bat
-    # the same steps replayed from captured 16-step graphs (lbib_set_graph), on
-    # a fresh batch over the same stretch of steps (the Dynamic loop's slow
-    # mode sets in later)
-    gb = lbib.Batch(cfgs)
-    gb.set_tile(tune["rows"], tune["resident"], tune["linear"])
-    gb.set_graph(True)
-    gb.step(max(1, warmup - 18))
-    gb.step(18)  # the blocks of both step parities are captured here
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    gb.step(steps)
-    torch.cuda.synchronize()
-    t_graph = (time.perf_counter() - t0) / steps
-    if gb.check():
-        raise RuntimeError("device flags in the graph-replayed ensemble")
-    del gb
+    # the same steps replayed from captured 16-step graphs (lbib_set_graph),
+    # and split into near and far passes on two streams (lbib_set_overlap),
+    # each on a fresh batch over the same stretch of steps (the Dynamic
+    # loop's slow mode sets in later)
+    def variant(graph, overlap):
+        gb = lbib.Batch(cfgs)
+        gb.set_tile(tune["rows"], tune["resident"], tune["linear"])
+        gb.set_overlap(overlap)
+        gb.set_graph(graph)
+        gb.step(max(1, warmup - 18))
+        gb.step(18)  # with graphs, the blocks of both step parities are captured here
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gb.step(steps)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        if gb.check():
+            raise RuntimeError("device flags in an ensemble variant")
+        del gb
+        return t
+
+    t_graph, t_split = variant(True, False), variant(False, True)
     grid_us = tm["grid_ms"] / max(1.0, tm["grid_launches"]) * 1e3
     ib_us = tm["ib_ms"] / max(1.0, tm["ib_launches"]) * 1e3
     sims = [lbib.Sim(c) for c in cfgs]
@@ -210,6 +215,7 @@ def bench_ensemble(steps: int, warmup: int, loop_steps: int):
         "grid_kernel_frac": round(BYTES_PER_CELL * cells / (grid_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
         "ib_kernel_us": round(ib_us, 2),
         "graph_ms_per_step": round(t_graph * 1e3, 4),
+        "overlapped_ms_per_step": round(t_split * 1e3, 4),
         "tile": {"rows": tune["rows"], "linear": tune["linear"], "resident": tune["resident"]},
         "tile_candidates_us": tune["us"],
     }
@@ -402,6 +408,7 @@ def main() -> int:
         side["biconcave_1024x256_mlups"] = round(c2r["mlups"], 1)
         ens = bench_ensemble(min(args.steps, 400), args.warmup, 20)
         log(f"ensemble: batched {ens['mlups']:.0f} MLUPS ({ens['ms_per_step']:.3f} ms/step, "
+            f"single pass {ens['single_pass_ms_per_step']:.3f}, "
             f"{ens['graph_ms_per_step']:.3f} with graph replays, "
             f"grid {ens['grid_kernel_us']:.1f} us, IB {ens['ib_kernel_us']:.1f} us), "
             f"per-simulation loop {ens['loop_ms_per_step']:.3f} ms/step, "

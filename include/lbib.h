@@ -194,15 +194,18 @@ lbib_status lbib_add_rigid_to(lbib_ctx* ctx, int32_t lattice, const double* node
  * with the forcing of this step) and one fused collide-stream kernel launch.
  * The call ends with the node update of the last step, so between calls the
  * state is the complete state at time n.
- * Overlapped schedule (lbib_set_overlap): a periodic single lattice with
- * 1..64 capsules and no contact force can split the collide-stream pass.  A
+ * Overlapped schedule (lbib_set_overlap): lattices periodic in x (one, or
+ * every lattice of a batch) with 1..4096 capsules and no contact force can
+ * split the collide-stream pass.  A
  * near kernel covers each capsule's near region (the bounding box of its
  * nodes at n-1 and n plus 5 cells) on the bound stream, and the next IB launch
  * follows it there; a far kernel covers the rest on a second stream of the
  * library's own, so the IB work runs beside it.  The results are
  * bit-identical to the single pass, and the call still returns with all work
- * ordered on the bound stream.  By default the split is used from 2^22
- * lattice cells on, where it pays.
+ * ordered on the bound stream.  By default the split is used for a single
+ * lattice of 2^22 cells or more, where it pays; a batch takes it only when
+ * asked (many small lattices: the far launch slows the IB launch beside it
+ * more than the split saves).
  * Captured steps (lbib_set_graph(ctx, 1)): otherwise, unless kernel timing is
  * on, the inner steps of a call go in blocks of 16 steps captured once into a
  * HIP graph (one for blocks that start on an even step, one for odd) and
@@ -258,8 +261,8 @@ lbib_status lbib_set_timing(lbib_ctx* ctx, int32_t enable);
 lbib_status lbib_set_contact(lbib_ctx* ctx, double cutoff);
 
 /* Schedule of lbib_step: enable = 1 always uses the overlapped near / far
- * schedule where it applies (see lbib_step), 0 never, -1 (the default) from
- * 2^22 lattice cells on.  Errors: EINVAL (other values). */
+ * schedule where it applies (see lbib_step), 0 never, -1 (the default) for
+ * one lattice of 2^22 cells or more.  Errors: EINVAL (other values). */
 lbib_status lbib_set_overlap(lbib_ctx* ctx, int32_t enable);
 
 /* Captured step blocks of lbib_step: enable = 1 replays them; 0 and -1 (the

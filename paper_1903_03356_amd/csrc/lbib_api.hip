@@ -150,7 +150,7 @@ static bool grid_ok(const lbib_grid* g)
 }
 
 constexpr int kMaxInstances = 1 << 16;
-constexpr int kMaxOverlapCapsules = 64;  // near regions per step (one near-kernel block group each)
+constexpr int kMaxOverlapCapsules = 4096;  // near regions per step (one near-kernel block group each)
 constexpr long long kOverlapMinCells = 1LL << 22;  // automatic overlap from 4.2 M cells
 
 // Fills L from the lattices' sizes and capacities; false if any is invalid or
@@ -803,17 +803,19 @@ static int batch_grid(const lbib_ctx* c, int shape, int resident)
     return (int)std::max<long long>(kNumXcd, std::min<long long>(want, tiles));
 }
 
+// The batched grid pass in tile shape `shape`; with a near map, only its far
+// part (units whose entry does not carry `stamp`, where no IB force reaches).
 template <typename T>
 static hipError_t launch_batch_shape(const lbib_ctx* c, const T* src, T* dst,
                                      const long long* fib_now, const int* flags_now,
                                      long long* fib_old, int* flags_old, int shape, int resident,
-                                     hipStream_t st)
+                                     hipStream_t st, const int* far_map = nullptr, int stamp = 0)
 {
     return launch_grid_step_batch<T>(src, dst, fib_now, flags_now, fib_old, flags_old,
                                      inst_table(c), round_table(c, shape), (int)c->L.tiles[shape],
                                      kTileRows[shape], kTileLinear[shape],
-                                     batch_grid(c, shape, resident),
-                                     any_open(c), st);
+                                     batch_grid(c, shape, resident), any_open(c), far_map, stamp,
+                                     status_word(c), st);
 }
 
 template <typename T>
@@ -851,23 +853,30 @@ template <typename T>
 static hipError_t do_far(lbib_ctx* c, void* p)
 {
     const long long n = *static_cast<const long long*>(p);
+    if (c->L.inst.size() > 1)
+        return launch_batch_shape<T>(c, static_cast<const T*>(pops(c, n)),
+                                     static_cast<T*>(pops(c, n + 1)), fib(c, n), flags(c, n),
+                                     fib(c, n + 1), flags(c, n + 1), c->tile_shape,
+                                     c->tile_resident, c->s_far, near_map(c, n), step_stamp(n));
     const GridArgs g = grid_args(c->L.inst[0]);
     return launch_grid_far<T>(static_cast<const T*>(pops(c, n)), static_cast<T*>(pops(c, n + 1)),
-                              flags(c, n), flags(c, n + 1), near_map(c, n), step_stamp(n),
-                              status_word(c), g, c->s_far);
+                              fib(c, n), flags(c, n), fib(c, n + 1), flags(c, n + 1),
+                              near_map(c, n), step_stamp(n), status_word(c), g, c->s_far);
 }
 
 template <typename T>
 static hipError_t do_near(lbib_ctx* c, void* p)
 {
     const long long n = *static_cast<const long long*>(p);
-    const GridArgs g = grid_args(c->L.inst[0]);
     return launch_grid_near<T>(static_cast<const T*>(pops(c, n)), static_cast<T*>(pops(c, n + 1)),
                                fib(c, n), flags(c, n), fib(c, n + 1), flags(c, n + 1),
-                               rect_table(c, n), c->ncap, g, c->stream);
+                               rect_table(c, n),
+                               reinterpret_cast<const CapsuleDev*>(bufp(c, LBIB_BUF_CAPS)),
+                               inst_table(c), c->ncap, c->stream);
 }
 
-// Overlapped schedule of a single lattice with capsules.  Per step n:
+// Overlapped schedule of a lattice, or of every lattice of a batch, with
+// capsules (periodic in x, no contact force).  Per step n:
 //   main stream: wait far(n-1) -> near(n) -> IB(n+1)
 //   far stream:  wait IB(n)    -> far(n)
 // IB(n) writes the near regions R_n and stamps them into the near map.
@@ -1002,15 +1011,18 @@ static lbib_status step_t(lbib_ctx* c, int nsteps)
     size_patches<T>(c);
     const bool contact = c->contact_cutoff > 0.0 && c->ncap > 1;
     const bool dyn = c->mode == LBIB_DYNAMIC;
-    const bool can_overlap = !contact && c->L.inst.size() == 1 &&
-                             c->L.inst[0].walls.periodic_x && c->ncap > 0 &&
+    const bool can_overlap = !contact && !any_open(c) && c->ncap > 0 &&
                              c->ncap <= kMaxOverlapCapsules;
-    const long long cells = (long long)c->L.inst[0].grid.nx * c->L.inst[0].grid.ny;
+    long long cells = 0;
+    for (const Inst& I : c->L.inst) cells += (long long)I.grid.nx * I.grid.ny;
     // automatic: the split pays once the grid step clearly outlasts the IB
     // launch, the near pass and the stream hand-offs (32 capsules, measured:
     // +7 % at 16.8 M cells, +12 % at 8.4 M, +5.5 % at 4.2 M, -10 % at 2.1 M,
-    // -19 % at 1.0 M)
-    const bool want = c->overlap == 1 || (c->overlap < 0 && cells >= kOverlapMinCells);
+    // -19 % at 1.0 M).  A batch of small lattices loses (256 lattices,
+    // 8.0 M cells, 388 capsules: -17 %, the IB launch runs 2.4x longer beside
+    // the far pass), so a batch splits only when asked.
+    const bool want = c->overlap == 1 || (c->overlap < 0 && c->L.inst.size() == 1 &&
+                                          cells >= kOverlapMinCells);
     if (can_overlap && want) return step_overlap_t<T>(c, nsteps);
     // replays of captured blocks for the inner steps; timed runs launch directly
     const bool graphs = c->graph == 1 && !c->timing;

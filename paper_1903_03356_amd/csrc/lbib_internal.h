@@ -163,15 +163,16 @@ template <typename T>
 hipError_t launch_grid_step_batch(const T* src, T* dst, const long long* fib_now,
                                   const int* flags_now, long long* fib_old, int* flags_old,
                                   const InstDev* inst, const int2* rounds, int tiles, int rows,
-                                  bool linear, int grid, bool any_open, hipStream_t s);
+                                  bool linear, int grid, bool any_open, const int* near_map,
+                                  int stamp, int* status, hipStream_t s);
 template <typename T>
-hipError_t launch_grid_far(const T* src, T* dst, const int* flags_now, const int* flags_old,
-                           const int* near_map, int stamp, int* status, const GridArgs& g,
-                           hipStream_t s);
+hipError_t launch_grid_far(const T* src, T* dst, const long long* fib_now, const int* flags_now,
+                           long long* fib_old, int* flags_old, const int* near_map, int stamp,
+                           int* status, const GridArgs& g, hipStream_t s);
 template <typename T>
 hipError_t launch_grid_near(const T* src, T* dst, const long long* fib_now, const int* flags_now,
-                            long long* fib_old, int* flags_old, const NearRect* rects, int ncap,
-                            const GridArgs& g, hipStream_t s);
+                            long long* fib_old, int* flags_old, const NearRect* rects,
+                            const CapsuleDev* caps, const InstDev* inst, int ncap, hipStream_t s);
 template <typename T>
 hipError_t launch_contact(const ContactArgs<T>& a, hipStream_t s);
 template <typename T>

@@ -136,15 +136,36 @@ __device__ __forceinline__ RectUnits rect_units(const NearRect& r, const GridArg
     return u;
 }
 
+// Grid arguments of one lattice of the lattice table.
+__device__ __forceinline__ GridArgs lattice_args(const InstDev& I)
+{
+    GridArgs g;
+    g.nx = I.nx;
+    g.ny = I.ny;
+    g.nxp = I.nxp;
+    g.nseg = I.nseg;
+    g.periodic_y = I.periodic_y;
+    g.periodic_x = I.periodic_x;
+    g.omega = I.omega;
+    g.gx = I.gx;
+    g.u_bot = I.u_bot;
+    g.u_top = I.u_top;
+    g.u_in = I.u_in;
+    g.rho_out = I.rho_out;
+    return g;
+}
+
 // Far part: every (row, segment) outside all near regions, i.e. whose entry
 // in this step's near map does not carry this step's stamp.  The IB force is
-// zero there (its supports lie inside the near regions), so the node sees the
-// body force only and no force level is read or cleared.  An active force
-// flag found here means the near regions were too small: ST_NEAR.
+// zero there (its supports lie inside the near regions): an active force flag
+// found here means the near regions were too small, ST_NEAR.  The unit runs
+// the very code of the single pass (grid_cell), so that the compiler forms
+// the same arithmetic and the split repeats the single pass bit for bit.
 template <typename T>
 __global__ __launch_bounds__(kSegW * 4) void k_grid_far(
-    const T* __restrict__ src, T* __restrict__ dst, const int* __restrict__ flags_now,
-    const int* __restrict__ flags_old, const int* __restrict__ near_map, int stamp, int* status,
+    const T* __restrict__ src, T* __restrict__ dst, const long long* __restrict__ fib_now,
+    const int* __restrict__ flags_now, long long* __restrict__ fib_old,
+    int* __restrict__ flags_old, const int* __restrict__ near_map, int stamp, int* status,
     GridArgs g)
 {
     const int b = blockIdx.x;
@@ -158,20 +179,23 @@ __global__ __launch_bounds__(kSegW * 4) void k_grid_far(
     const int fidx = y * g.nseg + seg;
     if (near_map[fidx] == stamp) return;
     if ((flags_now[fidx] | flags_old[fidx]) && lane == 0) atomicOr(status, ST_NEAR);
-    const int x = seg * kSegW + lane;
-    if (x < g.nx) collide_store<T, false>(src, dst, g, x, y, (T)g.gx, T(0));
+    grid_cell<false>(src, dst, fib_now, flags_now, fib_old, flags_old, g, y, seg, lane);
 }
 
 // Near part: the (row, segment) units of every capsule's near region, with
-// the IB force; `per_cap` blocks of 4 waves share one capsule's units.  Units
-// in several regions are computed more than once, with identical results.
+// the IB force; `per_cap` blocks of 4 waves share one capsule's units, on the
+// capsule's lattice.  Units in several regions are computed more than once,
+// with identical results.
 template <typename T>
 __global__ __launch_bounds__(kSegW * 4) void k_grid_near(
     const T* __restrict__ src, T* __restrict__ dst, const long long* __restrict__ fib_now,
     const int* __restrict__ flags_now, long long* __restrict__ fib_old,
-    int* __restrict__ flags_old, const NearRect* __restrict__ rects, int per_cap, GridArgs g)
+    int* __restrict__ flags_old, const NearRect* __restrict__ rects,
+    const CapsuleDev* __restrict__ caps, const InstDev* __restrict__ inst, int per_cap)
 {
     const int c = blockIdx.x / per_cap, kb = blockIdx.x - c * per_cap;
+    const InstDev& I = inst[caps[c].inst];
+    const GridArgs g = lattice_args(I);
     const RectUnits u = rect_units(rects[c], g);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kSegW - 1);
     const int units = u.nrows * u.nsegs;
@@ -180,7 +204,9 @@ __global__ __launch_bounds__(kSegW * 4) void k_grid_near(
         int y = u.ry0 + ri;
         if (y >= g.ny) y -= g.ny;
         const int seg = si < u.nA ? u.sa + si : si - u.nA;
-        grid_cell<false>(src, dst, fib_now, flags_now, fib_old, flags_old, g, y, seg, lane);
+        grid_cell<false>(src + I.pop_off, dst + I.pop_off, fib_now + I.fib_off,
+                         flags_now + I.flag_off, fib_old + I.fib_off, flags_old + I.flag_off, g, y,
+                         seg, lane);
     }
 }
 
@@ -237,25 +263,26 @@ hipError_t launch_grid_step(const T* src, T* dst, const long long* fib_now, cons
 }
 
 template <typename T>
-hipError_t launch_grid_far(const T* src, T* dst, const int* flags_now, const int* flags_old,
-                           const int* near_map, int stamp, int* status, const GridArgs& g,
-                           hipStream_t s)
+hipError_t launch_grid_far(const T* src, T* dst, const long long* fib_now, const int* flags_now,
+                           long long* fib_old, int* flags_old, const int* near_map, int stamp,
+                           int* status, const GridArgs& g, hipStream_t s)
 {
     const int blocks = grid_blocks(g.ny, g.nseg);
     hipLaunchKernelGGL(k_grid_far<T>, dim3((unsigned)blocks), dim3(kSegW * 4), 0, s, src, dst,
-                       flags_now, flags_old, near_map, stamp, status, g);
+                       fib_now, flags_now, fib_old, flags_old, near_map, stamp, status, g);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_grid_near(const T* src, T* dst, const long long* fib_now, const int* flags_now,
-                            long long* fib_old, int* flags_old, const NearRect* rects, int ncap,
-                            const GridArgs& g, hipStream_t s)
+                            long long* fib_old, int* flags_old, const NearRect* rects,
+                            const CapsuleDev* caps, const InstDev* inst, int ncap, hipStream_t s)
 {
     constexpr int per_cap = 16;
     if (ncap <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_grid_near<T>, dim3((unsigned)(ncap * per_cap)), dim3(kSegW * 4), 0, s,
-                       src, dst, fib_now, flags_now, fib_old, flags_old, rects, per_cap, g);
+                       src, dst, fib_now, flags_now, fib_old, flags_old, rects, caps, inst,
+                       per_cap);
     return hipGetLastError();
 }
 
@@ -268,29 +295,18 @@ hipError_t launch_grid_near(const T* src, T* dst, const long long* fib_now, cons
 // the run padded only to a multiple of 8 tiles (no empty bands).  With
 // gridDim.x < tiles (a multiple of 8) the launch is persistent: each block
 // walks the tiles t = blockIdx.x + k * gridDim.x.
-template <typename T, int ROWS, bool OPEN, bool LIN>
+template <typename T, int ROWS, bool OPEN, bool LIN, bool FAR>
 __global__ __launch_bounds__(kSegW * 4) void k_grid_step_batch(
     const T* __restrict__ src, T* __restrict__ dst, const long long* __restrict__ fib_now,
     const int* __restrict__ flags_now, long long* __restrict__ fib_old,
     int* __restrict__ flags_old, const InstDev* __restrict__ inst,
-    const int2* __restrict__ rounds, int tiles)
+    const int2* __restrict__ rounds, int tiles, const int* __restrict__ near_map, int stamp,
+    int* status)
 {
     for (int b = blockIdx.x; b < tiles; b += gridDim.x) {
         const int2 ri = rounds[b / kNumXcd];
         const InstDev& I = inst[ri.x];
-        GridArgs g;
-        g.nx = I.nx;
-        g.ny = I.ny;
-        g.nxp = I.nxp;
-        g.nseg = I.nseg;
-        g.periodic_y = I.periodic_y;
-        g.periodic_x = I.periodic_x;
-        g.omega = I.omega;
-        g.gx = I.gx;
-        g.u_bot = I.u_bot;
-        g.u_top = I.u_top;
-        g.u_in = I.u_in;
-        g.rho_out = I.rho_out;
+        const GridArgs g = lattice_args(I);
         const int lb = b - ri.y * kNumXcd;
         int band, seg;
         if (LIN) {
@@ -307,10 +323,15 @@ __global__ __launch_bounds__(kSegW * 4) void k_grid_step_batch(
 #pragma unroll
         for (int r = 0; r < ROWS; r++) {
             const int y = y0 + 4 * r;
-            if (y < g.ny)
-                grid_cell<OPEN>(src + I.pop_off, dst + I.pop_off, fib_now + I.fib_off,
-                                flags_now + I.flag_off, fib_old + I.fib_off,
-                                flags_old + I.flag_off, g, y, seg, lane);
+            if (y >= g.ny) continue;
+            if (FAR) {  // the far part of the split step, as k_grid_far on one lattice
+                const int fidx = I.flag_off + y * g.nseg + seg;
+                if (near_map[fidx] == stamp) continue;
+                if ((flags_now[fidx] | flags_old[fidx]) && lane == 0) atomicOr(status, ST_NEAR);
+            }
+            grid_cell<OPEN>(src + I.pop_off, dst + I.pop_off, fib_now + I.fib_off,
+                            flags_now + I.flag_off, fib_old + I.fib_off, flags_old + I.flag_off, g,
+                            y, seg, lane);
         }
     }
 }
@@ -332,33 +353,39 @@ template <typename T, int R, bool LIN>
 static void launch_batch_rows(const T* src, T* dst, const long long* fib_now, const int* flags_now,
                               long long* fib_old, int* flags_old, const InstDev* inst,
                               const int2* rounds, int tiles, int grid, bool any_open,
-                              hipStream_t s)
+                              const int* near_map, int stamp, int* status, hipStream_t s)
 {
-    if (any_open)
-        hipLaunchKernelGGL((k_grid_step_batch<T, R, true, LIN>), dim3((unsigned)grid),
-                           dim3(kSegW * 4), 0, s, src, dst, fib_now, flags_now, fib_old, flags_old,
-                           inst, rounds, tiles);
+    const dim3 gd((unsigned)grid), bd(kSegW * 4);
+    if (near_map)  // far part of the split step (periodic lattices only)
+        hipLaunchKernelGGL((k_grid_step_batch<T, R, false, LIN, true>), gd, bd, 0, s, src, dst,
+                           fib_now, flags_now, fib_old, flags_old, inst, rounds, tiles, near_map,
+                           stamp, status);
+    else if (any_open)
+        hipLaunchKernelGGL((k_grid_step_batch<T, R, true, LIN, false>), gd, bd, 0, s, src, dst,
+                           fib_now, flags_now, fib_old, flags_old, inst, rounds, tiles, near_map,
+                           stamp, status);
     else
-        hipLaunchKernelGGL((k_grid_step_batch<T, R, false, LIN>), dim3((unsigned)grid),
-                           dim3(kSegW * 4), 0, s, src, dst, fib_now, flags_now, fib_old, flags_old,
-                           inst, rounds, tiles);
+        hipLaunchKernelGGL((k_grid_step_batch<T, R, false, LIN, false>), gd, bd, 0, s, src, dst,
+                           fib_now, flags_now, fib_old, flags_old, inst, rounds, tiles, near_map,
+                           stamp, status);
 }
 
 template <typename T, bool LIN>
 static hipError_t launch_batch_lin(const T* src, T* dst, const long long* fib_now,
                                    const int* flags_now, long long* fib_old, int* flags_old,
                                    const InstDev* inst, const int2* rounds, int tiles, int rows,
-                                   int grid, bool any_open, hipStream_t s)
+                                   int grid, bool any_open, const int* near_map, int stamp,
+                                   int* status, hipStream_t s)
 {
     if (rows == 1)
         launch_batch_rows<T, 1, LIN>(src, dst, fib_now, flags_now, fib_old, flags_old, inst,
-                                     rounds, tiles, grid, any_open, s);
+                                     rounds, tiles, grid, any_open, near_map, stamp, status, s);
     else if (rows == 2)
         launch_batch_rows<T, 2, LIN>(src, dst, fib_now, flags_now, fib_old, flags_old, inst,
-                                     rounds, tiles, grid, any_open, s);
+                                     rounds, tiles, grid, any_open, near_map, stamp, status, s);
     else if (rows == 4)
         launch_batch_rows<T, 4, LIN>(src, dst, fib_now, flags_now, fib_old, flags_old, inst,
-                                     rounds, tiles, grid, any_open, s);
+                                     rounds, tiles, grid, any_open, near_map, stamp, status, s);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -368,14 +395,18 @@ template <typename T>
 hipError_t launch_grid_step_batch(const T* src, T* dst, const long long* fib_now,
                                   const int* flags_now, long long* fib_old, int* flags_old,
                                   const InstDev* inst, const int2* rounds, int tiles, int rows,
-                                  bool linear, int grid, bool any_open, hipStream_t s)
+                                  bool linear, int grid, bool any_open, const int* near_map,
+                                  int stamp, int* status, hipStream_t s)
 {
     if (tiles <= 0) return hipSuccess;
     if (grid <= 0 || grid > tiles || grid % kNumXcd != 0) return hipErrorInvalidValue;
+    if (near_map && any_open) return hipErrorInvalidValue;
     return linear ? launch_batch_lin<T, true>(src, dst, fib_now, flags_now, fib_old, flags_old,
-                                              inst, rounds, tiles, rows, grid, any_open, s)
+                                              inst, rounds, tiles, rows, grid, any_open, near_map,
+                                              stamp, status, s)
                   : launch_batch_lin<T, false>(src, dst, fib_now, flags_now, fib_old, flags_old,
-                                               inst, rounds, tiles, rows, grid, any_open, s);
+                                               inst, rounds, tiles, rows, grid, any_open, near_map,
+                                               stamp, status, s);
 }
 
 // ------------------------------------------------------------ init kernel
@@ -1022,6 +1053,7 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
     a.fib_prev += cap.fib_off;
     a.fib_next += cap.fib_off;
     a.flags_next += cap.flag_off;
+    if (a.near_map) a.near_map += cap.flag_off;
     GridArgs g;
     g.nx = cap.nx;
     g.ny = cap.ny;
@@ -1733,12 +1765,14 @@ hipError_t launch_set_nodes(T* nodes, CapsuleDev* caps, int cap, int nv, int nod
                                             long long*, int*, const GridArgs&, hipStream_t);      \
     template hipError_t launch_grid_step_batch<T>(const T*, T*, const long long*, const int*,     \
                                                   long long*, int*, const InstDev*, const int2*,  \
-                                                  int, int, bool, int, bool, hipStream_t);        \
-    template hipError_t launch_grid_far<T>(const T*, T*, const int*, const int*, const int*, int, \
-                                           int*, const GridArgs&, hipStream_t);                   \
+                                                  int, int, bool, int, bool, const int*, int,     \
+                                                  int*, hipStream_t);                             \
+    template hipError_t launch_grid_far<T>(const T*, T*, const long long*, const int*,            \
+                                           long long*, int*, const int*, int, int*,               \
+                                           const GridArgs&, hipStream_t);                         \
     template hipError_t launch_grid_near<T>(const T*, T*, const long long*, const int*,           \
-                                            long long*, int*, const NearRect*, int,               \
-                                            const GridArgs&, hipStream_t);                        \
+                                            long long*, int*, const NearRect*, const CapsuleDev*, \
+                                            const InstDev*, int, hipStream_t);                    \
     template hipError_t launch_contact<T>(const ContactArgs<T>&, hipStream_t);                   \
     template hipError_t launch_spread_tape<T>(const SpreadTapeArgs<T>&, int, hipStream_t);         \
     template hipError_t contact_set_lds_limit<T>(int);                                            \

@@ -291,3 +291,25 @@ def test_tile_arguments_are_checked():
     with pytest.raises(lbib.LbibError) as e:
         b.autotune(0)
     assert e.value.code == lbib.EINVAL
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("rows,linear,resident", [(1, False, 0), (2, True, 0), (4, True, 8)])
+def test_overlapped_batch_is_bit_identical(rows, linear, resident):
+    """The near / far split over a batch (each capsule's near region on its own
+    lattice, the far part as the batched pass in the chosen tile shape, beside
+    the IB launch) gives the bits of the single pass: a ragged channel with two
+    capsules, a capsule-free Couette channel, a periodic box and seeded
+    ensemble channels."""
+    cfgs = _mixed_lattices() + wl.ensemble(seed=6, n_inst=5)
+    a, b = lbib.Batch(cfgs), lbib.Batch(cfgs)
+    a.set_overlap(True)
+    b.set_overlap(False)
+    a.set_tile(rows, resident, linear)
+    for chunk in (1, 25, 34):
+        a.set_timing(chunk == 34)  # the last chunk counts the near launches
+        a.step(chunk)
+        b.step(chunk)
+    assert a.get_timing()["near_launches"] == 34  # the split did run
+    assert a.check() == 0 and b.check() == 0
+    _same_batches(a, b, len(cfgs))
