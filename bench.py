@@ -408,7 +408,7 @@ def main() -> int:
         side["biconcave_1024x256_mlups"] = round(c2r["mlups"], 1)
         ens = bench_ensemble(min(args.steps, 400), args.warmup, 20)
         log(f"ensemble: batched {ens['mlups']:.0f} MLUPS ({ens['ms_per_step']:.3f} ms/step, "
-            f"single pass {ens['single_pass_ms_per_step']:.3f}, "
+            f"{ens['overlapped_ms_per_step']:.3f} split near / far, "
             f"{ens['graph_ms_per_step']:.3f} with graph replays, "
             f"grid {ens['grid_kernel_us']:.1f} us, IB {ens['ib_kernel_us']:.1f} us), "
             f"per-simulation loop {ens['loop_ms_per_step']:.3f} ms/step, "
