@@ -267,6 +267,7 @@ hipError_t launch_grid_far(const T* src, T* dst, const long long* fib_now, const
                            long long* fib_old, int* flags_old, const int* near_map, int stamp,
                            int* status, const GridArgs& g, hipStream_t s)
 {
+    static_assert(kGridRowsPerThread == 1, "k_grid_far takes one row per thread");
     const int blocks = grid_blocks(g.ny, g.nseg);
     hipLaunchKernelGGL(k_grid_far<T>, dim3((unsigned)blocks), dim3(kSegW * 4), 0, s, src, dst,
                        fib_now, flags_now, fib_old, flags_old, near_map, stamp, status, g);
