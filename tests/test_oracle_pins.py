@@ -350,6 +350,34 @@ def test_hydro_piecewise_shear(orc):
     np.testing.assert_allclose(fext, [[-nu * (g1 - g2) * L, 0]] * 2, atol=1e-15)
 
 
+# ---------------------------------------------------------------- P12 -------
+
+def _area_drift(orc, mode, ka, steps):
+    cfg = wl.shear_capsule(mode=mode, g_num=0.1)
+    cfg["capsules"][0]["ka"] = ka
+    sim = orc.Sim(cfg)
+    A0 = sim.diag(0)["A0"]
+    worst = 0.0
+    for _ in range(steps // 500):
+        sim.step(500)
+        worst = max(worst, abs(sim.diag(0)["area"] / A0 - 1.0))
+    assert sim.status == 0
+    return worst
+
+
+@pytest.mark.parametrize("mode,steps", [("kinematic", 6000), ("dynamic", 3000)])
+def test_p12_area_penalty_limits_the_drift(orc, mode, steps):
+    """Area conservation (Eq. 14 with k_a = 1): a capsule sheared at G = 0.1
+    keeps |A / A0 - 1| below 1e-4, and the penalty more than halves the drift
+    of the same run without it.  A penalty with the wrong sign or scale would
+    widen the drift instead.  (Dynamic: 3000 steps, inside the stable period
+    of the Dynamic loop.)"""
+    with_penalty = _area_drift(orc, mode, 1.0, steps)
+    without = _area_drift(orc, mode, 0.0, steps)
+    assert with_penalty < 1e-4
+    assert with_penalty < 0.5 * without
+
+
 # ---------------------------------------------------------------- P13 -------
 
 @pytest.mark.parametrize("mode", ["kinematic", "dynamic"])
