@@ -394,7 +394,8 @@ def main() -> int:
         log(f"fused: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.4f} ms/step; grid kernel "
             f"{grid_ms * 1e3:.1f} us ({achieved:.0f} GB/s), IB kernel {ib_ms * 1e3:.1f} us")
 
-    # grid-only and the 1024 x 256 biconcave channel, reported beside the main line
+    # grid-only, the 1024 x 256 biconcave channel and the 2048 x 512 channel with
+    # 32 inertial capsules, reported beside the main line
     side = {}
     if not args.only_fused:
         g = time_gpu(wl.grid_bench(n=args.n), args.steps, args.warmup, timing=False)
@@ -406,6 +407,12 @@ def main() -> int:
         del c2r["sim"]
         log(f"1024x256 biconcave channel: {c2r['mlups']:.0f} MLUPS")
         side["biconcave_1024x256_mlups"] = round(c2r["mlups"], 1)
+        c3 = wl.inertial_capsules(seed=0, steps=args.steps)
+        c3r = time_gpu(c3, args.steps, args.warmup, timing=False)
+        del c3r["sim"]
+        log(f"2048x512 channel, 32 inertial capsules: {c3r['mlups']:.0f} MLUPS "
+            f"({c3r['ms_per_step'] * 1e3:.1f} us/step)")
+        side["inertial_2048x512_mlups"] = round(c3r["mlups"], 1)
         ens = bench_ensemble(min(args.steps, 400), args.warmup, 20)
         log(f"ensemble: batched {ens['mlups']:.0f} MLUPS ({ens['ms_per_step']:.3f} ms/step, "
             f"{ens['overlapped_ms_per_step']:.3f} split near / far, "

@@ -870,6 +870,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_ib_adj(IBAdjArgs<T> a)
         return;
     }
     const long long refx = (long long)rnx, refy = (long long)rny;
+    // the reference point on the periodic axes (x always periodic here)
+    const int wrx = wrap_ref(refx, g.nx), wry = g.periodic_y ? wrap_ref(refy, g.ny) : 0;
     {
         IBArgs<T> ia;
         ia.pops = a.pops + cap.pop_off;
@@ -911,11 +913,16 @@ __global__ __launch_bounds__(kAdjThreads) void k_ib_adj(IBAdjArgs<T> a)
                 double lfk[9][2];
                 double sLx = 0, sLy = 0, lcv = 0;
                 for (int k = 0; k < 9; k++) {
-                    long long gy = refy + cy + k / 3 - 1, gxx = refx + cx + k % 3 - 1;
                     lfk[k][0] = lfk[k][1] = 0.0;
-                    if (g.periodic_y) gy = ((gy % g.ny) + g.ny) % g.ny;
-                    else if (gy < 1 || gy > g.ny - 2) continue;
-                    gxx = ((gxx % g.nx) + g.nx) % g.nx;
+                    int gy;
+                    if (g.periodic_y) {
+                        gy = wrap_add(wry, cy + k / 3 - 1, g.ny);
+                    } else {
+                        const long long yv = refy + cy + k / 3 - 1;
+                        if (yv < 1 || yv > g.ny - 2) continue;
+                        gy = (int)yv;
+                    }
+                    const int gxx = wrap_add(wrx, cx + k % 3 - 1, g.nx);
                     const size_t cell = (size_t)gy * g.nxp + (size_t)gxx;
                     lfk[k][0] = (double)lft[2 * cell];
                     lfk[k][1] = (double)lft[2 * cell + 1];
@@ -966,11 +973,15 @@ __global__ __launch_bounds__(kAdjThreads) void k_ib_adj(IBAdjArgs<T> a)
                 const double Fx = S.Fvx[v], Fy = S.Fvy[v];
                 mls_dual<false>(S.Xn[v], S.Yn[v], cx, cy,
                                 [&](int k, const Dual<2>& phi, const Dual<2>&, const Dual<2>&) {
-                                    long long gy = refy + cy + k / 3 - 1;
-                                    long long gxx = refx + cx + k % 3 - 1;
-                                    if (g.periodic_y) gy = ((gy % g.ny) + g.ny) % g.ny;
-                                    else if (gy < 1 || gy > g.ny - 2) return;
-                                    gxx = ((gxx % g.nx) + g.nx) % g.nx;
+                                    int gy;
+                                    if (g.periodic_y) {
+                                        gy = wrap_add(wry, cy + k / 3 - 1, g.ny);
+                                    } else {
+                                        const long long yv = refy + cy + k / 3 - 1;
+                                        if (yv < 1 || yv > g.ny - 2) return;
+                                        gy = (int)yv;
+                                    }
+                                    const int gxx = wrap_add(wrx, cx + k % 3 - 1, g.nx);
                                     const size_t cell = (size_t)gy * g.nxp + (size_t)gxx;
                                     const double lx_ = (double)lft[2 * cell];
                                     const double ly_ = (double)lft[2 * cell + 1];
@@ -1072,15 +1083,16 @@ __global__ __launch_bounds__(kAdjThreads) void k_ib_adj(IBAdjArgs<T> a)
     // ---- moments adjoint -> lambda P^n (transpose of the pull), lambda F^{n-1}
     {
         const int ncell = P.W * P.H;
+        const int pbx = wrap_ref(refx + P.ox, g.nx);
+        const int pby = g.periodic_y ? wrap_ref(refy + P.oy, g.ny) : 0;
         for (int i = tid; i < ncell; i += nt) {
             const T Ld = S.Ld[i], Lu = S.Lu[i], Lv = S.Lv[i];
             if (Ld == T(0) && Lu == T(0) && Lv == T(0)) continue;
             if (isnan(S.pd[i])) continue;
             const int lxi = i % P.W, lyi = i / P.W;
-            long long wy = refy + P.oy + lyi;
-            if (g.periodic_y) wy = ((wy % g.ny) + g.ny) % g.ny;
-            long long wx = refx + P.ox + lxi;
-            wx = ((wx % g.nx) + g.nx) % g.nx;
+            const long long wy = g.periodic_y ? (long long)wrap_add(pby, lyi, g.ny)
+                                              : refy + P.oy + lyi;
+            const int wx = wrap_add(pbx, lxi, g.nx);
             const T rho = T(1) + S.pd[i];
             const T ux = S.pu[i], uy = S.pv[i];
             const T irho = T(1) / rho;

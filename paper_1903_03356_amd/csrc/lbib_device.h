@@ -233,6 +233,26 @@ __device__ __forceinline__ void stage_store(const Patch<T>& P, int i, const T (&
     P.uy[i] = (jy + T(0.5) * Fy) * irho;
 }
 
+// Lattice coordinate ref + off on a periodic axis of n nodes.  The reference
+// point (64-bit, unwrapped) is reduced once per call site with wrap_ref; each
+// coordinate then takes an add and at most one correction while |off| < n, and
+// the remainder only beyond that.  (A 64-bit remainder is a long software
+// sequence on the GPU.)
+__device__ __forceinline__ int wrap_ref(long long ref, int n)
+{
+    const long long r = ref % n;
+    return (int)(r < 0 ? r + n : r);
+}
+
+__device__ __forceinline__ int wrap_add(int base, int off, int n)
+{
+    int v = base + off;
+    if (v < 0) v += n;
+    else if (v >= n) v -= n;
+    if ((unsigned)v >= (unsigned)n) v = wrap_ref(v, n);
+    return v;
+}
+
 // K patch cells first, first + stride, ..., with the loads of all of them
 // issued before any is used (one memory latency for K cells).  A cell on a
 // wall row or an open end column is marked NaN; cells past the patch store
@@ -246,6 +266,11 @@ __device__ __forceinline__ void stage_cells(const IBArgs<T>& a, const GridArgs& 
 {
     const int ncell = P.W * P.H;
     const size_t plane = (size_t)g.ny * g.nxp;
+    const int bx = g.periodic_x ? wrap_ref(refx + P.ox, g.nx) : 0;
+    const int by = g.periodic_y ? wrap_ref(refy + P.oy, g.ny) : 0;
+    // patch column and row of cell `first`, advanced by `stride` per k
+    int lx = first % P.W, ly = first / P.W;
+    const int sx = stride % P.W, sy = stride / P.W;
     T s[K][9];
     long long fx[K], fy[K];
     int state[K];  // 0: past the patch, 1: off the lattice, 2: staged
@@ -255,18 +280,33 @@ __device__ __forceinline__ void stage_cells(const IBArgs<T>& a, const GridArgs& 
         int x = 1, y = 1;
         state[k] = 0;
         if (i < ncell) {
-            const int lx = i % P.W, ly = i / P.W;
-            long long wy = refy + P.oy + ly, wx = refx + P.ox + lx;
             bool on = true;
-            if (g.periodic_y) wy = ((wy % g.ny) + g.ny) % g.ny;
-            else on = wy >= 1 && wy <= g.ny - 2;
-            if (g.periodic_x) wx = ((wx % g.nx) + g.nx) % g.nx;
-            else on = on && wx >= 1 && wx <= g.nx - 2;
+            int wy, wx;
+            if (g.periodic_y) {
+                wy = wrap_add(by, ly, g.ny);
+            } else {
+                const long long v = refy + P.oy + ly;
+                on = v >= 1 && v <= g.ny - 2;
+                wy = (int)v;
+            }
+            if (g.periodic_x) {
+                wx = wrap_add(bx, lx, g.nx);
+            } else {
+                const long long v = refx + P.ox + lx;
+                on = on && v >= 1 && v <= g.nx - 2;
+                wx = (int)v;
+            }
             state[k] = on ? 2 : 1;
             if (on) {
-                x = (int)wx;
-                y = (int)wy;
+                x = wx;
+                y = wy;
             }
+        }
+        lx += sx;
+        ly += sy;
+        if (lx >= P.W) {
+            lx -= P.W;
+            ly++;
         }
         const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
         const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;

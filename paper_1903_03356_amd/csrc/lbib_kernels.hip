@@ -779,17 +779,42 @@ __device__ __forceinline__ long long to_fix(T v, int& st)
 // One spreading contribution (Dynamic step 3, Kinematic step iii): the value
 // (vx, vy) = c phi_k F goes to support node k of the 3x3 support centred on
 // (cx, cy), relative to the reference point.
+// (bx, by): the reference point reduced onto periodic axes (wrap_ref).
+struct SpreadRef {
+    long long rx, ry;
+    int bx, by;
+};
+
+__device__ __forceinline__ SpreadRef spread_ref(const GridArgs& g, long long refx, long long refy)
+{
+    SpreadRef r;
+    r.rx = refx;
+    r.ry = refy;
+    r.bx = g.periodic_x ? wrap_ref(refx, g.nx) : 0;
+    r.by = g.periodic_y ? wrap_ref(refy, g.ny) : 0;
+    return r;
+}
+
 template <typename T>
-__device__ __forceinline__ void spread_one(const IBArgs<T>& a, const GridArgs& g, long long refx,
-                                           long long refy, int cx, int cy, int k, T vx, T vy,
+__device__ __forceinline__ void spread_one(const IBArgs<T>& a, const GridArgs& g,
+                                           const SpreadRef& r, int cx, int cy, int k, T vx, T vy,
                                            int& st)
 {
-    long long gy = refy + cy + k / 3 - 1;
-    if (g.periodic_y) gy = ((gy % g.ny) + g.ny) % g.ny;
-    else if (gy < 1 || gy > g.ny - 2) { st |= ST_WALL; return; }
-    long long gx = refx + cx + k % 3 - 1;
-    if (g.periodic_x) gx = ((gx % g.nx) + g.nx) % g.nx;
-    else if (gx < 1 || gx > g.nx - 2) { st |= ST_WALL; return; }
+    int gy, gx;
+    if (g.periodic_y) {
+        gy = wrap_add(r.by, cy + k / 3 - 1, g.ny);
+    } else {
+        const long long v = r.ry + cy + k / 3 - 1;
+        if (v < 1 || v > g.ny - 2) { st |= ST_WALL; return; }
+        gy = (int)v;
+    }
+    if (g.periodic_x) {
+        gx = wrap_add(r.bx, cx + k % 3 - 1, g.nx);
+    } else {
+        const long long v = r.rx + cx + k % 3 - 1;
+        if (v < 1 || v > g.nx - 2) { st |= ST_WALL; return; }
+        gx = (int)v;
+    }
     const long long fx = to_fix(vx, st), fy = to_fix(vy, st);
     const size_t cell = (size_t)gy * g.nxp + (size_t)gx;
     unsigned long long* dst = reinterpret_cast<unsigned long long*>(a.fib_next + 2 * cell);
@@ -820,10 +845,11 @@ __device__ __forceinline__ void spread_cached(const IBArgs<T>& a, const GridArgs
 {
     const T* base = S.t[0];
     const size_t stride = S.t[1] - S.t[0];  // the scratch arrays are contiguous
+    const SpreadRef r = spread_ref(g, refx, refy);
     for (int w = threadIdx.x; w < 9 * nv; w += blockDim.x) {
         const int v = w / 9, k = w - 9 * v;
         const T phi = base[(size_t)(k < 8 ? k : 12) * stride + v];
-        spread_one(a, g, refx, refy, (int)S.t[10][v], (int)S.t[11][v], k, phi * S.t[8][v],
+        spread_one(a, g, r, (int)S.t[10][v], (int)S.t[11][v], k, phi * S.t[8][v],
                    phi * S.t[9][v], st);
     }
 }
@@ -1444,6 +1470,7 @@ __global__ __launch_bounds__(kIBThreads) void k_spread_tape(SpreadTapeArgs<T> a)
     const int off = cap.node_offset;
     const T* TN = a.tape;
     int st = 0;
+    const SpreadRef r = spread_ref(g, refx, refy);
     for (int v = threadIdx.x; v < cap.nv; v += blockDim.x) {
         int cx, cy;
         T phi[9];
@@ -1451,7 +1478,7 @@ __global__ __launch_bounds__(kIBThreads) void k_spread_tape(SpreadTapeArgs<T> a)
                       nullptr);
         const T fx = TN[kTapeFX * NS + off + v], fy = TN[kTapeFY * NS + off + v];
 #pragma unroll
-        for (int k = 0; k < 9; k++) spread_one(ia, g, refx, refy, cx, cy, k, phi[k] * fx, phi[k] * fy, st);
+        for (int k = 0; k < 9; k++) spread_one(ia, g, r, cx, cy, k, phi[k] * fx, phi[k] * fy, st);
     }
     if (st) atomicOr(a.status, st);
 }
