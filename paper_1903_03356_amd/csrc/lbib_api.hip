@@ -329,8 +329,11 @@ static hipEvent_t take_event(lbib_ctx* c)
         c->pool.pop_back();
         return e;
     }
+    // timing only: no system-scope fence, whose cache write-back would land
+    // inside the measured interval (lbib_get_timing synchronises the stream
+    // itself before it reads the events)
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
@@ -889,10 +892,14 @@ template <typename T>
 static lbib_status step_overlap_t(lbib_ctx* c, int nsteps)
 {
     if (!c->s_far) {
+        // The events only order the two streams of this device: a device-scope
+        // release and acquire suffice (the system-scope fence, there for host
+        // visibility, costs a cache write-back at every hand-off).
+        const unsigned ev = hipEventDisableTiming | hipEventDisableSystemFence;
         HIPCHK(c, hipStreamCreateWithFlags(&c->s_far, hipStreamNonBlocking));
-        HIPCHK(c, hipEventCreateWithFlags(&c->e_ib, hipEventDisableTiming));
-        HIPCHK(c, hipEventCreateWithFlags(&c->e_far[0], hipEventDisableTiming));
-        HIPCHK(c, hipEventCreateWithFlags(&c->e_far[1], hipEventDisableTiming));
+        HIPCHK(c, hipEventCreateWithFlags(&c->e_ib, ev));
+        HIPCHK(c, hipEventCreateWithFlags(&c->e_far[0], ev));
+        HIPCHK(c, hipEventCreateWithFlags(&c->e_far[1], ev));
     }
     {
         const long long n = c->steps;
@@ -1650,9 +1657,9 @@ static lbib_status autotune_t(lbib_ctx* c, int launches, double* us)
     T* dst = static_cast<T*>(pops(c, n + 1));
     long long* f = fib(c, n);
     int* fl = flags(c, n);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIPCHK(c, hipEventCreate(&e0));
-    if (hipEventCreate(&e1) != hipSuccess) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;  // timing only, as take_event's
+    HIPCHK(c, hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    if (hipEventCreateWithFlags(&e1, hipEventDisableSystemFence) != hipSuccess) {
         (void)hipEventDestroy(e0);
         return fail(c, LBIB_EDEVICE, "hipEventCreate failed");
     }
