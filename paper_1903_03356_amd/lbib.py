@@ -333,7 +333,7 @@ class Sim:
 
     def set_overlap(self, enable) -> None:
         """True / False force the overlapped schedule on / off; None restores
-        the automatic choice (large lattices only)."""
+        the automatic choice (a single lattice of 2^22 cells or more)."""
         v = -1 if enable is None else (1 if enable else 0)
         _check(load().lbib_set_overlap(self.h, v), self.h)
 
