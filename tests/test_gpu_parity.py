@@ -230,6 +230,31 @@ def test_fused_bench_full_size_single_step():
     log("fused 4096 single step: done")
 
 
+def test_overlapped_schedule_full_size_is_bit_identical():
+    """The benchmark workload (4096 x 4096, 32 capsules, FP32) in the schedule
+    the benchmark times (the automatic near / far split, far part on a second
+    stream) against the single pass: the same bits after 60 steps."""
+    from paper_1903_03356_amd import lbib
+    cfg = wl.fused_bench(seed=0, n=4096)
+    log("fused 4096 split vs single pass: 60 steps each")
+    a = lbib.Sim(cfg)
+    b = lbib.Sim(cfg)
+    a.set_overlap(None)  # automatic: this size splits
+    b.set_overlap(False)
+    a.set_timing(True)
+    for chunk in (1, 27, 32):
+        a.step(chunk)
+        b.step(chunk)
+    assert a.get_timing()["near_launches"] == 60
+    assert a.check() == 0 and b.check() == 0
+    assert np.array_equal(a.force(), b.force())
+    for c in range(len(cfg["capsules"])):
+        for x, y in zip(a.capsule(c), b.capsule(c)):
+            assert np.array_equal(x, y), c
+    assert np.array_equal(a.pops_dev(), b.pops_dev())
+    log("fused 4096 split vs single pass: done")
+
+
 def test_determinism():
     """The fixed-point spreading makes two identical runs bit-identical."""
     from paper_1903_03356_amd import lbib
