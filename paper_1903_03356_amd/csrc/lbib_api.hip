@@ -852,10 +852,13 @@ static lbib_status launch_contact_t(lbib_ctx* c)
     return LBIB_OK;
 }
 
+// Far part of step n.  Untimed single-lattice launches mark e_far(n)
+// complete with the kernel itself; everything else records it behind.
 template <typename T>
 static hipError_t do_far(lbib_ctx* c, void* p)
 {
     const long long n = *static_cast<const long long*>(p);
+    const bool own_event = c->L.inst.size() == 1 && !c->timing;
     if (c->L.inst.size() > 1)
         return launch_batch_shape<T>(c, static_cast<const T*>(pops(c, n)),
                                      static_cast<T*>(pops(c, n + 1)), fib(c, n), flags(c, n),
@@ -864,7 +867,8 @@ static hipError_t do_far(lbib_ctx* c, void* p)
     const GridArgs g = grid_args(c->L.inst[0]);
     return launch_grid_far<T>(static_cast<const T*>(pops(c, n)), static_cast<T*>(pops(c, n + 1)),
                               fib(c, n), flags(c, n), fib(c, n + 1), flags(c, n + 1),
-                              near_map(c, n), step_stamp(n), status_word(c), g, c->s_far);
+                              near_map(c, n), step_stamp(n), status_word(c), g, c->s_far,
+                              own_event ? c->e_far[n & 1] : nullptr);
 }
 
 template <typename T>
@@ -915,7 +919,8 @@ static lbib_status step_overlap_t(lbib_ctx* c, int nsteps)
         lbib_status s = launch_timed<T>(c, 0, do_far<T>, &nn, c->s_far);
         if (s != LBIB_OK) return s;
         if (k > 0) HIPCHK(c, hipStreamWaitEvent(c->stream, c->e_far[(n - 1) & 1], 0));
-        HIPCHK(c, hipEventRecord(c->e_far[n & 1], c->s_far));
+        if (c->L.inst.size() > 1 || c->timing)  // otherwise the far launch marked it
+            HIPCHK(c, hipEventRecord(c->e_far[n & 1], c->s_far));
         s = launch_timed<T>(c, 2, do_near<T>, &nn);
         if (s != LBIB_OK) return s;
         IBLaunch<T> q{n + 1, k + 1 < nsteps ? (PH_B | PH_A) : PH_B, k + 1 < nsteps};

@@ -168,7 +168,8 @@ hipError_t launch_grid_step_batch(const T* src, T* dst, const long long* fib_now
 template <typename T>
 hipError_t launch_grid_far(const T* src, T* dst, const long long* fib_now, const int* flags_now,
                            long long* fib_old, int* flags_old, const int* near_map, int stamp,
-                           int* status, const GridArgs& g, hipStream_t s);
+                           int* status, const GridArgs& g, hipStream_t s,
+                           hipEvent_t done = nullptr);
 template <typename T>
 hipError_t launch_grid_near(const T* src, T* dst, const long long* fib_now, const int* flags_now,
                             long long* fib_old, int* flags_old, const NearRect* rects,

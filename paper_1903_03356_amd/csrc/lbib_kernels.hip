@@ -14,6 +14,8 @@
 // the force field is bit-reproducible.
 #include "lbib_device.h"
 
+#include <hip/hip_ext.h>
+
 #include <math.h>
 
 namespace lbib {
@@ -262,16 +264,26 @@ hipError_t launch_grid_step(const T* src, T* dst, const long long* fib_now, cons
     return hipGetLastError();
 }
 
+// `done`, if given, is marked complete with the kernel itself (the launch's
+// stop event), in place of a marker packet recorded behind it on the stream.
 template <typename T>
 hipError_t launch_grid_far(const T* src, T* dst, const long long* fib_now, const int* flags_now,
                            long long* fib_old, int* flags_old, const int* near_map, int stamp,
-                           int* status, const GridArgs& g, hipStream_t s)
+                           int* status, const GridArgs& g, hipStream_t s, hipEvent_t done)
 {
     static_assert(kGridRowsPerThread == 1, "k_grid_far takes one row per thread");
     const int blocks = grid_blocks(g.ny, g.nseg);
-    hipLaunchKernelGGL(k_grid_far<T>, dim3((unsigned)blocks), dim3(kSegW * 4), 0, s, src, dst,
-                       fib_now, flags_now, fib_old, flags_old, near_map, stamp, status, g);
-    return hipGetLastError();
+    if (!done) {
+        hipLaunchKernelGGL(k_grid_far<T>, dim3((unsigned)blocks), dim3(kSegW * 4), 0, s, src, dst,
+                           fib_now, flags_now, fib_old, flags_old, near_map, stamp, status, g);
+        return hipGetLastError();
+    }
+    GridArgs ga = g;
+    void* args[] = {&src, &dst, &fib_now, &flags_now, &fib_old, &flags_old, &near_map, &stamp,
+                    &status, &ga};
+    return hipExtLaunchKernel(reinterpret_cast<const void*>(&k_grid_far<T>),
+                              dim3((unsigned)blocks), dim3(kSegW * 4), args, 0, s, nullptr, done,
+                              0);
 }
 
 template <typename T>
@@ -1797,7 +1809,7 @@ hipError_t launch_set_nodes(T* nodes, CapsuleDev* caps, int cap, int nv, int nod
                                                   int*, hipStream_t);                             \
     template hipError_t launch_grid_far<T>(const T*, T*, const long long*, const int*,            \
                                            long long*, int*, const int*, int, int*,               \
-                                           const GridArgs&, hipStream_t);                         \
+                                           const GridArgs&, hipStream_t, hipEvent_t);             \
     template hipError_t launch_grid_near<T>(const T*, T*, const long long*, const int*,           \
                                             long long*, int*, const NearRect*, const CapsuleDev*, \
                                             const InstDev*, int, hipStream_t);                    \
