@@ -402,6 +402,12 @@ def main() -> int:
         log(f"grid only: {g['mlups']:.0f} MLUPS")
         side["grid_only_mlups"] = round(g["mlups"], 1)
         del g["sim"]
+        g64 = time_gpu(wl.grid_bench(n=args.n, real_bytes=8), args.steps, args.warmup, timing=False)
+        del g64["sim"]
+        frac64 = 144 * args.n * args.n / (g64["ms_per_step"] * 1e-3) / 1e9 / PEAK_HBM_GBS
+        log(f"grid only, FP64: {g64['mlups']:.0f} MLUPS ({frac64 * 100:.1f} % of HBM peak at 144 B/cell)")
+        side["grid_only_fp64_mlups"] = round(g64["mlups"], 1)
+        side["grid_only_fp64_hbm_fraction"] = round(frac64, 4)
         c2 = wl.poiseuille_biconcave(1e-2, steps=args.steps)
         c2r = time_gpu(c2, args.steps, args.warmup, timing=False)
         del c2r["sim"]

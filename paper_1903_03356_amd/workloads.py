@@ -268,10 +268,11 @@ def fused_bench(seed: int = 0, n: int = 4096, n_caps: int = 32, steps: int = 100
                  body_force_x=g, init_profile=INIT_POISEUILLE, capsules=caps)
 
 
-def grid_bench(n: int = 4096, tau: float = 0.8, u_max: float = 0.02, steps: int = 1000) -> Dict[str, Any]:
+def grid_bench(n: int = 4096, tau: float = 0.8, u_max: float = 0.02, steps: int = 1000,
+               real_bytes: int = 4) -> Dict[str, Any]:
     """n x n channel without capsules (grid-only roofline case)."""
     g = poiseuille_body_force(tau, n, u_max)
-    return _base(f"grid{n}x{n}", n, n, tau, 4, "dynamic", steps,
+    return _base(f"grid{n}x{n}", n, n, tau, real_bytes, "dynamic", steps,
                  body_force_x=g, init_profile=INIT_POISEUILLE)
 
 
