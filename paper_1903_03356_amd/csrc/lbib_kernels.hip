@@ -866,6 +866,72 @@ __device__ __forceinline__ void spread_cached(const IBArgs<T>& a, const GridArgs
     }
 }
 
+// The same spreading through a pre-sum over the patch box in LDS: each
+// (node, support node) contribution is added there as 64-bit fixed point
+// (integer sums, so their order does not matter and the force level gets the
+// same bits), then every touched cell adds its two sums to the level with one
+// pair of global atomics and raises its segment flag.  The sums take the
+// patch arrays (dead once the forcing has interpolated); the caller checks
+// that 20 bytes per patch cell fit there.  A contribution outside the box
+// goes straight to the level.
+template <typename T>
+__device__ __forceinline__ void spread_patch(const IBArgs<T>& a, const GridArgs& g,
+                                             const Scratch<T>& S, const Patch<T>& P, int nv,
+                                             long long refx, long long refy, int& st)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int ncell = P.W * P.H;
+    unsigned long long* sx = reinterpret_cast<unsigned long long*>(P.drho);
+    unsigned long long* sy = sx + ncell;
+    int* touched = reinterpret_cast<int*>(sy + ncell);
+    for (int i = tid; i < ncell; i += nt) {
+        sx[i] = 0;
+        sy[i] = 0;
+        touched[i] = 0;
+    }
+    __syncthreads();
+    const T* base = S.t[0];
+    const size_t stride = S.t[1] - S.t[0];  // the scratch arrays are contiguous
+    const SpreadRef r = spread_ref(g, refx, refy);
+    for (int w = tid; w < 9 * nv; w += nt) {
+        const int v = w / 9, k = w - 9 * v;
+        const T phi = base[(size_t)(k < 8 ? k : 12) * stride + v];
+        const int cx = (int)S.t[10][v], cy = (int)S.t[11][v];
+        const T vx = phi * S.t[8][v], vy = phi * S.t[9][v];
+        int idx;
+        if (!patch_index(P, cx, cy, k, idx)) {
+            spread_one(a, g, r, cx, cy, k, vx, vy, st);
+            continue;
+        }
+        if (!g.periodic_y) {  // walls: as spread_one
+            const long long yv = r.ry + cy + k / 3 - 1;
+            if (yv < 1 || yv > g.ny - 2) { st |= ST_WALL; continue; }
+        }
+        if (!g.periodic_x) {
+            const long long xv = r.rx + cx + k % 3 - 1;
+            if (xv < 1 || xv > g.nx - 2) { st |= ST_WALL; continue; }
+        }
+        const long long fx = to_fix(vx, st), fy = to_fix(vy, st);
+        atomicAdd(&sx[idx], (unsigned long long)fx);
+        atomicAdd(&sy[idx], (unsigned long long)fy);
+        touched[idx] = 1;
+    }
+    __syncthreads();
+    const int bx = g.periodic_x ? wrap_ref(refx + P.ox, g.nx) : 0;
+    const int by = g.periodic_y ? wrap_ref(refy + P.oy, g.ny) : 0;
+    for (int i = tid; i < ncell; i += nt) {
+        if (!touched[i]) continue;
+        const int lx = i % P.W, ly = i / P.W;
+        const int gx = g.periodic_x ? wrap_add(bx, lx, g.nx) : (int)(refx + P.ox + lx);
+        const int gy = g.periodic_y ? wrap_add(by, ly, g.ny) : (int)(refy + P.oy + ly);
+        const size_t cell = (size_t)gy * g.nxp + (size_t)gx;
+        unsigned long long* dst = reinterpret_cast<unsigned long long*>(a.fib_next + 2 * cell);
+        if (sx[i]) atomicAdd(dst, sx[i]);
+        if (sy[i]) atomicAdd(dst + 1, sy[i]);
+        a.flags_next[gy * g.nseg + gx / kSegW] = 1;
+    }
+}
+
 // Sec. 3 diagnostics of the polygon (FP64): area, perimeter, centroid, central
 // second moments of area -> Taylor deformation of the equivalent ellipse,
 // swelling ratio, perimeter and area change.
@@ -1409,7 +1475,13 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
             }
         }
         __syncthreads();
-        spread_cached(a, g, S, nv, refx, refy, st);
+        // pre-sum in LDS where the staged patch box holds the sums (fewer
+        // global atomics: 388 capsules 42.7 -> 30.0 us per launch, 32 capsules
+        // 25.2 -> 24.3 us; a lone capsule pays about 0.3 us for the barriers)
+        if (need_field && (size_t)P.W * P.H * 20 <= (size_t)3 * a.patch_cap * sizeof(T))
+            spread_patch(a, g, S, P, nv, refx, refy, st);
+        else
+            spread_cached(a, g, S, nv, refx, refy, st);
     }
     if (prime && tid == 0) a.caps[c].primed = 1;
     if (need_field && a.hints && tid == 0) a.hints[c] = make_int4(P.ox, P.oy, P.W, P.H);
