@@ -1419,12 +1419,11 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
         }
         return LBIB_OK;
     };
-    // zero the force accumulators and flags of grid slots 1 .. m
+    // zero the force accumulators and flags of grid slots 1 .. m with one fill
+    // over the whole slot range (their populations are written before they are
+    // read), in place of one short fill launch per slot
     auto clear_slots = [&](int m) -> hipError_t {
-        hipError_t e = hipSuccess;
-        for (int r = 1; r <= m && e == hipSuccess; r++)
-            e = hipMemsetAsync(gF(r), 0, A.fib + A.flags, st);
-        return e;
+        return m > 0 ? hipMemsetAsync(gslot(1), 0, A.gslot * (size_t)m, st) : hipSuccess;
     };
     auto seg_lo = [&](int s) { return s * K; };
     auto seg_hi = [&](int s) { return std::min(s * K + K, N); };
