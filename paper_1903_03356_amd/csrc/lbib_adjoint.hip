@@ -286,7 +286,7 @@ __device__ __forceinline__ void zou_he_vjp(T sb[9], T& Fbx, T uw, bool top)
 __device__ __forceinline__ void block_add_partial(double v, double* slot)
 {
     __shared__ double part[4];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    v = wave_sum(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) part[wave] = v;
     __syncthreads();
@@ -415,7 +415,7 @@ __global__ void k_reduce_sum(const double* v, int n, double* out)
     __shared__ double part[kIBThreads / 64];
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) s += v[i];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {

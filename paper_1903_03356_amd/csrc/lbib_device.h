@@ -337,16 +337,75 @@ __device__ __forceinline__ void stage_cells(const IBArgs<T>& a, const GridArgs& 
     }
 }
 
+// Wave-wide reductions with DPP lane moves (register to register, no LDS
+// round trip): exchange within lane pairs and quads (quad_perm), mirror within
+// half-rows and rows of 16, then the row broadcasts of lanes 15 and 31 carry
+// the row results into the last row.  Lane 63 ends with the result, which is
+// broadcast from there; the combination order is fixed by the lane pattern.
+// Call with the whole wave active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_move(int old, int v)
+{
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xf, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move_f64(double v)  // rows outside ROWS read 0
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_move<CTRL, ROWS>(0, (int)(unsigned int)(b & 0xffffffffLL));
+    const int hi = dpp_move<CTRL, ROWS>(0, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v += dpp_move_f64<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_move_f64<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_move_f64<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp_move_f64<0x140, 0xF>(v);  // row_mirror
+    v += dpp_move_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned int)(b & 0xffffffffLL), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_move_f32(float v)  // rows outside ROWS keep v
+{
+    return __int_as_float(dpp_move<CTRL, ROWS>(__float_as_int(v), __float_as_int(v)));
+}
+
+template <bool MAX>
+__device__ __forceinline__ float wave_extreme(float v)
+{
+#define LBIB_STEP(C, R)                         \
+    {                                           \
+        const float o = dpp_move_f32<C, R>(v);  \
+        v = MAX ? fmaxf(v, o) : fminf(v, o);    \
+    }
+    LBIB_STEP(0xB1, 0xF)
+    LBIB_STEP(0x4E, 0xF)
+    LBIB_STEP(0x141, 0xF)
+    LBIB_STEP(0x140, 0xF)
+    LBIB_STEP(0x142, 0xA)
+    LBIB_STEP(0x143, 0xC)
+#undef LBIB_STEP
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // Deterministic block reductions over the wavefronts of a block (at most
-// kIBThreads / 64): butterfly within each wave, then the wave partials in order.
+// kIBThreads / 64): a DPP reduction within each wave, then the wave partials in
+// order.
 
 template <int N>
 __device__ __forceinline__ void block_sum(double (&v)[N], double (*red)[8])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < N; k++)
-        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
+    for (int k = 0; k < N; k++) v[k] = wave_sum(v[k]);
     if (lane == 0)
 #pragma unroll
         for (int k = 0; k < N; k++) red[wave][k] = v[k];
@@ -364,11 +423,10 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double (*red)[8])
 __device__ __forceinline__ void block_minmax(float (&mn)[2], float (&mx)[2], double (*red)[8])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int k = 0; k < 2; k++)
-        for (int o = 32; o > 0; o >>= 1) {
-            mn[k] = fminf(mn[k], __shfl_xor(mn[k], o));
-            mx[k] = fmaxf(mx[k], __shfl_xor(mx[k], o));
-        }
+    for (int k = 0; k < 2; k++) {
+        mn[k] = wave_extreme<false>(mn[k]);
+        mx[k] = wave_extreme<true>(mx[k]);
+    }
     if (lane == 0) {
         red[wave][0] = mn[0];
         red[wave][1] = mn[1];
