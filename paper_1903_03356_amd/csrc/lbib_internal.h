@@ -8,6 +8,7 @@ namespace lbib {
 
 // Force field: one 64-cell row segment per wavefront of the grid kernel.
 constexpr int kSegW = 64;
+constexpr double kPlainStoreMaxBytes = 384.0 * (1 << 20);  // single pass: plain stores up to here
 constexpr int kGridRowsPerThread = 1;  // grid kernel: nodes per thread, 4 rows apart
 constexpr int kNumXcd = 8;       // MI355X: workgroups are dealt round-robin to 8 XCDs
 constexpr int kIBThreads = 512;  // IB kernel block (one block per capsule)
