@@ -536,6 +536,40 @@ def test_wall_flag_raised_from_host_state():
     assert flags & lbib.FLAG_WALL
 
 
+@pytest.mark.parametrize("mode", ["kinematic", "dynamic"])
+def test_nan_population_is_flagged(mode):
+    """A NaN injected from the host into the populations under a capsule is
+    detected: the IB kernel sees a non-finite density in its patch (read there
+    as a wall cell) or, once it has spread, non-finite node positions.  Every
+    kernel keeps its accesses in bounds and the run reports it."""
+    from paper_1903_03356_amd import lbib
+    g = lbib.Sim(wl.shear_capsule(mode=mode, real_bytes=4))
+    g.step(5)
+    assert g.check() == 0
+    f = g.pops()
+    f[:, 31, 38] = np.nan  # 1.5 lu inside the membrane (R = 8 about (31.5, 31.5))
+    g.set_pops(f)
+    g.step(10)
+    assert g.check() & (lbib.FLAG_NONFINITE | lbib.FLAG_WALL)
+
+
+def test_unstable_stiffness_is_flagged():
+    """A Dynamic capsule far beyond the explicit update's stability limit
+    (2 k_s / m_v about 40): its nodes soon move a lattice unit or more in one
+    step, which the IB kernel flags; once they leave the stageable range the
+    launch stops early with the patch flag."""
+    from paper_1903_03356_amd import lbib
+    cfg = wl._base("stiff", 96, 64, 0.8, 4, "dynamic", 0,
+                   body_force_x=wl.poiseuille_body_force(0.8, 64, 0.02),
+                   init_profile=wl.INIT_POISEUILLE)
+    cap = wl.capsule(wl.circle_nodes(40.0, 30.0, 6.0, 48), 50.0, 0.0, 1.0, 1.0)
+    assert 30 < wl.stability_ratio(cap["ks"], cap["mass"], 48) < 60
+    cfg["capsules"] = [cap]
+    g = lbib.Sim(cfg)
+    g.step(200)
+    assert g.check() & (lbib.FLAG_MOVE | lbib.FLAG_PATCH | lbib.FLAG_NONFINITE)
+
+
 @pytest.mark.parametrize("real_bytes", [8, 4])
 def test_dynamic_first_step_closed_form_gpu(real_bytes):
     """The HIP path on the closed form of one Dynamic step (Eqs. 21-24): a
