@@ -15,7 +15,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "lbib_oracle.c")
-LIB = os.path.join(_HERE, "liblbib_oracle.so")
+# LBIB_ORACLE_LIB points the wrapper at another build of this source (the
+# mutation checks of the pins load deliberately broken copies this way)
+LIB = os.environ.get("LBIB_ORACLE_LIB") or os.path.join(_HERE, "liblbib_oracle.so")
 
 KINEMATIC, DYNAMIC = 0, 1
 E_WALL, E_NONFINITE = 1, 2
