@@ -350,6 +350,27 @@ def test_hydro_piecewise_shear(orc):
     np.testing.assert_allclose(fext, [[-nu * (g1 - g2) * L, 0]] * 2, atol=1e-15)
 
 
+def test_hydro_piecewise_cross_shear(orc):
+    """The same element across a kink in du_y/dx instead: only the transposed
+    gradient of the symmetric stress nu (grad u + grad u^T) (Eq. 16) reaches
+    the element's normal, so the force is again nu (h1 - h2) L along -x on each
+    node, and zero if the stress missed its transpose."""
+    nx, ny = 40, 24
+    tau = 0.9
+    nu = (tau - 0.5) / 3
+    sim = orc.Sim(wl.periodic_box(nx, ny, tau))
+    h1, h2 = 2e-3, -1.5e-3
+    yy, xx = np.mgrid[0:ny, 0:nx].astype(float)
+    field = np.zeros((3, ny, nx))
+    field[0] = 1.0
+    field[2] = np.where(yy <= 10.5, h1 * (xx - 20.0), h2 * (xx - 20.0))
+    sim.set_moments(field)
+    L = 0.8
+    x = np.array([[20.1, 10.4], [20.1 + L, 10.4]])  # element 0 has n+ = (0, -1)
+    fext = sim.external_forces(x)
+    np.testing.assert_allclose(fext, [[-nu * (h1 - h2) * L, 0]] * 2, atol=1e-15)
+
+
 # ---------------------------------------------------------------- P12 -------
 
 def _area_drift(orc, mode, ka, steps):

@@ -40,6 +40,23 @@ MUTANTS = [
      [("spread(s, k->x[2 * v], k->x[2 * v + 1], 0.5 * (ll + lr), Fx, Fy);",
        "spread(s, k->x[2 * v], k->x[2 * v + 1], 1.0, Fx, Fy);")],
      "test_dynamic_forcing_weight_is_arc_length"),
+    ("viscous_stress_without_transpose",
+     [("tp[a][b] = 1.0 * s->nu * (Gp[a][b] + Gp[b][a]);", "tp[a][b] = 1.0 * s->nu * (Gp[a][b]);"),
+      ("tm[a][b] = 1.0 * s->nu * (Gm[a][b] + Gm[b][a]);", "tm[a][b] = 1.0 * s->nu * (Gm[a][b]);")],
+     "test_hydro_piecewise"),
+    ("bending_force_sign",
+     [("double FLx = kb * sn * nLx / la, FLy = kb * sn * nLy / la;",
+       "double FLx = -kb * sn * nLx / la, FLy = -kb * sn * nLy / la;")],
+     "test_p9_forces_are_energy_gradients"),
+    ("contact_exponent",
+     [("double mag = C * sqrt(1.0 / (d * d * d * d * d));", "double mag = C * sqrt(1.0 / (d * d * d * d));")],
+     "test_contact_force_formula"),
+    ("inlet_profile",
+     [("double ux = 4.0 * s->u_in * y * (H - y) / (H * H);", "double ux = 4.0 * s->u_in * y * (H - y) / (H * (H + 1));")],
+     "test_open_channel_poiseuille"),
+    ("taylor_deformation",
+     [("out[4] = (a - b) / (a + b);", "out[4] = (a - b) / a;")],
+     "test_p10_affine_polygon_taylor"),
     ("kinematic_update_coefficient",
      [("xn[j] = 2.0 / 3.0 * (2.0 * k->x[j] - 0.5 * k->xm1[j] + U[d] * 1.0);",
        "xn[j] = 0.5 * (2.0 * k->x[j] - 0.5 * k->xm1[j] + U[d] * 1.0);")],
