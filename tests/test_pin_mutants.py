@@ -57,6 +57,19 @@ MUTANTS = [
     ("taylor_deformation",
      [("out[4] = (a - b) / (a + b);", "out[4] = (a - b) / a;")],
      "test_p10_affine_polygon_taylor"),
+    ("swelling_ratio",
+     [("out[5] = A / (P * P / (4.0 * M_PI));", "out[5] = A / (P * P / (2.0 * M_PI));")],
+     "test_p10_regular_polygon"),
+    ("node_mass", [("k->mv = mass / nv;", "k->mv = mass / (nv - 1);")],
+     "test_dynamic_first_step_closed_form"),
+    ("rigid_rotation_update",
+     [("double w = 2.0 / 3.0 * (2.0 * k->w - 0.5 * k->wm1 + aw * 1.0);",
+       "double w = 2.0 / 3.0 * (2.0 * k->w - 0.5 * k->wm1 - aw * 1.0);")],
+     "test_rigid_disc_rotates_at_half_the_shear_rate"),
+    ("outlet_zou_he",
+     [("g[7] = g[5] + 0.5 * (g[2] - g[4]) - s->rho_out * uo / 6.0;",
+       "g[7] = g[5] - 0.5 * (g[2] - g[4]) - s->rho_out * uo / 6.0;")],
+     "test_open_channel_poiseuille"),
     ("kinematic_update_coefficient",
      [("xn[j] = 2.0 / 3.0 * (2.0 * k->x[j] - 0.5 * k->xm1[j] + U[d] * 1.0);",
        "xn[j] = 0.5 * (2.0 * k->x[j] - 0.5 * k->xm1[j] + U[d] * 1.0);")],
