@@ -408,6 +408,15 @@ def main() -> int:
         log(f"grid only, FP64: {g64['mlups']:.0f} MLUPS ({frac64 * 100:.1f} % of HBM peak at 144 B/cell)")
         side["grid_only_fp64_mlups"] = round(g64["mlups"], 1)
         side["grid_only_fp64_hbm_fraction"] = round(frac64, 4)
+        # the same capsules with the Kinematic coupling: the cost of the Dynamic
+        # scheme over the Kinematic one on this workload
+        kin = dict(cfg, mode="kinematic")
+        rk = time_gpu(kin, args.steps, args.warmup, timing=False)
+        del rk["sim"]
+        log(f"fused, Kinematic coupling: {rk['mlups']:.0f} MLUPS; Dynamic / Kinematic time per step "
+            f"{r['ms_per_step'] / rk['ms_per_step']:.3f}")
+        side["kinematic_fused_mlups"] = round(rk["mlups"], 1)
+        side["dynamic_over_kinematic_time"] = round(r["ms_per_step"] / rk["ms_per_step"], 4)
         c2 = wl.poiseuille_biconcave(1e-2, steps=args.steps)
         c2r = time_gpu(c2, args.steps, args.warmup, timing=False)
         del c2r["sim"]
@@ -419,6 +428,12 @@ def main() -> int:
         log(f"2048x512 channel, 32 inertial capsules: {c3r['mlups']:.0f} MLUPS "
             f"({c3r['ms_per_step'] * 1e3:.1f} us/step)")
         side["inertial_2048x512_mlups"] = round(c3r["mlups"], 1)
+        c3k = time_gpu(dict(c3, mode="kinematic"), args.steps, args.warmup, timing=False)
+        del c3k["sim"]
+        side["inertial_2048x512_dynamic_over_kinematic_time"] = round(
+            c3r["ms_per_step"] / c3k["ms_per_step"], 4)
+        log(f"2048x512 channel, Kinematic coupling: {c3k['mlups']:.0f} MLUPS; Dynamic / Kinematic "
+            f"time per step {side['inertial_2048x512_dynamic_over_kinematic_time']:.3f}")
         ens = bench_ensemble(min(args.steps, 400), args.warmup, 20)
         log(f"ensemble: batched {ens['mlups']:.0f} MLUPS ({ens['ms_per_step']:.3f} ms/step, "
             f"{ens['overlapped_ms_per_step']:.3f} split near / far, "
