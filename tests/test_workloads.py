@@ -1,0 +1,34 @@
+"""The seeded synthetic inputs are reproducible and keep the figures quoted
+with the measurements (seed 0): the ensemble's cell and capsule counts, the
+4096^2 workload's node count, and the stability screen of the drawn capsules."""
+import numpy as np
+
+from paper_1903_03356_amd import workloads as wl
+
+
+def test_ensemble_seed0_figures():
+    cfgs = wl.ensemble(seed=0)
+    assert len(cfgs) == 256
+    assert sum(c["nx"] * c["ny"] for c in cfgs) == 8005365
+    assert sum(len(c["capsules"]) for c in cfgs) == 388
+    for c in cfgs:
+        assert 128 <= c["nx"] <= 512 and 64 <= c["ny"] <= 128
+        for cap in c["capsules"]:
+            assert wl.stability_ratio(cap["ks"], cap["mass"], len(cap["nodes"])) <= 1.5
+
+
+def test_fused_workload_figures():
+    cfg = wl.fused_bench(seed=0, n=4096)
+    assert (cfg["nx"], cfg["ny"], len(cfg["capsules"])) == (4096, 4096, 32)
+    assert sum(len(c["nodes"]) for c in cfg["capsules"]) == 4177
+    assert cfg["real_bytes"] == 4 and cfg["mode"] == "dynamic"
+
+
+def test_inputs_are_reproducible():
+    a, b = wl.inertial_capsules(seed=3), wl.inertial_capsules(seed=3)
+    for ca, cb in zip(a["capsules"], b["capsules"]):
+        assert np.array_equal(ca["nodes"], cb["nodes"]) and ca["ks"] == cb["ks"]
+    c = wl.inertial_capsules(seed=4)
+    assert not np.array_equal(a["capsules"][0]["nodes"], c["capsules"][0]["nodes"])
+    for cap in a["capsules"]:
+        assert wl.stability_ratio(cap["ks"], cap["mass"], len(cap["nodes"])) <= 1.5
