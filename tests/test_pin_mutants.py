@@ -3,6 +3,7 @@ copy of the oracle (a wrong coefficient, sign, constant, weight or lattice
 vector), builds it, and runs the pin that should notice.  That pin must fail.
 The correct oracle passes the same pins in test_oracle_pins.py."""
 import os
+import shutil
 import subprocess
 import sys
 
@@ -77,6 +78,7 @@ MUTANTS = [
 ]
 
 
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
 @pytest.mark.parametrize("name,edits,pin", MUTANTS, ids=[m[0] for m in MUTANTS])
 def test_pin_catches_planted_mistake(name, edits, pin, tmp_path):
     src = open(SRC).read()
