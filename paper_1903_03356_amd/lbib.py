@@ -505,7 +505,10 @@ def capsule_objectives(ks, u_max, build, nsteps: int, capsule: int = 0,
     force must be linear in u_max (g = 8 nu u_max / H^2, as the channel
     builders set it).  Forward: two lbib_adjoint runs (objectives D and y_c),
     whose gradients the backward combines with the incoming weights; dJ/du_max =
-    dJ/dg * g / u_max.  ``checkpoint_every`` as in Sim.adjoint."""
+    dJ/dg * dg/du_max, with the slope dg/du_max = the body force ``build`` gives
+    for u_max = 1 (also at u_max = 0).  The output and each gradient live on
+    the device and in the dtype of their input.  ``checkpoint_every`` as in
+    Sim.adjoint."""
     return _CapsuleObjectives.apply(ks, u_max, build, int(nsteps), int(capsule), mode,
                                     int(checkpoint_every))
 
@@ -519,23 +522,28 @@ def _make_objectives_function():
             ks_np = ks.detach().cpu().double().numpy()
             um = float(u_max.detach().cpu())
             cfg = build(ks_np, um)
-            g = float(cfg["body_force_x"])
+            slope = float(build(ks_np, 1.0)["body_force_x"])  # g is linear in u_max
             out, gks, gum = [], [], []
             for obj in (OBJ_TAYLOR, OBJ_CENTROID_Y):
                 r = Sim(cfg).adjoint(nsteps, obj, capsule, mode, checkpoint_every=every)
                 out.append(r["J"])
-                gks.append(torch.as_tensor(r["dJ_dks"][capsule], dtype=ks.dtype))
-                gum.append(r["dJ_dg"] * g / um if um != 0.0 else 0.0)
+                gks.append(torch.as_tensor(r["dJ_dks"][capsule], dtype=ks.dtype,
+                                           device=ks.device))
+                gum.append(r["dJ_dg"] * slope)
             ctx.save_for_backward(torch.stack(gks))
             ctx.gum = gum
-            return torch.tensor(out, dtype=ks.dtype)
+            ctx.um_meta = (u_max.dtype, u_max.device, u_max.shape)
+            return torch.tensor(out, dtype=ks.dtype, device=ks.device)
 
         @staticmethod
         def backward(ctx, grad_out):
             (gks,) = ctx.saved_tensors
-            w = grad_out.to(gks.dtype)
+            w = grad_out.to(device=gks.device, dtype=gks.dtype)
             grad_ks = w[0] * gks[0] + w[1] * gks[1]
-            grad_um = (w[0] * ctx.gum[0] + w[1] * ctx.gum[1]).reshape(())
+            dtype, device, shape = ctx.um_meta
+            wc = w.detach().cpu().double()
+            grad_um = torch.tensor(float(wc[0]) * ctx.gum[0] + float(wc[1]) * ctx.gum[1],
+                                   dtype=dtype, device=device).reshape(shape)
             return grad_ks, grad_um, None, None, None, None, None
 
     return CapsuleObjectives

@@ -338,3 +338,42 @@ def test_autograd_function_chain_rule():
     log(f"autograd: du_max {float(um.grad)} fd {fd_um}; dks[5] {float(ks.grad[5])} fd {fd_k5}")
     assert abs(float(um.grad) - fd_um) <= 1e-5 * abs(fd_um)
     assert abs(float(ks.grad[5]) - fd_k5) <= 1e-5 * abs(fd_k5)
+
+
+@pytest.mark.gpu
+def test_autograd_function_device_tensors():
+    """capsule_objectives with ks and u_max on the GPU: the output and both
+    gradients come back on the GPU, equal to those of CPU inputs.  At u_max = 0
+    the gradient in u_max is the slope of g (linear in u_max) times dJ/dg,
+    which is not zero."""
+    import torch
+    steps = 20
+    base = ellipse_channel(real_bytes=8)
+    nv = len(base["capsules"][0]["nodes"])
+    ks0 = base["capsules"][0]["ks"]
+
+    def build(ks, um):
+        cfg = ellipse_channel(real_bytes=8)
+        cfg["body_force_x"] = wl.poiseuille_body_force(cfg["tau"], cfg["ny"], um)
+        cfg["capsules"][0]["ks"] = np.asarray(ks, np.float64)
+        return cfg
+
+    grads = {}
+    for dev in ("cpu", "cuda"):
+        ks = torch.full((nv,), ks0, dtype=torch.float64, device=dev, requires_grad=True)
+        um = torch.tensor(0.02, dtype=torch.float64, device=dev, requires_grad=True)
+        out = lbib.capsule_objectives(ks, um, build, steps)
+        assert out.device.type == dev
+        (out[0] + 0.3 * out[1]).backward()
+        assert ks.grad.device.type == dev and um.grad.device.type == dev
+        grads[dev] = (out.detach().cpu(), ks.grad.cpu(), um.grad.cpu())
+    for a, b in zip(grads["cpu"], grads["cuda"]):
+        assert torch.equal(a, b)
+    ks = torch.full((nv,), ks0, dtype=torch.float64, device="cuda", requires_grad=True)
+    um = torch.zeros((), dtype=torch.float64, device="cuda", requires_grad=True)
+    out = lbib.capsule_objectives(ks, um, build, steps)
+    out[1].backward()
+    r = lbib.Sim(build(np.full(nv, ks0), 0.0)).adjoint(steps, lbib.OBJ_CENTROID_Y, 0)
+    slope = build(np.full(nv, ks0), 1.0)["body_force_x"]
+    assert float(um.grad) == pytest.approx(r["dJ_dg"] * slope, rel=1e-12)
+    assert float(um.grad) != 0.0
