@@ -411,6 +411,30 @@ lbib_status lbib_adjoint(lbib_ctx* ctx, int32_t nsteps, int32_t checkpoint_every
                          size_t workspace_bytes, double* out_J, double* out_dJ_dg,
                          double* out_dJ_dks, int32_t n_ks);
 
+/* ---- Gradient without allocation ----
+ *
+ * For callers that cannot allocate device memory: code being captured into a
+ * HIP graph, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * computation, arguments, outputs and errors as lbib_adjoint, without the
+ * workspace argument: the workspace is a static device array of
+ * LBIB_ADJOINT_SCRATCH_BYTES (64 MiB) inside the library, one copy on each
+ * GPU the library runs on, held until the process ends.  This call allocates
+ * nothing (no hipMalloc, no allocating library routine).  It fits gradients
+ * whose lbib_adjoint_bytes(ctx, nsteps, checkpoint_every) is at most that size:
+ * small lattices, short runs, or a checkpoint interval.
+ * Additional errors: ECAPACITY if the workspace would exceed
+ * LBIB_ADJOINT_SCRATCH_BYTES (checked before anything is launched); EDEVICE
+ * if the context's device is not the current one.
+ * Sharing: every call on one GPU uses the same array and leaves its contents
+ * behind; each call clears the bytes it uses before the forward run.  Calls
+ * that overlap in time on one GPU (several threads or streams) race on the
+ * array and give wrong results.  Waits for the stream. */
+#define LBIB_ADJOINT_SCRATCH_BYTES (64u * 1024u * 1024u)
+lbib_status lbib_adjoint_noalloc(lbib_ctx* ctx, int32_t nsteps, int32_t checkpoint_every,
+                                 lbib_mode mode, int32_t objective, int32_t capsule,
+                                 double* out_J, double* out_dJ_dg, double* out_dJ_dks,
+                                 int32_t n_ks);
+
 /* Frees the host-side context.  Device buffers stay with the caller.  Waits for
  * the stream first. */
 void lbib_destroy(lbib_ctx* ctx);

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -108,7 +109,39 @@ struct lbib_ctx {
     // per tile)
     int tile_shape = 0, tile_resident = 0;
     int num_cu = 256;
+    int device = 0;  // HIP device that was current at create
 };
+
+// ------------------------------------------------- static gradient scratch
+//
+// Workspace of lbib_adjoint_noalloc: a file-scope device array, one copy per
+// GPU that loads the library, held until the process ends.  Host code never
+// passes the array's name to a kernel or a copy (in host code it names a
+// host-side stand-in, not device memory): each device's address comes from
+// hipGetSymbolAddress, taken once per device with that device current (at the
+// first lbib_create on it, else at the entry point's first call there), and
+// only that address is used.
+static __device__ __align__(256) unsigned char scratch[LBIB_ADJOINT_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on device `dev`, which must be the current device.
+static hipError_t resolve_scratch(int dev, void** out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 // ----------------------------------------------------------------- helpers
 
@@ -402,6 +435,13 @@ static lbib_status create_common(const lbib_grid* grids, const double* taus,
 
     lbib_ctx* c = new lbib_ctx();
     c->L = L;
+    c->device = dev;
+    {
+        // set-up of the static gradient scratch on this device; a failure
+        // here only matters to lbib_adjoint_noalloc, which tries again
+        void* p = nullptr;
+        (void)resolve_scratch(dev, &p);
+    }
     if (prop.multiProcessorCount > 0) c->num_cu = prop.multiProcessorCount;
     for (int i = 0; i < n_inst; i++) {
         Inst& I = c->L.inst[i];
@@ -1549,14 +1589,15 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
     return LBIB_OK;
 }
 
-extern "C" lbib_status lbib_adjoint(lbib_ctx* c, int32_t nsteps, int32_t checkpoint_every,
+// Argument and state checks shared by lbib_adjoint and lbib_adjoint_noalloc;
+// fills the workspace layout.
+static lbib_status adjoint_validate(lbib_ctx* c, int32_t nsteps, int32_t checkpoint_every,
                                     lbib_mode mode, int32_t objective, int32_t capsule,
-                                    void* workspace, size_t workspace_bytes, double* out_J,
-                                    double* out_dJ_dg, double* out_dJ_dks, int32_t n_ks)
+                                    const double* out_J, const double* out_dJ_dg,
+                                    const double* out_dJ_dks, int32_t n_ks, AdjLayout& A)
 {
     if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
-    if (!workspace || !out_J || !out_dJ_dg || !out_dJ_dks)
-        return fail(c, LBIB_EINVAL, "NULL argument");
+    if (!out_J || !out_dJ_dg || !out_dJ_dks) return fail(c, LBIB_EINVAL, "NULL argument");
     if (c->L.inst.size() != 1) return fail(c, LBIB_EINVAL, "the adjoint needs a single lattice");
     if (nsteps < 1) return fail(c, LBIB_EINVAL, "nsteps must be >= 1");
     if (checkpoint_every < 0) return fail(c, LBIB_EINVAL, "checkpoint_every must be >= 0");
@@ -1576,11 +1617,54 @@ extern "C" lbib_status lbib_adjoint(lbib_ctx* c, int32_t nsteps, int32_t checkpo
     for (int r : c->cap_rigid)
         if (r) return fail(c, LBIB_EINVAL, "the adjoint does not differentiate rigid particles");
     if (n_ks < c->nodes_used) return fail(c, LBIB_EINVAL, "out_dJ_dks shorter than the node count");
-    AdjLayout A;
     if (!adj_layout(c, nsteps, checkpoint_every, A))
         return fail(c, LBIB_EINVAL, "invalid adjoint layout");
+    return LBIB_OK;
+}
+
+extern "C" lbib_status lbib_adjoint(lbib_ctx* c, int32_t nsteps, int32_t checkpoint_every,
+                                    lbib_mode mode, int32_t objective, int32_t capsule,
+                                    void* workspace, size_t workspace_bytes, double* out_J,
+                                    double* out_dJ_dg, double* out_dJ_dks, int32_t n_ks)
+{
+    AdjLayout A;
+    lbib_status v = adjoint_validate(c, nsteps, checkpoint_every, mode, objective, capsule, out_J,
+                                     out_dJ_dg, out_dJ_dks, n_ks, A);
+    if (v != LBIB_OK) return v;
+    if (!workspace) return fail(c, LBIB_EINVAL, "NULL argument");
     if (workspace_bytes < A.total) return fail(c, LBIB_EINVAL, "workspace too small");
     char* ws = static_cast<char*>(workspace);
+    return c->rb == 4 ? adjoint_t<float>(c, nsteps, mode, objective, capsule, ws, A, out_J,
+                                         out_dJ_dg, out_dJ_dks)
+                      : adjoint_t<double>(c, nsteps, mode, objective, capsule, ws, A, out_J,
+                                          out_dJ_dg, out_dJ_dks);
+}
+
+extern "C" lbib_status lbib_adjoint_noalloc(lbib_ctx* c, int32_t nsteps, int32_t checkpoint_every,
+                                            lbib_mode mode, int32_t objective, int32_t capsule,
+                                            double* out_J, double* out_dJ_dg, double* out_dJ_dks,
+                                            int32_t n_ks)
+{
+    AdjLayout A;
+    lbib_status v = adjoint_validate(c, nsteps, checkpoint_every, mode, objective, capsule, out_J,
+                                     out_dJ_dg, out_dJ_dks, n_ks, A);
+    if (v != LBIB_OK) return v;
+    if (A.total > (size_t)LBIB_ADJOINT_SCRATCH_BYTES)
+        return fail(c, LBIB_ECAPACITY,
+                    "the gradient needs " + std::to_string(A.total) +
+                        " workspace bytes; the static scratch holds " +
+                        std::to_string((size_t)LBIB_ADJOINT_SCRATCH_BYTES) +
+                        " (use lbib_adjoint with a caller-owned workspace, or a checkpoint interval)");
+    int cur = 0;
+    HIPCHK(c, hipGetDevice(&cur));
+    if (cur != c->device)
+        return fail(c, LBIB_EDEVICE, "call lbib_adjoint_noalloc with the context's device current");
+    void* p = nullptr;
+    hipError_t e = resolve_scratch(c->device, &p);
+    if (e != hipSuccess)
+        return fail(c, LBIB_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    // adjoint_t clears the A.total bytes it uses before the forward run
+    char* ws = static_cast<char*>(p);
     return c->rb == 4 ? adjoint_t<float>(c, nsteps, mode, objective, capsule, ws, A, out_J,
                                          out_dJ_dg, out_dJ_dks)
                       : adjoint_t<double>(c, nsteps, mode, objective, capsule, ws, A, out_J,

@@ -34,10 +34,11 @@ EXPORTS = ["lbib_required_bytes", "lbib_create", "lbib_add_capsule", "lbib_step"
            "lbib_get_state", "lbib_set_state", "lbib_check", "lbib_set_timing",
            "lbib_get_timing", "lbib_steps_done", "lbib_last_error", "lbib_destroy",
            "lbib_required_bytes_batch", "lbib_create_batch", "lbib_add_capsule_to",
-           "lbib_num_lattices", "lbib_adjoint_bytes", "lbib_adjoint", "lbib_set_overlap",
-           "lbib_set_graph", "lbib_graph_replays", "lbib_set_tile", "lbib_autotune",
+           "lbib_num_lattices", "lbib_adjoint_bytes", "lbib_adjoint", "lbib_adjoint_noalloc",
+           "lbib_set_overlap", "lbib_set_graph", "lbib_graph_replays", "lbib_set_tile", "lbib_autotune",
            "lbib_set_contact", "lbib_add_rigid_to"]
 OBJ_TAYLOR, OBJ_CENTROID_Y = 0, 1
+ADJOINT_SCRATCH_BYTES = 64 * 1024 * 1024  # LBIB_ADJOINT_SCRATCH_BYTES
 
 
 class lbib_grid(C.Structure):
@@ -135,6 +136,8 @@ def load() -> C.CDLL:
     dp = C.POINTER(C.c_double)
     L.lbib_adjoint.restype = i32
     L.lbib_adjoint.argtypes = [vp, i32, i32, i32, i32, i32, vp, C.c_size_t, dp, dp, dp, i32]
+    L.lbib_adjoint_noalloc.restype = i32
+    L.lbib_adjoint_noalloc.argtypes = [vp, i32, i32, i32, i32, i32, dp, dp, dp, i32]
     _lib = L
     return L
 
@@ -391,6 +394,27 @@ class Sim:
                                        C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(J),
                                        C.byref(g), ks.ctypes.data_as(C.POINTER(C.c_double)),
                                        nks), self.h)
+        caps, o = [], 0
+        for n in self.nv:
+            caps.append(ks[o:o + n].copy())
+            o += n
+        return {"J": J.value, "dJ_dg": g.value, "dJ_dks": caps}
+
+    def adjoint_noalloc(self, nsteps: int, objective: int = OBJ_TAYLOR, capsule: int = 0,
+                        mode: Optional[str] = None, checkpoint_every: int = 0) -> Dict[str, Any]:
+        """lbib_adjoint_noalloc: as ``adjoint``, with the library's static
+        workspace (at most ADJOINT_SCRATCH_BYTES) instead of a caller-owned one."""
+        mode = mode or self.cfg.get("mode", "dynamic")
+        m = DYNAMIC if mode == "dynamic" else KINEMATIC
+        nks = max(1, sum(self.nv))
+        ks = np.zeros(nks, np.float64)
+        J, g = C.c_double(), C.c_double()
+        with self.torch.cuda.device(self.device):
+            _check(load().lbib_adjoint_noalloc(self.h, int(nsteps), int(checkpoint_every), m,
+                                               int(objective), int(capsule), C.byref(J),
+                                               C.byref(g),
+                                               ks.ctypes.data_as(C.POINTER(C.c_double)), nks),
+                   self.h)
         caps, o = [], 0
         for n in self.nv:
             caps.append(ks[o:o + n].copy())

@@ -154,3 +154,18 @@ def test_missing_library_fails_loudly():
                          timeout=300)
     assert out.returncode == 0, out.stderr[-2000:]
     assert out.stdout.strip().splitlines()[-1] == "ImportError True", out.stdout
+
+
+def test_noalloc_gradient_declared_with_its_scratch_size(L):
+    """The allocation-free gradient call is exported, its static workspace size
+    in the header matches the binding's constant, and it rejects a NULL
+    context before touching a device."""
+    text = open(HEADER).read()
+    m = re.search(r"#define\s+LBIB_ADJOINT_SCRATCH_BYTES\s+\((\d+)u \* (\d+)u \* (\d+)u\)", text)
+    assert m, "LBIB_ADJOINT_SCRATCH_BYTES not found"
+    size = int(m.group(1)) * int(m.group(2)) * int(m.group(3))
+    assert size == lbib.ADJOINT_SCRATCH_BYTES == 64 << 20
+    J, g = C.c_double(), C.c_double()
+    ks = (C.c_double * 4)()
+    rc = L.lbib_adjoint_noalloc(None, 10, 0, 1, 0, 0, C.byref(J), C.byref(g), ks, 4)
+    assert rc == lbib.EINVAL
