@@ -63,7 +63,9 @@ enum lbib_device_flags {
     LBIB_FLAG_PATCH = 4,      /* a capsule's fluid patch exceeded the on-chip capacity */
     LBIB_FLAG_OVERFLOW = 8,   /* a spread force left the fixed-point range (|f| >= 2^14) */
     LBIB_FLAG_MOVE = 16,      /* a node moved one lattice unit or more in one step */
-    LBIB_FLAG_NEAR = 32       /* overlapped schedule: an IB force outside the near regions */
+    LBIB_FLAG_NEAR = 32,      /* overlapped schedule: an IB force outside the near regions */
+    LBIB_FLAG_SYNC = 64       /* overlapped schedule: a far-pass block stopped waiting for the IB
+                                 launch of its step (about 0.2 s); that step is not valid */
 };
 
 typedef struct {

@@ -110,6 +110,17 @@ struct lbib_ctx {
     int tile_shape = 0, tile_resident = 0;
     int num_cu = 256;
     int device = 0;  // HIP device that was current at create
+    // overlapped schedule of one lattice: IB blocks launched so far that add
+    // to the device counter (the far pass of step n waits for the count after
+    // the launch of step n)
+    unsigned long long ib_blocks_issued = 0;
+    bool far_waits_inside = false;  // the next far launch waits on that count
+    // the forcing (phase A: Dynamic steps 1-3) of step `steps` is already
+    // spread into its force level, with that step's near map stamped: the
+    // overlapped schedule of one lattice ends a call with it (Dynamic only:
+    // there phase A writes no node state), so the next call starts with the
+    // grid pass.  set_state drops it (the state it was computed from changes).
+    bool a_ready = false;
 };
 
 // ------------------------------------------------- static gradient scratch
@@ -184,6 +195,9 @@ static bool grid_ok(const lbib_grid* g)
 
 constexpr int kMaxInstances = 1 << 16;
 constexpr int kMaxOverlapCapsules = 4096;  // near regions per step (one near-kernel block group each)
+// one lattice from this size: the far kernel waits for the IB launch of its
+// step inside, from the second step of a call on (step_overlap_t)
+constexpr long long kFarWaitInsideCells = 1LL << 23;
 constexpr long long kOverlapMinCells = 1LL << 22;  // automatic overlap from 4.2 M cells
 
 // Fills L from the lattices' sizes and capacities; false if any is invalid or
@@ -354,6 +368,27 @@ static int* near_map(const lbib_ctx* c, long long parity)
 }
 
 static int step_stamp(long long n) { return (int)((n + 1) & 0x7fffffff); }
+
+// Device counter of finished IB blocks (overlapped schedule), beside the
+// status word in the diagnostics buffer; zeroed at create and only incremented.
+static unsigned long long* ib_done_counter(const lbib_ctx* c)
+{
+    return reinterpret_cast<unsigned long long*>(bufp(c, LBIB_BUF_DIAG) + status_offset(c->L) + 32);
+}
+
+// Undoes a forcing spread ahead (lbib_ctx::a_ready): clears the step's force
+// level, its segment flags and its near map, so that the next call spreads the
+// forcing again from the state as it then stands.
+static lbib_status drop_pending_forcing(lbib_ctx* c)
+{
+    if (!c->a_ready) return LBIB_OK;
+    const long long n = c->steps;
+    HIPCHK(c, hipMemsetAsync(fib(c, n), 0, c->L.fib_level * sizeof(long long), c->stream));
+    HIPCHK(c, hipMemsetAsync(flags(c, n), 0, c->L.flag_level * sizeof(int), c->stream));
+    HIPCHK(c, hipMemsetAsync(near_map(c, n), 0, c->L.flag_level * sizeof(int), c->stream));
+    c->a_ready = false;
+    return LBIB_OK;
+}
 
 static hipEvent_t take_event(lbib_ctx* c)
 {
@@ -793,6 +828,7 @@ static IBArgs<T> ib_args(const lbib_ctx* c, long long n, int phase)
     a.stamp = 0;
     a.contact = c->contact_cutoff > 0.0;
     a.hints = reinterpret_cast<int4*>(bufp(c, LBIB_BUF_CAPS) + c->L.hints);
+    a.done_count = nullptr;
     return a;
 }
 
@@ -832,8 +868,11 @@ static hipError_t do_ib(lbib_ctx* c, void* p)
         a.rects = rect_table(c, q->n);
         a.near_map = near_map(c, q->n);
         a.stamp = step_stamp(q->n);
+        if (c->L.inst.size() == 1) a.done_count = ib_done_counter(c);
     }
-    return launch_ib<T>(a, c->ncap, c->lds_use, c->stream);
+    hipError_t e = launch_ib<T>(a, c->ncap, c->lds_use, c->stream);
+    if (e == hipSuccess && a.done_count) c->ib_blocks_issued += (unsigned long long)c->ncap;
+    return e;
 }
 
 // Blocks of a persistent batched launch: `resident` per compute unit, a
@@ -908,7 +947,9 @@ static hipError_t do_far(lbib_ctx* c, void* p)
     return launch_grid_far<T>(static_cast<const T*>(pops(c, n)), static_cast<T*>(pops(c, n + 1)),
                               fib(c, n), flags(c, n), fib(c, n + 1), flags(c, n + 1),
                               near_map(c, n), step_stamp(n), status_word(c), g, c->s_far,
-                              own_event ? c->e_far[n & 1] : nullptr);
+                              own_event ? c->e_far[n & 1] : nullptr,
+                              c->far_waits_inside ? ib_done_counter(c) : nullptr,
+                              c->ib_blocks_issued);
 }
 
 template <typename T>
@@ -945,17 +986,35 @@ static lbib_status step_overlap_t(lbib_ctx* c, int nsteps)
         HIPCHK(c, hipEventCreateWithFlags(&c->e_far[0], ev));
         HIPCHK(c, hipEventCreateWithFlags(&c->e_far[1], ev));
     }
-    {
+    // the forcing of the first step, unless the last call spread it ahead;
+    // the event orders the first far launch after all work on the main stream
+    if (!c->a_ready) {
         const long long n = c->steps;
         IBLaunch<T> q{n, n == 0 ? (PH_PRIME | PH_A) : PH_A, true};
         lbib_status s = launch_timed<T>(c, 1, do_ib<T>, &q);
         if (s != LBIB_OK) return s;
-        HIPCHK(c, hipEventRecord(c->e_ib, c->stream));
     }
+    HIPCHK(c, hipEventRecord(c->e_ib, c->stream));
+    // Dynamic, one lattice: the last launch also spreads the next step's
+    // forcing (phase A writes no node state there), so the next call needs
+    // no opening IB launch in front of its first far pass
+    const bool ahead = c->mode == LBIB_DYNAMIC && c->L.inst.size() == 1;
+    // Far pass n waits for IB(n).  From the second step of a call on, on one
+    // large lattice, the far kernel waits inside, on the count of finished IB
+    // blocks: that spares the queue-level hand-off between the two streams
+    // (about 5 us of every step at 4096^2).  It needs IB(n) to be running by
+    // the time far(n) fills the device, which holds there: IB(n) becomes ready
+    // a near pass after far(n - 2) ends, far(n) only when far(n - 1) ends.  The
+    // first far launch of a call starts beside the call's first IB launch, so
+    // it, batches and smaller lattices wait on the queue.
+    long long cells = 0;
+    for (const Inst& I : c->L.inst) cells += (long long)I.grid.nx * I.grid.ny;
+    const bool inside = c->L.inst.size() == 1 && cells >= kFarWaitInsideCells;
     for (int k = 0; k < nsteps; k++) {
         const long long n = c->steps + k;
         long long nn = n;
-        HIPCHK(c, hipStreamWaitEvent(c->s_far, c->e_ib, 0));  // IB(n)
+        c->far_waits_inside = inside && k > 0;
+        if (!c->far_waits_inside) HIPCHK(c, hipStreamWaitEvent(c->s_far, c->e_ib, 0));
         lbib_status s = launch_timed<T>(c, 0, do_far<T>, &nn, c->s_far);
         if (s != LBIB_OK) return s;
         if (k > 0) HIPCHK(c, hipStreamWaitEvent(c->stream, c->e_far[(n - 1) & 1], 0));
@@ -963,11 +1022,13 @@ static lbib_status step_overlap_t(lbib_ctx* c, int nsteps)
             HIPCHK(c, hipEventRecord(c->e_far[n & 1], c->s_far));
         s = launch_timed<T>(c, 2, do_near<T>, &nn);
         if (s != LBIB_OK) return s;
-        IBLaunch<T> q{n + 1, k + 1 < nsteps ? (PH_B | PH_A) : PH_B, k + 1 < nsteps};
+        const bool more = k + 1 < nsteps || ahead;
+        IBLaunch<T> q{n + 1, more ? (PH_B | PH_A) : PH_B, more};
         s = launch_timed<T>(c, 1, do_ib<T>, &q);
         if (s != LBIB_OK) return s;
         HIPCHK(c, hipEventRecord(c->e_ib, c->stream));
     }
+    c->a_ready = ahead;
     HIPCHK(c, hipStreamWaitEvent(c->stream, c->e_far[(c->steps + nsteps - 1) & 1], 0));
     c->steps += nsteps;
     return LBIB_OK;
@@ -985,7 +1046,7 @@ static lbib_status step_overlap_t(lbib_ctx* c, int nsteps)
 template <typename T>
 static lbib_status step_body(lbib_ctx* c, long long n, int pb, int pa, bool contact, bool dyn)
 {
-    if (c->ncap > 0) {
+    if (c->ncap > 0 && (pb | pa)) {
         lbib_status s = LBIB_OK;
         if (contact && !dyn) {
             if (pb) {
@@ -1102,7 +1163,7 @@ static lbib_status step_t(lbib_ctx* c, int nsteps)
             continue;
         }
         const int pb = k == 0 ? 0 : PH_B;
-        const int pa = n == 0 ? (PH_PRIME | PH_A) : PH_A;
+        const int pa = k == 0 && c->a_ready ? 0 : n == 0 ? (PH_PRIME | PH_A) : PH_A;
         lbib_status s = step_body<T>(c, n, pb, pa, contact, dyn);
         if (s != LBIB_OK) return s;
         k++;
@@ -1116,6 +1177,7 @@ static lbib_status step_t(lbib_ctx* c, int nsteps)
         lbib_status s = launch_timed<T>(c, 1, do_ib<T>, &q);
         if (s != LBIB_OK) return s;
     }
+    c->a_ready = false;
     c->steps += nsteps;
     return LBIB_OK;
 }
@@ -1259,6 +1321,10 @@ template <typename T>
 static lbib_status set_t(lbib_ctx* c, int what, int cap, const void* src, size_t bytes, int on_dev)
 {
     double* stage = reinterpret_cast<double*>(bufp(c, LBIB_BUF_STAGE));
+    if (what == LBIB_F_POPS || what == LBIB_C_STATE) {
+        lbib_status d = drop_pending_forcing(c);
+        if (d != LBIB_OK) return d;
+    }
     if (what == LBIB_F_POPS) {
         if (cap < 0 || cap >= (int)c->L.inst.size())
             return fail(c, LBIB_EINVAL, "bad lattice index");
@@ -1502,6 +1568,7 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
     HIPCHK(c, hipMemcpyAsync(flags(c, N + 1), gFl(rN), (size_t)I.grid.ny * I.nseg * sizeof(int),
                              d2d, st));
     c->steps = N;
+    c->a_ready = false;
     int flags_fwd = 0;
     HIPCHK(c, hipMemcpyAsync(&flags_fwd, status_word(c), sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));

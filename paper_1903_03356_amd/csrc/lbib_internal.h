@@ -82,8 +82,14 @@ static_assert(sizeof(CapsuleDev) == 272, "CapsuleDev layout");
 constexpr int kDiagStride = 16;  // doubles per capsule in BUF_DIAG
 
 enum StatusBits {
-    ST_WALL = 1, ST_NONFINITE = 2, ST_PATCH = 4, ST_OVERFLOW = 8, ST_MOVE = 16, ST_NEAR = 32
+    ST_WALL = 1, ST_NONFINITE = 2, ST_PATCH = 4, ST_OVERFLOW = 8, ST_MOVE = 16, ST_NEAR = 32,
+    ST_SYNC = 64
 };
+
+// Bounded wait of the far pass for the IB launch of its step (overlapped
+// schedule): iterations of about 1 us before a block gives up with ST_SYNC
+// (the other blocks then stop waiting as well).
+constexpr int kSyncSpinLimit = 50000;
 
 // Near region of one capsule for the overlapped grid step: world cells,
 // inclusive, x unwrapped (taken modulo nx), y clamped to the lattice or
@@ -124,6 +130,9 @@ struct IBArgs {
     int stamp;
     int contact;       // add the contact force NF_CX/NF_CY (Dynamic B, Kinematic A)
     int4* hints;       // per capsule: the patch box (ox, oy, W, H) of its last launch, W = 0 none
+    // overlapped schedule: each block adds 1 here once all its stores are
+    // visible device-wide, so that the far pass can tell the launch is over
+    unsigned long long* done_count;
 };
 
 // Node tape of the gradient runs: per time level, the fields NF_HX .. NF_UY
@@ -170,7 +179,8 @@ template <typename T>
 hipError_t launch_grid_far(const T* src, T* dst, const long long* fib_now, const int* flags_now,
                            long long* fib_old, int* flags_old, const int* near_map, int stamp,
                            int* status, const GridArgs& g, hipStream_t s,
-                           hipEvent_t done = nullptr);
+                           hipEvent_t done = nullptr, const unsigned long long* ready = nullptr,
+                           unsigned long long ready_target = 0);
 template <typename T>
 hipError_t launch_grid_near(const T* src, T* dst, const long long* fib_now, const int* flags_now,
                             long long* fib_old, int* flags_old, const NearRect* rects,

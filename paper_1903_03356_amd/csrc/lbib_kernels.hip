@@ -175,13 +175,41 @@ __device__ __forceinline__ GridArgs lattice_args(const InstDev& I)
 // found here means the near regions were too small, ST_NEAR.  The unit runs
 // the very code of the single pass (grid_cell), so that the compiler forms
 // the same arithmetic and the split repeats the single pass bit for bit.
+//
+// With `ready`, the pass runs on its own stream without a queue-level wait for
+// the IB launch of its step: each block first waits until the IB blocks'
+// counter reaches `target` (the count after this step's launch; the counter
+// only grows, so any value at or above it is conclusive).  That launch stamped
+// this step's near map and ran after the near pass of the previous step on the
+// other stream, so both are complete and visible once the count is reached.
+// The wait is bounded: a block that gives up raises ST_SYNC and goes on.
+__device__ __forceinline__ void wait_for_count(const unsigned long long* ready,
+                                               unsigned long long target, int* status)
+{
+    if (threadIdx.x == 0 && *ready < target) {
+        int spins = 0;
+        while (__hip_atomic_load(ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            // give up after the limit, or at once once another block has
+            if (++spins > kSyncSpinLimit ||
+                ((spins & 63) == 0 &&
+                 (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_SYNC))) {
+                atomicOr(status, ST_SYNC);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+        }
+    }
+    __syncthreads();
+}
+
 template <typename T>
 __global__ __launch_bounds__(kSegW * 4) void k_grid_far(
     const T* __restrict__ src, T* __restrict__ dst, const long long* __restrict__ fib_now,
     const int* __restrict__ flags_now, long long* __restrict__ fib_old,
     int* __restrict__ flags_old, const int* __restrict__ near_map, int stamp, int* status,
-    GridArgs g)
+    GridArgs g, const unsigned long long* ready, unsigned long long target)
 {
+    if (ready) wait_for_count(ready, target, status);
     const int b = blockIdx.x;
     const int j = b / kNumXcd;
     const int group = j / g.nseg;
@@ -290,18 +318,20 @@ hipError_t launch_grid_step(const T* src, T* dst, const long long* fib_now, cons
 template <typename T>
 hipError_t launch_grid_far(const T* src, T* dst, const long long* fib_now, const int* flags_now,
                            long long* fib_old, int* flags_old, const int* near_map, int stamp,
-                           int* status, const GridArgs& g, hipStream_t s, hipEvent_t done)
+                           int* status, const GridArgs& g, hipStream_t s, hipEvent_t done,
+                           const unsigned long long* ready, unsigned long long ready_target)
 {
     static_assert(kGridRowsPerThread == 1, "k_grid_far takes one row per thread");
     const int blocks = grid_blocks(g.ny, g.nseg);
     if (!done) {
         hipLaunchKernelGGL(k_grid_far<T>, dim3((unsigned)blocks), dim3(kSegW * 4), 0, s, src, dst,
-                           fib_now, flags_now, fib_old, flags_old, near_map, stamp, status, g);
+                           fib_now, flags_now, fib_old, flags_old, near_map, stamp, status, g,
+                           ready, ready_target);
         return hipGetLastError();
     }
     GridArgs ga = g;
     void* args[] = {&src, &dst, &fib_now, &flags_now, &fib_old, &flags_old, &near_map, &stamp,
-                    &status, &ga};
+                    &status, &ga, &ready, &ready_target};
     return hipExtLaunchKernel(reinterpret_cast<const void*>(&k_grid_far<T>),
                               dim3((unsigned)blocks), dim3(kSegW * 4), args, 0, s, nullptr, done,
                               0);
@@ -1164,10 +1194,9 @@ __device__ void rigid_update(const IBArgs<T>& a, const Scratch<T>& S, const Patc
 //             forces, c_v = 1)
 //   PH_DIAG   diagnostics of the current shape only
 template <typename T>
-__global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
+__device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* smem,
+                                         double (*red)[8])
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[kIBThreads / 64][8];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int c = blockIdx.x;
     // the patch box of the last launch (used below) is loaded beside the record
@@ -1527,6 +1556,23 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
         }
     }
     if (st) atomicOr(a.status, st);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[kIBThreads / 64][8];
+    ib_block<T>(a0, smem, red);  // every exit of ib_block is block-uniform
+    if (a0.done_count) {
+        // the block's stores (near map, force level, node state) are made
+        // visible device-wide before the count announces them
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            atomicAdd(a0.done_count, 1ull);
+        }
+    }
 }
 
 template <typename T>
@@ -1902,7 +1948,8 @@ hipError_t launch_set_nodes(T* nodes, CapsuleDev* caps, int cap, int nv, int nod
                                                   int*, hipStream_t);                             \
     template hipError_t launch_grid_far<T>(const T*, T*, const long long*, const int*,            \
                                            long long*, int*, const int*, int, int*,               \
-                                           const GridArgs&, hipStream_t, hipEvent_t);             \
+                                           const GridArgs&, hipStream_t, hipEvent_t,              \
+                                           const unsigned long long*, unsigned long long);             \
     template hipError_t launch_grid_near<T>(const T*, T*, const long long*, const int*,           \
                                             long long*, int*, const NearRect*, const CapsuleDev*, \
                                             const InstDev*, int, hipStream_t);                    \

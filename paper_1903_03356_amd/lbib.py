@@ -21,7 +21,8 @@ OK, EINVAL, ECAPACITY, EDEVICE, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ECAPACITY", -3: "EDEVICE", -4: "ESTATE",
                 -5: "ENUMERIC"}
 KINEMATIC, DYNAMIC = 0, 1
-FLAG_WALL, FLAG_NONFINITE, FLAG_PATCH, FLAG_OVERFLOW, FLAG_MOVE, FLAG_NEAR = 1, 2, 4, 8, 16, 32
+FLAG_WALL, FLAG_NONFINITE, FLAG_PATCH, FLAG_OVERFLOW, FLAG_MOVE, FLAG_NEAR, FLAG_SYNC = \
+    1, 2, 4, 8, 16, 32, 64
 NUM_BUFFERS = 8
 BUFFER_NAMES = ["pops_a", "pops_b", "force", "flags", "nodes", "caps", "diag", "stage"]
 # lbib_state_id

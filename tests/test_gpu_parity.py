@@ -294,6 +294,47 @@ def test_overlapped_schedule_is_bit_identical():
                 assert np.array_equal(x, y)
 
 
+def test_forcing_spread_ahead_across_calls():
+    """A Dynamic call of the split schedule ends with the next step's forcing
+    already spread (the next call then opens with its grid pass).  Against the
+    single pass, stepped alike: the same bits after chunks in the split
+    schedule, after switching to the single pass and back (which takes the
+    forcing spread ahead), and after set_state of the populations and of a
+    capsule between calls (which drops it and spreads it again)."""
+    from paper_1903_03356_amd import lbib
+    cfg = wl.inertial_capsules(seed=3, nx=512, ny=128, n_caps=4, steps=60)
+    a = lbib.Sim(cfg)
+    b = lbib.Sim(cfg)
+    b.set_overlap(False)
+    a.set_overlap(True)
+    a.step(10)
+    b.step(10)
+    a.set_overlap(False)  # single pass, taking over the forcing spread ahead
+    a.step(7)
+    b.step(7)
+    a.set_overlap(True)
+    a.step(5)
+    b.step(5)
+    f = b.pops()
+    f[:, 40:60, 100:140] *= 1.0 + 1e-3  # a disturbance under the fluid of some capsules
+    for s in (a, b):
+        s.set_pops(f)
+    x, xm1, uv = b.capsule(1)
+    x2 = x + 0.05 * (x - x.mean(axis=0))  # a stretched capsule
+    for s in (a, b):
+        s.set_capsule(1, x2, xm1, uv)
+    a.step(6)
+    b.step(6)
+    a.step(3)
+    b.step(3)
+    assert a.check() == 0 and b.check() == 0
+    assert np.array_equal(a.pops_dev(), b.pops_dev())
+    assert np.array_equal(a.force(), b.force())
+    for c in range(len(cfg["capsules"])):
+        for p, q in zip(a.capsule(c), b.capsule(c)):
+            assert np.array_equal(p, q), c
+
+
 @pytest.mark.parametrize("mode", ["dynamic", "kinematic"])
 @pytest.mark.parametrize("real_bytes", [8, 4])
 def test_contact_pair(mode, real_bytes):
