@@ -264,7 +264,15 @@ lbib_status lbib_set_contact(lbib_ctx* ctx, double cutoff);
 
 /* Schedule of lbib_step: enable = 1 always uses the overlapped near / far
  * schedule where it applies (see lbib_step), 0 never, -1 (the default) for
- * one lattice of 2^22 cells or more.  Errors: EINVAL (other values). */
+ * one lattice of 2^22 cells or more.  In the overlapped schedule of one
+ * lattice of 2^23 cells or more, the far kernel of every step after a call's
+ * first waits for that step's IB launch on the device (a counter the IB blocks
+ * raise), not on the queue; this needs the two streams' kernels to run
+ * concurrently.  enable = 2 is the overlapped schedule with queue-level waits
+ * only, for tools that run kernels one at a time (counter collection, kernel
+ * serialisation): under such a tool the device-side wait gives up after about
+ * 0.05 s per block and raises LBIB_FLAG_SYNC.  Results are the same bits in
+ * every schedule.  Errors: EINVAL (other values). */
 lbib_status lbib_set_overlap(lbib_ctx* ctx, int32_t enable);
 
 /* Captured step blocks of lbib_step: enable = 1 replays them; 0 and -1 (the

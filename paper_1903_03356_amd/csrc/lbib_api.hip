@@ -88,7 +88,7 @@ struct lbib_ctx {
     std::vector<double> cap_kb, cap_P0;
     std::vector<int> cap_rigid;
     // overlapped schedule: far part of the grid step on a second stream
-    // (-1 automatic: large lattices only; 0 off; 1 on)
+    // (-1 automatic: large lattices only; 0 off; 1 on; 2 on, queue-level waits only)
     int overlap = -1;
     double contact_cutoff = 0.0;  // Eq. 27 contact force below this node distance; 0 = off
     hipStream_t s_far = nullptr;
@@ -1009,7 +1009,7 @@ static lbib_status step_overlap_t(lbib_ctx* c, int nsteps)
     // it, batches and smaller lattices wait on the queue.
     long long cells = 0;
     for (const Inst& I : c->L.inst) cells += (long long)I.grid.nx * I.grid.ny;
-    const bool inside = c->L.inst.size() == 1 && cells >= kFarWaitInsideCells;
+    const bool inside = c->L.inst.size() == 1 && cells >= kFarWaitInsideCells && c->overlap != 2;
     for (int k = 0; k < nsteps; k++) {
         const long long n = c->steps + k;
         long long nn = n;
@@ -1134,7 +1134,7 @@ static lbib_status step_t(lbib_ctx* c, int nsteps)
     // -19 % at 1.0 M).  A batch of small lattices loses (256 lattices,
     // 8.0 M cells, 388 capsules: -17 %, the IB launch runs 2.4x longer beside
     // the far pass), so a batch splits only when asked.
-    const bool want = c->overlap == 1 || (c->overlap < 0 && c->L.inst.size() == 1 &&
+    const bool want = c->overlap >= 1 || (c->overlap < 0 && c->L.inst.size() == 1 &&
                                           cells >= kOverlapMinCells);
     if (can_overlap && want) return step_overlap_t<T>(c, nsteps);
     // replays of captured blocks for the inner steps; timed runs launch directly
@@ -1769,7 +1769,7 @@ extern "C" lbib_status lbib_set_contact(lbib_ctx* c, double cutoff)
 extern "C" lbib_status lbib_set_overlap(lbib_ctx* c, int32_t enable)
 {
     if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
-    if (enable < -1 || enable > 1) return fail(c, LBIB_EINVAL, "enable must be -1, 0 or 1");
+    if (enable < -1 || enable > 2) return fail(c, LBIB_EINVAL, "enable must be -1, 0, 1 or 2");
     c->overlap = enable;
     return LBIB_OK;
 }

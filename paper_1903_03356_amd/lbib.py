@@ -335,10 +335,13 @@ class Sim:
         with self.torch.cuda.device(self.device):
             _check(load().lbib_set_contact(self.h, float(cutoff)), self.h)
 
-    def set_overlap(self, enable) -> None:
+    def set_overlap(self, enable, queue_waits: bool = False) -> None:
         """True / False force the overlapped schedule on / off; None restores
-        the automatic choice (a single lattice of 2^22 cells or more)."""
-        v = -1 if enable is None else (1 if enable else 0)
+        the automatic choice (a single lattice of 2^22 cells or more).
+        queue_waits=True (with enable=True) keeps every hand-off between the
+        two streams on the queue (lbib_set_overlap(ctx, 2)), for tools that run
+        kernels one at a time."""
+        v = -1 if enable is None else ((2 if queue_waits else 1) if enable else 0)
         _check(load().lbib_set_overlap(self.h, v), self.h)
 
     def set_graph(self, enable) -> None:

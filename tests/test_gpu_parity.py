@@ -237,22 +237,28 @@ def test_overlapped_schedule_full_size_is_bit_identical():
     and timed launches."""
     from paper_1903_03356_amd import lbib
     cfg = wl.fused_bench(seed=0, n=4096)
-    log("fused 4096 split vs single pass: 60 steps each")
+    log("fused 4096 split (device-side and queue-level waits) vs single pass: 60 steps each")
     a = lbib.Sim(cfg)
     b = lbib.Sim(cfg)
-    a.set_overlap(None)  # automatic: this size splits
+    q = lbib.Sim(cfg)
+    a.set_overlap(None)  # automatic: this size splits, far kernels wait on the device
     b.set_overlap(False)
+    q.set_overlap(True, queue_waits=True)
     for chunk in (1, 27, 32):
         a.set_timing(chunk == 32)  # untimed launches mark their events themselves
-        a.step(chunk)
-        b.step(chunk)
+        for s in (a, b, q):
+            s.step(chunk)
     assert a.get_timing()["near_launches"] == 32  # the split ran
-    assert a.check() == 0 and b.check() == 0
+    assert a.check() == 0 and b.check() == 0 and q.check() == 0
     assert np.array_equal(a.force(), b.force())
+    assert np.array_equal(q.force(), b.force())
     for c in range(len(cfg["capsules"])):
-        for x, y in zip(a.capsule(c), b.capsule(c)):
+        for x, y, z in zip(a.capsule(c), b.capsule(c), q.capsule(c)):
             assert np.array_equal(x, y), c
-    assert np.array_equal(a.pops_dev(), b.pops_dev())
+            assert np.array_equal(z, y), c
+    pb = b.pops_dev()
+    assert np.array_equal(a.pops_dev(), pb)
+    assert np.array_equal(q.pops_dev(), pb)
     log("fused 4096 split vs single pass: done")
 
 
