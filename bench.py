@@ -150,7 +150,7 @@ def bench_ensemble(steps: int, warmup: int, loop_steps: int):
     bat.step(warmup)
     torch.cuda.synchronize()
     tune = bat.autotune(20)  # tile shape of the batched grid pass
-    log(f"ensemble autotune: rows {tune['rows']}, linear {tune['linear']}, resident "
+    log(f"ensemble autotune: rows {tune['rows']}, order {tune['order']}, resident "
         f"{tune['resident']}; {tune['us']}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -220,25 +220,26 @@ def bench_ensemble(steps: int, warmup: int, loop_steps: int):
         "ib_kernel_us": round(ib_us, 2),
         "graph_ms_per_step": round(t_graph * 1e3, 4),
         "overlapped_ms_per_step": round(t_split * 1e3, 4),
-        "tile": {"rows": tune["rows"], "linear": tune["linear"], "resident": tune["resident"]},
+        "tile": {"rows": tune["rows"], "order": tune["order"], "resident": tune["resident"]},
         "tile_candidates_us": tune["us"],
     }
 
 
-def bench_ensemble_grid(steps: int, warmup: int):
-    """Only the 256-lattice batch, stepped in the tile shape the autotuner keeps
-    on it (linear tile order, one row per thread), for counter collection: no
-    tuning trials, timing events, graph or split copies and no per-simulation
-    loop, so that the profiled process holds few dispatches besides the
-    batched grid and IB launches."""
+def bench_ensemble_grid(steps: int, warmup: int, tile: str = "chunked,1,0"):
+    """Only the 256-lattice batch, stepped in a fixed tile shape ("order,rows,
+    resident", by default the one the autotuner keeps on it), for counter
+    collection: no tuning trials, timing events, graph or split copies and no
+    per-simulation loop, so that the profiled process holds few dispatches
+    besides the batched grid and IB launches."""
     import torch
     from paper_1903_03356_amd import lbib
     from paper_1903_03356_amd import workloads as wl
 
     cfgs = wl.ensemble(seed=0)
     cells = sum(c["nx"] * c["ny"] for c in cfgs)
+    order, rows, resident = tile.split(",")
     bat = lbib.Batch(cfgs)
-    bat.set_tile(1, 0, True)
+    bat.set_tile(int(rows), int(resident), order)
     bat.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -250,7 +251,8 @@ def bench_ensemble_grid(steps: int, warmup: int):
         raise RuntimeError(f"device flags {flags} in the batched ensemble")
     return {"workload": f"{len(cfgs)} independent Dynamic-IB channels (seed 0), {cells} cells",
             "cells": cells, "steps": steps, "ms_per_step": round(t * 1e3, 4),
-            "mlups": round(cells / t / 1e6, 1), "tile": {"rows": 1, "linear": True, "resident": 0}}
+            "mlups": round(cells / t / 1e6, 1),
+            "tile": {"rows": int(rows), "order": order, "resident": int(resident)}}
 
 
 def bench_adjoint(mode: str, steps: int):
@@ -378,6 +380,8 @@ def main() -> int:
                          "which runs kernels one at a time)")
     ap.add_argument("--only-ensemble-grid", action="store_true",
                     help="only the batched ensemble, stepped in a fixed tile shape (counter runs)")
+    ap.add_argument("--tile", default="chunked,1,0",
+                    help="tile shape order,rows,resident of --only-ensemble-grid")
     ap.add_argument("--only-adjoint", action="store_true",
                     help="only the gradient cost against the forward run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -407,7 +411,8 @@ def main() -> int:
         print(json.dumps({"batched": ens}), flush=True)
         return 0
     if args.only_ensemble_grid:
-        print(json.dumps({"batched_grid": bench_ensemble_grid(args.steps, args.warmup)}), flush=True)
+        print(json.dumps({"batched_grid": bench_ensemble_grid(args.steps, args.warmup, args.tile)}),
+              flush=True)
         return 0
     if args.only_adjoint:
         adj = [bench_adjoint("dynamic", 500), bench_adjoint("kinematic", 5000)]

@@ -287,10 +287,12 @@ int64_t lbib_graph_replays(const lbib_ctx* ctx);
 
 /* Tile shape of the batched grid pass of a batch context (more than one
  * lattice).  rows = nodes per thread (1, 2 or 4): a block of 4 wavefronts
- * covers a 64-cell segment of a band of 4 * rows rows.  linear = 0 deals each
- * lattice's bands to the 8 XCDs in groups of 8 (a band and its x-neighbours
- * stay in one XCD's L2; bands padded to a multiple of 8), linear = 1 orders
- * the tiles band by band, segment by segment (no band padding).  resident = 0
+ * covers a 64-cell segment of a band of 4 * rows rows.  linear = the tile
+ * order: 0 deals each lattice's bands to the 8 XCDs in groups of 8 (a band and
+ * its x-neighbours stay in one XCD's L2; bands padded to a multiple of 8);
+ * 1 orders the tiles band by band, segment by segment (no band padding);
+ * 2 cuts that linear order into 8 runs of consecutive tiles, one per XCD (a
+ * tile's x- and y-neighbours mostly in the same L2; no band padding).  resident = 0
  * launches one block per tile; k in 1..64 launches k blocks per compute unit
  * (rounded to a multiple of 8) that loop over the tiles (a persistent launch).
  * Every shape computes the same bits.  The default is rows 1, linear 0,
@@ -298,13 +300,13 @@ int64_t lbib_graph_replays(const lbib_ctx* ctx);
 lbib_status lbib_set_tile(lbib_ctx* ctx, int32_t rows, int32_t linear, int32_t resident);
 
 /* Autotuner of the batched grid pass: times every tile shape (rows 1, 2, 4 with
- * linear 0, then rows 1, 2, 4 with linear 1; each with resident 0, 2, 4, 8:
- * out_us[4 * shape + resident index], 24 values) over `launches` grid passes
+ * linear 0, then with linear 1, then with linear 2; each with resident 0, 2, 4,
+ * 8: out_us[4 * shape + resident index], 36 values) over `launches` grid passes
  * each on the context's own lattices and current state, with HIP events on
  * the bound stream, and keeps the fastest for lbib_step.  The trial passes
  * read no IB force and leave the state unchanged (they write only the
  * population buffer the next step overwrites).  Call it between lbib_step
- * calls.  Outputs (host, each may be NULL): the chosen rows, linear flag and
+ * calls.  Outputs (host, each may be NULL): the chosen rows, tile order and
  * resident count, and up to n_us of the mean times per pass in us.  Waits for
  * the stream.  Errors: EINVAL (single-lattice context, launches not in
  * [1, 1000]), EDEVICE. */

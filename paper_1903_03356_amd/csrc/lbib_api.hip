@@ -21,6 +21,15 @@ struct TimedLaunch {
     hipEvent_t start, stop;
 };
 
+// Tile shapes of the batched grid pass: nodes per thread (rows of a band / 4)
+// and the tile order (0 banded groups of 8 bands, 1 linear over band and
+// segment, 2 chunked: linear runs of a lattice's tiles, one per XCD)
+constexpr int kTileShapes = 9;
+constexpr int kTileRows[kTileShapes] = {1, 2, 4, 1, 2, 4, 1, 2, 4};
+constexpr int kTileOrder[kTileShapes] = {0, 0, 0, 1, 1, 1, 2, 2, 2};
+// Candidate resident blocks per compute unit of the persistent launch (0: one
+// block per tile)
+constexpr int kTileResident[4] = {0, 2, 4, 8};
 // Host record of one lattice and where its arrays sit in the shared buffers.
 struct Inst {
     lbib_grid grid;
@@ -30,24 +39,16 @@ struct Inst {
     size_t pop_off = 0;   // elements of a population buffer
     size_t fib_off = 0;   // long longs of one force level
     size_t flag_off = 0;  // ints of one flag level
-    long long tile0[6] = {0, 0, 0, 0, 0, 0};  // first tile in the batched pass, per tile shape
+    long long tile0[kTileShapes] = {};  // first tile in the batched pass, per tile shape
     int ncap = 0, nodes = 0;
 };
 
-// Tile shapes of the batched grid pass: nodes per thread (rows of a band / 4)
-// and the tile order (banded groups of 8 bands, or linear over band and segment)
-constexpr int kTileShapes = 6;
-constexpr int kTileRows[kTileShapes] = {1, 2, 4, 1, 2, 4};
-constexpr bool kTileLinear[kTileShapes] = {false, false, false, true, true, true};
-// Candidate resident blocks per compute unit of the persistent launch (0: one
-// block per tile)
-constexpr int kTileResident[4] = {0, 2, 4, 8};
 
 // Tiles of one lattice in tile shape k.
 static int lattice_tiles(int ny, int nseg, int k)
 {
-    return kTileLinear[k] ? grid_tiles_linear(ny, nseg, kTileRows[k])
-                          : grid_blocks_rows(ny, nseg, kTileRows[k]);
+    return kTileOrder[k] != 0 ? grid_tiles_linear(ny, nseg, kTileRows[k])
+                              : grid_blocks_rows(ny, nseg, kTileRows[k]);
 }
 
 // Buffer layout of a context: the lattices one after the other in every
@@ -59,11 +60,11 @@ struct Layout {
     int rb = 4;
     size_t pop_elems = 0, fib_level = 0, flag_level = 0;
     int max_caps = 0, max_nodes = 0, max_nv = 0;
-    long long tiles[6] = {0, 0, 0, 0, 0, 0};  // tiles of the batched pass, per tile shape
+    long long tiles[kTileShapes] = {};  // tiles of the batched pass, per tile shape
     size_t plane_max = 0;
     size_t inst_table = 0, round_table = 0, rect_table = 0, near_map = 0, bounds = 0,
            hints = 0;  // in BUF_CAPS
-    size_t round_off[6] = {0, 0, 0, 0, 0, 0};  // the round table of each tile shape
+    size_t round_off[kTileShapes] = {};  // the round table of each tile shape
 };
 
 struct lbib_ctx {
@@ -895,7 +896,7 @@ static hipError_t launch_batch_shape(const lbib_ctx* c, const T* src, T* dst,
 {
     return launch_grid_step_batch<T>(src, dst, fib_now, flags_now, fib_old, flags_old,
                                      inst_table(c), round_table(c, shape), (int)c->L.tiles[shape],
-                                     kTileRows[shape], kTileLinear[shape],
+                                     kTileRows[shape], kTileOrder[shape],
                                      batch_grid(c, shape, resident), any_open(c), far_map, stamp,
                                      status_word(c), st);
 }
@@ -1787,10 +1788,10 @@ extern "C" int64_t lbib_graph_replays(const lbib_ctx* c) { return c ? c->graph_r
 extern "C" lbib_status lbib_set_tile(lbib_ctx* c, int32_t rows, int32_t linear, int32_t resident)
 {
     if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
-    if (linear != 0 && linear != 1) return fail(c, LBIB_EINVAL, "linear must be 0 or 1");
+    if (linear < 0 || linear > 2) return fail(c, LBIB_EINVAL, "linear (tile order) must be 0, 1 or 2");
     int shape = -1;
     for (int k = 0; k < kTileShapes; k++)
-        if (kTileRows[k] == rows && kTileLinear[k] == (linear == 1)) shape = k;
+        if (kTileRows[k] == rows && kTileOrder[k] == linear) shape = k;
     if (shape < 0) return fail(c, LBIB_EINVAL, "rows must be 1, 2 or 4");
     if (resident < 0 || resident > 64) return fail(c, LBIB_EINVAL, "resident must be in [0, 64]");
     c->tile_shape = shape;
@@ -1865,7 +1866,7 @@ extern "C" lbib_status lbib_autotune(lbib_ctx* c, int32_t launches, int32_t* out
                                       : autotune_t<double>(c, launches, us);
     if (st != LBIB_OK) return st;
     if (out_rows) *out_rows = kTileRows[c->tile_shape];
-    if (out_linear) *out_linear = kTileLinear[c->tile_shape] ? 1 : 0;
+    if (out_linear) *out_linear = kTileOrder[c->tile_shape];
     if (out_resident) *out_resident = c->tile_resident;
     for (int i = 0; out_us && i < n_us && i < kTileShapes * 4; i++) out_us[i] = us[i];
     return LBIB_OK;

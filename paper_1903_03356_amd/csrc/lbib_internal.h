@@ -173,7 +173,7 @@ template <typename T>
 hipError_t launch_grid_step_batch(const T* src, T* dst, const long long* fib_now,
                                   const int* flags_now, long long* fib_old, int* flags_old,
                                   const InstDev* inst, const int2* rounds, int tiles, int rows,
-                                  bool linear, int grid, bool any_open, const int* near_map,
+                                  int order, int grid, bool any_open, const int* near_map,
                                   int stamp, int* status, hipStream_t s);
 template <typename T>
 hipError_t launch_grid_far(const T* src, T* dst, const long long* fib_now, const int* flags_now,

@@ -352,14 +352,19 @@ hipError_t launch_grid_near(const T* src, T* dst, const long long* fib_now, cons
 
 // Ensemble of lattices in one launch.  The tiles (a 64-cell segment of a band
 // of 4 * ROWS rows) of every lattice form a run that starts at a multiple of
-// kNumXcd.  rounds[t / 8] = (lattice, first round of that lattice).  Banded
-// (LIN = false): the lattice's bands go in groups of 8, so tile t, processed by
-// a block on XCD t % 8, keeps the band-to-XCD mapping above.  Linear (LIN =
-// true): tile t covers band t / nseg, segment t % nseg of its lattice, with
-// the run padded only to a multiple of 8 tiles (no empty bands).  With
-// gridDim.x < tiles (a multiple of 8) the launch is persistent: each block
-// walks the tiles t = blockIdx.x + k * gridDim.x.
-template <typename T, int ROWS, bool OPEN, bool LIN, bool FAR>
+// kNumXcd.  rounds[t / 8] = (lattice, first round of that lattice); tile t is
+// processed by a block on XCD t % 8.  Tile orders (ORD):
+//   0 banded: the lattice's bands go in groups of 8, which keeps the
+//     band-to-XCD mapping above (bands padded to a multiple of 8);
+//   1 linear: tile t covers band t / nseg, segment t % nseg of its lattice,
+//     the run padded only to a multiple of 8 tiles;
+//   2 chunked: the lattice's T tiles in linear order are cut into 8 runs of
+//     K = ceil(T / 8) consecutive tiles, one per XCD (tile t covers linear
+//     tile (t % 8) K + t / 8), so that most of a tile's x- and y-neighbours sit
+//     in the same XCD's L2; same padding as linear.
+// With gridDim.x < tiles (a multiple of 8) the launch is persistent: each
+// block walks the tiles t = blockIdx.x + k * gridDim.x.
+template <typename T, int ROWS, bool OPEN, int ORD, bool FAR>
 __global__ __launch_bounds__(kSegW * 4) void k_grid_step_batch(
     const T* __restrict__ src, T* __restrict__ dst, const long long* __restrict__ fib_now,
     const int* __restrict__ flags_now, long long* __restrict__ fib_old,
@@ -373,9 +378,15 @@ __global__ __launch_bounds__(kSegW * 4) void k_grid_step_batch(
         const GridArgs g = lattice_args(I);
         const int lb = b - ri.y * kNumXcd;
         int band, seg;
-        if (LIN) {
+        if (ORD == 1) {
             band = lb / g.nseg;
             seg = lb - band * g.nseg;
+        } else if (ORD == 2) {
+            const int bands = (g.ny + 4 * ROWS - 1) / (4 * ROWS);
+            const int K = (bands * g.nseg + kNumXcd - 1) / kNumXcd;
+            const int t = (lb % kNumXcd) * K + lb / kNumXcd;  // padding tiles land beyond the last band
+            band = t / g.nseg;
+            seg = t - band * g.nseg;
         } else {
             const int j = lb / kNumXcd;
             const int group = j / g.nseg;
@@ -413,7 +424,7 @@ int grid_tiles_linear(int ny, int nseg, int rows)
     return (bands * nseg + kNumXcd - 1) / kNumXcd * kNumXcd;
 }
 
-template <typename T, int R, bool LIN>
+template <typename T, int R, int ORD>
 static void launch_batch_rows(const T* src, T* dst, const long long* fib_now, const int* flags_now,
                               long long* fib_old, int* flags_old, const InstDev* inst,
                               const int2* rounds, int tiles, int grid, bool any_open,
@@ -421,34 +432,34 @@ static void launch_batch_rows(const T* src, T* dst, const long long* fib_now, co
 {
     const dim3 gd((unsigned)grid), bd(kSegW * 4);
     if (near_map)  // far part of the split step (periodic lattices only)
-        hipLaunchKernelGGL((k_grid_step_batch<T, R, false, LIN, true>), gd, bd, 0, s, src, dst,
+        hipLaunchKernelGGL((k_grid_step_batch<T, R, false, ORD, true>), gd, bd, 0, s, src, dst,
                            fib_now, flags_now, fib_old, flags_old, inst, rounds, tiles, near_map,
                            stamp, status);
     else if (any_open)
-        hipLaunchKernelGGL((k_grid_step_batch<T, R, true, LIN, false>), gd, bd, 0, s, src, dst,
+        hipLaunchKernelGGL((k_grid_step_batch<T, R, true, ORD, false>), gd, bd, 0, s, src, dst,
                            fib_now, flags_now, fib_old, flags_old, inst, rounds, tiles, near_map,
                            stamp, status);
     else
-        hipLaunchKernelGGL((k_grid_step_batch<T, R, false, LIN, false>), gd, bd, 0, s, src, dst,
+        hipLaunchKernelGGL((k_grid_step_batch<T, R, false, ORD, false>), gd, bd, 0, s, src, dst,
                            fib_now, flags_now, fib_old, flags_old, inst, rounds, tiles, near_map,
                            stamp, status);
 }
 
-template <typename T, bool LIN>
-static hipError_t launch_batch_lin(const T* src, T* dst, const long long* fib_now,
+template <typename T, int ORD>
+static hipError_t launch_batch_order(const T* src, T* dst, const long long* fib_now,
                                    const int* flags_now, long long* fib_old, int* flags_old,
                                    const InstDev* inst, const int2* rounds, int tiles, int rows,
                                    int grid, bool any_open, const int* near_map, int stamp,
                                    int* status, hipStream_t s)
 {
     if (rows == 1)
-        launch_batch_rows<T, 1, LIN>(src, dst, fib_now, flags_now, fib_old, flags_old, inst,
+        launch_batch_rows<T, 1, ORD>(src, dst, fib_now, flags_now, fib_old, flags_old, inst,
                                      rounds, tiles, grid, any_open, near_map, stamp, status, s);
     else if (rows == 2)
-        launch_batch_rows<T, 2, LIN>(src, dst, fib_now, flags_now, fib_old, flags_old, inst,
+        launch_batch_rows<T, 2, ORD>(src, dst, fib_now, flags_now, fib_old, flags_old, inst,
                                      rounds, tiles, grid, any_open, near_map, stamp, status, s);
     else if (rows == 4)
-        launch_batch_rows<T, 4, LIN>(src, dst, fib_now, flags_now, fib_old, flags_old, inst,
+        launch_batch_rows<T, 4, ORD>(src, dst, fib_now, flags_now, fib_old, flags_old, inst,
                                      rounds, tiles, grid, any_open, near_map, stamp, status, s);
     else
         return hipErrorInvalidValue;
@@ -459,18 +470,28 @@ template <typename T>
 hipError_t launch_grid_step_batch(const T* src, T* dst, const long long* fib_now,
                                   const int* flags_now, long long* fib_old, int* flags_old,
                                   const InstDev* inst, const int2* rounds, int tiles, int rows,
-                                  bool linear, int grid, bool any_open, const int* near_map,
+                                  int order, int grid, bool any_open, const int* near_map,
                                   int stamp, int* status, hipStream_t s)
 {
     if (tiles <= 0) return hipSuccess;
     if (grid <= 0 || grid > tiles || grid % kNumXcd != 0) return hipErrorInvalidValue;
     if (near_map && any_open) return hipErrorInvalidValue;
-    return linear ? launch_batch_lin<T, true>(src, dst, fib_now, flags_now, fib_old, flags_old,
-                                              inst, rounds, tiles, rows, grid, any_open, near_map,
-                                              stamp, status, s)
-                  : launch_batch_lin<T, false>(src, dst, fib_now, flags_now, fib_old, flags_old,
-                                               inst, rounds, tiles, rows, grid, any_open, near_map,
-                                               stamp, status, s);
+    switch (order) {
+    case 0:
+        return launch_batch_order<T, 0>(src, dst, fib_now, flags_now, fib_old, flags_old, inst,
+                                        rounds, tiles, rows, grid, any_open, near_map, stamp,
+                                        status, s);
+    case 1:
+        return launch_batch_order<T, 1>(src, dst, fib_now, flags_now, fib_old, flags_old, inst,
+                                        rounds, tiles, rows, grid, any_open, near_map, stamp,
+                                        status, s);
+    case 2:
+        return launch_batch_order<T, 2>(src, dst, fib_now, flags_now, fib_old, flags_old, inst,
+                                        rounds, tiles, rows, grid, any_open, near_map, stamp,
+                                        status, s);
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 // ------------------------------------------------------------ init kernel
@@ -1944,7 +1965,7 @@ hipError_t launch_set_nodes(T* nodes, CapsuleDev* caps, int cap, int nv, int nod
                                             long long*, int*, const GridArgs&, hipStream_t);      \
     template hipError_t launch_grid_step_batch<T>(const T*, T*, const long long*, const int*,     \
                                                   long long*, int*, const InstDev*, const int2*,  \
-                                                  int, int, bool, int, bool, const int*, int,     \
+                                                  int, int, int, int, bool, const int*, int,      \
                                                   int*, hipStream_t);                             \
     template hipError_t launch_grid_far<T>(const T*, T*, const long long*, const int*,            \
                                            long long*, int*, const int*, int, int*,               \

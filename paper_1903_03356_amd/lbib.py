@@ -40,6 +40,7 @@ EXPORTS = ["lbib_required_bytes", "lbib_create", "lbib_add_capsule", "lbib_step"
            "lbib_set_contact", "lbib_add_rigid_to"]
 OBJ_TAYLOR, OBJ_CENTROID_Y = 0, 1
 ADJOINT_SCRATCH_BYTES = 64 * 1024 * 1024  # LBIB_ADJOINT_SCRATCH_BYTES
+TILE_ORDERS = ("banded", "linear", "chunked")  # tile orders of the batched grid pass
 
 
 class lbib_grid(C.Structure):
@@ -354,21 +355,26 @@ class Sim:
     def graph_replays(self) -> int:
         return int(load().lbib_graph_replays(self.h))
 
-    def set_tile(self, rows: int, resident: int = 0, linear: bool = False) -> None:
-        """Tile shape of the batched grid pass (lbib_set_tile)."""
-        _check(load().lbib_set_tile(self.h, int(rows), 1 if linear else 0, int(resident)), self.h)
+    def set_tile(self, rows: int, resident: int = 0, linear=False) -> None:
+        """Tile shape of the batched grid pass (lbib_set_tile).  ``linear`` is
+        the tile order: False / 0 banded, True / 1 linear, "chunked" / 2."""
+        order = TILE_ORDERS.index(linear) if isinstance(linear, str) else int(linear)
+        _check(load().lbib_set_tile(self.h, int(rows), order, int(resident)), self.h)
 
     def autotune(self, launches: int = 20) -> Dict[str, Any]:
-        """lbib_autotune: times the 24 tile shapes of the batched grid pass and
-        keeps the fastest; returns the choice and the mean time per pass (us)
-        of every (order, rows, resident) candidate."""
+        """lbib_autotune: times the 36 tile shapes of the batched grid pass and
+        keeps the fastest; returns the choice (``order`` one of TILE_ORDERS,
+        ``linear`` its index) and the mean time per pass (us) of every (order,
+        rows, resident) candidate."""
         rows, lin, res = C.c_int32(), C.c_int32(), C.c_int32()
-        us = (C.c_double * 24)()
+        n = 4 * 3 * len(TILE_ORDERS)
+        us = (C.c_double * n)()
         with self.torch.cuda.device(self.device):
             _check(load().lbib_autotune(self.h, int(launches), C.byref(rows), C.byref(lin),
-                                        C.byref(res), us, 24), self.h)
-        cands = [(o, r, k) for o in ("banded", "linear") for r in (1, 2, 4) for k in (0, 2, 4, 8)]
-        return {"rows": rows.value, "linear": bool(lin.value), "resident": res.value,
+                                        C.byref(res), us, n), self.h)
+        cands = [(o, r, k) for o in TILE_ORDERS for r in (1, 2, 4) for k in (0, 2, 4, 8)]
+        return {"rows": rows.value, "linear": lin.value, "order": TILE_ORDERS[lin.value],
+                "resident": res.value,
                 "us": {f"{o}_rows{r}_resident{k}": round(us[i], 2)
                        for i, (o, r, k) in enumerate(cands)}}
 

@@ -242,11 +242,11 @@ def _same_batches(a, b, n_lattices):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("linear", [False, True])
+@pytest.mark.parametrize("linear", [False, True, "chunked"])
 @pytest.mark.parametrize("rows", [1, 2, 4])
 def test_every_tile_shape_is_bit_identical(rows, linear):
-    """The tile shapes of the batched grid pass (rows per thread, banded or
-    linear tile order, one block per tile or a persistent launch) compute the
+    """The tile shapes of the batched grid pass (rows per thread, banded,
+    linear or chunked tile order, one block per tile or a persistent launch) compute the
     same bits as the default, on lattices with ragged rows and segments, walls,
     a Couette channel and a periodic box."""
     cfgs = _mixed_lattices() + wl.ensemble(seed=4, n_inst=4)
@@ -270,7 +270,8 @@ def test_autotune_picks_a_shape_and_keeps_the_state():
     r = a.autotune(3)
     log(f"autotune: {r}")
     assert r["rows"] in (1, 2, 4) and r["resident"] in (0, 2, 4, 8)
-    assert len(r["us"]) == 24 and all(v > 0 for v in r["us"].values())
+    assert len(r["us"]) == 36 and all(v > 0 for v in r["us"].values())
+    assert r["order"] in lbib.TILE_ORDERS
     _same_batches(a, b, len(cfgs))  # tuning leaves the state alone
     a.step(25)
     b.step(25)
@@ -294,7 +295,8 @@ def test_tile_arguments_are_checked():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("rows,linear,resident", [(1, False, 0), (2, True, 0), (4, True, 8)])
+@pytest.mark.parametrize("rows,linear,resident", [(1, False, 0), (2, True, 0), (4, True, 8),
+                                                  (1, "chunked", 0), (2, "chunked", 4)])
 def test_overlapped_batch_is_bit_identical(rows, linear, resident):
     """The near / far split over a batch (each capsule's near region on its own
     lattice, the far part as the batched pass in the chosen tile shape, beside
