@@ -612,6 +612,67 @@ def test_p15_kinematic_deformation_grows_with_g(orc):
     assert d[0] < d[1] < d[2], d
 
 
+# Sec. 3.1 and Sec. 3.2 report the two couplings in close agreement (both
+# within 1 % of the benchmark in shear; a relative gap in the perimeter change
+# that falls with Ca, 3.8e-3 at Ca = 1e-1 down to 1e-4 at Ca = 1e-4).  The
+# Dynamic steps as printed do not reach that: the tentative velocity of Eq. 23
+# is the fluid's, so each step the node restarts from the fluid velocity and
+# its BDF2 velocity (Eq. 24) exceeds the fluid's by about F_tot / (2 m_v); the
+# direct forcing (steps 1-3) hands the fluid c_v times that slip, i.e. only
+# kappa / (1 + beta kappa) of the membrane force, kappa = ds / (2 m_v) (= 1/R
+# for a circle with the area mass) and beta the share of the traction jump the
+# probes of Eqs. 15-16 see (about 0.5 measured).  The capsule therefore deforms
+# as a much softer one, and the loop with the BDF2 target grows a node-scale
+# mode once its gain passes about 2/3.  These two pins state the paper's
+# results and fail on the printed scheme; they stay as strict expected
+# failures so that a change of reading that meets them shows up.
+DYN_XFAIL = ("the printed weak Dynamic coupling passes the fluid only about ds / (2 m_v) of "
+             "the membrane force and grows a node-scale mode (see the note above)")
+
+
+@pytest.mark.xfail(strict=True, reason=DYN_XFAIL)
+def test_p15_steady_shear_dynamic_agrees_with_kinematic(orc):
+    """Sec. 3.1: the centred capsule in shear (64 x 64, G = 0.05, E_b = 0.05,
+    rho_s / rho_f = 1) reaches the same steady Taylor deformation with both
+    couplings, within 2 %."""
+    orc.set_threads(min(8, os.cpu_count() or 1))
+    d = {}
+    for mode in ("kinematic", "dynamic"):
+        sim = orc.Sim(wl.shear_capsule(mode=mode))
+        sim.step(6000)
+        d[mode] = sim.diag(0)["D"]
+    assert abs(d["dynamic"] / d["kinematic"] - 1.0) < 0.02, d
+
+
+@pytest.mark.slow
+@pytest.mark.xfail(strict=True, reason=DYN_XFAIL)
+def test_p16_dynamic_kinematic_gap_falls_with_ca(orc):
+    """Sec. 3.2: a circular capsule at 6.5 / 15 of a Poiseuille channel, both
+    couplings run to t u_max / H = 2; the relative gap in the perimeter change
+    eps = |dp_Dyn - dp_Kin| / |dp_Kin| falls as Ca falls and is of the order of
+    the paper's values (below 1e-2 at Ca = 1e-3)."""
+    orc.set_threads(min(8, os.cpu_count() or 1))
+    nx, ny, tau, u_max = 128, 49, 0.8, 0.02
+    H = ny - 1
+    steps = int(2 * H / u_max)
+    eps = {}
+    for ca in (1e-1, 1e-2, 1e-3):
+        dp = {}
+        for mode in ("kinematic", "dynamic"):
+            cfg = wl._base("p16", nx, ny, tau, 8, mode, steps,
+                           body_force_x=wl.poiseuille_body_force(tau, ny, u_max),
+                           init_profile=wl.INIT_POISEUILLE)
+            cfg["capsules"] = [wl.capsule(wl.circle_nodes(40.0, 6.5 / 15.0 * H, 6.0, 48),
+                                          wl.ks_from_ca(tau, u_max, ca), 0.0, 1.0, 1.0)]
+            sim = orc.Sim(cfg)
+            sim.step(steps)
+            dp[mode] = sim.diag(0)["dp"]
+        eps[ca] = abs(dp["dynamic"] - dp["kinematic"]) / abs(dp["kinematic"])
+    assert all(np.isfinite(v) for v in eps.values()), eps
+    assert eps[1e-3] < eps[1e-2] < eps[1e-1], eps
+    assert eps[1e-3] < 1e-2, eps
+
+
 # ---- Eq. 27: contact repulsion between capsules ------------------------------
 
 def _diamond(cx, cy, h=2.0):
