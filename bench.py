@@ -34,6 +34,7 @@ import json
 import numpy as np
 import os
 import re
+import subprocess
 import sys
 import time
 
@@ -43,6 +44,20 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS & % HBM peak, fused LBM-IB step; batched speedup; adjoint/fwd cost"
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_CELL = 72  # 9 reads + 9 writes of FP32 populations
+
+
+def ca_summary(caps) -> dict:
+    """Capillary numbers of the drawn capsules: the draw is log-uniform in
+    [1e-3, 1e-1], with capsules whose explicit node update would be unstable
+    (2 k_s / m_v > 1.5) drawn again, so stiff capsules are fewer than the
+    plain draw gives (50 % below 1e-2, 24 % below 3e-3)."""
+    ca = np.array([c["ca"] for c in caps if "ca" in c])
+    if ca.size == 0:
+        return {}
+    return {"draw": "log-uniform [1e-3, 1e-1], redrawn where 2 k_s / m_v > 1.5",
+            "count": int(ca.size), "min": float(ca.min()), "median": float(np.median(ca)),
+            "frac_below_1e-2": round(float(np.mean(ca < 1e-2)), 3),
+            "frac_below_3e-3": round(float(np.mean(ca < 3e-3)), 3)}
 
 
 def log(msg: str) -> None:
@@ -221,6 +236,7 @@ def bench_ensemble(steps: int, warmup: int, loop_steps: int):
         "graph_ms_per_step": round(t_graph * 1e3, 4),
         "overlapped_ms_per_step": round(t_split * 1e3, 4),
         "tile": {"rows": tune["rows"], "order": tune["order"], "resident": tune["resident"]},
+        "ca": ca_summary([cap for c in cfgs for cap in c["capsules"]]),
         "tile_candidates_us": tune["us"],
     }
 
@@ -334,8 +350,16 @@ def cpu_model() -> str:
 
 def cpu_baseline(cfg, budget_s: float = 20.0, single_s: float = 10.0):
     """The FP64 oracle on the host: all threads for about budget_s seconds of
-    steps (the reported value), then one thread for about single_s seconds."""
+    steps (the reported value), then one thread for about single_s seconds.
+    The oracle source is compiled here for this host (-O3 -march=native)."""
+    import tempfile
     from oracle import oracle as orc
+
+    build = "gcc -O3 -march=native"
+    try:
+        orc.LIB = orc.build_native(os.path.join(tempfile.mkdtemp(), "liblbib_oracle_native.so"))
+    except (OSError, subprocess.CalledProcessError) as e:  # keep the in-tree -O2 build
+        build = f"in-tree gcc -O2 build (native build failed: {e})"
 
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     cells = cfg["nx"] * cfg["ny"]
@@ -360,7 +384,7 @@ def cpu_baseline(cfg, budget_s: float = 20.0, single_s: float = 10.0):
                       f"{len(cfg['capsules'])} capsules (FP64 oracle, {t:.1f} s)",
             "single_thread_mlups": round(cells * n1 / t1 / 1e6, 3),
             "single_thread_sample": f"{n1} steps on one thread ({t1:.1f} s)",
-            "cpu_model": cpu_model()}
+            "cpu_model": cpu_model(), "build": build}
 
 
 def main() -> int:
@@ -524,7 +548,7 @@ def main() -> int:
             "workload": f"fused Dynamic-IB step, {args.n}x{args.n} D2Q9 channel, "
                         f"{len(cfg['capsules'])} capsules ({nodes} nodes), FP32 populations",
             "nx": cfg["nx"], "ny": cfg["ny"], "tau": cfg["tau"], "capsules": len(cfg["capsules"]),
-            "nodes": nodes, "seed": 0, "mode": "dynamic",
+            "nodes": nodes, "seed": 0, "mode": "dynamic", "ca": ca_summary(cfg["capsules"]),
         },
         "roofline": {
             "bound": "hbm",

@@ -64,8 +64,10 @@ enum lbib_device_flags {
     LBIB_FLAG_OVERFLOW = 8,   /* a spread force left the fixed-point range (|f| >= 2^14) */
     LBIB_FLAG_MOVE = 16,      /* a node moved one lattice unit or more in one step */
     LBIB_FLAG_NEAR = 32,      /* overlapped schedule: an IB force outside the near regions */
-    LBIB_FLAG_SYNC = 64       /* overlapped schedule: a far-pass block stopped waiting for the IB
-                                 launch of its step (about 0.2 s); that step is not valid */
+    LBIB_FLAG_SYNC = 64,      /* overlapped schedule: a far-pass block stopped waiting for the IB
+                                 launch of its step (about 0.05 s); that step is not valid */
+    LBIB_FLAG_EDGE = 128,     /* an element longer than the limit of lbib_set_limits */
+    LBIB_FLAG_AREA = 256      /* |A / A0 - 1| beyond the limit of lbib_set_limits */
 };
 
 typedef struct {
@@ -274,6 +276,16 @@ lbib_status lbib_set_contact(lbib_ctx* ctx, double cutoff);
  * 0.05 s per block and raises LBIB_FLAG_SYNC.  Results are the same bits in
  * every schedule.  Errors: EINVAL (other values). */
 lbib_status lbib_set_overlap(lbib_ctx* ctx, int32_t enable);
+
+/* Membrane checks of the force pass (Eqs. 11-14, evaluated at every step's
+ * internal forces): max_edge > 0 raises LBIB_FLAG_EDGE when an element grows
+ * longer than max_edge lattice units (Sec. 3.2 keeps the element length below
+ * the lattice spacing, or the direct forcing may leave holes in the membrane:
+ * max_edge = 1); max_area_change > 0 raises LBIB_FLAG_AREA when the enclosed
+ * area leaves A0 by more than that fraction (the penalty of Eq. 14 holds it
+ * close).  0 switches a check off; both are off by default.  The flags report
+ * and stop nothing.  Errors: EINVAL (negative or non-finite values). */
+lbib_status lbib_set_limits(lbib_ctx* ctx, double max_edge, double max_area_change);
 
 /* Captured step blocks of lbib_step: enable = 1 replays them; 0 and -1 (the
  * default, automatic) launch every step directly (on MI355X the replays

@@ -36,6 +36,17 @@ def build(force: bool = True) -> str:
     return LIB
 
 
+def build_native(out: str) -> str:
+    """The same source built for the host it runs on (gcc -O3 -march=native),
+    used for the CPU-baseline timing; ``LIB`` must point at it before the
+    first ``lib()`` call."""
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-std=c11", "-D_DEFAULT_SOURCE",
+                           "-fopenmp", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
 _lib: Optional[C.CDLL] = None
 
 

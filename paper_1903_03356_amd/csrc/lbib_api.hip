@@ -122,6 +122,8 @@ struct lbib_ctx {
     // there phase A writes no node state), so the next call starts with the
     // grid pass.  set_state drops it (the state it was computed from changes).
     bool a_ready = false;
+    // membrane checks (lbib_set_limits), 0 = off
+    float max_edge = 0.0f, max_dA = 0.0f;
 };
 
 // ------------------------------------------------- static gradient scratch
@@ -830,6 +832,8 @@ static IBArgs<T> ib_args(const lbib_ctx* c, long long n, int phase)
     a.contact = c->contact_cutoff > 0.0;
     a.hints = reinterpret_cast<int4*>(bufp(c, LBIB_BUF_CAPS) + c->L.hints);
     a.done_count = nullptr;
+    a.max_edge = c->max_edge;
+    a.max_dA = c->max_dA;
     return a;
 }
 
@@ -1772,6 +1776,16 @@ extern "C" lbib_status lbib_set_overlap(lbib_ctx* c, int32_t enable)
     if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
     if (enable < -1 || enable > 2) return fail(c, LBIB_EINVAL, "enable must be -1, 0, 1 or 2");
     c->overlap = enable;
+    return LBIB_OK;
+}
+
+extern "C" lbib_status lbib_set_limits(lbib_ctx* c, double max_edge, double max_area_change)
+{
+    if (!c) return fail(nullptr, LBIB_EINVAL, "ctx is NULL");
+    if (!(max_edge >= 0.0 && max_edge < 1e30) || !(max_area_change >= 0.0 && max_area_change < 1e30))
+        return fail(c, LBIB_EINVAL, "limits must be finite and >= 0");
+    c->max_edge = (float)max_edge;
+    c->max_dA = (float)max_area_change;
     return LBIB_OK;
 }
 

@@ -83,7 +83,7 @@ constexpr int kDiagStride = 16;  // doubles per capsule in BUF_DIAG
 
 enum StatusBits {
     ST_WALL = 1, ST_NONFINITE = 2, ST_PATCH = 4, ST_OVERFLOW = 8, ST_MOVE = 16, ST_NEAR = 32,
-    ST_SYNC = 64
+    ST_SYNC = 64, ST_EDGE = 128, ST_AREA = 256
 };
 
 // Bounded wait of the far pass for the IB launch of its step (overlapped
@@ -133,6 +133,9 @@ struct IBArgs {
     // overlapped schedule: each block adds 1 here once all its stores are
     // visible device-wide, so that the far pass can tell the launch is over
     unsigned long long* done_count;
+    // membrane checks of the force pass, 0 = off: longest element length and
+    // largest |A / A0 - 1| before ST_EDGE / ST_AREA
+    float max_edge, max_dA;
 };
 
 // Node tape of the gradient runs: per time level, the fields NF_HX .. NF_UY

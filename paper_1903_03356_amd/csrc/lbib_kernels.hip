@@ -721,7 +721,7 @@ __device__ __forceinline__ T stretch(const Scratch<T>& S, int l, int m, T l0h, T
 // The area A is an FP64 block reduction.
 template <typename T>
 __device__ void internal_forces(const Scratch<T>& S, int nv, double kb, double ka, double A0,
-                                double (*red)[8])
+                                double (*red)[8], float max_edge, float max_dA, int& st)
 {
     const T* l0 = S.l0;
     const T* l0l = S.l0l;
@@ -738,6 +738,8 @@ __device__ void internal_forces(const Scratch<T>& S, int nv, double kb, double k
     block_sum<1>(acc, red);
     const double A = 0.5 * acc[0];
     const T cA = (T)(0.5 * ka * (1.0 - A / A0) / 3.0);  // half element area force per (t_y, -t_x)
+    // enclosed area away from its stress-free value beyond the set limit
+    if (max_dA > 0.0f && tid == 0 && !(fabs(A / A0 - 1.0) <= (double)max_dA)) st |= ST_AREA;
     T* Px = S.t[0];
     T* Py = S.t[1];
     T* Qx = S.t[2];
@@ -747,6 +749,8 @@ __device__ void internal_forces(const Scratch<T>& S, int nv, double kb, double k
         T tx, ty, len;
         edge(S, l, m, tx, ty);
         const T c = ks[l] * stretch(S, l, m, l0[l], l0l[l], len) / len;
+        // an element longer than the set limit (the forcing may leave holes, Sec. 3.2)
+        if (max_edge > 0.0f && !(len <= (T)max_edge)) st |= ST_EDGE;
         const T ax = cA * ty, ay = -cA * tx;
         Px[l] = c * tx + ax;  // onto node l
         Py[l] = c * ty + ay;
@@ -1386,7 +1390,7 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
         double csum[2] = {0.0, 0.0};
         if (cap.rigid) rigid_update(a, S, P, cap, c, st, red, csum);
         if (a.dynamic && !cap.rigid) {
-            internal_forces(S, nv, cap.kb, cap.ka, cap.A0, red);  // -> t8, t9
+            internal_forces(S, nv, cap.kb, cap.ka, cap.A0, red, a.max_edge, a.max_dA, st);  // -> t8, t9
             external_forces(S, P, nv, (T)cap.nu, st);                            // -> t2, t3
         }
         const T half_inv_m = (T)(0.5 / cap.mv);
@@ -1531,7 +1535,7 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
                 S.t[9][v] = cv * Fy;
             }
         } else {
-            internal_forces(S, nv, cap.kb, cap.ka, cap.A0, red);  // -> t8, t9
+            internal_forces(S, nv, cap.kb, cap.ka, cap.A0, red, a.max_edge, a.max_dA, st);  // -> t8, t9
             for (int v = tid; v < nv; v += nt) {
                 if (a.contact) {
                     S.t[8][v] += N[NF_CX * NS + off + v];

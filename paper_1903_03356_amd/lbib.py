@@ -21,8 +21,8 @@ OK, EINVAL, ECAPACITY, EDEVICE, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ECAPACITY", -3: "EDEVICE", -4: "ESTATE",
                 -5: "ENUMERIC"}
 KINEMATIC, DYNAMIC = 0, 1
-FLAG_WALL, FLAG_NONFINITE, FLAG_PATCH, FLAG_OVERFLOW, FLAG_MOVE, FLAG_NEAR, FLAG_SYNC = \
-    1, 2, 4, 8, 16, 32, 64
+(FLAG_WALL, FLAG_NONFINITE, FLAG_PATCH, FLAG_OVERFLOW, FLAG_MOVE, FLAG_NEAR, FLAG_SYNC,
+ FLAG_EDGE, FLAG_AREA) = 1, 2, 4, 8, 16, 32, 64, 128, 256
 NUM_BUFFERS = 8
 BUFFER_NAMES = ["pops_a", "pops_b", "force", "flags", "nodes", "caps", "diag", "stage"]
 # lbib_state_id
@@ -37,7 +37,7 @@ EXPORTS = ["lbib_required_bytes", "lbib_create", "lbib_add_capsule", "lbib_step"
            "lbib_required_bytes_batch", "lbib_create_batch", "lbib_add_capsule_to",
            "lbib_num_lattices", "lbib_adjoint_bytes", "lbib_adjoint", "lbib_adjoint_noalloc",
            "lbib_set_overlap", "lbib_set_graph", "lbib_graph_replays", "lbib_set_tile", "lbib_autotune",
-           "lbib_set_contact", "lbib_add_rigid_to"]
+           "lbib_set_contact", "lbib_add_rigid_to", "lbib_set_limits"]
 OBJ_TAYLOR, OBJ_CENTROID_Y = 0, 1
 ADJOINT_SCRATCH_BYTES = 64 * 1024 * 1024  # LBIB_ADJOINT_SCRATCH_BYTES
 TILE_ORDERS = ("banded", "linear", "chunked")  # tile orders of the batched grid pass
@@ -138,6 +138,8 @@ def load() -> C.CDLL:
     dp = C.POINTER(C.c_double)
     L.lbib_adjoint.restype = i32
     L.lbib_adjoint.argtypes = [vp, i32, i32, i32, i32, i32, vp, C.c_size_t, dp, dp, dp, i32]
+    L.lbib_set_limits.restype = i32
+    L.lbib_set_limits.argtypes = [vp, C.c_double, C.c_double]
     L.lbib_adjoint_noalloc.restype = i32
     L.lbib_adjoint_noalloc.argtypes = [vp, i32, i32, i32, i32, i32, dp, dp, dp, i32]
     _lib = L
@@ -344,6 +346,10 @@ class Sim:
         kernels one at a time."""
         v = -1 if enable is None else ((2 if queue_waits else 1) if enable else 0)
         _check(load().lbib_set_overlap(self.h, v), self.h)
+
+    def set_limits(self, max_edge: float = 0.0, max_area_change: float = 0.0) -> None:
+        """lbib_set_limits: element length and area-change checks (0 = off)."""
+        _check(load().lbib_set_limits(self.h, float(max_edge), float(max_area_change)), self.h)
 
     def set_graph(self, enable) -> None:
         """True replays captured 16-step blocks; False and None (the

@@ -169,3 +169,8 @@ def test_noalloc_gradient_declared_with_its_scratch_size(L):
     ks = (C.c_double * 4)()
     rc = L.lbib_adjoint_noalloc(None, 10, 0, 1, 0, 0, C.byref(J), C.byref(g), ks, 4)
     assert rc == lbib.EINVAL
+
+
+def test_membrane_limits_arguments(L):
+    """lbib_set_limits rejects a NULL context before touching a device."""
+    assert L.lbib_set_limits(None, 1.0, 0.05) == lbib.EINVAL

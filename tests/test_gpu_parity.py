@@ -617,6 +617,32 @@ def test_unstable_stiffness_is_flagged():
     assert g.check() & (lbib.FLAG_MOVE | lbib.FLAG_PATCH | lbib.FLAG_NONFINITE)
 
 
+@pytest.mark.parametrize("mode", ["dynamic", "kinematic"])
+def test_membrane_limits_are_flagged(mode):
+    """lbib_set_limits, forced from the host: a biconcave capsule (element
+    length 0.385) in a channel raises LBIB_FLAG_EDGE under a 0.3 limit and
+    LBIB_FLAG_AREA under a 1e-12 area limit, neither under limits it keeps
+    (element length 1, area change 5 %); the checks change no result."""
+    from paper_1903_03356_amd import lbib
+    cfg = wl.poiseuille_biconcave(1e-2, nx=128, ny=64, length=20.0, n_nodes=128,
+                                  centre=(40.0, 28.0), mode=mode)
+    l0 = np.hypot(*(np.roll(cfg["capsules"][0]["nodes"], -1, 0) - cfg["capsules"][0]["nodes"]).T)
+    assert 0.3 < l0.min() and l0.max() < 1.0
+    runs = {}
+    for name, lim in (("off", (0.0, 0.0)), ("kept", (1.0, 0.05)), ("edge", (0.3, 0.0)),
+                      ("area", (0.0, 1e-12))):
+        g = lbib.Sim(cfg)
+        g.set_limits(*lim)
+        g.step(30)
+        runs[name] = (g.check(), g.pops_dev(), g.capsule(0)[0])
+    assert runs["off"][0] == 0 and runs["kept"][0] == 0
+    assert runs["edge"][0] == lbib.FLAG_EDGE
+    assert runs["area"][0] == lbib.FLAG_AREA
+    for name in ("kept", "edge", "area"):
+        assert np.array_equal(runs[name][1], runs["off"][1])
+        assert np.array_equal(runs[name][2], runs["off"][2])
+
+
 @pytest.mark.parametrize("real_bytes", [8, 4])
 def test_dynamic_first_step_closed_form_gpu(real_bytes):
     """The HIP path on the closed form of one Dynamic step (Eqs. 21-24): a
