@@ -200,8 +200,8 @@ __device__ __forceinline__ void mls_dual(double px, double py, int cx, int cy, F
 // P^{n+1} at this node), it returns the adjoint of the nine pulled values and
 // of F.
 template <typename T>
-__device__ __forceinline__ void collide_vjp(const T s[9], T Fx, T Fy, T om, const T lo[9], T sb[9],
-                                            T& Fbx, T& Fby)
+__device__ __forceinline__ void collide_vjp(const T s[9], T Fx, T Fy, T ur, T om, const T lo[9],
+                                            T sb[9], T& Fbx, T& Fby)
 {
     const T drho = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])) + s[8];
     const T rho = T(1) + drho;
@@ -209,7 +209,7 @@ __device__ __forceinline__ void collide_vjp(const T s[9], T Fx, T Fy, T om, cons
     const T jy = (s[2] - s[4]) + (s[5] + s[6]) - (s[7] + s[8]);
     const T irho = T(1) / rho;
     const T mx = jx + T(0.5) * Fx, my = jy + T(0.5) * Fy;
-    const T ux = mx * irho, uy = my * irho;
+    const T ux = (ur + mx) * irho, uy = my * irho;  // ur: storage reference u_ref(y)
     const T pre = T(1) - T(0.5) * om;
     const T usq15 = T(1.5) * (ux * ux + uy * uy);
     T drhob = 0, rhob = 0, mbx = 0, mby = 0, ubx = 0, uby = 0, usqb = 0, uFb = 0;
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(kSegW * 4) void k_grid_adj(GridAdjArgs<T> a, GridAr
 #pragma unroll
             for (int i = 0; i < 9; i++) lo[i] = a.lam_in[i * plane + cell];
             T Fbx, Fby;
-            collide_vjp(s, Fx, Fy, (T)g.omega, lo, sb, Fbx, Fby);
+            collide_vjp(s, Fx, Fy, uref_at<T>(g, y), (T)g.omega, lo, sb, Fbx, Fby);
             const bool bot = !g.periodic_y && y == 0, top = !g.periodic_y && y == g.ny - 1;
             if (bot) zou_he_vjp(sb, Fbx, (T)g.u_bot, false);
             if (top) zou_he_vjp(sb, Fbx, (T)g.u_top, true);
@@ -787,6 +787,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_ib_adj(IBAdjArgs<T> a)
     g.u_bot = g.u_top = 0.0;
     g.u_in = 0.0;
     g.rho_out = 1.0;
+    g.uref_c = cap.uref_c;
     const size_t plane = (size_t)g.ny * g.nxp;
     T* lam_p = a.lam_p + cap.pop_off;
     T* lfm = a.lfm + cap.fib_off;

@@ -308,6 +308,10 @@ static GridArgs grid_args(const Inst& I)
     g.periodic_x = I.walls.periodic_x;
     g.u_in = I.walls.periodic_x ? 0.0 : I.walls.inlet_umax;
     g.rho_out = I.walls.periodic_x ? 1.0 : I.walls.outlet_rho;
+    // storage reference: the Poiseuille profile of a periodic channel that
+    // starts from it (zero on both wall rows, so Zou-He sees plain deviations)
+    const bool poiseuille = I.walls.init_profile == 2 && I.walls.periodic_x && !I.walls.periodic_y;
+    g.uref_c = poiseuille ? I.walls.body_force_x / (2.0 * I.nu) : 0.0;
     return g;
 }
 
@@ -540,6 +544,7 @@ static lbib_status create_common(const lbib_grid* grids, const double* taus,
         d.gx = g.gx;
         d.u_bot = g.u_bot;
         d.u_top = g.u_top;
+        d.uref_c = g.uref_c;
         for (int k = 0; k < kTileShapes; k++) {
             const int r0 = (int)(I.tile0[k] / kNumXcd);
             const int r1 = r0 + lattice_tiles(g.ny, g.nseg, k) / kNumXcd;
@@ -687,6 +692,7 @@ static lbib_status add_capsule_t(lbib_ctx* c, int inst, const double* xy, int n,
     cd.flag_off = (int64_t)I.flag_off;
     cd.gx = g.gx;
     cd.nu = I.nu;
+    cd.uref_c = g.uref_c;
     if (rigid) {
         cd.rigid = 1;
         cd.rX = rcx;

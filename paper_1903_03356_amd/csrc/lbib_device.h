@@ -37,11 +37,50 @@ struct FirstOrderW {
     static constexpr T diag = (T(1) - T(2) * axis) / T(4);
 };
 
+// Stored populations: slot i at a node of row y holds
+//   f_i - w_i - (3 w_i) e_ix u_ref(y),
+// the deviation from the rest weights and from the first-order term of the
+// equilibrium of a reference flow along x, u_ref(y) = uref_c y (H - y)
+// (H = ny - 1): the Poiseuille profile a periodic channel starts from, 0 for
+// every other lattice.  In a channel the stored values are then the
+// non-equilibrium and second-order parts (about 1e-4) instead of the whole
+// first-order term (about 1e-2), so the FP32 rounding of every store is about
+// a hundred times finer; in a steady flow each store rounds the same way at
+// every step, and at the coarser scale those roundings add up to a drift of
+// 1e-5 of the velocity over 2e4 steps.  (3 w_i) are the first-order weights
+// above, whose moments give u_ref back exactly.
+template <typename T>
+__device__ __forceinline__ T uref_at(const GridArgs& g, int y)
+{
+    return (T)g.uref_c * (T)(y * (g.ny - 1 - y));
+}
+
+// A population pulled from row y - e_iy to row y changes reference:
+// d_i = stored_i + (3 w_i) e_ix (u_ref(y - e_iy) - u_ref(y)), nonzero for the
+// four diagonals only: dm = (3 w_d)(u_ref(y - 1) - u_ref(y)) =
+// (3 w_d) uref_c (2y - H - 1) and dp = (3 w_d)(u_ref(y + 1) - u_ref(y)) =
+// (3 w_d) uref_c (H - 2y - 1), in the population type (the integer factors
+// are exact there; the offsets are about 1e-6 and carry a rounding of 1e-13).
+// Without a reference they are +0, which leaves every value unchanged; adding
+// them unconditionally measured no slower than a branch around them.
+template <typename T>
+__device__ __forceinline__ void add_pull_offsets(const GridArgs& g, int y, T s[9])
+{
+    const T c3 = (T)((double)FirstOrderW<T>::diag * g.uref_c);
+    const T dm = c3 * (T)(2 * y - g.ny);
+    const T dp = c3 * (T)(g.ny - 2 - 2 * y);
+    s[5] += dm;
+    s[6] -= dm;
+    s[7] -= dp;
+    s[8] += dp;
+}
+
 // BGK relaxation with the forcing term for one direction, deviation form:
-// s* = s - omega (s - (f_eq - w)) + (1 - omega/2) w [3 (e - u).F + 9 (e.u)(e.F)]
-// with f_eq - w = w (rho - 1) + 3 w (e . m) + w rho (4.5 (e.u)^2 - 1.5 u^2),
-// m = rho u = sum f e + F/2 taken as is, so that rho * (m / rho) rounding does
-// not leak into the momentum.
+// s* = s - omega (s - (f_eq - r)) + (1 - omega/2) w [3 (e - u).F + 9 (e.u)(e.F)]
+// with r = w + 3 w e.u_ref the reference of the stored values and
+// f_eq - r = w (rho - 1) + 3 w (e . (m - u_ref)) + w rho (4.5 (e.u)^2 - 1.5 u^2),
+// m - u_ref = sum s e + F/2 taken as is (em), so that rho * (m / rho) rounding
+// does not leak into the momentum; u = m / rho.
 template <typename T>
 __device__ __forceinline__ T relax(T s, T w, T w3, T eu, T em, T eF, T drho, T rho, T usq15,
                                    T uF, T om, T pre)
@@ -173,6 +212,7 @@ __device__ __forceinline__ void pull(const T* __restrict__ src, int x, int y, co
     s[6] = src[6 * plane + rm + xp];
     s[7] = src[7 * plane + rp + xp];
     s[8] = src[8 * plane + rp + xm];
+    add_pull_offsets(g, y, s);
     if (OPEN && !g.periodic_x && (x == 0 || x == g.nx - 1)) {
         open_boundary(src, x, y, g, s);
         return;
@@ -220,7 +260,7 @@ __device__ __forceinline__ bool patch_index(const Patch<T>& P, int cx, int cy, i
 // rho - 1 and the force-corrected velocity.
 template <typename T>
 __device__ __forceinline__ void stage_store(const Patch<T>& P, int i, const T (&s)[9],
-                                            long long fx, long long fy, T gxf)
+                                            long long fx, long long fy, T gxf, T ur)
 {
     const T Fx = gxf + fix_to_real<T>(fx);
     const T Fy = fix_to_real<T>(fy);
@@ -229,7 +269,7 @@ __device__ __forceinline__ void stage_store(const Patch<T>& P, int i, const T (&
     const T jy = (s[2] - s[4]) + (s[5] + s[6]) - (s[7] + s[8]);
     const T irho = T(1) / (T(1) + drho);
     P.drho[i] = drho;
-    P.ux[i] = (jx + T(0.5) * Fx) * irho;
+    P.ux[i] = (ur + (jx + T(0.5) * Fx)) * irho;
     P.uy[i] = (jy + T(0.5) * Fy) * irho;
 }
 
@@ -274,6 +314,7 @@ __device__ __forceinline__ void stage_cells(const IBArgs<T>& a, const GridArgs& 
     T s[K][9];
     long long fx[K], fy[K];
     int state[K];  // 0: past the patch, 1: off the lattice, 2: staged
+    int row[K];
 #pragma unroll
     for (int k = 0; k < K; k++) {
         const int i = first + k * stride;
@@ -321,6 +362,7 @@ __device__ __forceinline__ void stage_cells(const IBArgs<T>& a, const GridArgs& 
         s[k][6] = src[6 * plane + rm + xp];
         s[k][7] = src[7 * plane + rp + xp];
         s[k][8] = src[8 * plane + rp + xm];
+        row[k] = y;
         const longlong2 f = *reinterpret_cast<const longlong2*>(a.fib_prev + 2 * (r0 + x));
         fx[k] = f.x;
         fy[k] = f.y;
@@ -329,7 +371,8 @@ __device__ __forceinline__ void stage_cells(const IBArgs<T>& a, const GridArgs& 
     for (int k = 0; k < K; k++) {
         const int i = first + k * stride;
         if (state[k] == 2) {
-            stage_store(P, i, s[k], fx[k], fy[k], gxf);
+            add_pull_offsets(g, row[k], s[k]);
+            stage_store(P, i, s[k], fx[k], fy[k], gxf, uref_at<T>(g, row[k]));
         } else if (state[k] == 1) {
             P.drho[i] = T(NAN);
             P.ux[i] = P.uy[i] = T(0);

@@ -48,7 +48,7 @@ struct InstDev {
     int64_t pop_off;   // offset of the lattice's planes in a population buffer (elements)
     int64_t fib_off;   // offset in one time level of the force field (long long elements)
     int64_t flag_off;  // offset in one time level of the segment flags (ints)
-    int64_t pad2;
+    double uref_c;     // reference profile of the stored populations (GridArgs)
     double omega, gx, u_bot, u_top;
     double u_in, rho_out;        // inlet peak speed, outlet density (open channel)
 };
@@ -67,7 +67,7 @@ struct CapsuleDev {
     int32_t periodic_y, periodic_x;
     int64_t pop_off, fib_off, flag_off;
     double gx, nu;
-    double pad1;
+    double uref_c;  // reference profile of the lattice's stored populations (GridArgs)
     // rigid particle (Sec. 2.3.1): nodes x_v = X + R(theta) r0_v
     int32_t rigid, pad2;
     double rX, rY, rth;        // centroid (world coordinates) and angle
@@ -107,6 +107,9 @@ struct GridArgs {
     double gx;       // uniform body force
     double u_bot, u_top;
     double u_in, rho_out;  // inlet peak speed (parabolic profile), outlet density
+    // reference profile of the stored populations: u_ref(y) = uref_c y (ny - 1 - y)
+    // along x (the Poiseuille start of a periodic channel; 0 otherwise)
+    double uref_c;
 };
 
 // Buffer bases of an IB launch; each block adds its capsule's lattice offsets.

@@ -56,8 +56,9 @@ __device__ __forceinline__ void collide_store(const T* __restrict__ src, T* __re
     const T jx = (s[1] - s[3]) + (s[5] - s[6]) + (s[8] - s[7]);
     const T jy = (s[2] - s[4]) + (s[5] + s[6]) - (s[7] + s[8]);
     const T irho = T(1) / rho;
-    const T mx = jx + T(0.5) * Fx, my = jy + T(0.5) * Fy;  // rho u (Eq. 7)
-    const T ux = mx * irho, uy = my * irho;
+    // rho u (Eq. 7): mx = rho u_x - u_ref(y) is the momentum the stored values carry
+    const T mx = jx + T(0.5) * Fx, my = jy + T(0.5) * Fy;
+    const T ux = (uref_at<T>(g, y) + mx) * irho, uy = my * irho;
     const T om = (T)g.omega;
     const T pre = T(1) - T(0.5) * om;
     const T usq15 = T(1.5) * (ux * ux + uy * uy);
@@ -166,6 +167,7 @@ __device__ __forceinline__ GridArgs lattice_args(const InstDev& I)
     g.u_top = I.u_top;
     g.u_in = I.u_in;
     g.rho_out = I.rho_out;
+    g.uref_c = I.uref_c;
     return g;
 }
 
@@ -495,6 +497,16 @@ hipError_t launch_grid_step_batch(const T* src, T* dst, const long long* fib_now
 }
 
 // ------------------------------------------------------------ init kernel
+// First-order part (3 w_i) e_ix u_ref(y) of the storage reference of slot i in
+// row y, in FP64.
+template <typename T>
+__device__ __forceinline__ double ref_first(const GridArgs& g, int i, int y)
+{
+    if (g.uref_c == 0.0 || kEx[i] == 0) return 0.0;
+    const double w3 = i < 5 ? (double)FirstOrderW<T>::axis : (double)FirstOrderW<T>::diag;
+    return w3 * kEx[i] * (g.uref_c * (double)(y * (g.ny - 1 - y)));
+}
+
 // Post-collision field whose pull gives f^0 = f^eq(1, u_init(y)) (Eq. 2) at
 // every node: slot i at source (x, y) holds the equilibrium at (x, y + e_iy).
 template <typename T>
@@ -517,7 +529,7 @@ __global__ void k_init(T* pops, GridArgs g, int profile, double ux0, double uy0,
         const double eu = kEx[i] * ux + kEy[i] * uy;
         const double w = i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
         const double dev = w * (3.0 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy));
-        pops[i * plane + (size_t)y * g.nxp + x] = x < g.nx ? (T)dev : T(0);
+        pops[i * plane + (size_t)y * g.nxp + x] = x < g.nx ? (T)(dev - ref_first<T>(g, i, y)) : T(0);
     }
 }
 
@@ -1246,6 +1258,7 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
     g.u_bot = g.u_top = 0.0;  // wall rows and open-channel columns are never staged
     g.u_in = 0.0;
     g.rho_out = 1.0;
+    g.uref_c = cap.uref_c;
     const int nv = cap.nv, off = cap.node_offset;
     const size_t NS = a.node_stride;
     T* N = a.nodes;
@@ -1813,7 +1826,7 @@ __global__ void k_get_pop_plane(const T* src, double* out, int plane, int unshif
 #pragma unroll
     for (int i = 1; i < 9; i++)
         if (i == plane) v = s[i];
-    double d = (double)v;
+    double d = (double)v + ref_first<T>(g, plane, y);
     if (unshift) d += plane == 0 ? 4.0 / 9.0 : (plane < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
     out[(size_t)y * g.nx + x] = d;
 }
@@ -1839,7 +1852,8 @@ __global__ void k_set_pop_plane(T* dst, const double* in, int plane, GridArgs g)
     if (g.periodic_y) yd = yd < 0 ? yd + g.ny : (yd >= g.ny ? yd - g.ny : yd);
     else if (yd < 0 || yd >= g.ny) return;
     const double w = plane == 0 ? 4.0 / 9.0 : (plane < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
-    dst[(size_t)plane * g.ny * g.nxp + (size_t)y * g.nxp + x] = (T)(in[(size_t)yd * g.nx + xd] - w);
+    dst[(size_t)plane * g.ny * g.nxp + (size_t)y * g.nxp + x] =
+        (T)(in[(size_t)yd * g.nx + xd] - w - ref_first<T>(g, plane, y));
 }
 
 template <typename T>
@@ -1871,7 +1885,7 @@ __global__ void k_get_moments(const T* src, const long long* fib, double* out, G
     const double rho = 1.0 + drho;
     const size_t plane = (size_t)g.nx * g.ny, o = (size_t)y * g.nx + x;
     out[o] = rho;
-    out[plane + o] = (jx + 0.5 * Fx) / rho;
+    out[plane + o] = (g.uref_c * (double)(y * (g.ny - 1 - y)) + jx + 0.5 * Fx) / rho;
     out[2 * plane + o] = (jy + 0.5 * Fy) / rho;
 }
 
