@@ -179,13 +179,16 @@ __device__ __forceinline__ void open_boundary(const T* __restrict__ src, int x, 
 }
 
 // Pulls the nine populations arriving at (x, y) from the post-collision field
-// and completes the wall rows with Zou-He (unknowns from the knowns, tangential
-// momentum target rho_w u_w - F_x / 2) and, in an open channel, the inlet and
-// outlet columns.  OPEN = false compiles the periodic-x lattice only (the hot
-// path, and callers that never reach the end columns of an open channel).
+// (pull_loads: the loads and the storage reference's row change) and completes
+// the wall rows with Zou-He (unknowns from the knowns, tangential momentum
+// target rho_w u_w - F_x / 2) and, in an open channel, the inlet and outlet
+// columns (pull_complete).  OPEN = false compiles the periodic-x lattice only
+// (the hot path, and callers that never reach the end columns of an open
+// channel).  The split lets the grid pass issue the nine loads before it reads
+// the segment's flags, whose value the completion (F_x) depends on.
 template <typename T, bool OPEN = true>
-__device__ __forceinline__ void pull(const T* __restrict__ src, int x, int y, const GridArgs& g,
-                                     T Fx, T s[9])
+__device__ __forceinline__ void pull_loads(const T* __restrict__ src, int x, int y,
+                                           const GridArgs& g, T s[9])
 {
     const size_t plane = (size_t)g.ny * g.nxp;
     int xm = x == 0 ? g.nx - 1 : x - 1;
@@ -213,27 +216,44 @@ __device__ __forceinline__ void pull(const T* __restrict__ src, int x, int y, co
     s[7] = src[7 * plane + rp + xp];
     s[8] = src[8 * plane + rp + xm];
     add_pull_offsets(g, y, s);
+}
+
+template <typename T, bool OPEN = true>
+__device__ __forceinline__ void pull_complete(const T* __restrict__ src, int x, int y,
+                                              const GridArgs& g, T Fx, T s[9])
+{
     if (OPEN && !g.periodic_x && (x == 0 || x == g.nx - 1)) {
         open_boundary(src, x, y, g, s);
         return;
     }
-    if (!g.periodic_y) {
-        if (y == 0) {
-            const T rw = T(1) + s[0] + s[1] + s[3] + T(2) * (s[4] + s[7] + s[8]);
-            const T mx = rw * (T)g.u_bot - T(0.5) * Fx;
-            const T d13 = s[1] - s[3];
-            s[2] = s[4];
-            s[5] = s[7] - T(0.5) * d13 + T(0.5) * mx;
-            s[6] = s[8] + T(0.5) * d13 - T(0.5) * mx;
-        } else if (y == g.ny - 1) {
-            const T rw = T(1) + s[0] + s[1] + s[3] + T(2) * (s[2] + s[5] + s[6]);
-            const T mx = rw * (T)g.u_top - T(0.5) * Fx;
-            const T d13 = s[1] - s[3];
-            s[4] = s[2];
-            s[7] = s[5] + T(0.5) * d13 - T(0.5) * mx;
-            s[8] = s[6] - T(0.5) * d13 + T(0.5) * mx;
-        }
+    if (!g.periodic_y && (y == 0 || y == g.ny - 1)) {
+        // bottom row: s2, s5, s6 unknown from s4, s7, s8; top row: s4, s7, s8
+        // from s2, s5, s6 (the same formulas with e_y and the sign of the
+        // tangential terms mirrored).  Written with selects, so that every slot
+        // of s stays a register.
+        const bool top = y == g.ny - 1;
+        const T a2 = top ? s[2] : s[4], a5 = top ? s[5] : s[7], a6 = top ? s[6] : s[8];
+        const T rw = T(1) + s[0] + s[1] + s[3] + T(2) * (a2 + a5 + a6);
+        const T mx = rw * (top ? (T)g.u_top : (T)g.u_bot) - T(0.5) * Fx;
+        const T d13 = s[1] - s[3];
+        const T h = top ? T(-0.5) : T(0.5);
+        const T u5 = a5 - h * d13 + h * mx;  // bottom s5, top s7
+        const T u6 = a6 + h * d13 - h * mx;  // bottom s6, top s8
+        s[2] = top ? s[2] : a2;
+        s[4] = top ? a2 : s[4];
+        s[5] = top ? s[5] : u5;
+        s[7] = top ? u5 : s[7];
+        s[6] = top ? s[6] : u6;
+        s[8] = top ? u6 : s[8];
     }
+}
+
+template <typename T, bool OPEN = true>
+__device__ __forceinline__ void pull(const T* __restrict__ src, int x, int y, const GridArgs& g,
+                                     T Fx, T s[9])
+{
+    pull_loads<T, OPEN>(src, x, y, g, s);
+    pull_complete<T, OPEN>(src, x, y, g, Fx, s);
 }
 
 // Moments of the capsule's fluid patch, staged in LDS: density deviation

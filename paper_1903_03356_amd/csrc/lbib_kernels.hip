@@ -42,15 +42,13 @@ __device__ __forceinline__ void put_pop(T* p, T v)
     else *p = v;
 }
 
-// One lattice node with total force (Fx, Fy): pull, walls, force-corrected
-// moments, BGK + forcing, store.
-template <typename T, bool OPEN, bool NT = true>
-__device__ __forceinline__ void collide_store(const T* __restrict__ src, T* __restrict__ dst,
-                                              const GridArgs& g, int x, int y, T Fx, T Fy)
+// One lattice node with total force (Fx, Fy), from its pulled and completed
+// populations s: force-corrected moments, BGK + forcing, store.
+template <typename T, bool NT = true>
+__device__ __forceinline__ void collide_pulled(const T (&s)[9], T* __restrict__ dst,
+                                               const GridArgs& g, int x, int y, T Fx, T Fy)
 {
     const size_t cell = (size_t)y * g.nxp + x;
-    T s[9];
-    pull<T, OPEN>(src, x, y, g, Fx, s);
     const T drho = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])) + s[8];
     const T rho = T(1) + drho;
     const T jx = (s[1] - s[3]) + (s[5] - s[6]) + (s[8] - s[7]);
@@ -78,32 +76,58 @@ __device__ __forceinline__ void collide_store(const T* __restrict__ src, T* __re
     put_pop<T, NT>(&o[8 * plane], relax(s[8], wd, w3d, ux - uy, mx - my, Fx - Fy, drho, rho, usq15, uF, om, pre));
 }
 
-// One lattice node with the IB force of this step.  The wave that owns the
-// node's 64-cell row segment also clears the force accumulator of the
-// previous time level there (if that segment was active), so the next IB
-// launch finds it zeroed; each segment has exactly one owning wave, which
-// reads its two activity flags before clearing one.
-template <bool OPEN, bool NT = true, typename T>
+// One lattice node with the IB force of this step.  A wave holds one 64-cell
+// row segment (y and seg are the same in all its lanes).  The wave also clears
+// the force accumulator of the previous time level in its segment (if that
+// segment was active), so the next IB launch finds it zeroed; each segment has
+// exactly one owning wave, which reads its two activity flags before clearing
+// one.
+//
+// The nine population loads go out together with the segment's flags (and,
+// for the far part of a split step, FAR, its near-map entry), and the wave
+// waits for all of them once: the populations do not depend on the flags.
+// (Issued after the flags, they would wait for the flags' round trip first.)
+// The far part skips a segment whose near-map entry carries this step's stamp
+// (the near pass computes it) and raises ST_NEAR where it finds an active
+// force flag: the near regions were too small.
+template <bool OPEN, bool NT = true, bool FAR = false, typename T>
 __device__ __forceinline__ void grid_cell(const T* __restrict__ src, T* __restrict__ dst,
                                           const long long* __restrict__ fib_now,
                                           const int* __restrict__ flags_now,
                                           long long* __restrict__ fib_old,
                                           int* __restrict__ flags_old, const GridArgs& g, int y,
-                                          int seg, int lane)
+                                          int seg, int lane, const int* __restrict__ near_map = nullptr,
+                                          int stamp = 0, int* status = nullptr)
 {
     const int x = seg * kSegW + lane;
     const int fidx = y * g.nseg + seg;
+    const size_t cell = (size_t)y * g.nxp + x;
+    const bool in = x < g.nx;
+    // lanes past the row's end (x < nxp) load the last node's values and
+    // store nothing
+    T s[9];
+    pull_loads<T, OPEN>(src, in ? x : g.nx - 1, y, g, s);
     const int act = flags_now[fidx];
     const int old = flags_old[fidx];
-    const size_t cell = (size_t)y * g.nxp + x;
-    if (x < g.nx) {
+    const int mark = FAR ? near_map[fidx] : 0;
+    // keep these loads here, ahead of the branches on the flags (otherwise
+    // they may be moved into the branches that use them, one round trip each)
+#pragma unroll
+    for (int i = 0; i < 9; i++) asm volatile("" ::"v"(s[i]));
+    asm volatile("" ::"v"(act), "v"(old), "v"(mark));
+    if (FAR) {
+        if (mark == stamp) return;
+        if ((act | old) && lane == 0) atomicOr(status, ST_NEAR);
+    }
+    if (in) {
         T Fx = (T)g.gx, Fy = T(0);
         if (act) {
             const longlong2 f = *reinterpret_cast<const longlong2*>(fib_now + 2 * cell);
             Fx += fix_to_real<T>(f.x);
             Fy += fix_to_real<T>(f.y);
         }
-        collide_store<T, OPEN, NT>(src, dst, g, x, y, Fx, Fy);
+        pull_complete<T, OPEN>(src, x, y, g, Fx, s);
+        collide_pulled<T, NT>(s, dst, g, x, y, Fx, Fy);
     }
     if (old) {
         *reinterpret_cast<longlong2*>(fib_old + 2 * cell) = make_longlong2(0, 0);
@@ -220,10 +244,8 @@ __global__ __launch_bounds__(kSegW * 4) void k_grid_far(
     const int lane = threadIdx.x & (kSegW - 1);
     const int y = band * 4 + (threadIdx.x >> 6);
     if (y >= g.ny) return;
-    const int fidx = y * g.nseg + seg;
-    if (near_map[fidx] == stamp) return;
-    if ((flags_now[fidx] | flags_old[fidx]) && lane == 0) atomicOr(status, ST_NEAR);
-    grid_cell<false>(src, dst, fib_now, flags_now, fib_old, flags_old, g, y, seg, lane);
+    grid_cell<false, true, true>(src, dst, fib_now, flags_now, fib_old, flags_old, g, y, seg, lane,
+                                 near_map, stamp, status);
 }
 
 // Near part: the (row, segment) units of every capsule's near region, with
@@ -401,14 +423,11 @@ __global__ __launch_bounds__(kSegW * 4) void k_grid_step_batch(
         for (int r = 0; r < ROWS; r++) {
             const int y = y0 + 4 * r;
             if (y >= g.ny) continue;
-            if (FAR) {  // the far part of the split step, as k_grid_far on one lattice
-                const int fidx = I.flag_off + y * g.nseg + seg;
-                if (near_map[fidx] == stamp) continue;
-                if ((flags_now[fidx] | flags_old[fidx]) && lane == 0) atomicOr(status, ST_NEAR);
-            }
-            grid_cell<OPEN>(src + I.pop_off, dst + I.pop_off, fib_now + I.fib_off,
-                            flags_now + I.flag_off, fib_old + I.fib_off, flags_old + I.flag_off, g,
-                            y, seg, lane);
+            // FAR: the far part of the split step, as k_grid_far on one lattice
+            grid_cell<OPEN, true, FAR>(src + I.pop_off, dst + I.pop_off, fib_now + I.fib_off,
+                                       flags_now + I.flag_off, fib_old + I.fib_off,
+                                       flags_old + I.flag_off, g, y, seg, lane,
+                                       FAR ? near_map + I.flag_off : nullptr, stamp, status);
         }
     }
 }

@@ -150,17 +150,21 @@ def both_objectives(cfg, steps):
 
 def case_adjoint() -> None:
     """Central differences (J(p + h) - J(p - h)) / 2h of D and y_c after 5000
-    Kinematic steps, for k_s of two elements (h = 1e-3 and 5e-4 k_s) and the
-    body force g (h = 1e-6 and 1e-7 g); both step sizes are stored so that the
-    test can see how far the difference itself is settled."""
+    Kinematic steps, for k_s of two elements (h = 3e-2, 1e-2 and 3e-3 k_s) and
+    the body force g (h = 1e-3, 3e-4 and 1e-4 g).  Over 5000 steps the nodes'
+    MLS stencils switch many times, and at each switch the discrete map jumps
+    by a small amount; a difference over a step much smaller than these (h of
+    1e-6 g: 2e-12) is dominated by the jumps it happens to straddle, so the
+    steps are taken large enough to average over them.  All three are stored,
+    so that the test can see how far the difference itself is settled."""
     cfg = dict(wl.adjoint_channel(), mode="kinematic", real_bytes=8)
     steps = int(cfg["steps"])
     ks0 = float(np.asarray(cfg["capsules"][0]["ks"]).reshape(-1)[0])
     g0 = float(cfg["body_force_x"])
     t = time.time()
     base = both_objectives(cfg, steps)
-    params = [(("ks", 0, l), [1e-3 * ks0, 5e-4 * ks0]) for l in ADJ_ELEMENTS]
-    params.append(("g", [1e-6 * g0, 1e-7 * g0]))
+    params = [(("ks", 0, l), [r * ks0 for r in (3e-2, 1e-2, 3e-3)]) for l in ADJ_ELEMENTS]
+    params.append(("g", [r * g0 for r in (1e-3, 3e-4, 1e-4)]))
     fd = []
     for p, hs in params:
         for h in hs:

@@ -118,9 +118,15 @@ def test_inertial_channel_horizon():
 def test_adjoint_full_horizon():
     """The 512 x 128 gradient channel over all 5000 steps: the FP32 gradient
     with a checkpoint every 70 steps against the oracle's central differences,
-    for D and y_c, k_s of two elements and the body force g.  The bar is 1e-3
-    of the largest stored difference of that objective, plus the spread of the
-    two stored step sizes (how far the difference itself is settled)."""
+    for D and y_c, k_s of two elements and the body force g.
+
+    The stored differences use three step sizes each, large enough to average
+    over the small jumps of the discrete map at the nodes' MLS stencil switches
+    (thousands over 5000 steps; a step of 1e-6 g straddles a few and scatters
+    by 25 %).  The bar is 1e-3 of the largest difference of that objective and
+    parameter kind, plus the scatter of the three differences (max - min), which
+    measures how far the difference itself is settled: about 1e-3 for D, about
+    0.5 % for y_c, whose stencil jumps are larger relative to its slope."""
     ref = golden("long_adjoint.json")
     cfg = dict(wl.adjoint_channel(), mode="kinematic")
     steps = ref["steps"]
@@ -130,16 +136,17 @@ def test_adjoint_full_horizon():
         by = {}
         for e in ref["fd"]:
             by.setdefault(e["param"], []).append(e[key])
-        scale = {p: max(abs(v) for v in vals) for p, vals in by.items()}
-        ks_scale = max(s for p, s in scale.items() if p != "g")
+        ks_scale = max(max(abs(v) for v in vals) for p, vals in by.items() if p != "g")
         for p, vals in by.items():
+            assert len(vals) == 3
             got = r["dJ_dg"] if p == "g" else float(r["dJ_dks"][0][int(p[2:])])
-            fd = vals[0]
-            spread = abs(vals[0] - vals[1])
-            bar = 1e-3 * (scale[p] if p == "g" else ks_scale) + spread
-            log(f"adjoint {jkey} {p}: fp32 {got:.9g} fd {fd:.9g} (other h {vals[1]:.9g}), "
+            fd = vals[1]
+            spread = max(vals) - min(vals)
+            scale = max(abs(v) for v in vals) if p == "g" else ks_scale
+            bar = 1e-3 * scale + spread
+            log(f"adjoint {jkey} {p}: fp32 {got:.9g} fd {fd:.9g} (h scatter {spread:.2e}), "
                 f"bar {bar:.2e}")
-            assert abs(got - fd) <= bar, (jkey, p, got, fd, bar)
+            assert abs(got - fd) <= bar, (jkey, p, got, vals, bar)
 
 
 def test_golden_samples_follow_their_seed():
