@@ -132,50 +132,63 @@ template <typename T>
 __device__ __forceinline__ void open_boundary(const T* __restrict__ src, int x, int y,
                                               const GridArgs& g, T s[9])
 {
+    // Every case below sets all of n1..n8 (the untouched ones to themselves),
+    // so that the branches store to the same slots of s and s stays in
+    // registers (stores to different slots get merged into one with a computed
+    // index, which puts s in scratch memory).
+    T n1 = s[1], n2 = s[2], n3 = s[3], n4 = s[4], n5 = s[5], n6 = s[6], n7 = s[7], n8 = s[8];
     const bool bot = y == 0, top = y == g.ny - 1;
     if (bot || top) {
         T h[9];
         pull_interior(src, x == 0 ? 1 : g.nx - 2, bot ? 1 : g.ny - 2, g, h);
         const T drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
         if (x == 0 && bot) {
-            s[1] = s[3];
-            s[2] = s[4];
-            s[5] = s[7];
-            s[6] = s[8] = T(0.5) * (drho - (s[0] + s[1] + s[2] + s[3] + s[4] + s[5] + s[7]));
+            n1 = n3;
+            n2 = n4;
+            n5 = n7;
+            n6 = n8 = T(0.5) * (drho - (s[0] + n1 + n2 + n3 + n4 + n5 + n7));
         } else if (x == 0) {
-            s[1] = s[3];
-            s[4] = s[2];
-            s[8] = s[6];
-            s[5] = s[7] = T(0.5) * (drho - (s[0] + s[1] + s[2] + s[3] + s[4] + s[6] + s[8]));
+            n1 = n3;
+            n4 = n2;
+            n8 = n6;
+            n5 = n7 = T(0.5) * (drho - (s[0] + n1 + n2 + n3 + n4 + n6 + n8));
         } else if (bot) {
-            s[3] = s[1];
-            s[2] = s[4];
-            s[6] = s[8];
-            s[5] = s[7] = T(0.5) * (drho - (s[0] + s[1] + s[2] + s[3] + s[4] + s[6] + s[8]));
+            n3 = n1;
+            n2 = n4;
+            n6 = n8;
+            n5 = n7 = T(0.5) * (drho - (s[0] + n1 + n2 + n3 + n4 + n6 + n8));
         } else {
-            s[3] = s[1];
-            s[4] = s[2];
-            s[7] = s[5];
-            s[6] = s[8] = T(0.5) * (drho - (s[0] + s[1] + s[2] + s[3] + s[4] + s[5] + s[7]));
+            n3 = n1;
+            n4 = n2;
+            n7 = n5;
+            n6 = n8 = T(0.5) * (drho - (s[0] + n1 + n2 + n3 + n4 + n5 + n7));
         }
-        return;
-    }
-    const T H = (T)(g.ny - 1);
-    if (x == 0) {
-        const T ux = T(4) * (T)g.u_in * (T)y * (H - (T)y) / (H * H);
-        const T rho = (T(1) + s[0] + s[2] + s[4] + T(2) * (s[3] + s[6] + s[7])) / (T(1) - ux);
-        const T m = rho * ux;
-        s[1] = s[3] + T(2.0 / 3.0) * m;
-        s[5] = s[7] - T(0.5) * (s[2] - s[4]) + m * T(1.0 / 6.0);
-        s[8] = s[6] + T(0.5) * (s[2] - s[4]) + m * T(1.0 / 6.0);
     } else {
-        const T ro = (T)g.rho_out;
-        const T uo = (T(1) + s[0] + s[2] + s[4] + T(2) * (s[1] + s[5] + s[8])) / ro - T(1);
-        const T m = ro * uo;
-        s[3] = s[1] - T(2.0 / 3.0) * m;
-        s[7] = s[5] + T(0.5) * (s[2] - s[4]) - m * T(1.0 / 6.0);
-        s[6] = s[8] - T(0.5) * (s[2] - s[4]) - m * T(1.0 / 6.0);
+        const T H = (T)(g.ny - 1);
+        if (x == 0) {
+            const T ux = T(4) * (T)g.u_in * (T)y * (H - (T)y) / (H * H);
+            const T rho = (T(1) + s[0] + n2 + n4 + T(2) * (n3 + n6 + n7)) / (T(1) - ux);
+            const T m = rho * ux;
+            n1 = n3 + T(2.0 / 3.0) * m;
+            n5 = n7 - T(0.5) * (n2 - n4) + m * T(1.0 / 6.0);
+            n8 = n6 + T(0.5) * (n2 - n4) + m * T(1.0 / 6.0);
+        } else {
+            const T ro = (T)g.rho_out;
+            const T uo = (T(1) + s[0] + n2 + n4 + T(2) * (n1 + n5 + n8)) / ro - T(1);
+            const T m = ro * uo;
+            n3 = n1 - T(2.0 / 3.0) * m;
+            n7 = n5 + T(0.5) * (n2 - n4) - m * T(1.0 / 6.0);
+            n6 = n8 - T(0.5) * (n2 - n4) - m * T(1.0 / 6.0);
+        }
     }
+    s[1] = n1;
+    s[2] = n2;
+    s[3] = n3;
+    s[4] = n4;
+    s[5] = n5;
+    s[6] = n6;
+    s[7] = n7;
+    s[8] = n8;
 }
 
 // Pulls the nine populations arriving at (x, y) from the post-collision field
