@@ -503,7 +503,7 @@ static lbib_status create_common(const lbib_grid* grids, const double* taus,
     // holds the capsule's fluid patch.
     const size_t lds_max = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
     const size_t budget = lds_max - 1024;  // static shared memory of the kernel
-    const size_t per_node = (size_t)26 * c->rb, per_cell = (size_t)3 * c->rb;
+    const size_t per_node = (size_t)kNodeLdsArrays * c->rb, per_cell = (size_t)3 * c->rb;
     const size_t node_bytes = per_node * L.max_nv;
     if (node_bytes + 1024 * per_cell > budget)
         return bail(LBIB_ECAPACITY, "max_nodes_capsule too large for the on-chip memory");

@@ -12,6 +12,10 @@ constexpr double kPlainStoreMaxBytes = 384.0 * (1 << 20);  // single pass: plain
 constexpr int kGridRowsPerThread = 1;  // grid kernel: nodes per thread, 4 rows apart
 constexpr int kNumXcd = 8;       // MI355X: workgroups are dealt round-robin to 8 XCDs
 constexpr int kIBThreads = 512;  // IB kernel block (one block per capsule)
+// per-node arrays in the IB kernel's LDS: positions (4), node state (8) and
+// work arrays (kNodeScratch)
+constexpr int kNodeScratch = 22;
+constexpr int kNodeLdsArrays = 12 + kNodeScratch;
 
 // The spread force is accumulated as a signed 64-bit fixed-point number with
 // 48 fractional bits.  Integer addition is associative, so the sum of

@@ -706,7 +706,7 @@ struct Scratch {
     T* l0l;
     T* ks;
     T* th0;
-    T* t[14];
+    T* t[kNodeScratch];
 };
 
 // Edge vector x_m - x_l from compensated coordinates: the difference of the
@@ -883,6 +883,131 @@ __device__ void external_forces(const Scratch<T>& S, const Patch<T>& P, int nv, 
         const T fy = (-dpr * ny + nu * (d01 * nx + d11 * ny)) * len;
         Ex[l] = T(0.5) * fx;
         Ey[l] = T(0.5) * fy;
+    }
+    __syncthreads();
+    for (int v = tid; v < nv; v += nt) {
+        const int vl = v == 0 ? nv - 1 : v - 1;
+        S.t[2][v] = Ex[v] + Ex[vl];
+        S.t[3][v] = Ey[v] + Ey[vl];
+    }
+    __syncthreads();
+}
+
+// Dynamic step 7 force terms in one pass.  Given the positions and the staged
+// patch, the membrane forces (Eqs. 10-14), the probes of Eqs. 15-16 and the
+// tentative velocity of Eq. 23 are independent of one another, so one loop
+// over 4 nv work items evaluates them together: per element its stretching
+// and area terms and per node its bending terms (S.t[14..21]), per (element,
+// side) a probe (S.t[0..7]), per node the interpolated fluid velocity
+// (S.t[12], S.t[13]); each kind starts on a wave boundary.  A second pass sums the membrane terms onto the nodes
+// (S.t[8], S.t[9]) and combines each element's two probes into its half force
+// (S.t[10], S.t[11]); a third adds the halves onto the nodes (S.t[2], S.t[3]).
+// Each item runs the arithmetic of internal_forces / external_forces, so the
+// results are the same bits; done one after the other those took seven block
+// barriers, this takes three.  A: the enclosed area (FP64), reduced by the
+// caller from the same positions.
+template <typename T>
+__device__ void dynamic_forces(const Scratch<T>& S, const Patch<T>& P, int nv, double kb,
+                               double ka, double A0, double A, T nu, float max_edge,
+                               float max_dA, int& st)
+{
+    const T* l0 = S.l0;
+    const T* l0l = S.l0l;
+    const T* th0 = S.th0;
+    const T* ks = S.ks;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const T cA = (T)(0.5 * ka * (1.0 - A / A0) / 3.0);  // half element area force per (t_y, -t_x)
+    if (max_dA > 0.0f && tid == 0 && !(fabs(A / A0 - 1.0) <= (double)max_dA)) st |= ST_AREA;
+    T* Px = S.t[14];
+    T* Py = S.t[15];
+    T* Qx = S.t[16];
+    T* Qy = S.t[17];
+    T* BLx = S.t[18];
+    T* BLy = S.t[19];
+    T* BRx = S.t[20];
+    T* BRy = S.t[21];
+    const T kbt = (T)kb;
+    const size_t stride = S.t[1] - S.t[0];
+    // item ranges start on wave boundaries, so that no wave mixes two kinds;
+    // three loops rather than one with three branches keep the register
+    // pressure of each kind to itself
+    const int n1 = (nv + 63) & ~63, n2 = n1 + ((2 * nv + 63) & ~63);
+    for (int w = tid; w < nv; w += nt) {
+        const int l = w, m = l + 1 == nv ? 0 : l + 1;
+        T tx, ty, len;
+        edge(S, l, m, tx, ty);
+        const T c = ks[l] * stretch(S, l, m, l0[l], l0l[l], len) / len;
+        if (max_edge > 0.0f && !(len <= (T)max_edge)) st |= ST_EDGE;
+        const T ax = cA * ty, ay = -cA * tx;
+        Px[l] = c * tx + ax;  // onto node l
+        Py[l] = c * ty + ay;
+        Qx[l] = -c * tx + ax;  // onto node l+1
+        Qy[l] = -c * ty + ay;
+        if (kb != 0.0) {
+            const int v = w, vl = v == 0 ? nv - 1 : v - 1, vr = m;
+            T ax2, ay2, bx, by;
+            edge(S, vl, v, ax2, ay2);
+            edge(S, v, vr, bx, by);
+            const T la = sqrt(ax2 * ax2 + ay2 * ay2), lb = sqrt(bx * bx + by * by);
+            const T th = atan2(ax2 * by - ay2 * bx, ax2 * bx + ay2 * by);
+            const T sn = kbt * sin(th - th0[v]);
+            BLx[v] = sn * ay2 / (la * la);
+            BLy[v] = -sn * ax2 / (la * la);
+            BRx[v] = sn * by / (lb * lb);
+            BRy[v] = -sn * bx / (lb * lb);
+        }
+    }
+    for (int w = tid - n1; w < 2 * nv; w += nt) {
+        if (w < 0) continue;
+        const int l = w >> 1, side = w & 1;
+        const int m = l + 1 == nv ? 0 : l + 1;
+        T tx, ty;
+        edge(S, l, m, tx, ty);
+        const T len = sqrt(tx * tx + ty * ty);
+        const T sg = side ? T(-1.2) : T(1.2);
+        const T nx = ty / len, ny = -tx / len;  // outward normal n+
+        const T xc = T(0.5) * (S.px[l] + S.px[m]), yc = T(0.5) * (S.py[l] + S.py[m]);
+        T dp, G[2][2];
+        probe(P, xc + sg * nx, yc + sg * ny, dp, G, st);
+        T* o = S.t[0] + (size_t)side * 4 * stride;
+        o[l] = dp;
+        o[stride + l] = T(2) * G[0][0];
+        o[2 * stride + l] = T(2) * G[1][1];
+        o[3 * stride + l] = G[0][1] + G[1][0];
+    }
+    for (int v = tid - n2; v < nv; v += nt) {
+        if (v < 0) continue;
+        interp_u(P, S.px[v], S.py[v], S.t[12][v], S.t[13][v], st);
+    }
+    __syncthreads();
+    T* Ex = S.t[10];
+    T* Ey = S.t[11];
+    for (int w = tid; w < 2 * nv; w += nt) {
+        if (w < nv) {
+            const int v = w, vl = v == 0 ? nv - 1 : v - 1, vr = v + 1 == nv ? 0 : v + 1;
+            T fx = Px[v] + Qx[vl], fy = Py[v] + Qy[vl];
+            if (kb != 0.0) {
+                fx += BRx[vl] + BLx[vr] - BLx[v] - BRx[v];
+                fy += BRy[vl] + BLy[vr] - BLy[v] - BRy[v];
+            }
+            S.t[8][v] = fx;
+            S.t[9][v] = fy;
+        } else {
+            const int l = w - nv, m = l + 1 == nv ? 0 : l + 1;
+            T tx, ty;
+            edge(S, l, m, tx, ty);
+            const T len = sqrt(tx * tx + ty * ty);
+            const T nx = ty / len, ny = -tx / len;
+            // (tau+ - tau-) . n+ with tau = nu (G + G^T)
+            const T dpr = S.t[0][l] - S.t[4][l];
+            const T d00 = S.t[1][l] - S.t[5][l];
+            const T d11 = S.t[2][l] - S.t[6][l];
+            const T d01 = S.t[3][l] - S.t[7][l];
+            const T fx = (-dpr * nx + nu * (d00 * nx + d01 * ny)) * len;
+            const T fy = (-dpr * ny + nu * (d01 * nx + d11 * ny)) * len;
+            Ex[l] = T(0.5) * fx;
+            Ey[l] = T(0.5) * fy;
+        }
     }
     __syncthreads();
     for (int v = tid; v < nv; v += nt) {
@@ -1257,7 +1382,7 @@ __device__ void rigid_update(const IBArgs<T>& a, const Scratch<T>& S, const Patc
 //             with c_v = node arc length), Kinematic steps i-iii (internal
 //             forces, c_v = 1)
 //   PH_DIAG   diagnostics of the current shape only
-template <typename T>
+template <typename T, bool DYN>
 __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* smem,
                                          double (*red)[8])
 {
@@ -1314,14 +1439,14 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
     S.l0l = node_lds[5];
     S.ks = node_lds[6];
     S.th0 = node_lds[7];
-    for (int k = 0; k < 14; k++) S.t[k] = S.th0 + (size_t)(k + 1) * a.max_nv;
+    for (int k = 0; k < kNodeScratch; k++) S.t[k] = S.th0 + (size_t)(k + 1) * a.max_nv;
 
     int st = 0;
     const bool prime = (a.phase & PH_PRIME) && !cap.primed;
     const bool doB = (a.phase & PH_B) && cap.primed;
     const bool doA = (a.phase & PH_A) != 0;
     long long refx = (long long)cap.ref_x, refy = (long long)cap.ref_y;
-    const bool need_field = prime || doB || (doA && a.dynamic);
+    const bool need_field = prime || doB || (doA && DYN);
     const T gxf = (T)cap.gx;
 
     // The patch box of this capsule's last launch: the waves that hold no node
@@ -1367,6 +1492,21 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
     }
     if (!finite) { mn[0] = -3e38f; }
     block_minmax(mn, mxv, red);  // ends with a barrier, so S.px/py are visible
+    // Dynamic node update: the enclosed area of x^n for the membrane forces,
+    // as wave partials in red[.][7], summed in wave order (as block_sum) after
+    // the staging barrier below
+    const bool dyn_forces = doB && DYN && !cap.rigid;
+    if (dyn_forces) {
+        double acc = 0.0;
+        for (int l = tid; l < nv; l += nt) {
+            const int m = l + 1 == nv ? 0 : l + 1;
+            const double xl = (double)S.px[l] + (double)S.qx[l], yl = (double)S.py[l] + (double)S.qy[l];
+            const double xm = (double)S.px[m] + (double)S.qx[m], ym = (double)S.py[m] + (double)S.qy[m];
+            acc += xl * ym - xm * yl;
+        }
+        acc = wave_sum(acc);
+        if ((tid & 63) == 0) red[tid >> 6][7] = acc;
+    }
 
     // ---- fluid patch: bounding box + 3 cells (probe 1.2 + support 1.5 + motion)
     if (need_field) {
@@ -1429,14 +1569,16 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
     if (doB) {
         double csum[2] = {0.0, 0.0};
         if (cap.rigid) rigid_update(a, S, P, cap, c, st, red, csum);
-        if (a.dynamic && !cap.rigid) {
-            internal_forces(S, nv, cap.kb, cap.ka, cap.A0, red, a.max_edge, a.max_dA, st);  // -> t8, t9
-            external_forces(S, P, nv, (T)cap.nu, st);                            // -> t2, t3
+        if (dyn_forces) {  // -> t8, t9 (membrane), t2, t3 (hydrodynamic), t12, t13 (Eq. 23)
+            double area = red[0][7];
+            for (int w = 1; w < (int)(nt >> 6); w++) area += red[w][7];
+            dynamic_forces(S, P, nv, cap.kb, cap.ka, cap.A0, 0.5 * area, (T)cap.nu, a.max_edge,
+                           a.max_dA, st);
         }
         const T half_inv_m = (T)(0.5 / cap.mv);
         for (int v = cap.rigid ? nv : tid; v < nv; v += nt) {
             T Ux, Uy;  // tentative velocity, Eq. 23 (Dynamic: interpolated beside the probes)
-            if (a.dynamic) {
+            if (DYN) {
                 Ux = S.t[12][v];
                 Uy = S.t[13][v];
             } else {
@@ -1444,7 +1586,7 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
             }
             const T dox = S.dx[v], doy = S.dy[v];
             T dx, dy;
-            if (a.dynamic) {
+            if (DYN) {
                 T fx = S.t[8][v] + S.t[2][v], fy = S.t[9][v] + S.t[3][v];
                 if (a.contact) {
                     fx += N[NF_CX * NS + off + v];
@@ -1549,7 +1691,7 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
 
     // ---- forcing of the new step
     if (doA) {
-        if (a.dynamic) {
+        if (DYN) {
             for (int v = tid; v < nv; v += nt) {
                 const int vl = v == 0 ? nv - 1 : v - 1, vr = v + 1 == nv ? 0 : v + 1;
                 int cx, cy;
@@ -1623,12 +1765,14 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
     if (st) atomicOr(a.status, st);
 }
 
-template <typename T>
+// One instance per coupling (DYN = a0.dynamic): each holds only its own
+// scheme's phases, which keeps the code a launch runs together.
+template <typename T, bool DYN>
 __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[kIBThreads / 64][8];
-    ib_block<T>(a0, smem, red);  // every exit of ib_block is block-uniform
+    ib_block<T, DYN>(a0, smem, red);  // every exit of ib_block is block-uniform
     if (a0.done_count) {
         // the block's stores (near map, force level, node state) are made
         // visible device-wide before the count announces them
@@ -1643,13 +1787,16 @@ __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
 template <typename T>
 size_t ib_lds_bytes(int patch_cap, int max_nv)
 {
-    return sizeof(T) * ((size_t)3 * patch_cap + (size_t)26 * max_nv);
+    return sizeof(T) * ((size_t)3 * patch_cap + (size_t)kNodeLdsArrays * max_nv);
 }
 
 template <typename T>
 hipError_t ib_set_lds_limit(size_t bytes)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ib<T>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ib<T, true>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ib<T, false>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
@@ -1657,7 +1804,10 @@ template <typename T>
 hipError_t launch_ib(const IBArgs<T>& a, int ncap, size_t lds_bytes, hipStream_t s)
 {
     if (ncap <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ib<T>, dim3(ncap), dim3(kIBThreads), lds_bytes, s, a);
+    if (a.dynamic)
+        hipLaunchKernelGGL((k_ib<T, true>), dim3(ncap), dim3(kIBThreads), lds_bytes, s, a);
+    else
+        hipLaunchKernelGGL((k_ib<T, false>), dim3(ncap), dim3(kIBThreads), lds_bytes, s, a);
     return hipGetLastError();
 }
 
