@@ -496,7 +496,8 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double (*red)[8])
     __syncthreads();
 }
 
-__device__ __forceinline__ void block_minmax(float (&mn)[2], float (&mx)[2], double (*red)[8])
+__device__ __forceinline__ void block_minmax(float (&mn)[2], float (&mx)[2], double (*red)[8],
+                                             bool closing_barrier = true)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int k = 0; k < 2; k++) {
@@ -520,7 +521,7 @@ __device__ __forceinline__ void block_minmax(float (&mn)[2], float (&mx)[2], dou
         mn[k] = a;
         mx[k] = b;
     }
-    __syncthreads();
+    if (closing_barrier) __syncthreads();
 }
 
 }  // namespace lbib

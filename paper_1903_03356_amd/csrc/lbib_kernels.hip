@@ -895,17 +895,16 @@ __device__ void external_forces(const Scratch<T>& S, const Patch<T>& P, int nv, 
 
 // Dynamic step 7 force terms in one pass.  Given the positions and the staged
 // patch, the membrane forces (Eqs. 10-14), the probes of Eqs. 15-16 and the
-// tentative velocity of Eq. 23 are independent of one another, so one loop
-// over 4 nv work items evaluates them together: per element its stretching
-// and area terms and per node its bending terms (S.t[14..21]), per (element,
-// side) a probe (S.t[0..7]), per node the interpolated fluid velocity
-// (S.t[12], S.t[13]); each kind starts on a wave boundary.  A second pass sums the membrane terms onto the nodes
-// (S.t[8], S.t[9]) and combines each element's two probes into its half force
-// (S.t[10], S.t[11]); a third adds the halves onto the nodes (S.t[2], S.t[3]).
-// Each item runs the arithmetic of internal_forces / external_forces, so the
-// results are the same bits; done one after the other those took seven block
-// barriers, this takes three.  A: the enclosed area (FP64), reduced by the
-// caller from the same positions.
+// tentative velocity of Eq. 23 are independent of one another, so they are
+// evaluated side by side: per element its stretching and area terms and per
+// node its bending terms (S.t[14..21]), per (element, side) a probe
+// (S.t[0..7]), per node the interpolated fluid velocity (S.t[12], S.t[13]),
+// each kind on its own waves.  A second pass combines each element's two
+// probes into its half force (S.t[10], S.t[11]); the node update adds the
+// nodal sums itself (dynamic_node_forces).  Each item runs the arithmetic of
+// internal_forces / external_forces, so the results are the same bits; done
+// one after the other those took seven block barriers, this takes two.
+// A: the enclosed area (FP64), reduced by the caller from the same positions.
 template <typename T>
 __device__ void dynamic_forces(const Scratch<T>& S, const Patch<T>& P, int nv, double kb,
                                double ka, double A0, double A, T nu, float max_edge,
@@ -982,18 +981,9 @@ __device__ void dynamic_forces(const Scratch<T>& S, const Patch<T>& P, int nv, d
     __syncthreads();
     T* Ex = S.t[10];
     T* Ey = S.t[11];
-    for (int w = tid; w < 2 * nv; w += nt) {
-        if (w < nv) {
-            const int v = w, vl = v == 0 ? nv - 1 : v - 1, vr = v + 1 == nv ? 0 : v + 1;
-            T fx = Px[v] + Qx[vl], fy = Py[v] + Qy[vl];
-            if (kb != 0.0) {
-                fx += BRx[vl] + BLx[vr] - BLx[v] - BRx[v];
-                fy += BRy[vl] + BLy[vr] - BLy[v] - BRy[v];
-            }
-            S.t[8][v] = fx;
-            S.t[9][v] = fy;
-        } else {
-            const int l = w - nv, m = l + 1 == nv ? 0 : l + 1;
+    for (int l = tid; l < nv; l += nt) {
+        {
+            const int m = l + 1 == nv ? 0 : l + 1;
             T tx, ty;
             edge(S, l, m, tx, ty);
             const T len = sqrt(tx * tx + ty * ty);
@@ -1010,12 +1000,27 @@ __device__ void dynamic_forces(const Scratch<T>& S, const Patch<T>& P, int nv, d
         }
     }
     __syncthreads();
-    for (int v = tid; v < nv; v += nt) {
-        const int vl = v == 0 ? nv - 1 : v - 1;
-        S.t[2][v] = Ex[v] + Ex[vl];
-        S.t[3][v] = Ey[v] + Ey[vl];
+}
+
+// Nodal sums of the Dynamic force pass for node v, formed as internal_forces
+// and external_forces form them: membrane (fix, fiy) and hydrodynamic (fex,
+// fey).  The node update takes them directly, which spares a pass and its
+// barrier.
+template <typename T>
+__device__ __forceinline__ void dynamic_node_forces(const Scratch<T>& S, int v, int nv, double kb,
+                                                    T& fix, T& fiy, T& fex, T& fey)
+{
+    const int vl = v == 0 ? nv - 1 : v - 1, vr = v + 1 == nv ? 0 : v + 1;
+    const T *Px = S.t[14], *Py = S.t[15], *Qx = S.t[16], *Qy = S.t[17];
+    const T *BLx = S.t[18], *BLy = S.t[19], *BRx = S.t[20], *BRy = S.t[21];
+    fix = Px[v] + Qx[vl];
+    fiy = Py[v] + Qy[vl];
+    if (kb != 0.0) {
+        fix += BRx[vl] + BLx[vr] - BLx[v] - BRx[v];
+        fiy += BRy[vl] + BLy[vr] - BLy[v] - BRy[v];
     }
-    __syncthreads();
+    fex = S.t[10][v] + S.t[10][vl];
+    fey = S.t[11][v] + S.t[11][vl];
 }
 
 template <typename T>
@@ -1491,7 +1496,10 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
         mxv[1] = fmaxf(mxv[1], (float)y);
     }
     if (!finite) { mn[0] = -3e38f; }
-    block_minmax(mn, mxv, red);  // ends with a barrier, so S.px/py are visible
+    // S.px/py are visible after its first barrier.  Its closing barrier (which
+    // keeps red[.][0..3] from being written again before every wave has read
+    // them) is left to the staging barrier below where there is one.
+    block_minmax(mn, mxv, red, !need_field);
     // Dynamic node update: the enclosed area of x^n for the membrane forces,
     // as wave partials in red[.][7], summed in wave order (as block_sum) after
     // the staging barrier below
@@ -1569,7 +1577,7 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
     if (doB) {
         double csum[2] = {0.0, 0.0};
         if (cap.rigid) rigid_update(a, S, P, cap, c, st, red, csum);
-        if (dyn_forces) {  // -> t8, t9 (membrane), t2, t3 (hydrodynamic), t12, t13 (Eq. 23)
+        if (dyn_forces) {  // element and probe terms, t12, t13 (Eq. 23); nodal sums below
             double area = red[0][7];
             for (int w = 1; w < (int)(nt >> 6); w++) area += red[w][7];
             dynamic_forces(S, P, nv, cap.kb, cap.ka, cap.A0, 0.5 * area, (T)cap.nu, a.max_edge,
@@ -1587,7 +1595,11 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
             const T dox = S.dx[v], doy = S.dy[v];
             T dx, dy;
             if (DYN) {
-                T fx = S.t[8][v] + S.t[2][v], fy = S.t[9][v] + S.t[3][v];
+                T fix, fiy, fex, fey;
+                dynamic_node_forces(S, v, nv, cap.kb, fix, fiy, fex, fey);
+                S.t[8][v] = fix;  // (kept for the tape of a launch without phase A)
+                S.t[9][v] = fiy;
+                T fx = fix + fex, fy = fiy + fey;
                 if (a.contact) {
                     fx += N[NF_CX * NS + off + v];
                     fy += N[NF_CY * NS + off + v];
@@ -1601,8 +1613,8 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
                 S.uy[v] = uvy;
                 N[NF_FX * NS + off + v] = fx;
                 N[NF_FY * NS + off + v] = fy;
-                N[NF_EX * NS + off + v] = S.t[2][v];
-                N[NF_EY * NS + off + v] = S.t[3][v];
+                N[NF_EX * NS + off + v] = fex;
+                N[NF_EY * NS + off + v] = fey;
             } else {
                 dx = dox * T(1.0 / 3.0) + Ux * T(2.0 / 3.0);  // Eq. 25 as an increment
                 dy = doy * T(1.0 / 3.0) + Uy * T(2.0 / 3.0);
