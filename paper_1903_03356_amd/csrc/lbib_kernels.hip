@@ -752,210 +752,90 @@ __device__ __forceinline__ T stretch(const Scratch<T>& S, int l, int m, T l0h, T
     return diff / (len + (l0h + l0l));
 }
 
-// Eqs. 10-14: internal nodal forces at positions (px, py); result in
-// (S.t[8], S.t[9]).  Stretch on element l: k_s (len - l0) t / len on node l and
-// its negative on node l+1.  Area: F_l = -k_a (1 - A/A0) c_s^2 n- len, half to
-// each end.  Bending (outer terms of Eq. 13 as printed, middle node takes
-// minus their sum): k_b sin(theta - theta0) n / len on the two neighbours.
-// The area A is an FP64 block reduction.
+// Eqs. 10-14, per element l -> l+1 (the stretching and area terms) and per node
+// v (the bending terms); the caller sums them onto the nodes with
+// membrane_node_force.  Stretch: k_s (len - l0) t / len on node l and its
+// negative on node l+1.  Area: F_l = -k_a (1 - A/A0) c_s^2 n- len, half to each
+// end, with A the FP64 enclosed area.  Bending (outer terms of Eq. 13 as
+// printed, the middle node takes minus their sum): k_b sin(theta - theta0) n /
+// len on the two neighbours.  Results in S.t[14..21].
 template <typename T>
-__device__ void internal_forces(const Scratch<T>& S, int nv, double kb, double ka, double A0,
-                                double (*red)[8], float max_edge, float max_dA, int& st)
+__device__ __forceinline__ void membrane_terms(const Scratch<T>& S, int l, int nv, double kb, T cA,
+                                               float max_edge, int& st)
 {
-    const T* l0 = S.l0;
-    const T* l0l = S.l0l;
-    const T* th0 = S.th0;
-    const T* ks = S.ks;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    double acc[1] = {0.0};
-    for (int l = tid; l < nv; l += nt) {
+    const int m = l + 1 == nv ? 0 : l + 1;
+    T tx, ty, len;
+    edge(S, l, m, tx, ty);
+    const T c = S.ks[l] * stretch(S, l, m, S.l0[l], S.l0l[l], len) / len;
+    // an element longer than the set limit (the forcing may leave holes, Sec. 3.2)
+    if (max_edge > 0.0f && !(len <= (T)max_edge)) st |= ST_EDGE;
+    const T ax = cA * ty, ay = -cA * tx;
+    S.t[14][l] = c * tx + ax;  // onto node l
+    S.t[15][l] = c * ty + ay;
+    S.t[16][l] = -c * tx + ax;  // onto node l+1
+    S.t[17][l] = -c * ty + ay;
+    if (kb != 0.0) {
+        const int v = l, vl = v == 0 ? nv - 1 : v - 1, vr = m;
+        T ax2, ay2, bx, by;
+        edge(S, vl, v, ax2, ay2);
+        edge(S, v, vr, bx, by);
+        const T la = sqrt(ax2 * ax2 + ay2 * ay2), lb = sqrt(bx * bx + by * by);
+        const T th = atan2(ax2 * by - ay2 * bx, ax2 * bx + ay2 * by);
+        const T sn = (T)kb * sin(th - S.th0[v]);
+        S.t[18][v] = sn * ay2 / (la * la);  // k_b s n_left / l_left, n_left = (a_y, -a_x)/l
+        S.t[19][v] = -sn * ax2 / (la * la);
+        S.t[20][v] = sn * by / (lb * lb);
+        S.t[21][v] = -sn * bx / (lb * lb);
+    }
+}
+
+// The FP64 enclosed area (Green's theorem over the compensated positions) as
+// this thread's share of the sum; block_sum / the wave partials complete it.
+template <typename T>
+__device__ __forceinline__ double area_share(const Scratch<T>& S, int nv)
+{
+    double acc = 0.0;
+    for (int l = threadIdx.x; l < nv; l += blockDim.x) {
         const int m = l + 1 == nv ? 0 : l + 1;
         const double xl = (double)S.px[l] + (double)S.qx[l], yl = (double)S.py[l] + (double)S.qy[l];
         const double xm = (double)S.px[m] + (double)S.qx[m], ym = (double)S.py[m] + (double)S.qy[m];
-        acc[0] += xl * ym - xm * yl;
+        acc += xl * ym - xm * yl;
     }
-    block_sum<1>(acc, red);
-    const double A = 0.5 * acc[0];
-    const T cA = (T)(0.5 * ka * (1.0 - A / A0) / 3.0);  // half element area force per (t_y, -t_x)
-    // enclosed area away from its stress-free value beyond the set limit
-    if (max_dA > 0.0f && tid == 0 && !(fabs(A / A0 - 1.0) <= (double)max_dA)) st |= ST_AREA;
-    T* Px = S.t[0];
-    T* Py = S.t[1];
-    T* Qx = S.t[2];
-    T* Qy = S.t[3];
-    for (int l = tid; l < nv; l += nt) {
-        const int m = l + 1 == nv ? 0 : l + 1;
-        T tx, ty, len;
-        edge(S, l, m, tx, ty);
-        const T c = ks[l] * stretch(S, l, m, l0[l], l0l[l], len) / len;
-        // an element longer than the set limit (the forcing may leave holes, Sec. 3.2)
-        if (max_edge > 0.0f && !(len <= (T)max_edge)) st |= ST_EDGE;
-        const T ax = cA * ty, ay = -cA * tx;
-        Px[l] = c * tx + ax;  // onto node l
-        Py[l] = c * ty + ay;
-        Qx[l] = -c * tx + ax;  // onto node l+1
-        Qy[l] = -c * ty + ay;
-    }
-    T* BLx = S.t[4];
-    T* BLy = S.t[5];
-    T* BRx = S.t[6];
-    T* BRy = S.t[7];
-    const T kbt = (T)kb;
-    if (kb != 0.0) {
-        for (int v = tid; v < nv; v += nt) {
-            const int vl = v == 0 ? nv - 1 : v - 1, vr = v + 1 == nv ? 0 : v + 1;
-            T ax, ay, bx, by;
-            edge(S, vl, v, ax, ay);
-            edge(S, v, vr, bx, by);
-            const T la = sqrt(ax * ax + ay * ay), lb = sqrt(bx * bx + by * by);
-            const T th = atan2(ax * by - ay * bx, ax * bx + ay * by);
-            const T sn = kbt * sin(th - th0[v]);
-            BLx[v] = sn * ay / (la * la);  // k_b s n_left / l_left, n_left = (a_y, -a_x)/l
-            BLy[v] = -sn * ax / (la * la);
-            BRx[v] = sn * by / (lb * lb);
-            BRy[v] = -sn * bx / (lb * lb);
-        }
-    }
-    __syncthreads();
-    for (int v = tid; v < nv; v += nt) {
-        const int vl = v == 0 ? nv - 1 : v - 1, vr = v + 1 == nv ? 0 : v + 1;
-        T fx = Px[v] + Qx[vl], fy = Py[v] + Qy[vl];
-        if (kb != 0.0) {
-            fx += BRx[vl] + BLx[vr] - BLx[v] - BRx[v];
-            fy += BRy[vl] + BLy[vr] - BLy[v] - BRy[v];
-        }
-        S.t[8][v] = fx;
-        S.t[9][v] = fy;
-    }
-    __syncthreads();
+    return acc;
 }
 
-// Eqs. 15-16: hydrodynamic nodal forces at positions (px, py) into
-// (S.t[2], S.t[3]).  One work item per (element, side) evaluates a probe
-// (pressure deviation and the symmetric velocity-gradient terms) into
-// S.t[0..7]; one per element combines both sides into its half force
-// (S.t[10..11]); one per node adds the halves of its two elements.  The
-// same pass also interpolates the fluid velocity at every node (Eq. 8) into
-// (S.t[12], S.t[13]), one more work item per node: it needs the same patch
-// and no force, so it fills threads the probes leave idle.
-template <typename T>
-__device__ void external_forces(const Scratch<T>& S, const Patch<T>& P, int nv, T nu, int& st)
+// Half element area force per (t_y, -t_x), and the area-drift flag.
+__device__ __forceinline__ double area_coefficient(double A, double A0, double ka, float max_dA,
+                                                   int& st)
 {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int w = tid; w < 3 * nv; w += nt) {
-        if (w >= 2 * nv) {
-            const int v = w - 2 * nv;
-            interp_u(P, S.px[v], S.py[v], S.t[12][v], S.t[13][v], st);
-            continue;
-        }
-        const int l = w >> 1, side = w & 1;
-        const int m = l + 1 == nv ? 0 : l + 1;
-        T tx, ty;
-        edge(S, l, m, tx, ty);
-        const T len = sqrt(tx * tx + ty * ty);
-        const T sg = side ? T(-1.2) : T(1.2);
-        const T nx = ty / len, ny = -tx / len;  // outward normal n+
-        const T xc = T(0.5) * (S.px[l] + S.px[m]), yc = T(0.5) * (S.py[l] + S.py[m]);
-        T dp, G[2][2];
-        probe(P, xc + sg * nx, yc + sg * ny, dp, G, st);
-        T* o = S.t[0] + (size_t)side * 4 * (S.t[1] - S.t[0]);
-        const size_t stride = S.t[1] - S.t[0];
-        o[l] = dp;
-        o[stride + l] = T(2) * G[0][0];
-        o[2 * stride + l] = T(2) * G[1][1];
-        o[3 * stride + l] = G[0][1] + G[1][0];
-    }
-    __syncthreads();
-    T* Ex = S.t[10];
-    T* Ey = S.t[11];
-    for (int l = tid; l < nv; l += nt) {
-        const int m = l + 1 == nv ? 0 : l + 1;
-        T tx, ty;
-        edge(S, l, m, tx, ty);
-        const T len = sqrt(tx * tx + ty * ty);
-        const T nx = ty / len, ny = -tx / len;
-        // (tau+ - tau-) . n+ with tau = nu (G + G^T)
-        const T dpr = S.t[0][l] - S.t[4][l];
-        const T d00 = S.t[1][l] - S.t[5][l];
-        const T d11 = S.t[2][l] - S.t[6][l];
-        const T d01 = S.t[3][l] - S.t[7][l];
-        const T fx = (-dpr * nx + nu * (d00 * nx + d01 * ny)) * len;
-        const T fy = (-dpr * ny + nu * (d01 * nx + d11 * ny)) * len;
-        Ex[l] = T(0.5) * fx;
-        Ey[l] = T(0.5) * fy;
-    }
-    __syncthreads();
-    for (int v = tid; v < nv; v += nt) {
-        const int vl = v == 0 ? nv - 1 : v - 1;
-        S.t[2][v] = Ex[v] + Ex[vl];
-        S.t[3][v] = Ey[v] + Ey[vl];
-    }
-    __syncthreads();
+    if (max_dA > 0.0f && threadIdx.x == 0 && !(fabs(A / A0 - 1.0) <= (double)max_dA)) st |= ST_AREA;
+    return 0.5 * ka * (1.0 - A / A0) / 3.0;
 }
 
 // Dynamic step 7 force terms in one pass.  Given the positions and the staged
 // patch, the membrane forces (Eqs. 10-14), the probes of Eqs. 15-16 and the
 // tentative velocity of Eq. 23 are independent of one another, so they are
-// evaluated side by side: per element its stretching and area terms and per
-// node its bending terms (S.t[14..21]), per (element, side) a probe
-// (S.t[0..7]), per node the interpolated fluid velocity (S.t[12], S.t[13]),
-// each kind on its own waves.  A second pass combines each element's two
+// evaluated side by side, each kind on its own waves: the membrane terms
+// (membrane_terms), per (element, side) a probe (S.t[0..7]: pressure deviation
+// and the symmetric velocity-gradient terms), per node the interpolated fluid
+// velocity (S.t[12], S.t[13]).  A second pass combines each element's two
 // probes into its half force (S.t[10], S.t[11]); the node update adds the
-// nodal sums itself (dynamic_node_forces).  Each item runs the arithmetic of
-// internal_forces / external_forces, so the results are the same bits; done
-// one after the other those took seven block barriers, this takes two.
-// A: the enclosed area (FP64), reduced by the caller from the same positions.
+// nodal sums itself (dynamic_node_forces).  Two block barriers in all (one
+// after the other these passes took seven).  A: the FP64 enclosed area,
+// reduced by the caller from the same positions.
 template <typename T>
 __device__ void dynamic_forces(const Scratch<T>& S, const Patch<T>& P, int nv, double kb,
                                double ka, double A0, double A, T nu, float max_edge,
                                float max_dA, int& st)
 {
-    const T* l0 = S.l0;
-    const T* l0l = S.l0l;
-    const T* th0 = S.th0;
-    const T* ks = S.ks;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const T cA = (T)(0.5 * ka * (1.0 - A / A0) / 3.0);  // half element area force per (t_y, -t_x)
-    if (max_dA > 0.0f && tid == 0 && !(fabs(A / A0 - 1.0) <= (double)max_dA)) st |= ST_AREA;
-    T* Px = S.t[14];
-    T* Py = S.t[15];
-    T* Qx = S.t[16];
-    T* Qy = S.t[17];
-    T* BLx = S.t[18];
-    T* BLy = S.t[19];
-    T* BRx = S.t[20];
-    T* BRy = S.t[21];
-    const T kbt = (T)kb;
+    const T cA = (T)area_coefficient(A, A0, ka, max_dA, st);
     const size_t stride = S.t[1] - S.t[0];
     // item ranges start on wave boundaries, so that no wave mixes two kinds;
     // three loops rather than one with three branches keep the register
     // pressure of each kind to itself
     const int n1 = (nv + 63) & ~63, n2 = n1 + ((2 * nv + 63) & ~63);
-    for (int w = tid; w < nv; w += nt) {
-        const int l = w, m = l + 1 == nv ? 0 : l + 1;
-        T tx, ty, len;
-        edge(S, l, m, tx, ty);
-        const T c = ks[l] * stretch(S, l, m, l0[l], l0l[l], len) / len;
-        if (max_edge > 0.0f && !(len <= (T)max_edge)) st |= ST_EDGE;
-        const T ax = cA * ty, ay = -cA * tx;
-        Px[l] = c * tx + ax;  // onto node l
-        Py[l] = c * ty + ay;
-        Qx[l] = -c * tx + ax;  // onto node l+1
-        Qy[l] = -c * ty + ay;
-        if (kb != 0.0) {
-            const int v = w, vl = v == 0 ? nv - 1 : v - 1, vr = m;
-            T ax2, ay2, bx, by;
-            edge(S, vl, v, ax2, ay2);
-            edge(S, v, vr, bx, by);
-            const T la = sqrt(ax2 * ax2 + ay2 * ay2), lb = sqrt(bx * bx + by * by);
-            const T th = atan2(ax2 * by - ay2 * bx, ax2 * bx + ay2 * by);
-            const T sn = kbt * sin(th - th0[v]);
-            BLx[v] = sn * ay2 / (la * la);
-            BLy[v] = -sn * ax2 / (la * la);
-            BRx[v] = sn * by / (lb * lb);
-            BRy[v] = -sn * bx / (lb * lb);
-        }
-    }
+    for (int l = tid; l < nv; l += nt) membrane_terms(S, l, nv, kb, cA, max_edge, st);
     for (int w = tid - n1; w < 2 * nv; w += nt) {
         if (w < 0) continue;
         const int l = w >> 1, side = w & 1;
@@ -979,36 +859,30 @@ __device__ void dynamic_forces(const Scratch<T>& S, const Patch<T>& P, int nv, d
         interp_u(P, S.px[v], S.py[v], S.t[12][v], S.t[13][v], st);
     }
     __syncthreads();
-    T* Ex = S.t[10];
-    T* Ey = S.t[11];
+    // each element's hydrodynamic force (tau+ - tau-) . n+ len, tau = nu (G + G^T),
+    // half to each end node
     for (int l = tid; l < nv; l += nt) {
-        {
-            const int m = l + 1 == nv ? 0 : l + 1;
-            T tx, ty;
-            edge(S, l, m, tx, ty);
-            const T len = sqrt(tx * tx + ty * ty);
-            const T nx = ty / len, ny = -tx / len;
-            // (tau+ - tau-) . n+ with tau = nu (G + G^T)
-            const T dpr = S.t[0][l] - S.t[4][l];
-            const T d00 = S.t[1][l] - S.t[5][l];
-            const T d11 = S.t[2][l] - S.t[6][l];
-            const T d01 = S.t[3][l] - S.t[7][l];
-            const T fx = (-dpr * nx + nu * (d00 * nx + d01 * ny)) * len;
-            const T fy = (-dpr * ny + nu * (d01 * nx + d11 * ny)) * len;
-            Ex[l] = T(0.5) * fx;
-            Ey[l] = T(0.5) * fy;
-        }
+        const int m = l + 1 == nv ? 0 : l + 1;
+        T tx, ty;
+        edge(S, l, m, tx, ty);
+        const T len = sqrt(tx * tx + ty * ty);
+        const T nx = ty / len, ny = -tx / len;
+        const T dpr = S.t[0][l] - S.t[4][l];
+        const T d00 = S.t[1][l] - S.t[5][l];
+        const T d11 = S.t[2][l] - S.t[6][l];
+        const T d01 = S.t[3][l] - S.t[7][l];
+        const T fx = (-dpr * nx + nu * (d00 * nx + d01 * ny)) * len;
+        const T fy = (-dpr * ny + nu * (d01 * nx + d11 * ny)) * len;
+        S.t[10][l] = T(0.5) * fx;
+        S.t[11][l] = T(0.5) * fy;
     }
     __syncthreads();
 }
 
-// Nodal sums of the Dynamic force pass for node v, formed as internal_forces
-// and external_forces form them: membrane (fix, fiy) and hydrodynamic (fex,
-// fey).  The node update takes them directly, which spares a pass and its
-// barrier.
+// Nodal sum of the membrane terms (S.t[14..21]) for node v.
 template <typename T>
-__device__ __forceinline__ void dynamic_node_forces(const Scratch<T>& S, int v, int nv, double kb,
-                                                    T& fix, T& fiy, T& fex, T& fey)
+__device__ __forceinline__ void membrane_node_force(const Scratch<T>& S, int v, int nv, double kb,
+                                                    T& fix, T& fiy)
 {
     const int vl = v == 0 ? nv - 1 : v - 1, vr = v + 1 == nv ? 0 : v + 1;
     const T *Px = S.t[14], *Py = S.t[15], *Qx = S.t[16], *Qy = S.t[17];
@@ -1019,8 +893,44 @@ __device__ __forceinline__ void dynamic_node_forces(const Scratch<T>& S, int v, 
         fix += BRx[vl] + BLx[vr] - BLx[v] - BRx[v];
         fiy += BRy[vl] + BLy[vr] - BLy[v] - BRy[v];
     }
+}
+
+// Nodal sums of the Dynamic force pass for node v: membrane (fix, fiy) and
+// hydrodynamic (fex, fey, the halves of its two elements).  The node update
+// takes them directly, which spares a pass and its barrier.
+template <typename T>
+__device__ __forceinline__ void dynamic_node_forces(const Scratch<T>& S, int v, int nv, double kb,
+                                                    T& fix, T& fiy, T& fex, T& fey)
+{
+    membrane_node_force(S, v, nv, kb, fix, fiy);
+    const int vl = v == 0 ? nv - 1 : v - 1;
     fex = S.t[10][v] + S.t[10][vl];
     fey = S.t[11][v] + S.t[11][vl];
+}
+
+// Kinematic step i and the spreading weights of step iii in one pass: after
+// the FP64 area reduction, the membrane terms (membrane_terms) and, on their
+// own waves, each node's MLS fit at x^n (cache_weights) are independent, so
+// they run side by side; the caller then adds the nodal sums
+// (membrane_node_force).
+template <typename T>
+__device__ void kinematic_forces(const Scratch<T>& S, int nv, double kb, double ka, double A0,
+                                 double (*red)[8], float max_edge, float max_dA, int& st)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    double acc[1] = {area_share(S, nv)};
+    block_sum<1>(acc, red);
+    const T cA = (T)area_coefficient(0.5 * acc[0], A0, ka, max_dA, st);
+    const int n1 = (nv + 63) & ~63;
+    for (int l = tid; l < nv; l += nt) membrane_terms(S, l, nv, kb, cA, max_edge, st);
+    for (int v = tid - n1; v < nv; v += nt) {
+        if (v < 0) continue;
+        int cx, cy;
+        T phi[9];
+        mls<T, false>(S.px[v], S.py[v], cx, cy, phi, nullptr, nullptr);
+        cache_weights(S, v, cx, cy, phi);  // c_v = 1
+    }
+    __syncthreads();
 }
 
 template <typename T>
@@ -1505,14 +1415,7 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
     // the staging barrier below
     const bool dyn_forces = doB && DYN && !cap.rigid;
     if (dyn_forces) {
-        double acc = 0.0;
-        for (int l = tid; l < nv; l += nt) {
-            const int m = l + 1 == nv ? 0 : l + 1;
-            const double xl = (double)S.px[l] + (double)S.qx[l], yl = (double)S.py[l] + (double)S.qy[l];
-            const double xm = (double)S.px[m] + (double)S.qx[m], ym = (double)S.py[m] + (double)S.qy[m];
-            acc += xl * ym - xm * yl;
-        }
-        acc = wave_sum(acc);
+        const double acc = wave_sum(area_share(S, nv));
         if ((tid & 63) == 0) red[tid >> 6][7] = acc;
     }
 
@@ -1729,18 +1632,18 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
                 S.t[9][v] = cv * Fy;
             }
         } else {
-            internal_forces(S, nv, cap.kb, cap.ka, cap.A0, red, a.max_edge, a.max_dA, st);  // -> t8, t9
+            kinematic_forces(S, nv, cap.kb, cap.ka, cap.A0, red, a.max_edge, a.max_dA, st);
             for (int v = tid; v < nv; v += nt) {
+                T fx, fy;
+                membrane_node_force(S, v, nv, cap.kb, fx, fy);
                 if (a.contact) {
-                    S.t[8][v] += N[NF_CX * NS + off + v];
-                    S.t[9][v] += N[NF_CY * NS + off + v];
+                    fx += N[NF_CX * NS + off + v];
+                    fy += N[NF_CY * NS + off + v];
                 }
-                N[NF_FX * NS + off + v] = S.t[8][v];
-                N[NF_FY * NS + off + v] = S.t[9][v];
-                int cx, cy;
-                T phi[9];
-                mls<T, false>(S.px[v], S.py[v], cx, cy, phi, nullptr, nullptr);
-                cache_weights(S, v, cx, cy, phi);  // c_v = 1
+                S.t[8][v] = fx;
+                S.t[9][v] = fy;
+                N[NF_FX * NS + off + v] = fx;
+                N[NF_FY * NS + off + v] = fy;
             }
         }
         __syncthreads();
