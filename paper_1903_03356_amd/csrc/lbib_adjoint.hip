@@ -766,7 +766,8 @@ __device__ void external_vjp(const AdjScratch<T>& S, const Patch<T>& P, int nv, 
 // Carried adjoints lamx, lamd enter as those of x^n, d^n and leave as those
 // of x^{n-1}, d^{n-1}.  The adjoint of the moments M^n goes into lambda P^n
 // (transpose of the pull) and lambda F^{n-1} (its half-force term).
-template <typename T>
+// One instance per coupling (DYN = DYN), as the forward IB kernel.
+template <typename T, bool DYN>
 __global__ __launch_bounds__(kAdjThreads) void k_ib_adj(IBAdjArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -889,7 +890,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_ib_adj(IBAdjArgs<T> a)
 
     // ---- reverse of the forcing of step n (at x^n)
     if (a.doA) {
-        if (a.dynamic) {
+        if (DYN) {
             for (int v = tid; v < nv; v += nt) {
                 const int vl = v == 0 ? nv - 1 : v - 1, vr = v + 1 == nv ? 0 : v + 1;
                 const int cx = (int)floor(S.hxn[v] + T(0.5)), cy = (int)floor(S.hyn[v] + T(0.5));
@@ -1034,7 +1035,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_ib_adj(IBAdjArgs<T> a)
         const double m = cap.mv;
         for (int v = tid; v < nv; v += nt) {
             double lvx, lvy;  // adjoint of the interpolated velocity (xdot_0 / xdot)
-            if (a.dynamic) {
+            if (DYN) {
                 const double tx = S.ldx[v] + 1.5 * S.lux[v] + S.lx[v];
                 const double ty = S.ldy[v] + 1.5 * S.luy[v] + S.ly[v];
                 S.lFx[v] = tx / (2.0 * m);
@@ -1058,7 +1059,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_ib_adj(IBAdjArgs<T> a)
             S.ly[v] += gpy;
         }
         __syncthreads();
-        if (a.dynamic) {
+        if (DYN) {
             const T* N0 = a.consts;
             const double lA = internal_vjp(S, S.Xp, S.Yp, nv, N0 + NF_L0 * NS + off,
                                            N0 + NF_L0L * NS + off, N0 + NF_KS * NS + off, cap.ka,
@@ -1153,14 +1154,20 @@ template <typename T>
 hipError_t launch_ib_adj(const IBAdjArgs<T>& a, int ncap, size_t lds_bytes, hipStream_t s)
 {
     if (ncap <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ib_adj<T>, dim3(ncap), dim3(kAdjThreads), lds_bytes, s, a);
+    if (a.dynamic)
+        hipLaunchKernelGGL((k_ib_adj<T, true>), dim3(ncap), dim3(kAdjThreads), lds_bytes, s, a);
+    else
+        hipLaunchKernelGGL((k_ib_adj<T, false>), dim3(ncap), dim3(kAdjThreads), lds_bytes, s, a);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t ib_adj_set_lds_limit(size_t bytes)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ib_adj<T>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ib_adj<T, true>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ib_adj<T, false>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
