@@ -156,7 +156,9 @@ size_t lbib_required_bytes(const lbib_grid* grid, int32_t buffer_id);
  * populations f^0 = f^eq(1, u_init) (Eq. 2), queued on the stream.
  * Errors: EINVAL (nx or ny < 8, tau <= 1/2, periodic_x not 0 or 1, an open channel
  * with moving or periodic walls or a body force, real_bytes not 4 or 8,
- * non-finite values, NULL buffers), ECAPACITY (capacities out of range),
+ * non-finite values, NULL buffers), ECAPACITY (capacities out of range, or a
+ * max_nodes_capsule whose node arrays leave the IB kernel's on-chip memory too
+ * little room for a fluid patch: on MI355X about 1100 nodes in FP32, 500 in FP64),
  * EDEVICE (HIP failure).  *out is set only on success. */
 lbib_status lbib_create(const lbib_grid* grid, double tau, const lbib_walls* walls,
                         void* const* device_buffers, int32_t n_buffers, void* hip_stream,
