@@ -485,6 +485,13 @@ def main() -> int:
             c3r["ms_per_step"] / c3k["ms_per_step"], 4)
         log(f"2048x512 channel, Kinematic coupling: {c3k['mlups']:.0f} MLUPS; Dynamic / Kinematic "
             f"time per step {side['inertial_2048x512_dynamic_over_kinematic_time']:.3f}")
+        cc = wl.couette_migration()
+        ccr = time_gpu(cc, max(args.steps, 2000), args.warmup, timing=False)
+        del ccr["sim"]
+        side["couette_256x101_us_per_step"] = round(ccr["ms_per_step"] * 1e3, 2)
+        log(f"256x101 Couette migration (Kinematic): {ccr['ms_per_step'] * 1e3:.1f} us/step "
+            f"({ccr['mlups']:.0f} MLUPS), its {cc['steps']} steps in "
+            f"{ccr['ms_per_step'] * cc['steps'] * 1e-3:.0f} s")
         ens = bench_ensemble(min(args.steps, 400), args.warmup, 20)
         log(f"ensemble: batched {ens['mlups']:.0f} MLUPS ({ens['ms_per_step']:.3f} ms/step, "
             f"{ens['overlapped_ms_per_step']:.3f} split near / far, "

@@ -15,6 +15,7 @@ Run from the repository root, one case at a time:
     python tests/golden/make_long_runs.py ensemble   # 8 seeded lattices of the 256-lattice ensemble, 10000 steps
     python tests/golden/make_long_runs.py inertial   # 2048 x 512 channel, 32 capsules, STEPS steps
     python tests/golden/make_long_runs.py adjoint    # 512 x 128 gradient channel, 5000 steps, central differences
+    python tests/golden/make_long_runs.py couette    # 256 x 101 Couette flow, capsule released at 0.25 H, 2e6 steps
 
 Each case writes one JSON file beside this script, every float kept to ten
 significant digits.  A field sample is 256 cells drawn by numpy's
@@ -44,6 +45,7 @@ CHANNEL_CAS = (1e-3, 1e-2, 1e-1)
 ENSEMBLE_LATTICES = 8
 ENSEMBLE_PICK_SEED = 7
 ADJ_ELEMENTS = (0, 37)
+TRAJ_EVERY = 50000
 
 
 def sample_cells(nx: int, ny: int):
@@ -143,6 +145,33 @@ def case_inertial(steps: int) -> None:
     print(f"inertial: {time.time() - t:.0f} s", flush=True)
 
 
+def case_couette() -> None:
+    """The Sec. 3.5 Couette case at density ratio 1 over the whole migration:
+    the centroid, the Taylor deformation and the perimeter every TRAJ_EVERY
+    steps, and the sampled state at the end."""
+    t = time.time()
+    cfg = wl.couette_migration(real_bytes=8)
+    steps = int(cfg["steps"])
+    s = orc.Sim(cfg)
+    traj = []
+    while s.steps < steps:
+        s.step(min(TRAJ_EVERY, steps - s.steps))
+        if s.status:
+            raise RuntimeError(f"oracle status {s.status} at step {s.steps}")
+        d = s.diag(0)
+        traj.append({"steps": s.steps, "cx": d["cx"], "cy": d["cy"], "D": d["D"],
+                     "perimeter": d["perimeter"]})
+        print(traj[-1], f"{time.time() - t:.0f} s", flush=True)
+    write("long_couette.json", {
+        "_comment": "FP64 oracle, Kinematic coupling (Eq. 25), 256 x 101 Couette flow with a circular "
+                    "capsule released at 0.25 H (Sec. 3.5 set-up, density ratio 1, E_b = 0); written by "
+                    "make_long_runs.py",
+        "workload": {"fn": "couette_migration", "mode": "kinematic"},
+        "steps": steps, "H": cfg["ny"] - 1, "trajectory_every": TRAJ_EVERY, "trajectory": traj,
+        **snapshot(s, cfg)})
+    print(f"couette: {time.time() - t:.0f} s", flush=True)
+
+
 def both_objectives(cfg, steps):
     d = run(cfg, steps).diag(0)
     return d["D"], d["cy"]
@@ -193,6 +222,8 @@ def main() -> None:
         case_inertial(int(sys.argv[2]) if len(sys.argv) > 2 else 50000)
     elif which == "adjoint":
         case_adjoint()
+    elif which == "couette":
+        case_couette()
     else:
         raise SystemExit(__doc__)
 

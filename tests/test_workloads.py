@@ -32,3 +32,18 @@ def test_inputs_are_reproducible():
     assert not np.array_equal(a["capsules"][0]["nodes"], c["capsules"][0]["nodes"])
     for cap in a["capsules"]:
         assert wl.stability_ratio(cap["ks"], cap["mass"], len(cap["nodes"])) <= 1.5
+
+
+def test_couette_migration_figures():
+    """Sec. 3.5 set-up: H = 100, Re = 10 at tau = 0.8 gives a top-wall speed of
+    0.01; d = 0.25 H released at 0.25 H; Ca = 1e-3 gives k_s = 1."""
+    cfg = wl.couette_migration()
+    assert (cfg["nx"], cfg["ny"]) == (256, 101)
+    assert cfg["u_bottom"] == 0.0 and abs(cfg["u_top"] - 0.01) < 1e-15
+    assert cfg["init_profile"] == wl.INIT_COUETTE and cfg["mode"] == "kinematic"
+    cap = cfg["capsules"][0]
+    nodes = cap["nodes"]
+    np.testing.assert_allclose(nodes.mean(axis=0), (128.0, 25.0), atol=1e-12)
+    np.testing.assert_allclose(np.hypot(*(nodes - (128.0, 25.0)).T), 12.5, atol=1e-12)
+    assert abs(cap["ks"] - 1.0) < 1e-12 and cap["kb"] == 0.0 and len(nodes) == 100
+    assert abs(wl.couette_migration(eb=0.1)["capsules"][0]["kb"] - 15.625) < 1e-9
