@@ -843,6 +843,15 @@ static IBArgs<T> ib_args(const lbib_ctx* c, long long n, int phase)
     return a;
 }
 
+// The IB kernel's larger register budget holds one block per compute unit; it
+// serves the launches that run alone (no near regions: not beside a far pass)
+// and fit the device in one round.
+template <typename T>
+static bool ib_wide(const lbib_ctx* c, const IBArgs<T>& a)
+{
+    return a.rects == nullptr && c->ncap <= c->num_cu;
+}
+
 template <typename T>
 static lbib_status launch_timed(lbib_ctx* c, int kind, hipError_t (*fn)(lbib_ctx*, void*),
                                 void* arg, hipStream_t on = nullptr)
@@ -881,7 +890,7 @@ static hipError_t do_ib(lbib_ctx* c, void* p)
         a.stamp = step_stamp(q->n);
         if (c->L.inst.size() == 1) a.done_count = ib_done_counter(c);
     }
-    hipError_t e = launch_ib<T>(a, c->ncap, c->lds_use, c->stream);
+    hipError_t e = launch_ib<T>(a, c->ncap, c->lds_use, c->stream, ib_wide(c, a));
     if (e == hipSuccess && a.done_count) c->ib_blocks_issued += (unsigned long long)c->ncap;
     return e;
 }
@@ -1279,7 +1288,7 @@ static lbib_status get_t(lbib_ctx* c, int what, int cap, void* dst, size_t bytes
         if (bytes < kDiagStride * sizeof(double)) return fail(c, LBIB_EINVAL, "dst too small");
         size_patches<T>(c);
         IBArgs<T> a = ib_args<T>(c, c->steps, PH_DIAG);
-        HIPCHK(c, launch_ib<T>(a, c->ncap, c->lds_use, c->stream));
+        HIPCHK(c, launch_ib<T>(a, c->ncap, c->lds_use, c->stream, ib_wide(c, a)));
         const double* src = reinterpret_cast<const double*>(bufp(c, LBIB_BUF_DIAG)) +
                             (size_t)cap * kDiagStride;
         if (on_dev)
@@ -1529,7 +1538,7 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
                 a.flags_next = gFl(r + 1);
                 a.tape_nodes = sN(n);
                 a.tape_ref = sR(n);
-                HIPCHK(c, launch_ib<T>(a, c->ncap, c->lds_use, st));
+                HIPCHK(c, launch_ib<T>(a, c->ncap, c->lds_use, st, ib_wide(c, a)));
             }
             HIPCHK(c, launch_grid_step<T>(gP(r), gP(r + 1), gF(r + 1), gFl(r + 1), gF(r + 1),
                                           zero_flags, g, st));
@@ -1570,7 +1579,7 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
         a.flags_next = gFl(rN);
         a.tape_nodes = sN(N);
         a.tape_ref = sR(N);
-        HIPCHK(c, launch_ib<T>(a, c->ncap, c->lds_use, st));
+        HIPCHK(c, launch_ib<T>(a, c->ncap, c->lds_use, st, ib_wide(c, a)));
     }
     // the context now stands at step N
     HIPCHK(c, hipMemcpyAsync(pops(c, N), gP(rN), pop_bytes, d2d, st));

@@ -209,8 +209,12 @@ int grid_blocks_rows(int ny, int nseg, int rows);
 // Tiles of a lattice in the linear mapping: bands times segments, rounded up
 // to a multiple of 8.
 int grid_tiles_linear(int ny, int nseg, int rows);
+// One IB block per capsule.  `wide`: the instance with the larger register
+// budget, for a launch that runs alone with at most one block per compute
+// unit (not beside the far pass).
 template <typename T>
-hipError_t launch_ib(const IBArgs<T>& a, int ncap, size_t lds_bytes, hipStream_t s);
+hipError_t launch_ib(const IBArgs<T>& a, int ncap, size_t lds_bytes, hipStream_t s,
+                     bool wide);
 template <typename T>
 size_t ib_lds_bytes(int patch_cap, int max_nv);
 template <typename T>

@@ -1684,7 +1684,7 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
 // scheme's phases, which keeps the code a launch runs together.
 //
 // Two register budgets per coupling.  Beside the far pass of a split step
-// (a0.rects set) an IB block must stay within 112 VGPRs per lane, so that it
+// an IB block must stay within 112 VGPRs per lane, so that it
 // shares a compute unit with seven far waves per SIMD; the compiler's own
 // allocation for this kernel is 106 VGPRs, with 118-145 SGPRs spilled to
 // VGPR lanes.  Launched alone (the serial schedule, batches, diagnostics) it
@@ -1692,9 +1692,11 @@ __device__ __forceinline__ void ib_block(const IBArgs<T>& a0, unsigned char* sme
 // the default wave priority, so nothing changes at run time, but with it at
 // the entry this compiler allocates 151 VGPRs and spills half as many SGPRs.
 // Measured per step: 1024x256 channel 24.1 -> 23.7 us, 2048x512 channel with
-// 32 capsules 33.5 -> 33.1 us.  Beside the far pass a build with that
-// allocation took 190 us against 80 us and slowed the 4096^2 step by 11 us,
-// hence the two budgets.
+// 32 capsules 33.5 -> 33.1 us.  At 151 VGPRs one block fills a compute
+// unit's register file, so the wide instance serves only launches that run
+// alone with at most one block per compute unit; beside the far pass a build
+// with that allocation took 190 us against 80 us and slowed the 4096^2 step by
+// 11 us, and the 388-capsule ensemble's launch took 36 us against 27 us.
 template <typename T, bool DYN, bool WIDE>
 __global__ __launch_bounds__(kIBThreads) void k_ib(IBArgs<T> a0)
 {
@@ -1735,11 +1737,11 @@ hipError_t ib_set_lds_limit(size_t bytes)
 }
 
 template <typename T>
-hipError_t launch_ib(const IBArgs<T>& a, int ncap, size_t lds_bytes, hipStream_t s)
+hipError_t launch_ib(const IBArgs<T>& a, int ncap, size_t lds_bytes, hipStream_t s, bool wide)
 {
     if (ncap <= 0) return hipSuccess;
     const dim3 grid(ncap), block(kIBThreads);
-    if (a.rects) {  // beside the far pass: the compact register budget
+    if (!wide) {
         if (a.dynamic)
             hipLaunchKernelGGL((k_ib<T, true, false>), grid, block, lds_bytes, s, a);
         else
@@ -2114,7 +2116,7 @@ hipError_t launch_set_nodes(T* nodes, CapsuleDev* caps, int cap, int nv, int nod
     template hipError_t launch_contact<T>(const ContactArgs<T>&, hipStream_t);                   \
     template hipError_t launch_spread_tape<T>(const SpreadTapeArgs<T>&, int, hipStream_t);         \
     template hipError_t contact_set_lds_limit<T>(int);                                            \
-    template hipError_t launch_ib<T>(const IBArgs<T>&, int, size_t, hipStream_t);                 \
+    template hipError_t launch_ib<T>(const IBArgs<T>&, int, size_t, hipStream_t, bool);                 \
     template size_t ib_lds_bytes<T>(int, int);                                                    \
     template hipError_t ib_set_lds_limit<T>(size_t);                                              \
     template hipError_t launch_get_pop_plane<T>(const T*, double*, int, int, const GridArgs&,     \
