@@ -42,8 +42,10 @@ def golden(name: str):
         return json.load(f)
 
 
-def compare_snapshot(sim, lattice: int, cap_ids, ref, steps: int, tag: str, u_max: float = U_MAX):
-    """Checks one lattice of ``sim`` against an oracle snapshot; returns the errors."""
+def compare_snapshot(sim, lattice: int, cap_ids, ref, steps: int, tag: str, u_max: float = U_MAX,
+                     scale: float = 1.0):
+    """Checks one lattice of ``sim`` against an oracle snapshot; returns the errors.
+    ``scale`` multiplies every bar (below 1 for an FP64 run)."""
     m = sim.moments(lattice)
     cells = np.asarray(ref["cells"])
     got = m[:, cells[:, 1], cells[:, 0]].T
@@ -63,11 +65,11 @@ def compare_snapshot(sim, lattice: int, cap_ids, ref, steps: int, tag: str, u_ma
     out = {"u_l2_rel": e_u, "profile_rel": e_prof, "rho_max_abs": e_rho, "x_max_abs": e_x,
            "D_max_abs": e_d}
     log(f"{tag}: " + ", ".join(f"{k} {v:.2e}" for k, v in out.items()))
-    assert e_u <= 1e-5, (tag, out)
-    assert e_prof <= 1e-5, (tag, out)
-    assert e_rho <= 1e-5, (tag, out)
-    assert e_d <= 1e-4, (tag, out)
-    assert e_x <= 1e-5 * u_max * steps, (tag, out)
+    assert e_u <= 1e-5 * scale, (tag, out)
+    assert e_prof <= 1e-5 * scale, (tag, out)
+    assert e_rho <= 1e-5 * scale, (tag, out)
+    assert e_d <= 1e-4 * scale, (tag, out)
+    assert e_x <= 1e-5 * u_max * steps * scale, (tag, out)
     return out
 
 
@@ -150,12 +152,16 @@ def test_adjoint_full_horizon():
 
 
 @pytest.mark.gpu
-def test_couette_migration_full_horizon():
+@pytest.mark.parametrize("real_bytes", [4, 8])
+def test_couette_migration_full_horizon(real_bytes):
     """The Sec. 3.5 Couette case (256 x 101, capsule released at 0.25 H,
-    density ratio 1), FP32, all 2e6 steps: the centroid and the deformation
-    along the whole migration, and the sampled state at the end."""
+    density ratio 1), all 2e6 steps: the centroid and the deformation along
+    the whole migration, and the sampled state at the end.  FP32 to the bars
+    of this file; FP64 to 1e-3 of them (the same arithmetic as the oracle in
+    another order; the stored values keep ten significant digits)."""
     ref = golden("long_couette.json")
-    cfg = wl.couette_migration()
+    cfg = wl.couette_migration(real_bytes=real_bytes)
+    scale = 1.0 if real_bytes == 4 else 1e-3
     steps = ref["steps"]
     assert steps == cfg["steps"] == ref["trajectory"][-1]["steps"]
     u_top = cfg["u_top"]
@@ -169,12 +175,13 @@ def test_couette_migration_full_horizon():
         e_c = max(abs(d["cx"] - r["cx"]), abs(d["cy"] - r["cy"]))
         e_d = abs(d["D"] - r["D"])
         worst = {"c": max(worst["c"], e_c), "D": max(worst["D"], e_d)}
-        assert e_c <= 1e-5 * u_top * r["steps"], (r["steps"], d["cx"], d["cy"], r)
-        assert e_d <= 1e-4, (r["steps"], d["D"], r["D"])
-    log(f"couette trajectory: centroid {worst['c']:.2e}, D {worst['D']:.2e}, "
+        assert e_c <= 1e-5 * u_top * r["steps"] * scale, (r["steps"], d["cx"], d["cy"], r)
+        assert e_d <= 1e-4 * scale, (r["steps"], d["D"], r["D"])
+    log(f"couette trajectory ({8 * real_bytes} bit): centroid {worst['c']:.2e}, D {worst['D']:.2e}, "
         f"final y_c {sim.diag(0)['cy']:.4f} (oracle {ref['trajectory'][-1]['cy']:.4f})")
     assert sim.check() == 0
-    compare_snapshot(sim, 0, [0], ref, steps, f"couette 256x101, {steps} steps", u_max=u_top)
+    compare_snapshot(sim, 0, [0], ref, steps, f"couette 256x101 ({8 * real_bytes} bit), {steps} steps",
+                     u_max=u_top, scale=scale)
 
 
 def test_couette_migration_reaches_centreline():
