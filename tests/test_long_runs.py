@@ -1,5 +1,5 @@
 """Parity over the full horizons of the channel workloads: the HIP library in
-FP32 against the FP64 oracle's state after the whole run.
+FP32 (and in FP64) against the FP64 oracle's state after the whole run.
 
 The oracle runs take minutes to an hour on the CPU, so their sampled state is
 stored under tests/golden/ by make_long_runs.py, which calls only the oracle
@@ -14,6 +14,7 @@ Bars (after the run):
   the displacement a 1e-5 relative velocity error accumulates), 4e-3 lattice
   units over 20000 steps;
 - density at the sampled cells: within 1e-5.
+An FP64 run takes 1e-3 of each bar.
 
 The printed Dynamic coupling does not stay finite over these horizons (its
 membrane zigzag mode grows; the oracle shows the same), so the runs use the
@@ -73,26 +74,35 @@ def compare_snapshot(sim, lattice: int, cap_ids, ref, steps: int, tag: str, u_ma
     return out
 
 
+def bar_scale(real_bytes: int) -> float:
+    """FP32 runs take the bars above; FP64 runs 1e-3 of them (the oracle's
+    arithmetic in another order, against values stored to ten digits)."""
+    return 1.0 if real_bytes == 4 else 1e-3
+
+
 @pytest.mark.gpu
+@pytest.mark.parametrize("real_bytes", [4, 8])
 @pytest.mark.parametrize("ca", [1e-3, 1e-2, 1e-1])
-def test_channel_full_horizon(ca):
-    """1024 x 256 biconcave channel, FP32, all 20000 steps."""
+def test_channel_full_horizon(ca, real_bytes):
+    """1024 x 256 biconcave channel, all 20000 steps."""
     ref = golden(f"long_channel_ca{ca:g}.json")
-    cfg = wl.poiseuille_biconcave(ca, mode="kinematic")
+    cfg = wl.poiseuille_biconcave(ca, mode="kinematic", real_bytes=real_bytes)
     steps = ref["steps"]
     assert steps == cfg["steps"] == 20000
     sim = lbib.Sim(cfg)
     sim.step(steps, "kinematic")
     assert sim.check() == 0
-    compare_snapshot(sim, 0, [0], ref, steps, f"channel Ca {ca:g}, {steps} steps")
+    compare_snapshot(sim, 0, [0], ref, steps, f"channel Ca {ca:g} ({8 * real_bytes} bit), {steps} steps",
+                     scale=bar_scale(real_bytes))
 
 
 @pytest.mark.gpu
-def test_ensemble_full_horizon():
-    """The 256-lattice ensemble in one batched context, FP32, all 10000 steps;
+@pytest.mark.parametrize("real_bytes", [4, 8])
+def test_ensemble_full_horizon(real_bytes):
+    """The 256-lattice ensemble in one batched context, all 10000 steps;
     8 seeded lattices against the oracle."""
     ref = golden("long_ensemble.json")
-    cfgs = wl.ensemble(seed=0, mode="kinematic")
+    cfgs = wl.ensemble(seed=0, mode="kinematic", real_bytes=real_bytes)
     steps = ref["steps"]
     assert steps == cfgs[0]["steps"] == 10000
     bat = lbib.Batch(cfgs)
@@ -100,20 +110,23 @@ def test_ensemble_full_horizon():
     assert bat.check() == 0
     for r in ref["lattices"]:
         i = r["lattice"]
-        compare_snapshot(bat, i, bat.cap_ids[i], r, steps, f"ensemble lattice {i}")
+        compare_snapshot(bat, i, bat.cap_ids[i], r, steps, f"ensemble lattice {i} ({8 * real_bytes} bit)",
+                         scale=bar_scale(real_bytes))
 
 
 @pytest.mark.gpu
-def test_inertial_channel_horizon():
-    """2048 x 512 channel with 32 capsules, FP32, over the stored horizon."""
+@pytest.mark.parametrize("real_bytes", [4, 8])
+def test_inertial_channel_horizon(real_bytes):
+    """2048 x 512 channel with 32 capsules, over the stored horizon."""
     ref = golden("long_inertial.json")
-    cfg = wl.inertial_capsules(seed=0, mode="kinematic")
+    cfg = wl.inertial_capsules(seed=0, mode="kinematic", real_bytes=real_bytes)
     steps = ref["steps"]
     sim = lbib.Sim(cfg)
     sim.step(steps, "kinematic")
     assert sim.check() == 0
     compare_snapshot(sim, 0, list(range(len(cfg["capsules"]))), ref, steps,
-                     f"inertial 2048x512, {steps} steps")
+                     f"inertial 2048x512 ({8 * real_bytes} bit), {steps} steps",
+                     scale=bar_scale(real_bytes))
 
 
 @pytest.mark.gpu
@@ -161,7 +174,7 @@ def test_couette_migration_full_horizon(real_bytes):
     another order; the stored values keep ten significant digits)."""
     ref = golden("long_couette.json")
     cfg = wl.couette_migration(real_bytes=real_bytes)
-    scale = 1.0 if real_bytes == 4 else 1e-3
+    scale = bar_scale(real_bytes)
     steps = ref["steps"]
     assert steps == cfg["steps"] == ref["trajectory"][-1]["steps"]
     u_top = cfg["u_top"]
