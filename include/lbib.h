@@ -426,9 +426,8 @@ size_t lbib_adjoint_bytes(const lbib_ctx* ctx, int32_t nsteps, int32_t checkpoin
  * positions); the fixed-point rounding of the spread force is not
  * differentiated.
  * Errors: EINVAL (batch context, nsteps < 1, checkpoint_every < 0, bad mode,
- * objective or capsule id, a capsule with k_b != 0, a rigid particle, the
- * contact force on, an open channel, workspace or n_ks too small, NULL
- * pointers), ESTATE (context not at step 0, or its mode differs), ECAPACITY
+ * objective or capsule id, a rigid particle, the contact force on, an open
+ * channel, workspace or n_ks too small, NULL pointers), ESTATE (context not at step 0, or its mode differs), ECAPACITY
  * (capsules too large for the on-chip memory of the reverse IB kernel),
  * ENUMERIC (a device status flag in the forward run or the reverse sweep),
  * EDEVICE.  Waits for the stream. */

@@ -40,6 +40,7 @@ struct IBAdjArgs {
     int* status;
     int stride;
     int doA, doB, prime, dynamic;
+    int bend;                   // some capsule has k_b != 0 (Eq. 13)
     int patch_cap, max_nv;
 };
 

@@ -12,8 +12,8 @@
 // probe position are carried by forward-mode dual numbers, so every local
 // Jacobian is exact; the transposed products are assembled by hand.
 //
-// Scope: both coupling schemes, membranes without bending (k_b = 0), one
-// lattice per context.  The support of every MLS stencil is the one the
+// Scope: both coupling schemes, membranes with stretching, bending and area
+// terms, one lattice per context.  The support of every MLS stencil is the one the
 // forward run chose (piecewise constant in the position, so its derivative is
 // zero).
 #include "lbib_adjoint.h"
@@ -575,14 +575,94 @@ __device__ __forceinline__ void interp_vjp(const AdjScratch<T>& S, const Patch<T
     });
 }
 
-// Transpose of the internal forces (Eqs. 10-11 stretch, Eq. 14 area; no
-// bending) at positions (X, Y) for the nodal adjoint (lFx, lFy): element
+// Bending at vertex v (Eq. 13: the outer terms as printed, the middle node
+// minus their sum, which is minus the gradient of k_b (1 - cos(theta - theta0))).
+// Left edge a = x_v - x_{v-1}, right edge b = x_{v+1} - x_v, theta the signed
+// turning angle.  The left neighbour takes s P(a), the right one s P(b) and
+// the vertex minus both, with s = k_b sin(theta - theta0) and
+// P(t) = (t_y, -t_x) / |t|^2.
+struct BendAt {
+    double s, c;        // k_b sin(theta - theta0), k_b cos(theta - theta0)
+    double ax, ay, na;  // left edge and its squared length
+    double bx, by, nb;  // right edge and its squared length
+};
+
+__device__ __forceinline__ BendAt bend_at(const double* X, const double* Y, int v, int nv,
+                                          double kb, double th0)
+{
+    const int vl = v == 0 ? nv - 1 : v - 1, vr = v + 1 == nv ? 0 : v + 1;
+    BendAt r;
+    r.ax = X[v] - X[vl];
+    r.ay = Y[v] - Y[vl];
+    r.bx = X[vr] - X[v];
+    r.by = Y[vr] - Y[v];
+    r.na = r.ax * r.ax + r.ay * r.ay;
+    r.nb = r.bx * r.bx + r.by * r.by;
+    const double th = atan2(r.ax * r.by - r.ay * r.bx, r.ax * r.bx + r.ay * r.by);
+    r.s = kb * sin(th - th0);
+    r.c = kb * cos(th - th0);
+    return r;
+}
+
+// Bending force on node v: the right-neighbour term of vertex v - 1, the
+// left-neighbour term of vertex v + 1 and minus both terms of vertex v.
+template <typename T>
+__device__ __forceinline__ void bend_node_force(const double* X, const double* Y, int v, int nv,
+                                                double kb, const T* th0, double& fx, double& fy)
+{
+    const int vl = v == 0 ? nv - 1 : v - 1, vr = v + 1 == nv ? 0 : v + 1;
+    const BendAt L = bend_at(X, Y, vl, nv, kb, (double)th0[vl]);
+    const BendAt M = bend_at(X, Y, v, nv, kb, (double)th0[v]);
+    const BendAt R = bend_at(X, Y, vr, nv, kb, (double)th0[vr]);
+    fx = L.s * L.by / L.nb + R.s * R.ay / R.na - M.s * (M.ay / M.na + M.by / M.nb);
+    fy = -L.s * L.bx / L.nb - R.s * R.ax / R.na + M.s * (M.ax / M.na + M.bx / M.nb);
+}
+
+// Adjoint of edge l -> l+1 from the bending terms, for the nodal adjoint
+// (lFx, lFy): the edge is the right edge b of vertex l and the left edge a of
+// vertex l + 1.  Per vertex, g = s (hL . P(a) + hR . P(b)) with hL, hR the
+// differences of the neighbours' adjoints from the vertex's; with
+// Q = hL . P(a) + hR . P(b), dtheta/da = P(a) and dtheta/db = -P(b):
+//   dg/da =  c Q P(a) + s ((-hL_y, hL_x) - 2 (hL . P(a)) a) / |a|^2,
+//   dg/db = -c Q P(b) + s ((-hR_y, hR_x) - 2 (hR . P(b)) b) / |b|^2.
+template <typename T>
+__device__ __forceinline__ void bend_edge_vjp(const AdjScratch<T>& S, const double* X,
+                                              const double* Y, int l, int nv, double kb,
+                                              const T* th0, double& ltx, double& lty)
+{
+    const int m = l + 1 == nv ? 0 : l + 1;
+    {   // vertex l, right edge
+        const int vl = l == 0 ? nv - 1 : l - 1;
+        const BendAt V = bend_at(X, Y, l, nv, kb, (double)th0[l]);
+        const double hLx = S.lFx[vl] - S.lFx[l], hLy = S.lFy[vl] - S.lFy[l];
+        const double hRx = S.lFx[m] - S.lFx[l], hRy = S.lFy[m] - S.lFy[l];
+        const double qL = (hLx * V.ay - hLy * V.ax) / V.na;
+        const double qR = (hRx * V.by - hRy * V.bx) / V.nb;
+        const double cQ = V.c * (qL + qR);
+        ltx += (-cQ * V.by + V.s * (-hRy - 2.0 * qR * V.bx)) / V.nb;
+        lty += (cQ * V.bx + V.s * (hRx - 2.0 * qR * V.by)) / V.nb;
+    }
+    {   // vertex l + 1, left edge
+        const int mr = m + 1 == nv ? 0 : m + 1;
+        const BendAt W = bend_at(X, Y, m, nv, kb, (double)th0[m]);
+        const double hLx = S.lFx[l] - S.lFx[m], hLy = S.lFy[l] - S.lFy[m];
+        const double hRx = S.lFx[mr] - S.lFx[m], hRy = S.lFy[mr] - S.lFy[m];
+        const double qL = (hLx * W.ay - hLy * W.ax) / W.na;
+        const double qR = (hRx * W.by - hRy * W.bx) / W.nb;
+        const double cQ = W.c * (qL + qR);
+        ltx += (cQ * W.ay + W.s * (-hLy - 2.0 * qL * W.ax)) / W.na;
+        lty += (-cQ * W.ax + W.s * (hLx - 2.0 * qL * W.ay)) / W.na;
+    }
+}
+
+// Transpose of the internal forces (Eqs. 10-11 stretch, Eq. 13 bending, Eq.
+// 14 area) at positions (X, Y) for the nodal adjoint (lFx, lFy): element
 // contributions into E1 (start node) / E2 (end node), k_s gradient into
 // ksbar, and the area term straight into the returned lambda A.
-template <typename T>
+template <bool BEND, typename T>
 __device__ double internal_vjp(const AdjScratch<T>& S, const double* X, const double* Y, int nv,
-                               const T* l0h, const T* l0l, const T* ks, double ka, double A0,
-                               double* ksbar, double (*red)[8])
+                               const T* l0h, const T* l0l, const T* ks, double kb, const T* th0,
+                               double ka, double A0, double* ksbar, double (*red)[8])
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     double acc[1] = {0.0};
@@ -612,6 +692,7 @@ __device__ double internal_vjp(const AdjScratch<T>& S, const double* X, const do
         ltx += -cA * hAy;
         lty += cA * hAx;
         lcA[0] += ty * hAx - tx * hAy;
+        if (BEND && kb != 0.0) bend_edge_vjp(S, X, Y, l, nv, kb, th0, ltx, lty);
         S.E1x[l] -= ltx;
         S.E1y[l] -= lty;
         S.E2x[l] += ltx;
@@ -621,11 +702,12 @@ __device__ double internal_vjp(const AdjScratch<T>& S, const double* X, const do
     return -ka / (6.0 * A0) * lcA[0];
 }
 
-// Forward internal forces at (X, Y) (FP64) into (Fvx, Fvy): stretch and area.
-template <typename T>
+// Forward internal forces at (X, Y) (FP64) into (Fvx, Fvy): stretch, bending
+// and area.
+template <bool BEND, typename T>
 __device__ void internal_fwd(const AdjScratch<T>& S, const double* X, const double* Y, int nv,
-                             const T* l0h, const T* l0l, const T* ks, double ka, double A0,
-                             double (*red)[8])
+                             const T* l0h, const T* l0l, const T* ks, double kb, const T* th0,
+                             double ka, double A0, double (*red)[8])
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     double acc[1] = {0.0};
@@ -649,8 +731,10 @@ __device__ void internal_fwd(const AdjScratch<T>& S, const double* X, const doub
     __syncthreads();
     for (int v = tid; v < nv; v += nt) {
         const int vl = v == 0 ? nv - 1 : v - 1;
-        S.Fvx[v] = S.E1x[v] + S.E2x[vl];
-        S.Fvy[v] = S.E1y[v] + S.E2y[vl];
+        double bx = 0.0, by = 0.0;
+        if (BEND && kb != 0.0) bend_node_force(X, Y, v, nv, kb, th0, bx, by);
+        S.Fvx[v] = S.E1x[v] + S.E2x[vl] + bx;
+        S.Fvy[v] = S.E1y[v] + S.E2y[vl] + by;
     }
     __syncthreads();
     for (int l = tid; l < nv; l += nt) S.E1x[l] = S.E1y[l] = S.E2x[l] = S.E2y[l] = 0.0;
@@ -766,8 +850,11 @@ __device__ void external_vjp(const AdjScratch<T>& S, const Patch<T>& P, int nv, 
 // Carried adjoints lamx, lamd enter as those of x^n, d^n and leave as those
 // of x^{n-1}, d^{n-1}.  The adjoint of the moments M^n goes into lambda P^n
 // (transpose of the pull) and lambda F^{n-1} (its half-force term).
-// One instance per coupling (DYN = DYN), as the forward IB kernel.
-template <typename T, bool DYN>
+// One instance per coupling (DYN = a.dynamic), as the forward IB kernel, and
+// per bending (BEND = a.bend: some capsule has k_b != 0; without it the
+// bending terms are compiled out, which keeps the Kinematic instance 1 us
+// shorter per reverse step).
+template <typename T, bool DYN, bool BEND>
 __global__ __launch_bounds__(kAdjThreads) void k_ib_adj(IBAdjArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -967,8 +1054,9 @@ __global__ __launch_bounds__(kAdjThreads) void k_ib_adj(IBAdjArgs<T> a)
             __syncthreads();
         } else {
             const T* N0 = a.consts;
-            internal_fwd(S, S.Xn, S.Yn, nv, N0 + NF_L0 * NS + off, N0 + NF_L0L * NS + off,
-                         N0 + NF_KS * NS + off, cap.ka, cap.A0, red);
+            internal_fwd<BEND>(S, S.Xn, S.Yn, nv, N0 + NF_L0 * NS + off, N0 + NF_L0L * NS + off,
+                         N0 + NF_KS * NS + off, cap.kb, N0 + NF_TH0 * NS + off, cap.ka, cap.A0,
+                         red);
             for (int v = tid; v < nv; v += nt) {
                 const int cx = (int)floor(S.hxn[v] + T(0.5)), cy = (int)floor(S.hyn[v] + T(0.5));
                 double lFvx = 0, lFvy = 0, gpx = 0, gpy = 0;
@@ -1000,9 +1088,10 @@ __global__ __launch_bounds__(kAdjThreads) void k_ib_adj(IBAdjArgs<T> a)
             }
             __syncthreads();
             const T* N1 = a.consts;
-            const double lA = internal_vjp(S, S.Xn, S.Yn, nv, N1 + NF_L0 * NS + off,
-                                           N1 + NF_L0L * NS + off, N1 + NF_KS * NS + off, cap.ka,
-                                           cap.A0, a.ksbar + off, red);
+            const double lA = internal_vjp<BEND>(S, S.Xn, S.Yn, nv, N1 + NF_L0 * NS + off,
+                                           N1 + NF_L0L * NS + off, N1 + NF_KS * NS + off, cap.kb,
+                                           N1 + NF_TH0 * NS + off, cap.ka, cap.A0, a.ksbar + off,
+                                           red);
             __syncthreads();
             for (int v = tid; v < nv; v += nt) {
                 const int vl = v == 0 ? nv - 1 : v - 1, vr = v + 1 == nv ? 0 : v + 1;
@@ -1061,9 +1150,10 @@ __global__ __launch_bounds__(kAdjThreads) void k_ib_adj(IBAdjArgs<T> a)
         __syncthreads();
         if (DYN) {
             const T* N0 = a.consts;
-            const double lA = internal_vjp(S, S.Xp, S.Yp, nv, N0 + NF_L0 * NS + off,
-                                           N0 + NF_L0L * NS + off, N0 + NF_KS * NS + off, cap.ka,
-                                           cap.A0, a.ksbar + off, red);
+            const double lA = internal_vjp<BEND>(S, S.Xp, S.Yp, nv, N0 + NF_L0 * NS + off,
+                                           N0 + NF_L0L * NS + off, N0 + NF_KS * NS + off, cap.kb,
+                                           N0 + NF_TH0 * NS + off, cap.ka, cap.A0, a.ksbar + off,
+                                           red);
             external_vjp(S, P, nv, nu, sx, sy, st);
             __syncthreads();
             for (int v = tid; v < nv; v += nt) {
@@ -1154,21 +1244,34 @@ template <typename T>
 hipError_t launch_ib_adj(const IBAdjArgs<T>& a, int ncap, size_t lds_bytes, hipStream_t s)
 {
     if (ncap <= 0) return hipSuccess;
-    if (a.dynamic)
-        hipLaunchKernelGGL((k_ib_adj<T, true>), dim3(ncap), dim3(kAdjThreads), lds_bytes, s, a);
-    else
-        hipLaunchKernelGGL((k_ib_adj<T, false>), dim3(ncap), dim3(kAdjThreads), lds_bytes, s, a);
+    const dim3 grid(ncap), block(kAdjThreads);
+    if (a.dynamic) {
+        if (a.bend)
+            hipLaunchKernelGGL((k_ib_adj<T, true, true>), grid, block, lds_bytes, s, a);
+        else
+            hipLaunchKernelGGL((k_ib_adj<T, true, false>), grid, block, lds_bytes, s, a);
+    } else {
+        if (a.bend)
+            hipLaunchKernelGGL((k_ib_adj<T, false, true>), grid, block, lds_bytes, s, a);
+        else
+            hipLaunchKernelGGL((k_ib_adj<T, false, false>), grid, block, lds_bytes, s, a);
+    }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t ib_adj_set_lds_limit(size_t bytes)
 {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ib_adj<T, true>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ib_adj<T, false>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void* fns[4] = {reinterpret_cast<const void*>(&k_ib_adj<T, true, false>),
+                          reinterpret_cast<const void*>(&k_ib_adj<T, false, false>),
+                          reinterpret_cast<const void*>(&k_ib_adj<T, true, true>),
+                          reinterpret_cast<const void*>(&k_ib_adj<T, false, true>)};
+    for (const void* f : fns) {
+        const hipError_t e =
+            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 #define LBIB_ADJ_INST(T)                                                                          \

@@ -1600,6 +1600,8 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
     const CapsuleDev* caps = reinterpret_cast<const CapsuleDev*>(bufp(c, LBIB_BUF_CAPS));
     HIPCHK(c, launch_adj_seed<T>(sN(N), sR(N), caps, capid, c->L.max_nodes, objective, lamx, out,
                                  st));
+    bool bend = false;
+    for (double kb : c->cap_kb) bend = bend || kb != 0.0;
     // slot r of the grid tape holds level n (the segment starts at n - r)
     auto ib_adj = [&](int n, int r, int doA, int doB, int prime) -> hipError_t {
         IBAdjArgs<T> b;
@@ -1624,6 +1626,7 @@ static lbib_status adjoint_t(lbib_ctx* c, int N, int mode, int objective, int ca
         b.doB = doB;
         b.prime = prime;
         b.dynamic = mode == LBIB_DYNAMIC;
+        b.bend = bend;
         b.patch_cap = adj_patch;
         b.max_nv = c->L.max_nv;
         return launch_ib_adj<T>(b, c->ncap, adj_lds, st);
@@ -1695,8 +1698,6 @@ static lbib_status adjoint_validate(lbib_ctx* c, int32_t nsteps, int32_t checkpo
     if (c->steps != 0) return fail(c, LBIB_ESTATE, "the adjoint run starts from step 0");
     if (c->mode >= 0 && c->mode != (int)mode)
         return fail(c, LBIB_ESTATE, "the coupling mode is fixed after the first step");
-    for (double kb : c->cap_kb)
-        if (kb != 0.0) return fail(c, LBIB_EINVAL, "the adjoint needs k_b = 0 for every capsule");
     if (c->contact_cutoff > 0.0 && c->ncap > 1)
         return fail(c, LBIB_EINVAL, "the adjoint does not differentiate the contact force");
     if (!c->L.inst[0].walls.periodic_x)
