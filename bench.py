@@ -408,6 +408,9 @@ def main() -> int:
                     help="tile shape order,rows,resident of --only-ensemble-grid")
     ap.add_argument("--only-adjoint", action="store_true",
                     help="only the gradient cost against the forward run")
+    ap.add_argument("--only-channels", action="store_true",
+                    help="only the 1024x256 biconcave channel and the 2048x512 channel with 32 "
+                         "capsules, both couplings (IB-latency-bound workloads, trace runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 20 device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -441,6 +444,16 @@ def main() -> int:
     if args.only_adjoint:
         adj = [bench_adjoint("dynamic", 500), bench_adjoint("kinematic", 5000)]
         print(json.dumps({"adjoint": adj}), flush=True)
+        return 0
+    if args.only_channels:
+        out = {}
+        for name, cfg in (("biconcave_1024x256", wl.poiseuille_biconcave(1e-2, steps=args.steps)),
+                          ("inertial_2048x512", wl.inertial_capsules(seed=0, steps=args.steps))):
+            for mode in ("dynamic", "kinematic"):
+                r = time_gpu(dict(cfg, mode=mode), args.steps, args.warmup, timing=False)
+                del r["sim"]
+                out[f"{name}_{mode}_us_per_step"] = round(r["ms_per_step"] * 1e3, 2)
+        print(json.dumps({"channels": out}), flush=True)
         return 0
     cfg = wl.fused_bench(seed=0, n=args.n, steps=args.steps)
     # The side measurements run first, so that the headline below is taken on a
