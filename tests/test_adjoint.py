@@ -213,13 +213,20 @@ def test_adjoint_two_capsules_vs_fd(mode):
 
 
 @pytest.mark.gpu
-def test_adjoint_fp32_vs_fp64():
-    """The FP32 adjoint of the same run, against the FP64 adjoint."""
-    r8 = lbib.Sim(ellipse_channel(real_bytes=8)).adjoint(100, lbib.OBJ_TAYLOR)
-    r4 = lbib.Sim(ellipse_channel(real_bytes=4)).adjoint(100, lbib.OBJ_TAYLOR)
+@pytest.mark.parametrize("eb", [0.0, 0.2])
+def test_adjoint_fp32_vs_fp64(eb):
+    """The FP32 adjoint of the same run, against the FP64 adjoint (without
+    and with bending)."""
+    cfgs = []
+    for rb in (8, 4):
+        cfg = ellipse_channel(real_bytes=rb)
+        cfg["capsules"][0]["kb"] = eb * cfg["capsules"][0]["ks"] * 6.0 * 4.5
+        cfgs.append(cfg)
+    r8 = lbib.Sim(cfgs[0]).adjoint(100, lbib.OBJ_TAYLOR)
+    r4 = lbib.Sim(cfgs[1]).adjoint(100, lbib.OBJ_TAYLOR)
     k8, k4 = r8["dJ_dks"][0], r4["dJ_dks"][0]
     err = np.abs(k4 - k8).max() / np.abs(k8).max()
-    log(f"fp32 vs fp64 adjoint: ks rel {err:.2e}, g {r4['dJ_dg']} vs {r8['dJ_dg']}")
+    log(f"fp32 vs fp64 adjoint, E_b {eb}: ks rel {err:.2e}, g {r4['dJ_dg']} vs {r8['dJ_dg']}")
     assert err < 1e-3
     assert abs(r4["dJ_dg"] - r8["dJ_dg"]) < 1e-3 * abs(r8["dJ_dg"])
 
