@@ -505,7 +505,14 @@ def main() -> int:
         log(f"256x101 Couette migration (Kinematic): {ccr['ms_per_step'] * 1e3:.1f} us/step "
             f"({ccr['mlups']:.0f} MLUPS), its {cc['steps']} steps in "
             f"{ccr['ms_per_step'] * cc['steps'] * 1e-3:.0f} s")
-        ens = bench_ensemble(min(args.steps, 400), args.warmup, 20)
+        cd = wl.wall_detachment()
+        cdr = time_gpu(cd, max(args.steps, 2000), args.warmup, timing=False)
+        del cdr["sim"]
+        side["detach_128x101_us_per_step"] = round(cdr["ms_per_step"] * 1e3, 2)
+        log(f"128x101 wall detachment (Kinematic): {cdr['ms_per_step'] * 1e3:.1f} us/step "
+            f"({cdr['mlups']:.0f} MLUPS), its {cd['steps']} steps (t u_max / H = 2) in "
+            f"{cdr['ms_per_step'] * cd['steps'] * 1e-3:.0f} s")
+        ens =bench_ensemble(min(args.steps, 400), args.warmup, 20)
         log(f"ensemble: batched {ens['mlups']:.0f} MLUPS ({ens['ms_per_step']:.3f} ms/step, "
             f"{ens['overlapped_ms_per_step']:.3f} split near / far, "
             f"{ens['graph_ms_per_step']:.3f} with graph replays, "

@@ -16,6 +16,7 @@ Run from the repository root, one case at a time:
     python tests/golden/make_long_runs.py inertial   # 2048 x 512 channel, 32 capsules, STEPS steps
     python tests/golden/make_long_runs.py adjoint    # 512 x 128 gradient channel, 5000 steps, central differences
     python tests/golden/make_long_runs.py couette    # 256 x 101 Couette flow, capsule released at 0.25 H, 2e6 steps
+    python tests/golden/make_long_runs.py detach [HORIZON]  # 128 x 101 Poiseuille channel, capsule at the wall, to t u_max / H = HORIZON
 
 Each case writes one JSON file beside this script, every float kept to ten
 significant digits.  A field sample is 256 cells drawn by numpy's
@@ -172,6 +173,35 @@ def case_couette() -> None:
     print(f"couette: {time.time() - t:.0f} s", flush=True)
 
 
+def case_detach(horizon: float) -> None:
+    """The Sec. 3.5 wall-detachment case at density ratio 1: a circular capsule
+    released against the bottom wall of the Poiseuille channel, run to
+    t u_max / H = horizon; centroid, deformation, perimeter change and swelling
+    ratio at twenty equal intervals, and the sampled state at the end."""
+    t = time.time()
+    cfg = wl.wall_detachment(real_bytes=8, horizon=horizon)
+    steps = int(cfg["steps"])
+    every = steps // 20
+    s = orc.Sim(cfg)
+    traj = []
+    while s.steps < steps:
+        s.step(min(every, steps - s.steps))
+        if s.status:
+            raise RuntimeError(f"oracle status {s.status} at step {s.steps}")
+        d = s.diag(0)
+        traj.append({"steps": s.steps, "cx": d["cx"], "cy": d["cy"], "D": d["D"],
+                     "perimeter": d["perimeter"], "dp": d["dp"], "Sw": d["Sw"]})
+        print(traj[-1], f"{time.time() - t:.0f} s", flush=True)
+    write("long_detach.json", {
+        "_comment": "FP64 oracle, Kinematic coupling (Eq. 25), 128 x 101 Poiseuille channel at Re 1e-2 "
+                    "with a circular capsule released against the bottom wall (Sec. 3.5 set-up, density "
+                    "ratio 1, E_b = 0); written by make_long_runs.py",
+        "workload": {"fn": "wall_detachment", "mode": "kinematic", "horizon": horizon},
+        "steps": steps, "H": cfg["ny"] - 1, "u_max": cfg["u_max"], "trajectory_every": every,
+        "trajectory": traj, **snapshot(s, cfg)})
+    print(f"detach: {time.time() - t:.0f} s", flush=True)
+
+
 def both_objectives(cfg, steps):
     d = run(cfg, steps).diag(0)
     return d["D"], d["cy"]
@@ -224,6 +254,8 @@ def main() -> None:
         case_adjoint()
     elif which == "couette":
         case_couette()
+    elif which == "detach":
+        case_detach(float(sys.argv[2]) if len(sys.argv) > 2 else 2.0)
     else:
         raise SystemExit(__doc__)
 

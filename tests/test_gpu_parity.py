@@ -208,6 +208,26 @@ def test_couette_migration_window(real_bytes):
     assert g.check() == 0
 
 
+@pytest.mark.parametrize("real_bytes", [8, 4])
+def test_wall_detachment_window(real_bytes):
+    """Sec. 3.5 wall-detachment case (128 x 101 Poiseuille channel at
+    Re = 1e-2, capsule released against the bottom wall), Kinematic IB, over
+    its first steps, in both precisions."""
+    n = _steps(1000)
+    cfg = wl.wall_detachment(real_bytes=real_bytes)
+    g, o = pair(cfg)
+    for chunk in (1, n - 1):
+        g.step(chunk)
+        o.step(chunk)
+    if real_bytes == 8:
+        compare_fields(g, o, 1e-10, 1e-12)
+        compare_capsules(g, o, 1e-10, 1e-10)
+    else:
+        compare_fields(g, o, 1e-5, 1e-6)
+        compare_capsules(g, o, 1e-4, 1e-4)
+    assert g.check() == 0
+
+
 def test_inertial_capsules_fp32():
     """2048 x 512 channel, 32 seeded capsules (circular and biconcave, density
     ratio 1-2, Ca 1e-3..1e-1), Dynamic IB, FP32."""

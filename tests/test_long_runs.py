@@ -219,6 +219,80 @@ def test_couette_migration_reaches_centreline():
         assert abs(r["perimeter"] - p_end) <= 0.01 * p_end, r
 
 
+def detach_config(ref, real_bytes: int):
+    """The wall-detachment workload at the horizon the stored run covers."""
+    return wl.wall_detachment(real_bytes=real_bytes, horizon=ref["workload"]["horizon"])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("real_bytes", [4, 8])
+def test_wall_detachment_full_horizon(real_bytes):
+    """The Sec. 3.5 wall-detachment case (128 x 101 Poiseuille channel at
+    Re = 1e-2, capsule released against the bottom wall, density ratio 1) over
+    the stored run: centroid, deformation and perimeter change at every stored
+    interval, and the sampled state at the end.  FP32 to the bars of this
+    file; FP64 to 1e-3 of them."""
+    ref = golden("long_detach.json")
+    cfg = detach_config(ref, real_bytes)
+    scale = bar_scale(real_bytes)
+    steps = ref["steps"]
+    assert steps == cfg["steps"] == ref["trajectory"][-1]["steps"]
+    u_max = cfg["u_max"]
+    sim = lbib.Sim(cfg)
+    worst = {"c": 0.0, "D": 0.0, "dp": 0.0}
+    done = 0
+    for r in ref["trajectory"]:
+        sim.step(r["steps"] - done, "kinematic")
+        done = r["steps"]
+        d = sim.diag(0)
+        e_c = max(abs(d["cx"] - r["cx"]), abs(d["cy"] - r["cy"]))
+        e_d = abs(d["D"] - r["D"])
+        e_p = abs(d["dp"] - r["dp"])
+        worst = {"c": max(worst["c"], e_c), "D": max(worst["D"], e_d), "dp": max(worst["dp"], e_p)}
+        assert e_c <= 1e-5 * u_max * r["steps"] * scale, (r["steps"], d["cx"], d["cy"], r)
+        assert e_d <= 1e-4 * scale, (r["steps"], d["D"], r["D"])
+        assert e_p <= 1e-4 * scale, (r["steps"], d["dp"], r["dp"])
+    log(f"detach trajectory ({8 * real_bytes} bit): centroid {worst['c']:.2e}, D {worst['D']:.2e}, "
+        f"dp {worst['dp']:.2e}, final y_c {sim.diag(0)['cy']:.6f} "
+        f"(oracle {ref['trajectory'][-1]['cy']:.6f})")
+    assert sim.check() == 0
+    compare_snapshot(sim, 0, [0], ref, steps, f"detach 128x101 ({8 * real_bytes} bit), {steps} steps",
+                     u_max=u_max, scale=scale)
+
+
+def test_wall_detachment_leaves_the_wall():
+    """Sec. 3.5, the capsule released against the wall of a Poiseuille flow at
+    density ratio 1 (the case the Kinematic coupling covers), checked on the
+    oracle's stored run (host only):
+    - it detaches: the centroid's height above the wall rises at every stored
+      interval;
+    - it lags the flow: over every interval its mean x-velocity is below the
+      undisturbed parabola 4 u_max y (H - y) / H^2 at the interval's lowest
+      centroid height (a body near a wall, and in a curved profile, trails the
+      fluid at its centre);
+    - it deforms while it travels: D and the perimeter change dp both grow
+      over the run and stay positive from the first interval on."""
+    ref = golden("long_detach.json")
+    H, u_max = ref["H"], ref["u_max"]
+    tr = ref["trajectory"]
+    cfg = detach_config(ref, 8)
+    x0 = cfg["capsules"][0]["nodes"]
+    start = {"steps": 0, "cx": float(np.mean(x0[:, 0])), "cy": float(np.mean(x0[:, 1]))}
+    pts = [start] + tr
+    ys = [p["cy"] for p in pts]
+    assert all(b > a for a, b in zip(ys, ys[1:])), ys
+    for a, b in zip(pts, pts[1:]):
+        dx = b["cx"] - a["cx"]
+        if dx < -0.5 * cfg["nx"]:
+            dx += cfg["nx"]
+        v = dx / (b["steps"] - a["steps"])
+        y = min(a["cy"], b["cy"])
+        u_ref = 4.0 * u_max * y * (H - y) / H ** 2
+        assert 0.0 < v < u_ref, (b["steps"], v, u_ref)
+    assert all(r["D"] > 0.0 and r["dp"] > 0.0 for r in tr), tr
+    assert tr[-1]["D"] > tr[0]["D"] and tr[-1]["dp"] > tr[0]["dp"], (tr[0], tr[-1])
+
+
 def test_golden_samples_follow_their_seed():
     """The stored sample cells are the ones the generator's seed draws on each
     workload's lattice, the ensemble lattices the ones its pick seed draws, and
@@ -229,7 +303,7 @@ def test_golden_samples_follow_their_seed():
     mk = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mk)
     dims = {"poiseuille_biconcave": (1024, 256), "inertial_capsules": (2048, 512),
-            "couette_migration": (256, 101)}
+            "couette_migration": (256, 101), "wall_detachment": (128, 101)}
     found = 0
     for name in sorted(os.listdir(GOLDEN)):
         if not (name.startswith("long_") and name.endswith(".json")):

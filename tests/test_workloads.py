@@ -47,3 +47,22 @@ def test_couette_migration_figures():
     np.testing.assert_allclose(np.hypot(*(nodes - (128.0, 25.0)).T), 12.5, atol=1e-12)
     assert abs(cap["ks"] - 1.0) < 1e-12 and cap["kb"] == 0.0 and len(nodes) == 100
     assert abs(wl.couette_migration(eb=0.1)["capsules"][0]["kb"] - 15.625) < 1e-9
+
+
+def test_wall_detachment_figures():
+    """Sec. 3.5 detachment set-up: H = 100 and Re = 1e-2 at tau = 3.5 (nu = 1)
+    give u_max = 1e-4, body force 8 nu u_max / H^2 = 8e-8 and 2e6 steps to
+    t u_max / H = 2; d = 0.25 H with its lowest node 3 lattice units above
+    the wall; Ca = 1e-3 gives k_s = 0.1."""
+    cfg = wl.wall_detachment()
+    assert (cfg["nx"], cfg["ny"]) == (128, 101)
+    assert abs(cfg["u_max"] - 1e-4) < 1e-18 and abs(cfg["body_force_x"] - 8e-8) < 1e-20
+    assert cfg["steps"] == 2000000 and wl.wall_detachment(horizon=0.25)["steps"] == 250000
+    assert cfg["init_profile"] == wl.INIT_POISEUILLE and cfg["mode"] == "kinematic"
+    assert cfg["u_bottom"] == cfg["u_top"] == 0.0
+    cap = cfg["capsules"][0]
+    nodes = cap["nodes"]
+    np.testing.assert_allclose(nodes.mean(axis=0), (64.0, 15.5), atol=1e-12)
+    np.testing.assert_allclose(np.hypot(*(nodes - (64.0, 15.5)).T), 12.5, atol=1e-12)
+    assert nodes[:, 1].min() >= 3.0
+    assert abs(cap["ks"] - 0.1) < 1e-12 and cap["kb"] == 0.0 and len(nodes) == 100
