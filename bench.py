@@ -15,6 +15,9 @@ Prints one JSON line:
             recorded around every launch of the timed region, against 8 TB/s
   cpu_baseline  the FP64 oracle on the host cores, a bounded sample of steps of
             the same workload
+  copy_1gib_gbs  side measurement: bytes read + written per second by a plain
+            1 GiB device-to-device copy, the rate a read-once write-once kernel
+            can expect here beside the nominal 8 TB/s
   multi_body_open_channel  side measurement: MLUPS of a 1536 x 256 open channel
             with 14 capsules and 2 rigid discs in contact range
   adjoint   side measurement: time of one gradient (lbib_adjoint: taped forward
@@ -387,6 +390,28 @@ def cpu_baseline(cfg, budget_s: float = 20.0, single_s: float = 10.0):
             "cpu_model": cpu_model(), "build": build}
 
 
+def copy_bandwidth(nbytes: int, steps: int, warmup: int) -> float:
+    """GB/s (bytes read + bytes written) of a plain device-to-device copy of
+    ``nbytes``, timed with events over ``steps`` copies after ``warmup``: the
+    rate a kernel that reads and writes each byte once can expect on this
+    device, beside the nominal peak."""
+    import torch
+    a = torch.ones(nbytes // 4, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    for _ in range(max(warmup, 1)):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(max(steps, 1)):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / max(steps, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / sec / 1e9
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -463,6 +488,10 @@ def main() -> int:
     # 32 inertial capsules, reported beside the main line
     side = {}
     if not args.only_fused:
+        cp = copy_bandwidth(1 << 30, args.steps, args.warmup)
+        side["copy_1gib_gbs"] = round(cp, 1)
+        log(f"device-to-device copy of 1 GiB: {cp:.0f} GB/s read + written "
+            f"({cp / PEAK_HBM_GBS * 100:.1f} % of the HBM peak)")
         g = time_gpu(wl.grid_bench(n=args.n), args.steps, args.warmup, timing=False)
         log(f"grid only: {g['mlups']:.0f} MLUPS")
         side["grid_only_mlups"] = round(g["mlups"], 1)
