@@ -541,6 +541,13 @@ def main() -> int:
         log(f"128x101 wall detachment (Kinematic): {cdr['ms_per_step'] * 1e3:.1f} us/step "
             f"({cdr['mlups']:.0f} MLUPS), its {cd['steps']} steps (t u_max / H = 2) in "
             f"{cdr['ms_per_step'] * cd['steps'] * 1e-3:.0f} s")
+        cs = wl.dense_suspension()
+        csr = time_gpu(cs, max(args.steps, 2000), args.warmup, timing=False)
+        del csr["sim"]
+        side["dense_130x81_us_per_step"] = round(csr["ms_per_step"] * 1e3, 2)
+        log(f"130x81 dense suspension, 16 capsules at {cs['hematocrit'] * 100:.1f} % hematocrit "
+            f"(Kinematic, contact): {csr['ms_per_step'] * 1e3:.1f} us/step, its {cs['steps']} steps "
+            f"(t u_max / H = 2) in {csr['ms_per_step'] * cs['steps']:.0f} ms")
         ens =bench_ensemble(min(args.steps, 400), args.warmup, 20)
         log(f"ensemble: batched {ens['mlups']:.0f} MLUPS ({ens['ms_per_step']:.3f} ms/step, "
             f"{ens['overlapped_ms_per_step']:.3f} split near / far, "

@@ -444,6 +444,45 @@ def multi_capsule_channel(seed: int = 0, nx: int = 1536, ny: int = 256, tau: flo
     return cfg
 
 
+def dense_suspension(seed: int = 0, length: float = 30.0, gap: float = 0.5, tau: float = 0.8,
+                     u_max: float = 0.02, ca: float = 1e-2, n_nodes: int = 96,
+                     max_angle: float = 0.1, horizon: float = 2.0, mode: str = "kinematic",
+                     real_bytes: int = 4) -> Dict[str, Any]:
+    """Sixteen biconcave capsules filling a plane-Poiseuille channel at the
+    paper's hematocrit of about 30 % (the Sec. 3.4 set-up, at a capsule length
+    the IB kernel's on-chip patch holds): a 4 x 4 block at pitches
+    (L + gap + 2, L/2 + gap + 2) that tiles the periodic x direction, with
+    five lattice units between the block and each wall; body-force channel
+    starting from the parabola (as the other channel cases); Ca from u_max,
+    E_b = 0, k_a = 1, density ratio 1; contact force (Eq. 27, cutoff 2).
+    Draws from default_rng(seed): per capsule, orientation U[-max_angle,
+    max_angle] rad and a centre jitter U[-1, 1] lu in x and y.  The horizon
+    is t u_max / H (Fig. 5 shows the fields at 2)."""
+    rng = np.random.default_rng(seed)
+    pitch_x = length + gap + 2.0
+    pitch_y = 0.5 * length + gap + 2.0
+    nx = int(round(4 * pitch_x))
+    H = int(math.ceil(4 * pitch_y + 10.0))
+    ny = H + 1
+    ks = ks_from_ca(tau, u_max, ca)
+    caps: List[Dict[str, Any]] = []
+    for k in range(16):
+        i, j = k % 4, k // 4
+        angle = float(rng.uniform(-max_angle, max_angle))
+        jx, jy = rng.uniform(-1.0, 1.0, 2)
+        cx = (i + 0.5) * nx / 4.0 + jx
+        cy = 0.5 * H + (j - 1.5) * pitch_y + jy
+        caps.append(capsule(biconcave_nodes(cx, cy, length, n_nodes, angle), ks, 0.0, 1.0, 1.0))
+    steps = int(round(horizon * H / u_max))
+    cfg = _base(f"dense16_{nx}x{ny}", nx, ny, tau, real_bytes, mode, steps,
+                body_force_x=poiseuille_body_force(tau, ny, u_max), init_profile=INIT_POISEUILLE,
+                capsules=caps)
+    cfg["contact_cutoff"] = 2.0
+    cfg["u_max"] = u_max
+    cfg["hematocrit"] = sum(polygon_area(c["nodes"]) for c in caps) / float(nx * H)
+    return cfg
+
+
 def periodic_box(nx: int, ny: int, tau: float, u0=(0.0, 0.0), real_bytes: int = 8,
                  mode: str = "dynamic", steps: int = 10) -> Dict[str, Any]:
     """Fully periodic box at uniform velocity u0 (no walls, no body force)."""

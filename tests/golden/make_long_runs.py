@@ -17,6 +17,7 @@ Run from the repository root, one case at a time:
     python tests/golden/make_long_runs.py adjoint    # 512 x 128 gradient channel, 5000 steps, central differences
     python tests/golden/make_long_runs.py couette    # 256 x 101 Couette flow, capsule released at 0.25 H, 2e6 steps
     python tests/golden/make_long_runs.py detach [HORIZON]  # 128 x 101 Poiseuille channel, capsule at the wall, to t u_max / H = HORIZON
+    python tests/golden/make_long_runs.py dense      # 130 x 81 channel, 16 biconcave capsules at 30 % hematocrit, contact, 8000 steps
 
 Each case writes one JSON file beside this script, every float kept to ten
 significant digits.  A field sample is 256 cells drawn by numpy's
@@ -202,6 +203,32 @@ def case_detach(horizon: float) -> None:
     print(f"detach: {time.time() - t:.0f} s", flush=True)
 
 
+def case_dense() -> None:
+    """The Sec. 3.4 dense suspension (16 biconcave capsules at about 30 %
+    hematocrit, contact force on) to t u_max / H = 2: every capsule's
+    diagnostics at each quarter of the run, and the sampled state at the end."""
+    t = time.time()
+    cfg = wl.dense_suspension(real_bytes=8)
+    steps = int(cfg["steps"])
+    every = steps // 4
+    s = orc.Sim(cfg)
+    traj = []
+    while s.steps < steps:
+        s.step(min(every, steps - s.steps))
+        if s.status:
+            raise RuntimeError(f"oracle status {s.status} at step {s.steps}")
+        traj.append({"steps": s.steps, "diag": [s.diag(c) for c in range(len(cfg["capsules"]))]})
+        print(s.steps, f"{time.time() - t:.0f} s", flush=True)
+    write("long_dense.json", {
+        "_comment": "FP64 oracle, Kinematic coupling (Eq. 25), 130 x 81 Poiseuille channel with 16 "
+                    "biconcave capsules at about 30 % hematocrit and the Eq. 27 contact force (Sec. 3.4 "
+                    "set-up); written by make_long_runs.py",
+        "workload": {"fn": "dense_suspension", "mode": "kinematic", "seed": 0},
+        "steps": steps, "H": cfg["ny"] - 1, "u_max": cfg["u_max"], "hematocrit": cfg["hematocrit"],
+        "trajectory_every": every, "trajectory": traj, **snapshot(s, cfg)})
+    print(f"dense: {time.time() - t:.0f} s", flush=True)
+
+
 def both_objectives(cfg, steps):
     d = run(cfg, steps).diag(0)
     return d["D"], d["cy"]
@@ -254,6 +281,8 @@ def main() -> None:
         case_adjoint()
     elif which == "couette":
         case_couette()
+    elif which == "dense":
+        case_dense()
     elif which == "detach":
         case_detach(float(sys.argv[2]) if len(sys.argv) > 2 else 2.0)
     else:

@@ -228,6 +228,30 @@ def test_wall_detachment_window(real_bytes):
     assert g.check() == 0
 
 
+@pytest.mark.parametrize("mode,real_bytes", [("kinematic", 8), ("kinematic", 4),
+                                             ("dynamic", 8), ("dynamic", 4)])
+def test_dense_suspension_window(mode, real_bytes):
+    """Sec. 3.4 dense suspension (130 x 81 channel, 16 biconcave capsules at
+    about 30 % hematocrit, contact force on), both couplings, both precisions,
+    over its first 300 steps: fields and every capsule against the oracle,
+    with the contact force acting."""
+    n = _steps(300)
+    cfg = dict(wl.dense_suspension(real_bytes=real_bytes), mode=mode)
+    log(f"dense suspension 130x81 {mode} real_bytes={real_bytes} steps={n}")
+    g, o = pair(cfg)
+    for chunk in (1, n - 1):
+        g.step(chunk)
+        o.step(chunk)
+    assert any(np.abs(o.contact(c)).max() > 0 for c in range(len(cfg["capsules"])))
+    if real_bytes == 8:
+        compare_fields(g, o, 1e-10, 1e-12)
+        compare_capsules(g, o, 1e-10, 1e-10)
+    else:
+        compare_fields(g, o, 1e-5, 1e-6)
+        compare_capsules(g, o, 1e-4, 1e-4)
+    assert g.check() == 0
+
+
 def test_inertial_capsules_fp32():
     """2048 x 512 channel, 32 seeded capsules (circular and biconcave, density
     ratio 1-2, Ca 1e-3..1e-1), Dynamic IB, FP32."""

@@ -299,6 +299,41 @@ def test_wall_detachment_leaves_the_wall():
     assert all(b <= a + 1e-4 for a, b in zip(ds[peak:], ds[peak + 1:])), ds
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("real_bytes", [4, 8])
+def test_dense_suspension_full_horizon(real_bytes):
+    """The Sec. 3.4 dense suspension (130 x 81 channel, 16 biconcave capsules
+    at about 30 % hematocrit, contact force on) over t u_max / H = 2 (8000
+    steps): every capsule's centroid, D and perimeter change at each quarter
+    of the run, and the sampled state with all 16 capsules at the end.  FP32
+    to the bars of this file; FP64 to 1e-3 of them."""
+    ref = golden("long_dense.json")
+    cfg = wl.dense_suspension(real_bytes=real_bytes)
+    scale = bar_scale(real_bytes)
+    steps = ref["steps"]
+    assert steps == cfg["steps"] == ref["trajectory"][-1]["steps"]
+    u_max = cfg["u_max"]
+    sim = lbib.Sim(cfg)
+    worst = {"c": 0.0, "D": 0.0, "dp": 0.0}
+    done = 0
+    for r in ref["trajectory"]:
+        sim.step(r["steps"] - done, "kinematic")
+        done = r["steps"]
+        for c, rd in enumerate(r["diag"]):
+            d = sim.diag(c)
+            e_c = max(abs(d["cx"] - rd["cx"]), abs(d["cy"] - rd["cy"]))
+            worst = {"c": max(worst["c"], e_c), "D": max(worst["D"], abs(d["D"] - rd["D"])),
+                     "dp": max(worst["dp"], abs(d["dp"] - rd["dp"]))}
+            assert e_c <= 1e-5 * u_max * r["steps"] * scale, (r["steps"], c, d, rd)
+            assert abs(d["D"] - rd["D"]) <= 1e-4 * scale, (r["steps"], c, d["D"], rd["D"])
+            assert abs(d["dp"] - rd["dp"]) <= 1e-4 * scale, (r["steps"], c, d["dp"], rd["dp"])
+    log(f"dense suspension ({8 * real_bytes} bit): centroid {worst['c']:.2e}, D {worst['D']:.2e}, "
+        f"dp {worst['dp']:.2e}")
+    assert sim.check() == 0
+    compare_snapshot(sim, 0, list(range(16)), ref, steps,
+                     f"dense 130x81 ({8 * real_bytes} bit), {steps} steps", u_max=u_max, scale=scale)
+
+
 def test_golden_samples_follow_their_seed():
     """The stored sample cells are the ones the generator's seed draws on each
     workload's lattice, the ensemble lattices the ones its pick seed draws, and
@@ -309,7 +344,8 @@ def test_golden_samples_follow_their_seed():
     mk = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mk)
     dims = {"poiseuille_biconcave": (1024, 256), "inertial_capsules": (2048, 512),
-            "couette_migration": (256, 101), "wall_detachment": (128, 101)}
+            "couette_migration": (256, 101), "wall_detachment": (128, 101),
+            "dense_suspension": (130, 81)}
     found = 0
     for name in sorted(os.listdir(GOLDEN)):
         if not (name.startswith("long_") and name.endswith(".json")):

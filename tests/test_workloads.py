@@ -66,3 +66,31 @@ def test_wall_detachment_figures():
     np.testing.assert_allclose(np.hypot(*(nodes - (64.0, 15.5)).T), 12.5, atol=1e-12)
     assert nodes[:, 1].min() >= 3.0
     assert abs(cap["ks"] - 0.1) < 1e-12 and cap["kb"] == 0.0 and len(nodes) == 100
+
+
+def test_dense_suspension_figures():
+    """Sec. 3.4 set-up at about 30 % hematocrit: 16 biconcave capsules of
+    length 30 fill a 130 x 81 channel (capsule area over channel area between
+    0.29 and 0.32); every node keeps 3 lattice units off the walls; capsules
+    of neighbouring rows and columns (x periodic) start within the contact
+    cutoff of one another but do not overlap; the horizon t u_max / H = 2 is
+    8000 steps; the draw repeats for a seed and changes with it."""
+    cfg = wl.dense_suspension()
+    assert (cfg["nx"], cfg["ny"]) == (130, 81) and cfg["steps"] == 8000
+    assert 0.29 <= cfg["hematocrit"] <= 0.32, cfg["hematocrit"]
+    assert cfg["contact_cutoff"] == 2.0 and cfg["init_profile"] == wl.INIT_POISEUILLE
+    caps = [c["nodes"] for c in cfg["capsules"]]
+    assert len(caps) == 16
+    ys = np.concatenate([c[:, 1] for c in caps])
+    assert ys.min() >= 3.0 and ys.max() <= cfg["ny"] - 4
+    dmin = np.inf
+    for a in range(16):
+        for b in range(a + 1, 16):
+            for sh in (-cfg["nx"], 0, cfg["nx"]):
+                d = caps[a][:, None, :] - (caps[b][None, :, :] + [sh, 0.0])
+                dmin = min(dmin, float(np.hypot(d[..., 0], d[..., 1]).min()))
+    assert 0.5 < dmin < cfg["contact_cutoff"], dmin
+    again = wl.dense_suspension()
+    assert all(np.array_equal(a["nodes"], b["nodes"]) for a, b in zip(cfg["capsules"], again["capsules"]))
+    other = wl.dense_suspension(seed=1)
+    assert not np.array_equal(cfg["capsules"][0]["nodes"], other["capsules"][0]["nodes"])
