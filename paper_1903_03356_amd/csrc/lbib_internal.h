@@ -16,6 +16,13 @@ constexpr int kIBThreads = 512;  // IB kernel block (one block per capsule)
 // work arrays (kNodeScratch)
 constexpr int kNodeScratch = 22;
 constexpr int kNodeLdsArrays = 12 + kNodeScratch;
+// contact kernel: at most this many thread groups share one capsule's pairs;
+// its LDS holds eight FP64 node arrays and two FP64 partial sums per thread
+constexpr int kContactGroups = 8;
+constexpr size_t contact_lds_bytes(int max_nv)
+{
+    return sizeof(double) * (8 * (size_t)max_nv + 2 * (size_t)kIBThreads);
+}
 
 // The spread force is accumulated as a signed 64-bit fixed-point number with
 // 48 fractional bits.  Integer addition is associative, so the sum of

@@ -1833,6 +1833,13 @@ __global__ __launch_bounds__(kIBThreads) void k_bounds(ContactArgs<T> a)
 // node's two elements.  Distances take the nearest periodic image.  One
 // block per capsule; capsules whose boxes (grown by the cutoff) miss this
 // one's are skipped, the others are staged in LDS.  FP64.
+// The pairs (node of this capsule, node of the other) are dealt to
+// K = min(nt / nv, kContactGroups) groups of nv threads: thread t takes node
+// t % nv against every K-th node of the other capsule from t / nv on, and the
+// K partial sums of a node are added in group order (fixed, so runs repeat bit
+// for bit).  The periodic image needs the division only where |dx| exceeds
+// half the period (below it the rounded quotient is 0), and the root and the
+// force only for pairs whose squared distance is below the cutoff's.
 template <typename T>
 __global__ __launch_bounds__(kIBThreads) void k_contact(ContactArgs<T> a)
 {
@@ -1850,6 +1857,8 @@ __global__ __launch_bounds__(kIBThreads) void k_contact(ContactArgs<T> a)
     double* FY = FX + a.max_nv;
     double* BX = FY + a.max_nv;  // the other capsule, in this capsule's frame
     double* BY = BX + a.max_nv;
+    double* PX = BY + a.max_nv;  // per-thread partial sums, nt each
+    double* PY = PX + nt;
     for (int v = tid; v < nv; v += nt) {
         X[v] = (double)N[NF_HX * NS + off + v] + (double)N[NF_LX * NS + off + v];
         Y[v] = (double)N[NF_HY * NS + off + v] + (double)N[NF_LY * NS + off + v];
@@ -1870,6 +1879,11 @@ __global__ __launch_bounds__(kIBThreads) void k_contact(ContactArgs<T> a)
     const double Lx = cap.nx, Ly = cap.ny;
     const double C = 1e-4 / (8.0 * sqrt(2.0));
     const float cut = (float)a.cutoff;
+    // squared-distance screen, a little wider than the cutoff: every pair the
+    // exact test below accepts passes it
+    const double cut2 = a.cutoff * a.cutoff * (1.0 + 1e-6);
+    const int K = nv > 0 ? max(1, min(nt / nv, kContactGroups)) : 1;
+    const int vq = nv > 0 ? tid % nv : 0, kq = nv > 0 ? tid / nv : 0;
     for (int o = 0; o < a.ncap; o++) {
         if (o == c) continue;
         const CapsuleDev oc = a.caps[o];
@@ -1892,21 +1906,46 @@ __global__ __launch_bounds__(kIBThreads) void k_contact(ContactArgs<T> a)
                     (double)N[NF_LY * NS + oc.node_offset + j];
         }
         __syncthreads();
-        for (int v = tid; v < nv; v += nt) {
-            double fx = 0.0, fy = 0.0;
-            for (int j = 0; j < oc.nv; j++) {
-                double dx = BX[j] - X[v], dy = BY[j] - Y[v];
-                if (cap.periodic_x) dx -= Lx * rint(dx / Lx);
-                if (cap.periodic_y) dy -= Ly * rint(dy / Ly);
-                const double d = sqrt(dx * dx + dy * dy);
-                if (d < a.cutoff && d > 0.0) {
-                    const double mag = C * sqrt(1.0 / (d * d * d * d * d));
-                    fx += mag * IX[v];
-                    fy += mag * IY[v];
+        // the force on node v from nodes j0, j0 + step, ... of the other capsule
+        auto pair_sum = [&](int v, int j0, int step, double& fx, double& fy) {
+            const double xv = X[v], yv = Y[v];
+            for (int j = j0; j < oc.nv; j += step) {
+                double dx = BX[j] - xv, dy = BY[j] - yv;
+                if (cap.periodic_x && fabs(dx) > 0.5 * Lx) dx -= Lx * rint(dx / Lx);
+                if (cap.periodic_y && fabs(dy) > 0.5 * Ly) dy -= Ly * rint(dy / Ly);
+                const double d2 = dx * dx + dy * dy;
+                if (d2 < cut2) {
+                    const double d = sqrt(d2);
+                    if (d < a.cutoff && d > 0.0) {
+                        const double mag = C * sqrt(1.0 / (d * d * d * d * d));
+                        fx += mag * IX[v];
+                        fy += mag * IY[v];
+                    }
                 }
             }
-            FX[v] += fx;
-            FY[v] += fy;
+        };
+        if (K == 1) {
+            for (int v = tid; v < nv; v += nt) {
+                double fx = 0.0, fy = 0.0;
+                pair_sum(v, 0, 1, fx, fy);
+                FX[v] += fx;
+                FY[v] += fy;
+            }
+        } else {
+            double fx = 0.0, fy = 0.0;
+            if (kq < K) pair_sum(vq, kq, K, fx, fy);
+            PX[tid] = fx;
+            PY[tid] = fy;
+            __syncthreads();
+            for (int v = tid; v < nv; v += nt) {
+                double sx = 0.0, sy = 0.0;
+                for (int k = 0; k < K; k++) {
+                    sx += PX[v + k * nv];
+                    sy += PY[v + k * nv];
+                }
+                FX[v] += sx;
+                FY[v] += sy;
+            }
         }
     }
     T* W = a.nodes;
@@ -1921,7 +1960,7 @@ hipError_t contact_set_lds_limit(int max_nv)
 {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_contact<T>),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(8 * sizeof(double) * (size_t)max_nv));
+                               (int)(contact_lds_bytes(max_nv)));
 }
 
 template <typename T>
@@ -1930,7 +1969,7 @@ hipError_t launch_contact(const ContactArgs<T>& a, hipStream_t s)
     if (a.ncap <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_bounds<T>, dim3(a.ncap), dim3(kIBThreads), 0, s, a);
     hipLaunchKernelGGL(k_contact<T>, dim3(a.ncap), dim3(kIBThreads),
-                       8 * sizeof(double) * (size_t)a.max_nv, s, a);
+                       contact_lds_bytes(a.max_nv), s, a);
     return hipGetLastError();
 }
 
