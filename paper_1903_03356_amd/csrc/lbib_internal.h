@@ -19,6 +19,7 @@ constexpr int kNodeLdsArrays = 12 + kNodeScratch;
 // contact kernel: at most this many thread groups share one capsule's pairs;
 // its LDS holds eight FP64 node arrays and two FP64 partial sums per thread
 constexpr int kContactGroups = 8;
+constexpr int kContactChunk = 128;  // capsule records staged per round in the contact kernel
 constexpr size_t contact_lds_bytes(int max_nv)
 {
     return sizeof(double) * (8 * (size_t)max_nv + 2 * (size_t)kIBThreads);

@@ -1837,9 +1837,11 @@ __global__ __launch_bounds__(kIBThreads) void k_bounds(ContactArgs<T> a)
 // K = min(nt / nv, kContactGroups) groups of nv threads: thread t takes node
 // t % nv against every K-th node of the other capsule from t / nv on, and the
 // K partial sums of a node are added in group order (fixed, so runs repeat bit
-// for bit).  The periodic image needs the division only where |dx| exceeds
-// half the period (below it the rounded quotient is 0), and the root and the
-// force only for pairs whose squared distance is below the cutoff's.
+// for bit).  The other capsules' records are staged in LDS in chunks, and
+// each capsule is staged at the periodic image nearest to this one, so that a
+// pair's own image needs the division only where |dx| still exceeds half the
+// period (below it the rounded quotient is 0); the root and the force only for
+// pairs whose squared distance is below the cutoff's.
 template <typename T>
 __global__ __launch_bounds__(kIBThreads) void k_contact(ContactArgs<T> a)
 {
@@ -1884,67 +1886,89 @@ __global__ __launch_bounds__(kIBThreads) void k_contact(ContactArgs<T> a)
     const double cut2 = a.cutoff * a.cutoff * (1.0 + 1e-6);
     const int K = nv > 0 ? max(1, min(nt / nv, kContactGroups)) : 1;
     const int vq = nv > 0 ? tid % nv : 0, kq = nv > 0 ? tid / nv : 0;
-    for (int o = 0; o < a.ncap; o++) {
-        if (o == c) continue;
-        const CapsuleDev oc = a.caps[o];
-        if (oc.inst != cap.inst) continue;
-        const float4 ob = a.bounds[o];
-        // box test with the nearest periodic image in x (and y when periodic)
-        float sx = (0.5f * (ob.x + ob.z)) - (0.5f * (me.x + me.z));
-        if (cap.periodic_x) sx -= (float)Lx * rintf(sx / (float)Lx);
-        float sy = (0.5f * (ob.y + ob.w)) - (0.5f * (me.y + me.w));
-        if (cap.periodic_y) sy -= (float)Ly * rintf(sy / (float)Ly);
-        const float hx = 0.5f * ((ob.z - ob.x) + (me.z - me.x)) + cut;
-        const float hy = 0.5f * ((ob.w - ob.y) + (me.w - me.y)) + cut;
-        if (fabsf(sx) > hx || fabsf(sy) > hy) continue;
-        __syncthreads();
-        const double rx = oc.ref_x - cap.ref_x, ry = oc.ref_y - cap.ref_y;
-        for (int j = tid; j < oc.nv; j += nt) {
-            BX[j] = rx + (double)N[NF_HX * NS + oc.node_offset + j] +
-                    (double)N[NF_LX * NS + oc.node_offset + j];
-            BY[j] = ry + (double)N[NF_HY * NS + oc.node_offset + j] +
-                    (double)N[NF_LY * NS + oc.node_offset + j];
+    // the other capsules' records, kContactChunk at a time, one per thread
+    // (their loads in flight together, not one dependent load per capsule)
+    __shared__ float4 s_box[kContactChunk];
+    __shared__ double s_rx[kContactChunk], s_ry[kContactChunk];
+    __shared__ int s_nv[kContactChunk], s_off[kContactChunk], s_inst[kContactChunk];
+    for (int o0 = 0; o0 < a.ncap; o0 += kContactChunk) {
+        const int m = min(kContactChunk, a.ncap - o0);
+        __syncthreads();  // the last chunk's records are read no more
+        if (tid < m) {
+            const CapsuleDev& r = a.caps[o0 + tid];
+            s_box[tid] = a.bounds[o0 + tid];
+            s_rx[tid] = r.ref_x;
+            s_ry[tid] = r.ref_y;
+            s_nv[tid] = r.nv;
+            s_off[tid] = r.node_offset;
+            s_inst[tid] = r.inst;
         }
         __syncthreads();
-        // the force on node v from nodes j0, j0 + step, ... of the other capsule
-        auto pair_sum = [&](int v, int j0, int step, double& fx, double& fy) {
-            const double xv = X[v], yv = Y[v];
-            for (int j = j0; j < oc.nv; j += step) {
-                double dx = BX[j] - xv, dy = BY[j] - yv;
-                if (cap.periodic_x && fabs(dx) > 0.5 * Lx) dx -= Lx * rint(dx / Lx);
-                if (cap.periodic_y && fabs(dy) > 0.5 * Ly) dy -= Ly * rint(dy / Ly);
-                const double d2 = dx * dx + dy * dy;
-                if (d2 < cut2) {
-                    const double d = sqrt(d2);
-                    if (d < a.cutoff && d > 0.0) {
-                        const double mag = C * sqrt(1.0 / (d * d * d * d * d));
-                        fx += mag * IX[v];
-                        fy += mag * IY[v];
+        for (int q = 0; q < m; q++) {
+            const int o = o0 + q;
+            if (o == c || s_inst[q] != cap.inst) continue;
+            const float4 ob = s_box[q];
+            const int onv = s_nv[q], ooff = s_off[q];
+            // box test with the nearest periodic image in x (and y when periodic)
+            float sx = (0.5f * (ob.x + ob.z)) - (0.5f * (me.x + me.z));
+            const float ix = cap.periodic_x ? rintf(sx / (float)Lx) : 0.0f;
+            sx -= (float)Lx * ix;
+            float sy = (0.5f * (ob.y + ob.w)) - (0.5f * (me.y + me.w));
+            const float iy = cap.periodic_y ? rintf(sy / (float)Ly) : 0.0f;
+            sy -= (float)Ly * iy;
+            const float hx = 0.5f * ((ob.z - ob.x) + (me.z - me.x)) + cut;
+            const float hy = 0.5f * ((ob.w - ob.y) + (me.w - me.y)) + cut;
+            if (fabsf(sx) > hx || fabsf(sy) > hy) continue;
+            __syncthreads();
+            // staged at the periodic image nearest to this capsule (box centres),
+            // so that the pair loop rarely needs the image division
+            const double rx = s_rx[q] - cap.ref_x - (double)ix * Lx;
+            const double ry = s_ry[q] - cap.ref_y - (double)iy * Ly;
+            for (int j = tid; j < onv; j += nt) {
+                BX[j] = rx + (double)N[NF_HX * NS + ooff + j] + (double)N[NF_LX * NS + ooff + j];
+                BY[j] = ry + (double)N[NF_HY * NS + ooff + j] + (double)N[NF_LY * NS + ooff + j];
+            }
+            __syncthreads();
+            // the force on node v from nodes j0, j0 + step, ... of the other capsule
+            auto pair_sum = [&](int v, int j0, int step, double& fx, double& fy) {
+                const double xv = X[v], yv = Y[v];
+                for (int j = j0; j < onv; j += step) {
+                    double dx = BX[j] - xv, dy = BY[j] - yv;
+                    if (cap.periodic_x && fabs(dx) > 0.5 * Lx) dx -= Lx * rint(dx / Lx);
+                    if (cap.periodic_y && fabs(dy) > 0.5 * Ly) dy -= Ly * rint(dy / Ly);
+                    const double d2 = dx * dx + dy * dy;
+                    if (d2 < cut2) {
+                        const double d = sqrt(d2);
+                        if (d < a.cutoff && d > 0.0) {
+                            const double mag = C * sqrt(1.0 / (d * d * d * d * d));
+                            fx += mag * IX[v];
+                            fy += mag * IY[v];
+                        }
                     }
                 }
-            }
-        };
-        if (K == 1) {
-            for (int v = tid; v < nv; v += nt) {
-                double fx = 0.0, fy = 0.0;
-                pair_sum(v, 0, 1, fx, fy);
-                FX[v] += fx;
-                FY[v] += fy;
-            }
-        } else {
-            double fx = 0.0, fy = 0.0;
-            if (kq < K) pair_sum(vq, kq, K, fx, fy);
-            PX[tid] = fx;
-            PY[tid] = fy;
-            __syncthreads();
-            for (int v = tid; v < nv; v += nt) {
-                double sx = 0.0, sy = 0.0;
-                for (int k = 0; k < K; k++) {
-                    sx += PX[v + k * nv];
-                    sy += PY[v + k * nv];
+            };
+            if (K == 1) {
+                for (int v = tid; v < nv; v += nt) {
+                    double fx = 0.0, fy = 0.0;
+                    pair_sum(v, 0, 1, fx, fy);
+                    FX[v] += fx;
+                    FY[v] += fy;
                 }
-                FX[v] += sx;
-                FY[v] += sy;
+            } else {
+                double fx = 0.0, fy = 0.0;
+                if (kq < K) pair_sum(vq, kq, K, fx, fy);
+                PX[tid] = fx;
+                PY[tid] = fy;
+                __syncthreads();
+                for (int v = tid; v < nv; v += nt) {
+                    double sx = 0.0, sy = 0.0;
+                    for (int k = 0; k < K; k++) {
+                        sx += PX[v + k * nv];
+                        sy += PY[v + k * nv];
+                    }
+                    FX[v] += sx;
+                    FY[v] += sy;
+                }
             }
         }
     }
