@@ -433,6 +433,9 @@ def main() -> int:
                     help="tile shape order,rows,resident of --only-ensemble-grid")
     ap.add_argument("--only-adjoint", action="store_true",
                     help="only the gradient cost against the forward run")
+    ap.add_argument("--only-contact", action="store_true",
+                    help="time only the workloads with the Eq. 27 contact force (dense suspension, "
+                         "multi-body open channel) and print their JSON")
     ap.add_argument("--only-channels", action="store_true",
                     help="only the 1024x256 biconcave channel and the 2048x512 channel with 32 "
                          "capsules, both couplings (IB-latency-bound workloads, trace runs)")
@@ -469,6 +472,15 @@ def main() -> int:
     if args.only_adjoint:
         adj = [bench_adjoint("dynamic", 500), bench_adjoint("kinematic", 5000)]
         print(json.dumps({"adjoint": adj}), flush=True)
+        return 0
+    if args.only_contact:
+        cs = wl.dense_suspension()
+        rd = time_gpu(cs, args.steps, args.warmup, timing=False)
+        del rd["sim"]
+        out = {"dense_130x81_kinematic_us_per_step": round(rd["ms_per_step"] * 1e3, 2),
+               "hematocrit": round(cs["hematocrit"], 4),
+               "multi_body_open_channel": bench_multi(args.steps, args.warmup)}
+        print(json.dumps({"contact": out}), flush=True)
         return 0
     if args.only_channels:
         out = {}
