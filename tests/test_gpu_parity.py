@@ -252,6 +252,53 @@ def test_dense_suspension_window(mode, real_bytes):
     assert g.check() == 0
 
 
+def crowded_contact_channel(real_bytes: int, mode: str):
+    """132 capsules with the contact force on one 320 x 200 channel: two large
+    capsules (R = 20, 300 nodes; their FP64 patch fits beside 300 nodes of node
+    state) 1.5 lattice units apart, and 130 small ones
+    (R = 2, 12 nodes) in a 20 x 7 block at a 5.5 pitch, 1.5 apart.  More
+    capsules than the contact kernel reads in one round of records, and nodes
+    enough on the large pair that one thread group takes all of a node's pairs."""
+    tau, u_max, ca = 0.8, 0.01, 1e-2
+    ny = 200
+    cfg = wl._base("crowded320x200", 320, ny, tau, real_bytes, mode, 0,
+                   body_force_x=wl.poiseuille_body_force(tau, ny, u_max),
+                   init_profile=wl.INIT_POISEUILLE)
+    ks = wl.ks_from_ca(tau, u_max, ca)
+    caps = [wl.capsule(wl.circle_nodes(60.0, 100.0, 20.0, 300), ks, 0.0, 1.0, 1.0),
+            wl.capsule(wl.circle_nodes(101.5, 100.0, 20.0, 300, phase=0.0), ks, 0.0, 1.0, 1.0)]
+    for k in range(130):
+        i, j = k % 20, k // 20
+        caps.append(wl.capsule(wl.circle_nodes(200.0 + 5.5 * i, 70.0 + 5.5 * j, 2.0, 12),
+                               ks, 0.0, 1.0, 1.0))
+    cfg["capsules"] = caps
+    cfg["contact_cutoff"] = 2.0
+    return cfg
+
+
+@pytest.mark.parametrize("mode,real_bytes", [("kinematic", 8), ("dynamic", 8), ("kinematic", 4)])
+def test_contact_many_capsules(mode, real_bytes):
+    """The contact force (Eq. 27) with 132 capsules on one lattice, some of 300
+    nodes: fields, nodes and diagnostics of every capsule against the oracle
+    after 20 steps, the force acting on the large pair and on the block."""
+    n = _steps(20)
+    cfg = crowded_contact_channel(real_bytes, mode)
+    log(f"crowded contact channel 320x200 {mode} real_bytes={real_bytes} steps={n}")
+    g, o = pair(cfg)
+    for chunk in (1, n - 1):
+        g.step(chunk)
+        o.step(chunk)
+    assert np.abs(o.contact(0)).max() > 0 and np.abs(o.contact(1)).max() > 0
+    assert np.abs(o.contact(131)).max() > 0
+    if real_bytes == 8:
+        compare_fields(g, o, 1e-10, 1e-12)
+        compare_capsules(g, o, 1e-10, 1e-10)
+    else:
+        compare_fields(g, o, 1e-5, 1e-6)
+        compare_capsules(g, o, 1e-4, 1e-4)
+    assert g.check() == 0
+
+
 def test_inertial_capsules_fp32():
     """2048 x 512 channel, 32 seeded capsules (circular and biconcave, density
     ratio 1-2, Ca 1e-3..1e-1), Dynamic IB, FP32."""
